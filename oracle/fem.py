@@ -1,0 +1,331 @@
+"""Q1 hexahedral finite elements, written plainly in NumPy (FP64).
+
+Oracle module (test infrastructure only).  Each function cites the passage of
+the paper it follows.
+
+* Isotropic linear elasticity: K_e = int B^T D B dX with Lame constants from
+  (E, nu); used by the linear cube experiments (section 5.1).
+* Holzapfel-Gasser-Ogden material (section 2, eqs. (decompositionStrain),
+  (iso), (aniso_1), (aniso_2)): the strain energy is written out, the second
+  Piola-Kirchhoff stress follows the additive split of eq. (additiveStress),
+  and the volumetric part uses a pressure that is constant per element and
+  condensed element-wise (section 3.2, static condensation, P0 pressure).
+* The element internal force is the weak form of eq. (WeakReference); the
+  consistent tangent of eq. (Tangent) is obtained as the exact derivative of
+  that internal force by complex-step differentiation, so no closed-form
+  elasticity tensor is needed here (the paper leaves it to its references).
+* Follower pressure on the current surface without load stiffness
+  (section 3.2, last paragraph).
+
+Quadrature: 2x2x2 Gauss points at +-1/sqrt(3) for volumes, 2x2 for faces.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# reference corner coordinates of local node a = i + 2j + 4k
+XI = np.array([[2 * (a & 1) - 1, 2 * ((a >> 1) & 1) - 1, 2 * ((a >> 2) & 1) - 1]
+               for a in range(8)], dtype=np.float64)
+_G = 1.0 / np.sqrt(3.0)
+GAUSS_PTS = XI * _G          # 8 points, unit weights
+
+
+def shape_hex8(xi):
+    """Trilinear shape functions N_a and dN_a/dxi at one reference point."""
+    xi = np.asarray(xi, dtype=np.float64)
+    f = 1.0 + XI * xi[None, :]             # (8,3)
+    N = 0.125 * f.prod(axis=1)
+    dN = np.empty((8, 3))
+    for k in range(3):
+        others = [d for d in range(3) if d != k]
+        dN[:, k] = 0.125 * XI[:, k] * f[:, others[0]] * f[:, others[1]]
+    return N, dN
+
+
+_SHAPES = [shape_hex8(g) for g in GAUSS_PTS]
+
+
+def ref_gradients(Xe):
+    """For each Gauss point: (N, dN/dX [ne,8,3], detJ [ne]) of elements Xe [ne,8,3]."""
+    out = []
+    for N, dNxi in _SHAPES:
+        Jm = np.einsum("ead,ak->edk", Xe, dNxi)           # dX_d/dxi_k
+        det = np.linalg.det(Jm)
+        inv = np.linalg.inv(Jm)                             # dxi_k/dX_d
+        dNX = np.einsum("ak,ekd->ead", dNxi, inv)
+        out.append((N, dNX, det))
+    return out
+
+
+def lame(E, nu):
+    E = np.asarray(E, dtype=np.float64)
+    nu = np.asarray(nu, dtype=np.float64)
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+def linear_stiffness(Xe, lam, mu):
+    """Element stiffness of isotropic linear elasticity, K_e[3a+i, 3b+j].
+
+    The bilinear form is int (lam div v div w + 2 mu eps(v):eps(w)) dX, i.e.
+    K_{ai,bj} = int lam dN_a/dX_i dN_b/dX_j + mu (dN_a/dX_j dN_b/dX_i
+    + delta_ij grad N_a . grad N_b) dX.
+    """
+    ne = Xe.shape[0]
+    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (ne,))
+    mu = np.broadcast_to(np.asarray(mu, dtype=np.float64), (ne,))
+    K = np.zeros((ne, 8, 3, 8, 3))
+    eye = np.eye(3)
+    for _, dN, det in ref_gradients(Xe):
+        w = det
+        t1 = np.einsum("eai,ebj->eaibj", dN, dN)
+        t2 = np.einsum("eaj,ebi->eaibj", dN, dN)
+        dot = np.einsum("eak,ebk->eab", dN, dN)
+        t3 = dot[:, :, None, :, None] * eye[None, None, :, None, :]
+        K += w[:, None, None, None, None] * (lam[:, None, None, None, None] * t1
+                                             + mu[:, None, None, None, None] * (t2 + t3))
+    return K.reshape(ne, 24, 24)
+
+
+def body_force_vector(Xe, b):
+    """f_e[3a+i] = int N_a b_i dX for a force b [ne,3] per unit reference volume."""
+    ne = Xe.shape[0]
+    f = np.zeros((ne, 8, 3))
+    for N, _, det in ref_gradients(Xe):
+        f += det[:, None, None] * N[None, :, None] * b[:, None, :]
+    return f.reshape(ne, 24)
+
+
+# ---------------------------------------------------------------------------
+# Holzapfel-Gasser-Ogden model
+# ---------------------------------------------------------------------------
+
+def _inv3(A):
+    """Inverse and determinant of a stack of 3x3 matrices (real or complex)."""
+    a, b, c = A[..., 0, 0], A[..., 0, 1], A[..., 0, 2]
+    d, e, f = A[..., 1, 0], A[..., 1, 1], A[..., 1, 2]
+    g, h, i = A[..., 2, 0], A[..., 2, 1], A[..., 2, 2]
+    co00 = e * i - f * h
+    co01 = -(d * i - f * g)
+    co02 = d * h - e * g
+    det = a * co00 + b * co01 + c * co02
+    inv = np.empty_like(A)
+    inv[..., 0, 0] = co00
+    inv[..., 1, 0] = co01
+    inv[..., 2, 0] = co02
+    inv[..., 0, 1] = -(b * i - c * h)
+    inv[..., 1, 1] = a * i - c * g
+    inv[..., 2, 1] = -(a * h - b * g)
+    inv[..., 0, 2] = b * f - c * e
+    inv[..., 1, 2] = -(a * f - c * d)
+    inv[..., 2, 2] = a * e - b * d
+    inv /= det[..., None, None]
+    return inv, det
+
+
+def _fibre_terms(C, Jm23, a, k1, k2):
+    """E = Ibar_4 - 1, the fibre stretch measure, and dPsi/dIbar_4 (zero unless E > 0)."""
+    I4 = Jm23 * np.einsum("...i,...ij,...j->...", a, C, a)
+    E = I4 - 1.0
+    active = np.real(E) > 0.0                 # fibres carry tension only (section 2)
+    dpsi = np.where(active, k1 * E * np.exp(k2 * E * E), 0.0)
+    psi = np.where(active, k1 / (2.0 * k2) * (np.exp(k2 * E * E) - 1.0), 0.0)
+    return E, dpsi, psi
+
+
+def hgo_isochoric_energy(C, a1, a2, c, k1, k2):
+    """Psi_iso + Psi_aniso(a1) + Psi_aniso(a2) of eqs. (iso), (aniso_1), (aniso_2)."""
+    _, J2 = _inv3(C)
+    Jm23 = J2 ** (-1.0 / 3.0)
+    I1 = Jm23 * np.einsum("...ii->...", C)
+    _, _, p4 = _fibre_terms(C, Jm23, a1, k1, k2)
+    _, _, p6 = _fibre_terms(C, Jm23, a2, k1, k2)
+    return 0.5 * c * (I1 - 3.0) + p4 + p6
+
+
+def hgo_isochoric_stress(C, a1, a2, c, k1, k2):
+    """S_iso = 2 dPsi_bar/dC for the HGO energy (isochoric part of eq. (additiveStress)).
+
+    With Sbar = c I + 2 psi4' a1(x)a1 + 2 psi6' a2(x)a2 the chain rule through
+    Cbar = J^{-2/3} C gives S_iso = J^{-2/3} (Sbar - (Sbar:C)/3 C^{-1}).
+    Works for complex input (used for complex-step derivatives).
+    """
+    Cinv, J2 = _inv3(C)
+    Jm23 = J2 ** (-1.0 / 3.0)
+    _, d4, _ = _fibre_terms(C, Jm23, a1, k1, k2)
+    _, d6, _ = _fibre_terms(C, Jm23, a2, k1, k2)
+    eye = np.eye(3)
+    Sbar = (np.asarray(c)[..., None, None] * eye + 2.0 * d4[..., None, None] * np.einsum("...i,...j->...ij", a1, a1)
+            + 2.0 * d6[..., None, None] * np.einsum("...i,...j->...ij", a2, a2))
+    tr = np.einsum("...ij,...ij->...", Sbar, C)
+    return Jm23[..., None, None] * (Sbar - (tr / 3.0)[..., None, None] * Cinv)
+
+
+def _deformation(Xe, Ue):
+    """Per Gauss point: (N, dN/dX, detJ0, F) with F = I + Grad U."""
+    out = []
+    eye = np.eye(3)
+    for N, dNX, det0 in ref_gradients(Xe):
+        F = eye[None] + np.einsum("eai,eaJ->eiJ", Ue, dNX)
+        out.append((N, dNX, det0, F))
+    return out
+
+
+def hgo_element_energy(Xe, Ue, a1, a2, c, k1, k2, kappa):
+    """Pi_e = int Psi_bar(C) dX + V_e kappa/2 (Jbar_e - 1)^2 with Jbar_e = v_e / V_e.
+
+    The volumetric energy Psi_vol = kappa/2 (J-1)^2 is evaluated on the element
+    mean dilatation, which is the element-wise condensation of a P0 pressure.
+    """
+    W = 0.0
+    V = 0.0
+    v = 0.0
+    for _, _, det0, F in _deformation(Xe, Ue):
+        C = np.einsum("...kI,...kJ->...IJ", F, F)
+        W = W + det0 * hgo_isochoric_energy(C, a1, a2, c, k1, k2)
+        _, J = _inv3(F)
+        V = V + det0
+        v = v + det0 * J
+    Jbar = v / V
+    return W + V * 0.5 * kappa * (Jbar - 1.0) ** 2
+
+
+def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa):
+    """Internal force f_e[3a+i] = dPi_e/du_ai (eq. (WeakReference), left side).
+
+    Isochoric part: int F S_iso Grad N_a dX.  Volumetric part: p_e g_a with
+    p_e = kappa (Jbar_e - 1) and g_a = dv_e/du_a = int J F^{-T} Grad N_a dX.
+    Returns (f [ne,24], p_e [ne], Jbar [ne]).
+    """
+    ne = Xe.shape[0]
+    dtype = np.result_type(Ue, np.float64)
+    f = np.zeros((ne, 8, 3), dtype=dtype)
+    g = np.zeros((ne, 8, 3), dtype=dtype)
+    V = np.zeros(ne)
+    v = np.zeros(ne, dtype=dtype)
+    for _, dNX, det0, F in _deformation(Xe, Ue):
+        C = np.einsum("ekI,ekJ->eIJ", F, F)
+        S = hgo_isochoric_stress(C, a1, a2, c, k1, k2)
+        Finv, J = _inv3(F)
+        P = np.einsum("eiI,eIJ->eiJ", F, S)
+        f += det0[:, None, None] * np.einsum("eiJ,eaJ->eai", P, dNX)
+        # J F^{-T} Grad N_a : (J F^{-T})_{iI} = J Finv_{Ii}
+        g += (det0 * J)[:, None, None] * np.einsum("eIi,eaI->eai", Finv, dNX)
+        V += det0
+        v = v + det0 * J
+    Jbar = v / V
+    p = kappa * (Jbar - 1.0)
+    f = f + p[:, None, None] * g
+    return f.reshape(ne, 24), p, Jbar
+
+
+def hgo_element_tangent(Xe, Ue, a1, a2, c, k1, k2, kappa, h=1e-30):
+    """Consistent tangent K_e = d f_e / d u_e (eq. (Tangent) with the condensed
+    pressure), computed exactly by complex-step differentiation of
+    :func:`hgo_element_force`: column (b,j) is Im f(u + i h e_bj) / h.
+    Returns (K [ne,24,24], f [ne,24]).
+    """
+    ne = Xe.shape[0]
+    f0, _, _ = hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa)
+    K = np.empty((ne, 24, 24))
+    Uc = Ue.astype(np.complex128)
+    for col in range(24):
+        a, j = divmod(col, 3)
+        Up = Uc.copy()
+        Up[:, a, j] += 1j * h
+        fc, _, _ = hgo_element_force(Xe, Up, a1, a2, c, k1, k2, kappa)
+        K[:, :, col] = fc.imag / h
+    return K, f0.real
+
+
+def pressure_face_load(xf, p):
+    """Follower pressure load on quadrilateral faces in the current geometry.
+
+    f_a = -p int N_a n da, with n da = (dx/deta1 x dx/deta2) deta; the corner
+    order makes this normal point out of the body.  xf [nf,4,3] -> [nf,4,3].
+    """
+    eta = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
+    f = np.zeros_like(xf)
+    for g1 in (-_G, _G):
+        for g2 in (-_G, _G):
+            N = 0.25 * (1 + eta[:, 0] * g1) * (1 + eta[:, 1] * g2)
+            d1 = 0.25 * eta[:, 0] * (1 + eta[:, 1] * g2)
+            d2 = 0.25 * eta[:, 1] * (1 + eta[:, 0] * g1)
+            t1 = np.einsum("fad,a->fd", xf, d1)
+            t2 = np.einsum("fad,a->fd", xf, d2)
+            n = np.cross(t1, t2)
+            f += -p * N[None, :, None] * n[:, None, :]
+    return f
+
+
+# ---------------------------------------------------------------------------
+# global assembly
+# ---------------------------------------------------------------------------
+
+def _elem_material(mesh):
+    m = mesh.mat[mesh.elem_mat]
+    return m
+
+
+def element_matrices(mesh, U=None, chunk=4096):
+    """Element tangents and internal forces for every element of ``mesh``.
+
+    Linear material: K_e = int B^T D B and f_int = K_e u_e.  HGO: exact tangent
+    and internal force at displacement U (global [n_nodes,3] or None = 0).
+    """
+    from workloads.meshes import MAT_HGO
+    ne = mesh.n_elems
+    Xe = mesh.xyz[mesh.hex8]
+    Ue = np.zeros_like(Xe) if U is None else np.asarray(U).reshape(-1, 3)[mesh.hex8]
+    m = _elem_material(mesh)
+    Ke = np.empty((ne, 24, 24))
+    fe = np.zeros((ne, 24))
+    hgo = m[:, 0] == MAT_HGO
+    lin = ~hgo
+    if lin.any():
+        idx = np.nonzero(lin)[0]
+        lam, mu = lame(m[idx, 1], m[idx, 2])
+        for s in range(0, idx.size, chunk):
+            ii = idx[s:s + chunk]
+            Ke[ii] = linear_stiffness(Xe[ii], lam[s:s + chunk], mu[s:s + chunk])
+            fe[ii] = np.einsum("eij,ej->ei", Ke[ii], Ue[ii].reshape(-1, 24))
+    if hgo.any():
+        idx = np.nonzero(hgo)[0]
+        for s in range(0, idx.size, chunk):
+            ii = idx[s:s + chunk]
+            mm = m[ii]
+            a1 = mesh.fibers[ii, 0]
+            a2 = mesh.fibers[ii, 1]
+            K, f = hgo_element_tangent(Xe[ii], Ue[ii], a1, a2, mm[:, 3], mm[:, 4], mm[:, 5],
+                                       mm[:, 6])
+            Ke[ii] = K
+            fe[ii] = f
+    return Ke, fe
+
+
+def assemble(mesh, U=None, tau=1.0):
+    """Global tangent K (CSR), internal force f_int and external load tau*f_ext.
+
+    f_ext = body force (dead load) + follower pressure on the geometry X + U.
+    """
+    import scipy.sparse as sp
+    Ke, fe = element_matrices(mesh, U)
+    dofs = (3 * mesh.hex8[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 24)
+    rows = np.repeat(dofs, 24, axis=1).ravel()
+    cols = np.tile(dofs, (1, 24)).ravel()
+    n = mesh.n_dofs
+    K = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+    K.sum_duplicates()
+    f_int = np.bincount(dofs.ravel(), weights=fe.ravel(), minlength=n)
+    f_ext = np.zeros(n)
+    if mesh.body_force is not None:
+        Xe = mesh.xyz[mesh.hex8]
+        fb = body_force_vector(Xe, mesh.body_force)
+        f_ext += np.bincount(dofs.ravel(), weights=fb.ravel(), minlength=n)
+    if mesh.pface is not None and mesh.pressure != 0.0:
+        x = mesh.xyz + (0.0 if U is None else np.asarray(U).reshape(-1, 3))
+        fp = pressure_face_load(x[mesh.pface], mesh.pressure)
+        pd = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).ravel()
+        f_ext += np.bincount(pd, weights=fp.ravel(), minlength=n)
+    return K, f_int, tau * f_ext

@@ -1,0 +1,404 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test pins one part of the oracle so that a plausible mistake (a dropped
+term, a wrong sign, a transposed index) fails at least one of them:
+closed forms, invariants, special cases, brute force on tiny inputs and the
+convergence order the paper reports.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, monolithic, feti_ref
+from workloads import cube_mesh, kelvin_displacement, tube_mesh, config_mesh
+
+
+def _affine_element(seed=0):
+    rng = np.random.default_rng(seed)
+    A = np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+    if np.linalg.det(A) < 0:
+        A[:, 0] *= -1
+    X = (fem.XI + 1.0) * 0.5 @ A.T + rng.standard_normal(3)
+    return X, abs(np.linalg.det(A))
+
+
+def _distorted_element(seed=1):
+    rng = np.random.default_rng(seed)
+    X = (fem.XI + 1.0) * 0.5 + 0.08 * rng.standard_normal((8, 3))
+    return X
+
+
+# ---------------------------------------------------------------- Q1 linear
+def test_q1_rigid_modes_span_kernel():
+    """K_e annihilates the six rigid motions and has rank 24 - 6 = 18."""
+    X = _distorted_element()
+    lam, mu = fem.lame(1.0, 0.3)
+    K = fem.linear_stiffness(X[None], lam, mu)[0]
+    R = feti_ref.rigid_modes(X)
+    assert np.allclose(K, K.T, atol=1e-14)
+    assert np.linalg.norm(K @ R) <= 1e-13 * np.linalg.norm(K) * np.linalg.norm(R)
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(ev < 1e-10 * ev[-1]) == 6
+    assert ev[6] > 1e-6 * ev[-1]
+
+
+def test_q1_uniform_strain_energy_closed_form():
+    """For u = A x the energy u^T K u equals V (lam tr(eps)^2 + 2 mu eps:eps)."""
+    X, vol = _affine_element()
+    lam, mu = fem.lame(2.5, 0.27)
+    K = fem.linear_stiffness(X[None], lam, mu)[0]
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((3, 3))
+    u = (X @ A.T).reshape(-1)
+    eps = 0.5 * (A + A.T)
+    exact = vol * (lam * np.trace(eps) ** 2 + 2 * mu * np.sum(eps * eps))
+    assert abs(u @ K @ u - exact) <= 1e-12 * abs(exact)
+
+
+def test_body_force_total():
+    """Nodal forces of a constant body force sum to b * volume."""
+    X, vol = _affine_element(5)
+    b = np.array([[0.3, -1.0, 2.0]])
+    f = fem.body_force_vector(X[None], b)[0].reshape(8, 3)
+    assert np.allclose(f.sum(axis=0), b[0] * vol, rtol=1e-13)
+
+
+def _perturbed_cube(n, seed=0):
+    m = cube_mesh(n, 1, body_force=None)
+    rng = np.random.default_rng(seed)
+    x = m.xyz.copy()
+    inner = np.all((x > 1e-12) & (x < 1 - 1e-12), axis=1)
+    x[inner] += 0.15 / n * rng.uniform(-1, 1, size=(inner.sum(), 3))
+    m.xyz = x
+    return m
+
+
+def test_patch_test_monolithic():
+    """Linear displacement data on a distorted mesh is reproduced at every node."""
+    m = _perturbed_cube(4)
+    rng = np.random.default_rng(7)
+    A = 0.01 * rng.standard_normal((3, 3))
+    c = 0.01 * rng.standard_normal(3)
+    exact = m.xyz @ A.T + c
+    m.dir_val = exact.reshape(-1)[m.dir_dof]
+    u = monolithic.solve_linear(m)
+    assert np.max(np.abs(u - exact.reshape(-1))) <= 1e-12 * np.max(np.abs(exact)) * 10
+
+
+def _l2_error(mesh, u, exact_fn):
+    """||u - u_h||_L2 with 3x3x3 Gauss quadrature per element."""
+    g = np.sqrt(3.0 / 5.0)
+    pts = [(-g, 5 / 9), (0.0, 8 / 9), (g, 5 / 9)]
+    Xe = mesh.xyz[mesh.hex8]
+    ue = u.reshape(-1, 3)[mesh.hex8]
+    err2 = 0.0
+    for a, wa in pts:
+        for b, wb in pts:
+            for c, wc in pts:
+                N, dN = fem.shape_hex8([a, b, c])
+                x = np.einsum("a,ead->ed", N, Xe)
+                J = np.einsum("ead,ak->edk", Xe, dN)
+                det = np.linalg.det(J)
+                uh = np.einsum("a,ead->ed", N, ue)
+                d = uh - exact_fn(x)
+                err2 += np.sum(wa * wb * wc * det * np.sum(d * d, axis=1))
+    return np.sqrt(err2)
+
+
+def test_kelvin_second_order():
+    """Kelvin's solution as Dirichlet data: the L2 error of Q1 falls with order 2
+    (section 5.1, eqs. (fundSol), (L2Error), (L2Errora); Table 2 shows eoc ~ 2)."""
+    E, nu = 1.0, 0.3
+    errs = []
+    for n in (4, 8, 16):
+        m = cube_mesh(n, 1, E=E, nu=nu, body_force=None,
+                      dirichlet_fn=lambda x: kelvin_displacement(x, E, nu))
+        u = monolithic.solve_linear(m)
+        errs.append(_l2_error(m, u, lambda x: kelvin_displacement(x, E, nu)))
+    eoc = [np.log(errs[i] / errs[i + 1]) / np.log(2.0) for i in range(2)]
+    assert 1.85 < eoc[0] < 2.2 and 1.9 < eoc[1] < 2.1, (errs, eoc)
+
+
+def test_sparse_solve_matches_dense_cholesky():
+    m = config_mesh("cube8_s2")
+    K, _, f = fem.assemble(m)
+    u = monolithic.solve_linear(m)
+    free = np.setdiff1d(np.arange(m.n_dofs), m.dir_dof)
+    import scipy.linalg as sla
+    ud = sla.cho_solve(sla.cho_factor(K[free][:, free].toarray()), f[free])
+    assert np.allclose(u[free], ud, rtol=1e-12, atol=1e-15 * np.abs(ud).max())
+    r = K[free][:, free] @ u[free] - f[free]
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(f[free])
+
+
+# ---------------------------------------------------------------- FETI reference
+def _tiny_mesh():
+    # 2x1x1 elements, split into two subdomains of one element each; partial
+    # Dirichlet boundary (x = 0 face) so that classical FETI has a floating subdomain.
+    m = cube_mesh(2, 1, body_force=(0.2, -0.5, 1.0))
+    m.xyz = m.xyz * np.array([1.0, 0.5, 0.5])
+    m.hex8 = m.hex8[:0]
+    from workloads.meshes import _grid_hex, _grid_nodes
+    m.xyz = _grid_nodes(2, 1, 1, 1.0, 0.5, 0.5)
+    m.hex8, _ = _grid_hex(2, 1, 1)
+    m.elem_sub = np.array([0, 1], dtype=np.int32)
+    m.n_sub = 2
+    m.elem_mat = np.zeros(2, dtype=np.int32)
+    m.body_force = np.tile([0.2, -0.5, 1.0], (2, 1))
+    left = np.nonzero(np.isclose(m.xyz[:, 0], 0.0))[0]
+    m.dir_dof = (3 * left[:, None] + np.arange(3)).ravel()
+    m.dir_val = 0.01 * np.arange(m.dir_dof.size, dtype=np.float64)
+    return m
+
+
+@pytest.mark.parametrize("variant", ["af", "classical"])
+def test_feti_ref_matches_kkt_bruteforce(variant):
+    """Subdomain displacements of the FETI reference equal those of the full
+    saddle-point system (eqs. (classicalFetiLGS), (AFFETI)) solved densely."""
+    m = _tiny_mesh()
+    tp = feti_ref.linear_torn_problem(m, variant)
+    sol = feti_ref.FetiRef(tp, "dirichlet").solve(rtol=1e-14)
+    ub = feti_ref.kkt_bruteforce(tp)
+    for i in range(2):
+        assert np.allclose(sol["u_loc"][i], ub[i], rtol=1e-9, atol=1e-12)
+    u_mono = monolithic.solve_linear(m)
+    assert np.allclose(sol["u"], u_mono, rtol=1e-9, atol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def cube8():
+    m = config_mesh("cube8_s2")
+    return m, monolithic.solve_linear(m)
+
+
+@pytest.mark.parametrize("variant", ["af", "classical"])
+def test_feti_ref_preconditioners_agree_with_monolithic(cube8, variant):
+    m, u_ref = cube8
+    tp = feti_ref.linear_torn_problem(m, variant)
+    its = {}
+    for pc in ("identity", "lumped", "dirichlet"):
+        sol = feti_ref.FetiRef(tp, pc).solve(rtol=1e-12, track_invariants=True)
+        err = np.linalg.norm(sol["u"] - u_ref) / np.linalg.norm(u_ref)
+        assert err <= 1e-9, (pc, err)
+        its[pc] = sol["iters"]
+        if sol["n_coarse"]:
+            assert max(sol["inv_err"]) <= 1e-10          # G^T lambda_k = e
+    # Dirichlet <= lumped <= identity (Tables 2-7)
+    assert its["dirichlet"] <= its["lumped"] <= its["identity"], its
+    if variant == "af":
+        assert tp.n_lam == 2556
+    else:
+        assert tp.n_lam == 732
+
+
+def test_feti_ref_constraint_residual(cube8):
+    m, _ = cube8
+    tp = feti_ref.linear_torn_problem(m, "af")
+    sol = feti_ref.FetiRef(tp, "lumped").solve(rtol=1e-12)
+    jump = -tp.b.copy()
+    for i in range(m.n_sub):
+        jump += tp.B(i) @ sol["u_loc"][i]
+    assert np.linalg.norm(jump) <= 1e-9 * np.linalg.norm(sol["u"])
+
+
+def test_floating_subdomain_kernel_dimension_six():
+    m = config_mesh("cube8_s2")
+    tp = feti_ref.linear_torn_problem(m, "af")
+    K = tp.subs[0]["K"]
+    R = feti_ref.rigid_modes(tp.subs[0]["x"])
+    assert np.linalg.norm(K @ R) <= 1e-12 * np.linalg.norm(K) * np.linalg.norm(R)
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(ev < 1e-10 * ev[-1]) == 6
+
+
+def test_projected_operator_symmetric_psd():
+    """P^T F P is symmetric positive semi-definite (section 4.3 uses CG on it)."""
+    m = cube_mesh(4, 2)
+    tp = feti_ref.linear_torn_problem(m, "af")
+    fr = feti_ref.FetiRef(tp, "lumped")
+    n = tp.n_lam
+    Fm = np.stack([fr.F(e) for e in np.eye(n)], axis=1)
+    Gm = np.stack([fr.G(e) for e in np.eye(fr.n_coarse)], axis=1)
+    P = np.eye(n) - Gm @ np.linalg.solve(Gm.T @ Gm, Gm.T)
+    A = P.T @ Fm @ P
+    assert np.allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert ev.min() >= -1e-10 * ev.max()
+
+
+def test_af_and_classical_same_displacement():
+    m = cube_mesh(6, 3)
+    u_ref = monolithic.solve_linear(m)
+    for variant in ("af", "classical"):
+        sol = feti_ref.FetiRef(feti_ref.linear_torn_problem(m, variant), "dirichlet").solve(rtol=1e-12)
+        assert np.linalg.norm(sol["u"] - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.slow
+def test_dirichlet_condition_log_growth():
+    """kappa of Dirichlet-preconditioned AF FETI grows like (1 + log(H/h))^2:
+    kappa / (1+log(H/h))^2 stays within a factor 2.5 for H/h = 2, 4, 8."""
+    ratios = []
+    kap = {}
+    for Hh in (2, 4, 8):
+        m = cube_mesh(2 * Hh, 2)
+        tp = feti_ref.linear_torn_problem(m, "af")
+        sol = feti_ref.FetiRef(tp, "dirichlet").solve(rtol=1e-10)
+        kap[Hh] = sol["kappa"]
+        ratios.append(sol["kappa"] / (1 + np.log(Hh)) ** 2)
+    assert max(ratios) / min(ratios) <= 2.5, (kap, ratios)
+    assert kap[2] <= kap[4] <= kap[8]
+
+
+# ---------------------------------------------------------------- HGO
+HGO = dict(c=3.0, k1=2.3632, k2=0.8393)
+
+
+def _rand_F(rng, scale=0.15):
+    F = np.eye(3) + scale * rng.standard_normal((3, 3))
+    if np.linalg.det(F) < 0:
+        F[:, 0] *= -1
+    return F
+
+
+def _unit(v):
+    return v / np.linalg.norm(v)
+
+
+def test_hgo_stress_is_energy_derivative():
+    """S_iso = 2 dPsi/dC (complex-step derivative of the written-out energy)."""
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        F = _rand_F(rng, 0.2)
+        C = F.T @ F
+        a1, a2 = _unit(rng.standard_normal(3)), _unit(rng.standard_normal(3))
+        S = fem.hgo_isochoric_stress(C[None], a1[None], a2[None], **HGO)[0]
+        h = 1e-30
+        Sfd = np.zeros((3, 3))
+        for I in range(3):
+            for J in range(3):
+                dC = np.zeros((3, 3), dtype=complex)
+                dC[I, J] += 0.5j * h
+                dC[J, I] += 0.5j * h
+                Sfd[I, J] = 2 * fem.hgo_isochoric_energy((C + dC)[None], a1[None], a2[None],
+                                                         **HGO)[0].imag / h
+        assert np.allclose(S, Sfd, rtol=1e-12, atol=1e-12)
+
+
+def test_hgo_uniaxial_fibre_stress_hand_derived():
+    """Isochoric uniaxial stretch along both fibre families: the Cauchy stress
+    difference sigma_11 - sigma_22 = c (l^2 - 1/l) + 4 k1 (l^2-1) exp(k2 (l^2-1)^2) l^2."""
+    c, k1, k2 = HGO["c"], HGO["k1"], HGO["k2"]
+    e1 = np.array([1.0, 0.0, 0.0])
+    for lam in (1.05, 1.2, 1.4):
+        F = np.diag([lam, lam ** -0.5, lam ** -0.5])
+        S = fem.hgo_isochoric_stress((F.T @ F)[None], e1[None], e1[None], c, k1, k2)[0]
+        sig = F @ S @ F.T / np.linalg.det(F)
+        E = lam ** 2 - 1
+        exact = c * (lam ** 2 - 1 / lam) + 4 * k1 * E * np.exp(k2 * E * E) * lam ** 2
+        assert abs((sig[0, 0] - sig[1, 1]) - exact) <= 1e-12 * abs(exact)
+    # compression: fibres inactive, pure neo-Hooke
+    lam = 0.9
+    F = np.diag([lam, lam ** -0.5, lam ** -0.5])
+    S = fem.hgo_isochoric_stress((F.T @ F)[None], e1[None], e1[None], c, k1, k2)[0]
+    sig = F @ S @ F.T
+    assert abs((sig[0, 0] - sig[1, 1]) - c * (lam ** 2 - 1 / lam)) <= 1e-12
+
+
+def _hgo_elem(rng, scale=0.1):
+    X = _distorted_element(4)
+    U = scale * rng.standard_normal((8, 3))
+    a1, a2 = _unit(rng.standard_normal(3)), _unit(rng.standard_normal(3))
+    return X, U, a1, a2
+
+
+def test_hgo_force_is_energy_gradient_and_tangent_is_force_gradient():
+    rng = np.random.default_rng(11)
+    X, U, a1, a2 = _hgo_elem(rng)
+    kap = 50.0
+    args = (a1[None], a2[None], HGO["c"], HGO["k1"], HGO["k2"], kap)
+    f, _, _ = fem.hgo_element_force(X[None], U[None], *args)
+    K, f2 = fem.hgo_element_tangent(X[None], U[None], *args)
+    eps = 1e-6
+    gfd = np.zeros(24)
+    Kfd = np.zeros((24, 24))
+    for k in range(24):
+        dU = np.zeros(24)
+        dU[k] = eps
+        Ep = fem.hgo_element_energy(X[None], (U.reshape(-1) + dU).reshape(1, 8, 3), *args)[0]
+        Em = fem.hgo_element_energy(X[None], (U.reshape(-1) - dU).reshape(1, 8, 3), *args)[0]
+        gfd[k] = (Ep - Em) / (2 * eps)
+        fp, _, _ = fem.hgo_element_force(X[None], (U.reshape(-1) + dU).reshape(1, 8, 3), *args)
+        fm, _, _ = fem.hgo_element_force(X[None], (U.reshape(-1) - dU).reshape(1, 8, 3), *args)
+        Kfd[:, k] = (fp[0] - fm[0]) / (2 * eps)
+    assert np.allclose(f[0], gfd, rtol=1e-7, atol=1e-7 * np.abs(f).max())
+    assert np.allclose(K[0], Kfd, rtol=1e-6, atol=1e-6 * np.abs(K).max())
+    assert np.allclose(K[0], K[0].T, atol=1e-10 * np.abs(K).max())   # hyperelastic => symmetric
+    assert np.allclose(f2[0], f[0].real)
+
+
+def test_hgo_tangent_at_reference_is_mean_dilatation_elasticity():
+    """At U = 0 the tangent is isotropic elasticity with mu = c, lambda = -2c/3,
+    plus the condensed volumetric term (kappa / V_e) g g^T with g_a = int grad N_a."""
+    X = _distorted_element(9)
+    rng = np.random.default_rng(2)
+    a1, a2 = _unit(rng.standard_normal(3)), _unit(rng.standard_normal(3))
+    c, kap = 3.0, 300.0
+    K, f = fem.hgo_element_tangent(X[None], np.zeros((1, 8, 3)), a1[None], a2[None], c,
+                                   HGO["k1"], HGO["k2"], kap)
+    Kdev = fem.linear_stiffness(X[None], -2.0 * c / 3.0, c)[0]
+    g = np.zeros(24)
+    V = 0.0
+    for _, dN, det in fem.ref_gradients(X[None]):
+        g += det[0] * dN[0].reshape(-1)
+        V += det[0]
+    assert np.allclose(K[0], Kdev + kap / V * np.outer(g, g), rtol=1e-10,
+                       atol=1e-10 * np.abs(K).max())
+    assert np.abs(f).max() < 1e-12
+
+
+def test_hgo_objectivity_and_translations():
+    """K(U)(W x) = W f_int(U) for skew W, x = X + U; translations are in ker K(U)."""
+    rng = np.random.default_rng(5)
+    X, U, a1, a2 = _hgo_elem(rng, 0.08)
+    args = (a1[None], a2[None], HGO["c"], HGO["k1"], HGO["k2"], 100.0)
+    K, f = fem.hgo_element_tangent(X[None], U[None], *args)
+    w = rng.standard_normal(3)
+    W = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    x = X + U
+    lhs = K[0] @ (x @ W.T).reshape(-1)
+    rhs = (f[0].reshape(8, 3) @ W.T).reshape(-1)
+    assert np.allclose(lhs, rhs, atol=1e-9 * np.abs(K).max())
+    for k in range(3):
+        t = np.zeros((8, 3))
+        t[:, k] = 1.0
+        assert np.abs(K[0] @ t.reshape(-1)).max() <= 1e-11 * np.abs(K).max()
+
+
+def test_pressure_load_total_force():
+    """The follower pressure on a closed flat face sums to -p * area * n."""
+    xf = np.array([[[0, 0, 0], [2, 0, 0], [2, 3, 0], [0, 3, 0]]], dtype=np.float64)
+    f = fem.pressure_face_load(xf, 1.5)
+    assert np.allclose(f[0].sum(axis=0), [0, 0, -1.5 * 6.0])
+    # a full closed tube surface integrates to zero net force
+    m = tube_mesh(nr=1, nth=16, nz=2, sub=(1, 1, 1))
+    fp = fem.pressure_face_load(m.xyz[m.pface], 1.0)
+    tot = fp.sum(axis=(0, 1))
+    assert abs(tot[0]) < 1e-12 and abs(tot[1]) < 1e-12
+
+
+def test_newton_quadratic_with_dead_load():
+    """Newton on the HGO tube with a dead body load converges quadratically."""
+    m = tube_mesh(nr=2, nth=16, nz=4, sub=(1, 1, 1), pressure=0.0)
+    m.body_force = np.tile([0.0, 0.0, 0.1], (m.n_elems, 1))
+    U = np.zeros(m.n_dofs)
+    res = []
+    for _ in range(10):
+        dU, rn = monolithic.newton_increment(m, U, 1.0)
+        res.append(rn)
+        U = U + dU
+        if rn < 1e-12:
+            break
+    rates = [res[k + 1] / res[k] ** 2 for k in range(1, len(res) - 1) if res[k + 1] > 1e-11]
+    assert res[-1] < 1e-10, res
+    # the last contractions are quadratic: r_{k+1} <= C r_k^2
+    assert len(rates) >= 2 and all(r < 50.0 for r in rates[-2:]), (res, rates)
