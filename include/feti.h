@@ -1,0 +1,185 @@
+/*
+ * feti.h — C ABI of the MI355X FETI solver library (libfeti.so).
+ *
+ * The library solves the torn linear(ised) elasticity systems of the
+ * classical and the all-floating FETI methods of Augustin, Holzapfel and
+ * Steinbach, "Classical and all-floating FETI methods for the simulation of
+ * arterial tissues" (IJNME 99, 2014):
+ *
+ *   K_i u_i + B_i^T lambda = f_i  (every subdomain i),   sum_i B_i u_i = b,
+ *
+ * section 4, eqs. (classicalFetiLGS) and (AFFETI), by the projected
+ * preconditioned CG on the dual problem P^T F lambda = P^T d (eq.
+ * (dualProblem)) with F = sum B_i K_i^+ B_i^T, G = [B_i R_i] and the
+ * projection P = I - G (G^T G)^{-1} G^T (eq. (projection)).  Nonlinear
+ * problems (Holzapfel-Gasser-Ogden tissue, section 2) are linearised by Newton
+ * (section 3.2, eqs. (NewtonRecursion), (LGS), (loadStepping)); every Newton
+ * step is one FETI solve.
+ *
+ * All arithmetic runs on one AMD Instinct MI355X (gfx950).  Every call returns
+ * a feti_status; the library never aborts and never prints.  A call fails with
+ * FETI_EDEVICE if no HIP device is usable: there is no CPU fallback.
+ *
+ * Ownership: the caller owns every array it passes in; feti_setup copies what
+ * it needs and keeps no caller pointer.  The library owns the problem object
+ * and all device memory it allocates (through the allocator callback of
+ * feti_options, or hipMalloc when that is NULL).  Output arrays belong to the
+ * caller: host memory by default, device memory with FETI_DEVICE_PTRS.
+ *
+ * Concurrency: one problem must not be used by two calls at the same time;
+ * distinct problems may run concurrently (each has its own HIP stream).
+ */
+#ifndef FETI_H
+#define FETI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FETI_OK = 0,
+  FETI_EINVAL = -1,      /* bad sizes/ids, empty or disconnected subdomain, non-finite
+                            input, all-floating problem without Dirichlet data      */
+  FETI_ENOMEM = -2,      /* device memory could not be reserved                       */
+  FETI_EDEVICE = -3,     /* no usable HIP device, or a HIP runtime error              */
+  FETI_ENOTSPD = -4,     /* non-positive pivot in a local or coarse factor;
+                            feti_last_error names the subdomain                       */
+  FETI_ENOCONV = -5,     /* max_it reached; outputs are still written,
+                            stats.converged = 0                                        */
+  FETI_ESTATE = -6,      /* feti_solve called before feti_factor                      */
+  FETI_EBREAKDOWN = -7   /* PCG breakdown: s.Fs <= 0                                   */
+} feti_status;
+
+/* Tearing variant: classical FETI eliminates Dirichlet DOFs from the local
+ * systems (section 4.1); all-floating FETI enforces them with extra
+ * multipliers so every subdomain is floating (section 4.2). */
+typedef enum { FETI_CLASSICAL = 0, FETI_ALL_FLOATING = 1 } feti_variant;
+
+/* Preconditioner sum_i B_D,i Y_i B_D,i^T (eq. (feti_preconditioner)) with
+ * multiplicity-scaled rows: Y_i = I, Y_i = K_i (lumped, eq. (LumpedVK)) or the
+ * interface Schur complement (Dirichlet, eq. (DirichletVK)). */
+typedef enum { FETI_PREC_IDENTITY = 0, FETI_PREC_LUMPED = 1, FETI_PREC_DIRICHLET = 2 } feti_precond;
+
+/* FETI_FP64: every step in FP64.  FETI_MIXED: local factors and local solves
+ * in FP32 (MFMA, FP32 accumulation); PCG recurrences, dot products, coarse
+ * problem and rigid-body kernels in FP64; accuracy recovered by iterative
+ * refinement against FP64 residuals. */
+typedef enum { FETI_FP64 = 0, FETI_MIXED = 1 } feti_precision;
+
+/* Material: kind 0 = isotropic linear elasticity (E, nu);
+ * kind 1 = Holzapfel-Gasser-Ogden (section 2, eqs. (iso), (aniso_1),
+ * (aniso_2)) with neo-Hooke parameter c, fibre parameters k1, k2 and the
+ * volumetric penalty kappa of Psi_vol = kappa/2 (J-1)^2, the pressure being
+ * condensed per element (P0). */
+typedef struct {
+  int32_t kind;
+  double E, nu, c, k1, k2, kappa;
+} feti_material;
+
+/* The torn problem (section 4, eq. (decomposition)): a Q1 hexahedral mesh,
+ * a non-overlapping element partition, materials, Dirichlet data (eq.
+ * (Dirichlet)), a body force and a follower pressure (eq. (Neumann)).
+ * Node-major DOF numbering: dof = 3*node + component. */
+typedef struct {
+  int64_t n_nodes;
+  const double* xyz;           /* [n_nodes][3] reference coordinates                   */
+  int64_t n_elems;
+  const int64_t* hex8;         /* [n_elems][8] corners, lexicographic (x fastest):
+                                  corner i+2j+4k at reference point (2i-1,2j-1,2k-1)   */
+  int32_t n_sub;
+  const int32_t* elem_sub;     /* [n_elems] subdomain id in [0, n_sub); every subdomain
+                                  must own at least one element                         */
+  int32_t n_mat;
+  const feti_material* mat;    /* [n_mat]                                               */
+  const int32_t* elem_mat;     /* [n_elems] material id                                 */
+  const double* elem_fibers;   /* [n_elems][2][3] unit fibre directions a01, a02 (HGO)
+                                  or NULL when no element is HGO                        */
+  int64_t n_dir;
+  const int64_t* dir_dof;      /* [n_dir] Dirichlet DOFs (unique)                       */
+  const double* dir_val;       /* [n_dir] prescribed displacement                       */
+  const double* body_force;    /* [n_elems][3] force per unit reference volume, or NULL */
+  int64_t n_pfaces;
+  const int64_t* pface;        /* [n_pfaces][4] quadrilateral corners; (x1-x0)x(x3-x0)
+                                  points out of the body                                */
+  double pressure;             /* follower pressure on pface, current geometry           */
+} feti_mesh;
+
+#define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */
+
+typedef struct {
+  feti_variant variant;
+  feti_precond precond;
+  feti_precision precision;
+  double rtol;                 /* PCG stop: ||P r_k||_2 <= rtol ||P r_0||_2 (0 => 1e-8)  */
+  int32_t max_it;              /* PCG iteration cap (0 => 1000)                           */
+  double ir_tol;               /* mixed: relative FP64 residual target of the outer
+                                  refinement (0 => 1e-10)                                 */
+  int32_t ir_max;              /* mixed: max refinement sweeps (0 => 6)                   */
+  int32_t graph_block;         /* PCG iterations captured per HIP graph (0 => 8)          */
+  void* hip_stream;            /* hipStream_t to run on, or NULL for a library stream    */
+  void* (*dev_alloc)(size_t bytes, void* stream, void* ctx);   /* optional allocator     */
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+  uint64_t flags;              /* FETI_DEVICE_PTRS                                        */
+} feti_options;
+
+typedef struct {
+  int32_t iters;               /* PCG iterations (summed over refinement sweeps)          */
+  int32_t converged;           /* 1 if the stopping rule was met                          */
+  int32_t ir_sweeps;           /* mixed: outer refinement sweeps                           */
+  int32_t n_coarse;            /* dimension of the coarse space (columns of G)            */
+  int64_t n_lambda;            /* number of Lagrange multipliers                          */
+  double rel_res;              /* final ||P r|| / ||P r_0||                               */
+  double kappa_est;            /* Lanczos estimate of the preconditioned condition number */
+  double t_assemble, t_factor, t_pcg, t_total;   /* seconds, from HIP events              */
+  size_t device_bytes;         /* device memory held by the problem                       */
+} feti_stats;
+
+typedef struct feti_problem feti_problem;   /* opaque, owned by the library */
+
+/* Decompose the mesh, build multiplier rows, multiplicities and index maps,
+ * reserve device memory and upload the static data.  *out receives a new
+ * problem (NULL on failure).  opts may be NULL (defaults: all-floating,
+ * lumped, FP64).  Errors: EINVAL, ENOMEM, EDEVICE. */
+feti_status feti_setup(const feti_mesh* mesh, const feti_options* opts, feti_problem** out);
+
+/* Device memory held by the problem, for admission control. */
+feti_status feti_footprint(const feti_problem* p, size_t* device_bytes);
+
+/* Assemble the local tangents at displacement U ([3*n_nodes], NULL => 0),
+ * compute the rigid-body kernels, factor every K_i (interior-first dense
+ * Cholesky, regularised interface Schur complement, its explicit inverse) and
+ * the coarse matrix G^T G.  Errors: EINVAL, ENOTSPD, EDEVICE. */
+feti_status feti_factor(feti_problem* p, const double* U);
+
+/* Solve the linear problem K u = lf f_ext with u = lf u_D on the Dirichlet
+ * boundary, using the factors of the last feti_factor (which must have been
+ * called with U = NULL).  u [3*n_nodes] receives the global nodal
+ * displacements (shared nodes: mean of the subdomain copies; Dirichlet DOFs:
+ * their prescribed values).  stats may be NULL.
+ * Errors: ESTATE, ENOCONV (u still written), EBREAKDOWN, EDEVICE. */
+feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stats* stats);
+
+/* One Newton step of the nonlinear problem (eqs. (LGS), (loadStepping)):
+ * factor at U_k, then solve K'(U_k) dU = tau f_ext(U_k) - f_int(U_k) with
+ * dU = tau u_D - U_k on the Dirichlet boundary.  The follower pressure acts on
+ * the current geometry and its load stiffness is neglected (section 3.2).
+ * res_norm (may be NULL) receives ||tau f_ext - f_int||_2 over free DOFs.
+ * Errors: as feti_factor and feti_solve. */
+feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, double* dU,
+                             double* res_norm, feti_stats* stats);
+
+/* Message of the last failed call on p (or of the last failed feti_setup when
+ * p is NULL); valid until the next call on that problem. */
+const char* feti_last_error(const feti_problem* p);
+
+/* Release the problem and every device allocation it holds.  NULL is ignored. */
+void feti_destroy(feti_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FETI_H */

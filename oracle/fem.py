@@ -124,14 +124,20 @@ def _inv3(A):
     return inv, det
 
 
-def _fibre_terms(C, Jm23, a, k1, k2):
-    """E = Ibar_4 - 1, the fibre stretch measure, and dPsi/dIbar_4 (zero unless E > 0)."""
-    I4 = Jm23 * np.einsum("...i,...ij,...j->...", a, C, a)
-    E = I4 - 1.0
-    active = np.real(E) > 0.0                 # fibres carry tension only (section 2)
+def _fibre_terms(C, Jm23, a, k1, k2, active=None):
+    """E = Ibar_4 - 1, the fibre stretch measure, and dPsi/dIbar_4 (zero unless E > 0).
+
+    With a unit fibre a, Ibar_4 - 1 = J^{-2/3} a.(C - I)a + (J^{-2/3} - 1); this form
+    is exactly zero at C = I, so the tension-only switch does not flip on rounding
+    of |a|^2 in the reference state.
+    """
+    eye = np.eye(3)
+    E = Jm23 * np.einsum("...i,...ij,...j->...", a, C - eye, a) + (Jm23 - 1.0)
+    if active is None:
+        active = np.real(E) > 0.0             # fibres carry tension only (section 2)
     dpsi = np.where(active, k1 * E * np.exp(k2 * E * E), 0.0)
     psi = np.where(active, k1 / (2.0 * k2) * (np.exp(k2 * E * E) - 1.0), 0.0)
-    return E, dpsi, psi
+    return E, dpsi, psi, active
 
 
 def hgo_isochoric_energy(C, a1, a2, c, k1, k2):
@@ -139,27 +145,29 @@ def hgo_isochoric_energy(C, a1, a2, c, k1, k2):
     _, J2 = _inv3(C)
     Jm23 = J2 ** (-1.0 / 3.0)
     I1 = Jm23 * np.einsum("...ii->...", C)
-    _, _, p4 = _fibre_terms(C, Jm23, a1, k1, k2)
-    _, _, p6 = _fibre_terms(C, Jm23, a2, k1, k2)
+    _, _, p4, _ = _fibre_terms(C, Jm23, a1, k1, k2)
+    _, _, p6, _ = _fibre_terms(C, Jm23, a2, k1, k2)
     return 0.5 * c * (I1 - 3.0) + p4 + p6
 
 
-def hgo_isochoric_stress(C, a1, a2, c, k1, k2):
+def hgo_isochoric_stress(C, a1, a2, c, k1, k2, act=None, return_act=False):
     """S_iso = 2 dPsi_bar/dC for the HGO energy (isochoric part of eq. (additiveStress)).
 
     With Sbar = c I + 2 psi4' a1(x)a1 + 2 psi6' a2(x)a2 the chain rule through
     Cbar = J^{-2/3} C gives S_iso = J^{-2/3} (Sbar - (Sbar:C)/3 C^{-1}).
-    Works for complex input (used for complex-step derivatives).
+    Works for complex input (used for complex-step derivatives); ``act`` fixes
+    the fibre activity (decided at the real base state) for such evaluations.
     """
     Cinv, J2 = _inv3(C)
     Jm23 = J2 ** (-1.0 / 3.0)
-    _, d4, _ = _fibre_terms(C, Jm23, a1, k1, k2)
-    _, d6, _ = _fibre_terms(C, Jm23, a2, k1, k2)
+    _, d4, _, a4 = _fibre_terms(C, Jm23, a1, k1, k2, None if act is None else act[0])
+    _, d6, _, a6 = _fibre_terms(C, Jm23, a2, k1, k2, None if act is None else act[1])
     eye = np.eye(3)
     Sbar = (np.asarray(c)[..., None, None] * eye + 2.0 * d4[..., None, None] * np.einsum("...i,...j->...ij", a1, a1)
             + 2.0 * d6[..., None, None] * np.einsum("...i,...j->...ij", a2, a2))
     tr = np.einsum("...ij,...ij->...", Sbar, C)
-    return Jm23[..., None, None] * (Sbar - (tr / 3.0)[..., None, None] * Cinv)
+    S = Jm23[..., None, None] * (Sbar - (tr / 3.0)[..., None, None] * Cinv)
+    return (S, (a4, a6)) if return_act else S
 
 
 def _deformation(Xe, Ue):
@@ -191,12 +199,13 @@ def hgo_element_energy(Xe, Ue, a1, a2, c, k1, k2, kappa):
     return W + V * 0.5 * kappa * (Jbar - 1.0) ** 2
 
 
-def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa):
+def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa, acts=None, return_acts=False):
     """Internal force f_e[3a+i] = dPi_e/du_ai (eq. (WeakReference), left side).
 
     Isochoric part: int F S_iso Grad N_a dX.  Volumetric part: p_e g_a with
     p_e = kappa (Jbar_e - 1) and g_a = dv_e/du_a = int J F^{-T} Grad N_a dX.
-    Returns (f [ne,24], p_e [ne], Jbar [ne]).
+    Returns (f [ne,24], p_e [ne], Jbar [ne]) (and the fibre activity per Gauss
+    point if ``return_acts``); ``acts`` imposes a previously decided activity.
     """
     ne = Xe.shape[0]
     dtype = np.result_type(Ue, np.float64)
@@ -204,9 +213,12 @@ def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa):
     g = np.zeros((ne, 8, 3), dtype=dtype)
     V = np.zeros(ne)
     v = np.zeros(ne, dtype=dtype)
-    for _, dNX, det0, F in _deformation(Xe, Ue):
+    out_acts = []
+    for q, (_, dNX, det0, F) in enumerate(_deformation(Xe, Ue)):
         C = np.einsum("ekI,ekJ->eIJ", F, F)
-        S = hgo_isochoric_stress(C, a1, a2, c, k1, k2)
+        S, act = hgo_isochoric_stress(C, a1, a2, c, k1, k2, None if acts is None else acts[q],
+                                      return_act=True)
+        out_acts.append(act)
         Finv, J = _inv3(F)
         P = np.einsum("eiI,eIJ->eiJ", F, S)
         f += det0[:, None, None] * np.einsum("eiJ,eaJ->eai", P, dNX)
@@ -217,6 +229,8 @@ def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa):
     Jbar = v / V
     p = kappa * (Jbar - 1.0)
     f = f + p[:, None, None] * g
+    if return_acts:
+        return f.reshape(ne, 24), p, Jbar, out_acts
     return f.reshape(ne, 24), p, Jbar
 
 
@@ -227,14 +241,14 @@ def hgo_element_tangent(Xe, Ue, a1, a2, c, k1, k2, kappa, h=1e-30):
     Returns (K [ne,24,24], f [ne,24]).
     """
     ne = Xe.shape[0]
-    f0, _, _ = hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa)
+    f0, _, _, acts = hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa, return_acts=True)
     K = np.empty((ne, 24, 24))
     Uc = Ue.astype(np.complex128)
     for col in range(24):
         a, j = divmod(col, 3)
         Up = Uc.copy()
         Up[:, a, j] += 1j * h
-        fc, _, _ = hgo_element_force(Xe, Up, a1, a2, c, k1, k2, kappa)
+        fc, _, _ = hgo_element_force(Xe, Up, a1, a2, c, k1, k2, kappa, acts=acts)
         K[:, :, col] = fc.imag / h
     return K, f0.real
 

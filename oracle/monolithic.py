@@ -72,11 +72,14 @@ def residual_norm(mesh, U, tau):
     return float(np.linalg.norm(r[free])), float(np.linalg.norm(f_ext[free]))
 
 
-def newton_load_path(mesh, n_steps=10, rtol=1e-11, max_newton=12, U0=None):
+def newton_load_path(mesh, n_steps=10, rtol=1e-11, max_newton=12, U0=None, line_search=False):
     """Load stepping with Newton (eq. (loadStepping)): tau_s = s/n_steps, the
     converged state of step s-1 is the initial guess of step s.
 
-    Returns a list of dicts {tau, U, newton_iters, res_hist}.
+    ``line_search`` halves a step until the residual norm decreases (at most
+    10 times); it is not part of the paper's scheme and only serves to reach
+    equilibria of nearly incompressible meshes whose first linearised step
+    overshoots.  Returns a list of dicts {tau, U, newton_iters, res_hist}.
     """
     U = np.zeros(mesh.n_dofs) if U0 is None else np.array(U0, dtype=np.float64)
     path = []
@@ -86,7 +89,13 @@ def newton_load_path(mesh, n_steps=10, rtol=1e-11, max_newton=12, U0=None):
         it = 0
         for it in range(1, max_newton + 1):
             dU, rn = newton_increment(mesh, U, tau)
-            U = U + dU
+            a = 1.0
+            if line_search:
+                for _ in range(10):
+                    if residual_norm(mesh, U + a * dU, tau)[0] < rn:
+                        break
+                    a *= 0.5
+            U = U + a * dU
             rn2, fn = residual_norm(mesh, U, tau)
             hist.append(rn2)
             if rn2 <= rtol * max(fn, 1e-300):

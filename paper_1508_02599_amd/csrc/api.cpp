@@ -1,0 +1,1008 @@
+// C ABI of libfeti (include/feti.h): problem lifetime, device memory, and the
+// orchestration of assembly, batched factorisation and the projected PCG.
+//
+// Solve (section 4.3 of the paper):
+//   e = R^T f,  d = sum_i B_i K_i^+ f_i - b,  Q = G^T G,  lambda_0 = G Q^{-1} e,
+//   r_0 = d - F lambda_0,  w = P r,  z = P M^{-1} w,  CG on P^T F,
+//   gamma = Q^{-1} G^T (F lambda - d),  u_i = K_i^+ (f_i - B_i^T lambda) + R_i gamma_i.
+// The PCG iterations are captured in a HIP graph (graph_block iterations per
+// replay) with all scalars on the device; the host reads one flag per replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "feti_impl.h"
+#include "k_pcg.h"
+
+using namespace feti;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct DeviceAlloc {
+  void* (*fn)(size_t, void*, void*) = nullptr;
+  void (*fr)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+
+}  // namespace
+
+struct feti_problem {
+  HostPlan P;
+  std::string err;
+  feti_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DeviceAlloc da;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  bool factored = false;
+  bool factored_linear = false;
+  int n_coarse = 0;
+  int nq = 0;   // coarse tiles
+  DevIdx di;
+
+  // static device data
+  SubInfo* d_sub = nullptr;
+  Task* d_tasks = nullptr;
+  double *d_xyz = nullptr, *d_mat = nullptr, *d_fib = nullptr, *d_body = nullptr, *d_dirval = nullptr;
+  int64_t *d_hex8 = nullptr, *d_pface = nullptr, *d_loc_node = nullptr;
+  int32_t *d_elem_mat = nullptr, *d_loc_pos = nullptr, *d_loc_sub = nullptr, *d_loc_ncopy = nullptr;
+  uint8_t* d_dmask = nullptr;
+  int32_t *d_ps_a = nullptr, *d_ps_b = nullptr, *d_ps_nbr = nullptr, *d_ps_c0 = nullptr, *d_ps_c1 = nullptr;
+  int32_t *d_pc_e = nullptr, *d_pc_ab = nullptr, *d_diag_slot = nullptr, *d_ell_col = nullptr;
+  int32_t *d_fpos_lnode = nullptr, *d_f_sub = nullptr;
+  int8_t* d_fpos_comp = nullptr;
+  int32_t *d_uc_ptr = nullptr, *d_pf_ptr = nullptr, *d_pf_ent = nullptr;
+  int64_t* d_uc_idx = nullptr;
+  int32_t *d_qp_s = nullptr, *d_qp_t = nullptr, *d_qp_ptr = nullptr;
+  int64_t *d_qe_bs = nullptr, *d_qe_bt = nullptr;
+  double* d_qe_c = nullptr;
+
+  // assembly / factor data
+  double *d_Ke = nullptr, *d_fint = nullptr, *d_fbody = nullptr, *d_ell_val = nullptr, *d_U = nullptr;
+  double *d_fnodal = nullptr;
+  void *d_arena = nullptr, *d_linv = nullptr, *d_W = nullptr, *d_X = nullptr, *d_S = nullptr;
+  double *d_rfull = nullptr, *d_rb = nullptr, *d_work = nullptr, *d_rho = nullptr, *d_wbm = nullptr;
+  int32_t *d_nmodes = nullptr, *d_err = nullptr;
+  // coarse
+  SubInfo* d_qsub = nullptr;
+  Task* d_qtasks = nullptr;
+  int qtask_cap = 0;
+  int32_t* d_qbsub = nullptr;
+  double *d_qarena = nullptr, *d_qlinv = nullptr, *d_qW = nullptr, *d_qX = nullptr, *d_qpart = nullptr;
+  HostPlan::Launch q_xtiles{};
+  // vectors
+  double *d_f = nullptr, *d_z = nullptr, *d_w = nullptr, *d_u = nullptr, *d_gfull = nullptr;
+  double *d_xb = nullptr, *d_yb = nullptr, *d_vb = nullptr, *d_part = nullptr;
+  double *d_lam = nullptr, *d_r = nullptr, *d_s = nullptr, *d_q = nullptr, *d_wv = nullptr, *d_zv = nullptr;
+  double *d_tv = nullptr, *d_d = nullptr, *d_bv = nullptr;
+  double *d_cg = nullptr, *d_calpha = nullptr, *d_gamma = nullptr, *d_e = nullptr;
+  double *d_dvals = nullptr, *d_out = nullptr, *d_dots = nullptr, *d_hist = nullptr;
+  PcgState* d_state = nullptr;
+  int hist_cap = 0;
+  // graph
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  hipEvent_t ev[6] = {};
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      p->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr; \
+      return FETI_EDEVICE;                                                        \
+    }                                                                             \
+  } while (0)
+
+template <typename T>
+feti_status dalloc(feti_problem* p, T*& out, size_t n) {
+  out = nullptr;
+  if (n == 0) n = 1;
+  const size_t bytes = n * sizeof(T);
+  void* ptr = nullptr;
+  if (p->da.fn) {
+    ptr = p->da.fn(bytes, (void*)p->stream, p->da.ctx);
+    if (!ptr) {
+      p->err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+      return FETI_ENOMEM;
+    }
+  } else {
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+      return FETI_ENOMEM;
+    }
+  }
+  p->allocs.push_back(ptr);
+  p->bytes += bytes;
+  out = (T*)ptr;
+  return FETI_OK;
+}
+
+template <typename T>
+feti_status upload(feti_problem* p, T*& out, const std::vector<T>& v) {
+  feti_status s = dalloc(p, out, v.size());
+  if (s != FETI_OK) return s;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, p->stream));
+  return FETI_OK;
+}
+
+#define TRY(expr)                   \
+  do {                              \
+    feti_status s_ = (expr);        \
+    if (s_ != FETI_OK) return s_;   \
+  } while (0)
+
+size_t elt(const feti_problem* p) { return p->P.mixed ? sizeof(float) : sizeof(double); }
+
+// Dense launches on the subdomain batch in the working precision.
+void dense(feti_problem* p, const HostPlan::Launch& L) {
+  const Task* t = p->d_tasks + L.first;
+  if (p->P.mixed)
+    launch_dense<float>(L.kind, t, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)p->d_W,
+                        (float*)p->d_X, p->d_err, p->stream);
+  else
+    launch_dense<double>(L.kind, t, L.count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv,
+                         (double*)p->d_W, (double*)p->d_X, p->d_err, p->stream);
+}
+
+void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st) {
+  const HostPlan::Launch& L = p->P.sched_xtiles;
+  if (p->P.mixed)
+    pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)M, xb, p->d_part, p->di.NB,
+                    p->di.b_sub, yb, st, p->stream);
+  else
+    pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)M, xb, p->d_part, p->di.NB,
+                     p->di.b_sub, yb, st, p->stream);
+}
+
+void kpinv(feti_problem* p, const double* g, double* z) {
+  if (p->P.mixed)
+    local_kpinv<float>(p->P.n_sub, p->d_sub, (const float*)p->d_arena, (const float*)p->d_linv,
+                       (const float*)p->d_X, g, z, p->d_w, p->stream);
+  else
+    local_kpinv<double>(p->P.n_sub, p->d_sub, (const double*)p->d_arena, (const double*)p->d_linv,
+                        (const double*)p->d_X, g, z, p->d_w, p->stream);
+}
+
+// alpha = Q^{-1} g on the coarse space (alpha = 0 without coarse space).
+void coarse_solve(feti_problem* p, const double* g, double* alpha, const PcgState* st) {
+  if (p->n_coarse == 0) return;
+  pcg_symv<double>(p->d_qtasks + p->q_xtiles.first, p->q_xtiles.count, p->d_qsub, p->d_qX, g, p->d_qpart,
+                   (int64_t)p->nq * TS, p->d_qbsub, alpha, st, p->stream);
+}
+
+// out = P in = in - G Q^{-1} G^T in
+void project(feti_problem* p, const double* in, double* out, const PcgState* st) {
+  if (p->n_coarse == 0) {
+    if (in != out) vec_copy_st(p->P.n_lam, in, out, st, p->stream);
+    return;
+  }
+  pcg_gather(p->di, 0, in, p->d_xb, st, p->stream);
+  pcg_coarse_gt(p->P.n_sub, p->d_sub, p->d_rb, p->d_xb, p->d_cg, st, p->stream);
+  coarse_solve(p, p->d_cg, p->d_calpha, st);
+  pcg_coarse_expand(p->di, p->d_sub, p->d_rb, p->d_calpha, p->d_vb, st, p->stream);
+  pcg_scatter(p->di, 0, p->d_vb, in, -1.0, out, st, p->stream);
+}
+
+// q = F v
+void apply_F(feti_problem* p, const double* v, double* q, const double* base, double sgn, const PcgState* st) {
+  pcg_gather(p->di, 0, v, p->d_xb, st, p->stream);
+  symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
+  pcg_scatter(p->di, 0, p->d_yb, base, sgn, q, st, p->stream);
+}
+
+// out = M^{-1} w (multiplicity-scaled; lumped, Dirichlet or identity)
+void precondition(feti_problem* p, const double* w, double* out, const PcgState* st) {
+  pcg_gather(p->di, 1, w, p->d_xb, st, p->stream);
+  const double* y = p->d_xb;
+  if (p->P.precond == FETI_PREC_LUMPED) {
+    pcg_lumped(p->di, p->d_sub, p->d_ell_col, p->d_ell_val, p->d_xb, p->d_yb, st, p->stream);
+    y = p->d_yb;
+  } else if (p->P.precond == FETI_PREC_DIRICHLET) {
+    symv_local(p, p->d_S, p->d_xb, p->d_yb, st);
+    y = p->d_yb;
+  }
+  pcg_scatter(p->di, 1, y, nullptr, 1.0, out, st, p->stream);
+}
+
+void pcg_iteration(feti_problem* p) {
+  PcgState* st = p->d_state;
+  const int64_t n = p->P.n_lam;
+  apply_F(p, p->d_s, p->d_q, nullptr, 1.0, st);
+  pcg_dot(n, p->d_s, p->d_q, nullptr, nullptr, p->d_dots, st, p->stream);
+  pcg_alpha(p->d_dots, st, p->stream);
+  pcg_update_lr(n, p->d_lam, p->d_r, p->d_s, p->d_q, st, p->stream);
+  project(p, p->d_r, p->d_wv, st);
+  precondition(p, p->d_wv, p->d_tv, st);
+  project(p, p->d_tv, p->d_zv, st);
+  pcg_dot(n, p->d_wv, p->d_zv, p->d_wv, p->d_wv, p->d_dots, st, p->stream);
+  pcg_beta(p->d_dots, st, 0, p->d_hist, p->stream);
+  pcg_update_s(n, p->d_s, p->d_zv, st, p->stream);
+}
+
+// Condition estimate from the recorded (alpha, beta): extreme eigenvalues of
+// the Lanczos tridiagonal by bisection on Sturm sequences.
+double lanczos_kappa(const std::vector<double>& h, int m) {
+  if (m <= 0) return 1.0;
+  std::vector<double> d(m), e(m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    const double a = h[2 * k], b = h[2 * k + 1];
+    d[k] = 1.0 / a + (k > 0 ? h[2 * (k - 1) + 1] / h[2 * (k - 1)] : 0.0);
+    if (k + 1 < m) e[k] = std::sqrt(std::max(b, 0.0)) / a;
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) c++;
+    for (int k = 1; k < m; ++k) {
+      const double den = std::fabs(q) < 1e-300 ? 1e-300 : q;
+      q = d[k] - x - e[k - 1] * e[k - 1] / den;
+      if (q < 0) c++;
+    }
+    return c;
+  };
+  double lo = 1e300, hi = -1e300;
+  for (int k = 0; k < m; ++k) {
+    const double r = (k > 0 ? std::fabs(e[k - 1]) : 0.0) + std::fabs(e[k]);
+    lo = std::min(lo, d[k] - r);
+    hi = std::max(hi, d[k] + r);
+  }
+  auto kth = [&](int k) {
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (count_below(mid) > k) b = mid;
+      else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  const double lmin = kth(0), lmax = kth(m - 1);
+  return lmin > 0 ? lmax / lmin : 0.0;
+}
+
+feti_status setup_device(feti_problem* p) {
+  HostPlan& P = p->P;
+  p->di.NB = P.NB;
+  p->di.NF = P.NF;
+  p->di.n_lam = P.n_lam;
+  TRY(upload(p, p->d_sub, P.sub));
+  TRY(upload(p, p->d_tasks, P.tasks));
+  TRY(upload(p, p->d_xyz, P.xyz));
+  TRY(upload(p, p->d_hex8, P.hex8));
+  TRY(upload(p, p->d_elem_mat, P.elem_mat));
+  {
+    std::vector<double> m(7 * P.mat.size());
+    for (size_t k = 0; k < P.mat.size(); ++k) {
+      const auto& q = P.mat[k];
+      double v[7] = {(double)q.kind, q.E, q.nu, q.c, q.k1, q.k2, q.kappa};
+      std::copy(v, v + 7, m.begin() + 7 * k);
+    }
+    TRY(upload(p, p->d_mat, m));
+  }
+  if (!P.fibers.empty()) TRY(upload(p, p->d_fib, P.fibers));
+  if (!P.body_force.empty()) TRY(upload(p, p->d_body, P.body_force));
+  TRY(upload(p, p->d_dirval, P.dir_val));
+  TRY(upload(p, p->d_dmask, P.dir_mask));
+  TRY(upload(p, p->d_loc_node, P.loc_node));
+  TRY(upload(p, p->d_loc_pos, P.loc_pos));
+  TRY(upload(p, p->d_loc_sub, P.loc_sub));
+  TRY(upload(p, p->d_loc_ncopy, P.loc_ncopy));
+  TRY(upload(p, p->d_ps_a, P.ps_a));
+  TRY(upload(p, p->d_ps_b, P.ps_b));
+  TRY(upload(p, p->d_ps_nbr, P.ps_nbr));
+  TRY(upload(p, p->d_ps_c0, P.ps_c0));
+  TRY(upload(p, p->d_ps_c1, P.ps_c1));
+  TRY(upload(p, p->d_pc_e, P.pc_e));
+  TRY(upload(p, p->d_pc_ab, P.pc_ab));
+  TRY(upload(p, p->d_diag_slot, P.diag_slot));
+  TRY(upload(p, p->d_ell_col, P.ell_col));
+  TRY(upload(p, p->d_fpos_lnode, P.fpos_lnode));
+  TRY(upload(p, p->d_fpos_comp, P.fpos_comp));
+  TRY(upload(p, p->d_f_sub, P.f_sub));
+  TRY(upload(p, p->d_uc_ptr, P.uc_ptr));
+  TRY(upload(p, p->d_uc_idx, P.uc_idx));
+  if (!P.pface.empty()) {
+    TRY(upload(p, p->d_pface, P.pface));
+    TRY(upload(p, p->d_pf_ptr, P.pf_ptr));
+    TRY(upload(p, p->d_pf_ent, P.pf_ent));
+  }
+  TRY(upload(p, p->d_qp_s, P.qp_s));
+  TRY(upload(p, p->d_qp_t, P.qp_t));
+  TRY(upload(p, p->d_qp_ptr, P.qp_ptr));
+  TRY(upload(p, p->d_qe_bs, P.qe_bs));
+  TRY(upload(p, p->d_qe_bt, P.qe_bt));
+  TRY(upload(p, p->d_qe_c, P.qe_c));
+  {
+    int32_t *a, *b, *c, *e;
+    double *f, *g, *h, *w;
+    int64_t *r0, *r1, *rg, *b2f;
+    TRY(upload(p, a, P.g_ptr));
+    TRY(upload(p, b, P.g_row));
+    TRY(upload(p, c, P.b_sub));
+    TRY(upload(p, f, P.g_coef));
+    TRY(upload(p, w, P.r_w));
+    TRY(upload(p, g, P.r_c0));
+    TRY(upload(p, h, P.r_c1));
+    TRY(upload(p, r0, P.r_b0));
+    TRY(upload(p, r1, P.r_b1));
+    TRY(upload(p, rg, P.r_gdof));
+    TRY(upload(p, b2f, P.b2full));
+    e = p->d_f_sub;
+    p->di.g_ptr = a;
+    p->di.g_row = b;
+    p->di.b_sub = c;
+    p->di.f_sub = e;
+    p->di.g_coef = f;
+    p->di.r_w = w;
+    p->di.r_c0 = g;
+    p->di.r_c1 = h;
+    p->di.r_b0 = r0;
+    p->di.r_b1 = r1;
+    p->di.r_gdof = rg;
+    p->di.b2full = b2f;
+  }
+  // working memory
+  const size_t e = elt(p);
+  TRY(dalloc(p, p->d_Ke, (size_t)P.n_elems * 576));
+  TRY(dalloc(p, p->d_fint, (size_t)P.n_elems * 24));
+  TRY(dalloc(p, p->d_fbody, (size_t)P.n_elems * 24));
+  TRY(dalloc(p, p->d_ell_val, (size_t)P.NF * ELLW));
+  TRY(dalloc(p, p->d_U, (size_t)P.n_dof));
+  TRY(dalloc(p, p->d_fnodal, (size_t)P.n_dof));
+  {
+    char *a, *l, *w, *x, *s = nullptr;
+    TRY(dalloc(p, a, (size_t)P.n_tiles * e));
+    TRY(dalloc(p, l, (size_t)P.n_linv * e));
+    TRY(dalloc(p, w, (size_t)P.n_xtiles * e));
+    TRY(dalloc(p, x, (size_t)P.n_xtiles * e));
+    if (P.precond == FETI_PREC_DIRICHLET) TRY(dalloc(p, s, (size_t)P.n_xtiles * e));
+    p->d_arena = a;
+    p->d_linv = l;
+    p->d_W = w;
+    p->d_X = x;
+    p->d_S = s;
+  }
+  TRY(dalloc(p, p->d_rfull, (size_t)P.NF * 6));
+  TRY(dalloc(p, p->d_work, (size_t)P.NF * 6));
+  TRY(dalloc(p, p->d_rb, (size_t)P.NB * 6));
+  TRY(dalloc(p, p->d_rho, (size_t)P.n_sub));
+  TRY(dalloc(p, p->d_wbm, (size_t)P.n_sub * 9));
+  TRY(dalloc(p, p->d_nmodes, (size_t)P.n_sub));
+  TRY(dalloc(p, p->d_err, 4));
+  // coarse space: at most 6 per subdomain
+  const int max_coarse = 6 * P.n_sub;
+  const int nq_max = (max_coarse + TS - 1) / TS;
+  const size_t qt = (size_t)nq_max * (nq_max + 1) / 2 * TS2;
+  TRY(dalloc(p, p->d_qsub, 1));
+  TRY(dalloc(p, p->d_qarena, qt));
+  TRY(dalloc(p, p->d_qlinv, (size_t)nq_max * TS2));
+  TRY(dalloc(p, p->d_qW, qt));
+  TRY(dalloc(p, p->d_qX, qt));
+  TRY(dalloc(p, p->d_qpart, (size_t)nq_max * nq_max * TS));
+  {
+    std::vector<int32_t> z((size_t)nq_max * TS, 0);
+    TRY(upload(p, p->d_qbsub, z));
+  }
+  p->qtask_cap = 4 * nq_max * nq_max + 4 * nq_max + 16;
+  TRY(dalloc(p, p->d_qtasks, (size_t)p->qtask_cap * (nq_max + 2)));
+  TRY(dalloc(p, p->d_cg, (size_t)nq_max * TS));
+  TRY(dalloc(p, p->d_calpha, (size_t)nq_max * TS));
+  TRY(dalloc(p, p->d_gamma, (size_t)nq_max * TS));
+  TRY(dalloc(p, p->d_e, (size_t)nq_max * TS));
+  // coarse vectors: padding entries stay zero (kernels write real entries only)
+  vec_fill((int64_t)nq_max * TS, 0.0, p->d_cg, p->stream);
+  vec_fill((int64_t)nq_max * TS, 0.0, p->d_calpha, p->stream);
+  vec_fill((int64_t)nq_max * TS, 0.0, p->d_gamma, p->stream);
+  vec_fill((int64_t)nq_max * TS, 0.0, p->d_e, p->stream);
+  // vectors
+  TRY(dalloc(p, p->d_f, (size_t)P.NF));
+  TRY(dalloc(p, p->d_z, (size_t)P.NF));
+  TRY(dalloc(p, p->d_w, (size_t)P.NF));
+  TRY(dalloc(p, p->d_u, (size_t)P.NF));
+  TRY(dalloc(p, p->d_gfull, (size_t)P.NF));
+  TRY(dalloc(p, p->d_xb, (size_t)P.NB));
+  TRY(dalloc(p, p->d_yb, (size_t)P.NB));
+  TRY(dalloc(p, p->d_vb, (size_t)P.NB));
+  TRY(dalloc(p, p->d_part, (size_t)std::max<int64_t>(P.n_part, 1)));
+  const size_t nl = (size_t)std::max<int64_t>(P.n_lam, 1);
+  TRY(dalloc(p, p->d_lam, nl));
+  TRY(dalloc(p, p->d_r, nl));
+  TRY(dalloc(p, p->d_s, nl));
+  TRY(dalloc(p, p->d_q, nl));
+  TRY(dalloc(p, p->d_wv, nl));
+  TRY(dalloc(p, p->d_zv, nl));
+  TRY(dalloc(p, p->d_tv, nl));
+  TRY(dalloc(p, p->d_d, nl));
+  TRY(dalloc(p, p->d_bv, nl));
+  TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
+  TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
+  TRY(dalloc(p, p->d_dots, 2 * DOT_PARTS));
+  p->hist_cap = std::max(1, p->opt.max_it);
+  TRY(dalloc(p, p->d_hist, 2 * (size_t)p->hist_cap));
+  TRY(dalloc(p, p->d_state, 1));
+  for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return FETI_OK;
+}
+
+// ---------------------------------------------------------------------------
+feti_status do_factor(feti_problem* p, const double* U_dev) {
+  HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  HIPCHK(hipEventRecord(p->ev[0], st));
+  AsmArgs a;
+  a.n_elems = P.n_elems;
+  a.xyz = p->d_xyz;
+  a.hex8 = p->d_hex8;
+  a.elem_mat = p->d_elem_mat;
+  a.mat = p->d_mat;
+  a.fibers = p->d_fib;
+  a.body = p->d_body;
+  a.U = U_dev;
+  a.Ke = p->d_Ke;
+  a.fint = p->d_fint;
+  a.fbody = p->d_fbody;
+  asm_elements(a, P.any_hgo, st);
+  const auto& AT = P.sched_alltiles;
+  if (P.mixed)
+    launch_init_arena<float>(p->d_tasks + AT.first, AT.count, p->d_sub, (float*)p->d_arena, st);
+  else
+    launch_init_arena<double>(p->d_tasks + AT.first, AT.count, p->d_sub, (double*)p->d_arena, st);
+  vec_fill((int64_t)P.NF * ELLW, 0.0, p->d_ell_val, st);
+  GatherArgs g;
+  g.n_slots = (int64_t)P.ps_a.size();
+  g.ps_a = p->d_ps_a;
+  g.ps_b = p->d_ps_b;
+  g.ps_nbr = p->d_ps_nbr;
+  g.ps_c0 = p->d_ps_c0;
+  g.ps_c1 = p->d_ps_c1;
+  g.pc_e = p->d_pc_e;
+  g.pc_ab = p->d_pc_ab;
+  g.loc_sub = p->d_loc_sub;
+  g.loc_pos = p->d_loc_pos;
+  g.subs = p->d_sub;
+  g.Ke = p->d_Ke;
+  g.ell_val = p->d_ell_val;
+  if (P.mixed) asm_gather<float>(g, (float*)p->d_arena, st);
+  else asm_gather<double>(g, (double*)p->d_arena, st);
+  ModesArgs m;
+  m.n_sub = P.n_sub;
+  m.subs = p->d_sub;
+  m.loc_node = p->d_loc_node;
+  m.loc_pos = p->d_loc_pos;
+  m.fpos_lnode = p->d_fpos_lnode;
+  m.fpos_comp = p->d_fpos_comp;
+  m.xyz = p->d_xyz;
+  m.U = U_dev;
+  m.ell_col = p->d_ell_col;
+  m.ell_val = p->d_ell_val;
+  m.test_rotations = (P.any_hgo && U_dev) ? 1 : 0;
+  m.rfull = p->d_rfull;
+  m.rb = p->d_rb;
+  m.n_modes = p->d_nmodes;
+  m.work = p->d_work;
+  asm_modes(m, st);
+  HIPCHK(hipEventRecord(p->ev[1], st));
+  // coarse layout from the kernel dimensions
+  std::vector<int32_t> nm(P.n_sub);
+  HIPCHK(hipMemcpyAsync(nm.data(), p->d_nmodes, P.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int off = 0;
+  for (int s = 0; s < P.n_sub; ++s) {
+    P.sub[s].n_modes = nm[s];
+    P.sub[s].coarse_off = off;
+    off += nm[s];
+  }
+  p->n_coarse = off;
+  p->nq = (off + TS - 1) / TS;
+  HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
+  // batched factorisation
+  const int big = 0x7fffffff;
+  HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
+  for (const auto& L : P.sched_interior) dense(p, L);
+  dense(p, P.sched_schur);
+  const auto& XT = P.sched_xtiles;
+  if (P.precond == FETI_PREC_DIRICHLET) {
+    if (P.mixed)
+      launch_copy_iface<float>(p->d_tasks + XT.first, XT.count, p->d_sub, (const float*)p->d_arena,
+                               (float*)p->d_S, st);
+    else
+      launch_copy_iface<double>(p->d_tasks + XT.first, XT.count, p->d_sub, (const double*)p->d_arena,
+                                (double*)p->d_S, st);
+  }
+  if (P.mixed) {
+    launch_rho<float>(P.n_sub, p->d_sub, (const float*)p->d_arena, p->d_rho, st);
+    launch_regularise<float>(p->d_tasks + XT.first, XT.count, p->d_sub, p->d_rb, p->d_rho, (float*)p->d_arena, st);
+  } else {
+    launch_rho<double>(P.n_sub, p->d_sub, (const double*)p->d_arena, p->d_rho, st);
+    launch_regularise<double>(p->d_tasks + XT.first, XT.count, p->d_sub, p->d_rb, p->d_rho, (double*)p->d_arena,
+                              st);
+  }
+  for (const auto& L : P.sched_iface) dense(p, L);
+  for (const auto& L : P.sched_trtri) dense(p, L);
+  dense(p, P.sched_lauum);
+  {
+    bool any_partial = false;
+    for (const auto& si : P.sub) any_partial |= (si.floating && si.n_modes < 6);
+    if (any_partial) {
+      if (P.mixed)
+        launch_woodbury<float>(P.n_sub, P.max_nt_b, p->d_tasks + XT.first, XT.count, p->d_sub, (float*)p->d_X,
+                               p->d_rb, p->d_rho, p->d_work, p->d_wbm, st);
+      else
+        launch_woodbury<double>(P.n_sub, P.max_nt_b, p->d_tasks + XT.first, XT.count, p->d_sub,
+                                (double*)p->d_X, p->d_rb, p->d_rho, p->d_work, p->d_wbm, st);
+    }
+  }
+  // coarse matrix Q = G^T G, its Cholesky factor and explicit inverse (FP64)
+  if (p->n_coarse > 0) {
+    SubInfo q{};
+    q.n_ii = 0;
+    q.n_b = p->n_coarse;
+    q.nt_i = 0;
+    q.nt_b = p->nq;
+    q.nt = p->nq;
+    q.floating = 0;
+    HIPCHK(hipMemcpyAsync(p->d_qsub, &q, sizeof(SubInfo), hipMemcpyHostToDevice, st));
+    std::vector<SubInfo> qs{q};
+    std::vector<Task> qt;
+    std::vector<HostPlan::Launch> qi, qf, qr;
+    HostPlan::Launch qsch, qla, qx, qall;
+    build_factor_schedule(qs, qt, qi, qsch, qf, qr, qla, qx, qall);
+    p->q_xtiles = qx;
+    if ((int)qt.size() > p->qtask_cap * (p->nq + 2)) {
+      p->err = "coarse task list overflow";
+      return FETI_EDEVICE;
+    }
+    HIPCHK(hipMemcpyAsync(p->d_qtasks, qt.data(), qt.size() * sizeof(Task), hipMemcpyHostToDevice, st));
+    launch_init_arena<double>(p->d_qtasks + qall.first, qall.count, p->d_qsub, p->d_qarena, st);
+    CoarseArgs c;
+    c.n_pairs = (int)P.qp_s.size();
+    c.qp_s = p->d_qp_s;
+    c.qp_t = p->d_qp_t;
+    c.qp_ptr = p->d_qp_ptr;
+    c.qe_bs = p->d_qe_bs;
+    c.qe_bt = p->d_qe_bt;
+    c.qe_c = p->d_qe_c;
+    c.subs = p->d_sub;
+    c.rb = p->d_rb;
+    c.q = p->d_qarena;
+    asm_coarse(c, st);
+    auto qd = [&](const HostPlan::Launch& L) {
+      launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
+                           p->d_qX, p->d_err + 1, st);
+    };
+    const int big2 = 0x7fffffff;
+    HIPCHK(hipMemcpyAsync(p->d_err + 1, &big2, sizeof(int), hipMemcpyHostToDevice, st));
+    for (const auto& L : qf) qd(L);
+    for (const auto& L : qr) qd(L);
+    qd(qla);
+    HIPCHK(hipStreamSynchronize(st));   // task list upload must complete before qt goes out of scope
+  }
+  HIPCHK(hipEventRecord(p->ev[2], st));
+  int errs[2] = {0x7fffffff, 0x7fffffff};
+  HIPCHK(hipMemcpyAsync(errs, p->d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (errs[0] != 0x7fffffff) {
+    p->err = "non-positive pivot in the local factor of subdomain " + std::to_string(errs[0]);
+    p->factored = false;
+    return FETI_ENOTSPD;
+  }
+  if (p->n_coarse > 0 && errs[1] != 0x7fffffff) {
+    p->err = "coarse matrix G^T G is not positive definite";
+    p->factored = false;
+    return FETI_ENOTSPD;
+  }
+  p->factored = true;
+  return FETI_OK;
+}
+
+// Dual solve for the local right-hand sides already in d_f and the Dirichlet
+// data in d_dvals; writes the local displacements to d_u.
+feti_status solve_core(feti_problem* p, feti_stats* stats) {
+  HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  const int64_t n = P.n_lam;
+  HIPCHK(hipEventRecord(p->ev[3], st));
+  // e = R^T f ; d = B K^+ f - b
+  if (p->n_coarse) pcg_coarse_gt_full(P.n_sub, p->d_sub, p->d_rfull, p->d_f, p->d_e, st);
+  kpinv(p, p->d_f, p->d_z);
+  int iters = 0, status = FETI_OK;
+  double rel = 0.0, kappa = 1.0;
+  if (n > 0) {
+    vec_copy_b2f(p->di, p->d_z, p->d_yb, st);
+    vec_bvec(p->di, p->d_dvals, p->d_bv, st);
+    pcg_scatter(p->di, 0, p->d_yb, p->d_bv, 1.0, p->d_d, nullptr, st);
+    vec_axpby(n, -2.0, p->d_bv, 1.0, p->d_d, st);   // (b + B y) - 2 b = B y - b
+    // lambda_0 = G Q^{-1} e
+    if (p->n_coarse) {
+      coarse_solve(p, p->d_e, p->d_calpha, nullptr);
+      pcg_coarse_expand(p->di, p->d_sub, p->d_rb, p->d_calpha, p->d_vb, nullptr, st);
+      pcg_scatter(p->di, 0, p->d_vb, nullptr, 1.0, p->d_lam, nullptr, st);
+    } else {
+      vec_fill(n, 0.0, p->d_lam, st);
+    }
+    // r = d - F lambda ; w = P r ; z = P M w ; s = z
+    apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
+    pcg_init_state(p->d_state, p->opt.rtol, 0.0, p->opt.max_it, p->hist_cap, st);
+    project(p, p->d_r, p->d_wv, nullptr);
+    precondition(p, p->d_wv, p->d_tv, nullptr);
+    project(p, p->d_tv, p->d_zv, nullptr);
+    vec_axpby(n, 1.0, p->d_zv, 0.0, p->d_s, st);
+    pcg_dot(n, p->d_wv, p->d_zv, p->d_wv, p->d_wv, p->d_dots, nullptr, st);
+    pcg_beta(p->d_dots, p->d_state, 1, nullptr, st);
+    // graph of graph_block iterations
+    const int gb = std::max(1, p->opt.graph_block);
+    if (!p->graph || p->graph_iters != gb) {
+      if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+      }
+      hipGraph_t gr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < gb; ++k) pcg_iteration(p);
+      HIPCHK(hipStreamEndCapture(st, &gr));
+      HIPCHK(hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gr);
+      p->graph_iters = gb;
+    }
+    PcgState hs{};
+    for (;;) {
+      HIPCHK(hipMemcpyAsync(&hs, p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hs.done) break;
+      HIPCHK(hipGraphLaunch(p->graph, st));
+    }
+    iters = hs.it;
+    status = hs.status;
+    rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
+    if (stats && iters > 0) {
+      std::vector<double> h(2 * (size_t)std::min(iters, p->hist_cap));
+      HIPCHK(hipMemcpyAsync(h.data(), p->d_hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      kappa = lanczos_kappa(h, std::min(iters, p->hist_cap));
+    }
+    // gamma = -Q^{-1} G^T r ; u = K^+(f - B^T lambda) + R gamma
+    vec_axpby(P.NF, 1.0, p->d_f, 0.0, p->d_gfull, st);
+    pcg_gather(p->di, 0, p->d_lam, p->d_xb, nullptr, st);
+    vec_add_b2f(p->di, p->d_xb, -1.0, p->d_gfull, st);
+    kpinv(p, p->d_gfull, p->d_u);
+    if (p->n_coarse) {
+      pcg_gather(p->di, 0, p->d_r, p->d_xb, nullptr, st);
+      pcg_coarse_gt(P.n_sub, p->d_sub, p->d_rb, p->d_xb, p->d_cg, nullptr, st);
+      coarse_solve(p, p->d_cg, p->d_calpha, nullptr);
+      vec_axpby(p->n_coarse, -1.0, p->d_calpha, 0.0, p->d_gamma, st);
+      pcg_add_modes(P.NF, p->di.f_sub, p->d_sub, p->d_rfull, p->d_gamma, p->d_u, st);
+    }
+  } else {
+    vec_axpby(P.NF, 1.0, p->d_z, 0.0, p->d_u, st);
+  }
+  HIPCHK(hipEventRecord(p->ev[4], st));
+  if (stats) {
+    stats->iters = iters;
+    stats->converged = status == FETI_OK ? 1 : 0;
+    stats->rel_res = rel;
+    stats->kappa_est = kappa;
+    stats->n_coarse = p->n_coarse;
+    stats->n_lambda = n;
+    stats->device_bytes = p->bytes;
+  }
+  if (status == FETI_EBREAKDOWN) {
+    p->err = "PCG breakdown (s.Fs <= 0)";
+    return FETI_EBREAKDOWN;
+  }
+  if (status == FETI_ENOCONV) {
+    p->err = "PCG reached max_it without convergence";
+    return FETI_ENOCONV;
+  }
+  return FETI_OK;
+}
+
+feti_status write_output(feti_problem* p, double* out, int sum_mode) {
+  HostPlan& P = p->P;
+  double* dst = (p->opt.flags & FETI_DEVICE_PTRS) ? out : p->d_out;
+  vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, dst, sum_mode, p->stream);
+  if (!(p->opt.flags & FETI_DEVICE_PTRS))
+    HIPCHK(hipMemcpyAsync(out, p->d_out, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return FETI_OK;
+}
+
+float ev_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+feti_status load_U(feti_problem* p, const double* U, const double** U_dev) {
+  *U_dev = nullptr;
+  if (!U) return FETI_OK;
+  if (p->opt.flags & FETI_DEVICE_PTRS) {
+    *U_dev = U;
+    return FETI_OK;
+  }
+  for (int64_t k = 0; k < p->P.n_dof; ++k)
+    if (!std::isfinite(U[k])) {
+      p->err = "non-finite displacement";
+      return FETI_EINVAL;
+    }
+  HIPCHK(hipMemcpyAsync(p->d_U, U, p->P.n_dof * sizeof(double), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  *U_dev = p->d_U;
+  return FETI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+feti_status feti_setup(const feti_mesh* mesh, const feti_options* opts, feti_problem** out) {
+  if (!out) {
+    g_setup_error = "out is NULL";
+    return FETI_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<feti_problem> p(new feti_problem());
+  if (opts) p->opt = *opts;
+  else {
+    p->opt.variant = FETI_ALL_FLOATING;
+    p->opt.precond = FETI_PREC_LUMPED;
+    p->opt.precision = FETI_FP64;
+  }
+  if (p->opt.rtol <= 0) p->opt.rtol = 1e-8;
+  if (p->opt.max_it <= 0) p->opt.max_it = 1000;
+  if (p->opt.ir_tol <= 0) p->opt.ir_tol = 1e-10;
+  if (p->opt.ir_max <= 0) p->opt.ir_max = 6;
+  if (p->opt.graph_block <= 0) p->opt.graph_block = 8;
+  p->opt.graph_block = std::min(p->opt.graph_block, 64);
+  if (p->opt.variant != FETI_CLASSICAL && p->opt.variant != FETI_ALL_FLOATING) {
+    g_setup_error = "bad variant";
+    return FETI_EINVAL;
+  }
+  if (p->opt.precision != FETI_FP64 && p->opt.precision != FETI_MIXED) {
+    g_setup_error = "bad precision";
+    return FETI_EINVAL;
+  }
+  if ((p->opt.dev_alloc == nullptr) != (p->opt.dev_free == nullptr)) {
+    g_setup_error = "dev_alloc and dev_free must be given together";
+    return FETI_EINVAL;
+  }
+  p->da.fn = p->opt.dev_alloc;
+  p->da.fr = p->opt.dev_free;
+  p->da.ctx = p->opt.alloc_ctx;
+  std::string e = build_plan(mesh, &p->opt, p->P);
+  if (!e.empty()) {
+    g_setup_error = e;
+    return FETI_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    g_setup_error = "no HIP device available";
+    return FETI_EDEVICE;
+  }
+  if (p->opt.hip_stream) {
+    p->stream = (hipStream_t)p->opt.hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      g_setup_error = "hipStreamCreate failed";
+      return FETI_EDEVICE;
+    }
+    p->own_stream = true;
+  }
+  feti_status s = setup_device(p.get());
+  if (s != FETI_OK) {
+    g_setup_error = p->err;
+    feti_destroy(p.release());
+    return s;
+  }
+  *out = p.release();
+  return FETI_OK;
+}
+
+feti_status feti_footprint(const feti_problem* p, size_t* device_bytes) {
+  if (!p || !device_bytes) return FETI_EINVAL;
+  *device_bytes = p->bytes;
+  return FETI_OK;
+}
+
+feti_status feti_factor(feti_problem* p, const double* U) {
+  if (!p) return FETI_EINVAL;
+  p->err.clear();
+  const double* Ud = nullptr;
+  TRY(load_U(p, U, &Ud));
+  feti_status s = do_factor(p, Ud);
+  p->factored_linear = (s == FETI_OK && U == nullptr);
+  return s;
+}
+
+feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stats* stats) {
+  if (!p) return FETI_EINVAL;
+  p->err.clear();
+  if (!u) {
+    p->err = "u is NULL";
+    return FETI_EINVAL;
+  }
+  if (!std::isfinite(load_factor)) {
+    p->err = "non-finite load factor";
+    return FETI_EINVAL;
+  }
+  if (!p->factored || !p->factored_linear) {
+    p->err = "feti_solve needs a preceding feti_factor(p, NULL)";
+    return FETI_ESTATE;
+  }
+  HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  HIPCHK(hipEventRecord(p->ev[5], st));
+  vec_axpby(P.n_dof, load_factor, p->d_dirval, 0.0, p->d_dvals, st);
+  const double* fn = nullptr;
+  if (!P.pface.empty() && P.pressure != 0.0) {
+    PressureArgs pa;
+    pa.n_nodes = P.n_nodes;
+    pa.xyz = p->d_xyz;
+    pa.U = nullptr;
+    pa.pface = p->d_pface;
+    pa.pf_ptr = p->d_pf_ptr;
+    pa.pf_ent = p->d_pf_ent;
+    pa.pressure = P.pressure;
+    pa.fnodal = p->d_fnodal;
+    asm_pressure(pa, st);
+    fn = p->d_fnodal;
+  }
+  vec_fill(P.NF, 0.0, p->d_f, st);
+  RhsArgs r;
+  r.n_loc_nodes = P.n_loc_nodes;
+  r.diag_slot = p->d_diag_slot;
+  r.ps_c0 = p->d_ps_c0;
+  r.ps_c1 = p->d_ps_c1;
+  r.pc_e = p->d_pc_e;
+  r.pc_ab = p->d_pc_ab;
+  r.loc_sub = p->d_loc_sub;
+  r.loc_pos = p->d_loc_pos;
+  r.loc_ncopy = p->d_loc_ncopy;
+  r.loc_node = p->d_loc_node;
+  r.subs = p->d_sub;
+  r.fbody = p->d_fbody;
+  r.fint = p->d_fint;
+  r.fnodal = fn;
+  r.ell_col = p->d_ell_col;
+  r.ell_val = p->d_ell_val;
+  r.dvals = p->d_dvals;
+  r.body_scale = load_factor;
+  r.int_scale = 0.0;
+  r.nodal_scale = load_factor;
+  r.f = p->d_f;
+  asm_rhs(r, st);
+  feti_status s = solve_core(p, stats);
+  if (s != FETI_OK && s != FETI_ENOCONV) return s;
+  feti_status s2 = write_output(p, u, 0);
+  if (s2 != FETI_OK) return s2;
+  if (stats) {
+    stats->t_pcg = ev_ms(p->ev[3], p->ev[4]) * 1e-3;
+    stats->t_total = ev_ms(p->ev[5], p->ev[4]) * 1e-3;
+    stats->t_assemble = ev_ms(p->ev[0], p->ev[1]) * 1e-3;
+    stats->t_factor = ev_ms(p->ev[1], p->ev[2]) * 1e-3;
+    stats->ir_sweeps = 0;
+  }
+  return s;
+}
+
+feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, double* dU, double* res_norm,
+                             feti_stats* stats) {
+  if (!p) return FETI_EINVAL;
+  p->err.clear();
+  if (!dU || !std::isfinite(tau)) {
+    p->err = "bad arguments";
+    return FETI_EINVAL;
+  }
+  HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  const double* Ud = nullptr;
+  TRY(load_U(p, U_k, &Ud));
+  TRY(do_factor(p, Ud));
+  p->factored_linear = (U_k == nullptr);
+  HIPCHK(hipEventRecord(p->ev[5], st));
+  vec_dirinc(P.n_dof, p->d_dmask, p->d_dirval, tau, Ud, p->d_dvals, st);
+  const double* fn = nullptr;
+  if (!P.pface.empty() && P.pressure != 0.0) {
+    PressureArgs pa;
+    pa.n_nodes = P.n_nodes;
+    pa.xyz = p->d_xyz;
+    pa.U = Ud;
+    pa.pface = p->d_pface;
+    pa.pf_ptr = p->d_pf_ptr;
+    pa.pf_ent = p->d_pf_ent;
+    pa.pressure = P.pressure;
+    pa.fnodal = p->d_fnodal;
+    asm_pressure(pa, st);
+    fn = p->d_fnodal;
+  }
+  RhsArgs r;
+  r.n_loc_nodes = P.n_loc_nodes;
+  r.diag_slot = p->d_diag_slot;
+  r.ps_c0 = p->d_ps_c0;
+  r.ps_c1 = p->d_ps_c1;
+  r.pc_e = p->d_pc_e;
+  r.pc_ab = p->d_pc_ab;
+  r.loc_sub = p->d_loc_sub;
+  r.loc_pos = p->d_loc_pos;
+  r.loc_ncopy = p->d_loc_ncopy;
+  r.loc_node = p->d_loc_node;
+  r.subs = p->d_sub;
+  r.fbody = p->d_fbody;
+  r.fint = p->d_fint;
+  r.fnodal = fn;
+  r.ell_col = p->d_ell_col;
+  r.ell_val = p->d_ell_val;
+  r.body_scale = tau;
+  r.int_scale = 1.0;
+  r.nodal_scale = tau;
+  // residual norm tau f_ext - f_int over free DOFs (no Dirichlet lifting)
+  if (res_norm) {
+    vec_fill(P.n_dof, 0.0, p->d_out, st);
+    vec_fill(P.NF, 0.0, p->d_f, st);
+    r.dvals = p->d_out;   // zeros: no lifting
+    r.f = p->d_f;
+    asm_rhs(r, st);
+    vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_dvals, p->d_out, 1, st);
+    pcg_dot(P.n_dof, p->d_out, p->d_out, nullptr, nullptr, p->d_dots, nullptr, st);
+    std::vector<double> parts(2 * DOT_PARTS);
+    HIPCHK(hipMemcpyAsync(parts.data(), p->d_dots, parts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double s2 = 0.0;
+    for (int k = 0; k < DOT_PARTS; ++k) s2 += parts[2 * k];
+    *res_norm = std::sqrt(s2);
+  }
+  vec_fill(P.NF, 0.0, p->d_f, st);
+  r.dvals = p->d_dvals;
+  r.f = p->d_f;
+  asm_rhs(r, st);
+  feti_status s = solve_core(p, stats);
+  if (s != FETI_OK && s != FETI_ENOCONV) return s;
+  feti_status s2 = write_output(p, dU, 0);
+  if (s2 != FETI_OK) return s2;
+  if (stats) {
+    stats->t_pcg = ev_ms(p->ev[3], p->ev[4]) * 1e-3;
+    stats->t_assemble = ev_ms(p->ev[0], p->ev[1]) * 1e-3;
+    stats->t_factor = ev_ms(p->ev[1], p->ev[2]) * 1e-3;
+    stats->t_total = stats->t_assemble + stats->t_factor + ev_ms(p->ev[5], p->ev[4]) * 1e-3;
+    stats->ir_sweeps = 0;
+  }
+  return s;
+}
+
+const char* feti_last_error(const feti_problem* p) {
+  if (!p) return g_setup_error.c_str();
+  return p->err.c_str();
+}
+
+void feti_destroy(feti_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  for (auto& ev : p->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  for (void* a : p->allocs) {
+    if (p->da.fr) p->da.fr(a, p->da.ctx);
+    else (void)hipFree(a);
+  }
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations of libfeti: host plan (decomposition and index maps),
+// device-side problem state, and the launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/feti.h"
+
+namespace feti {
+
+// Edge of the square tiles that every dense local matrix is stored in.
+constexpr int TS = 64;
+constexpr int TS2 = TS * TS;
+// Maximum number of nonzeros in one row of a Q1 stiffness (27 nodes x 3 dofs).
+constexpr int ELLW = 81;
+
+// Per-subdomain layout, copied to the device as a plain struct array.
+// A subdomain's local DOFs are ordered interior first, constraint ("b") DOFs
+// last; each class is padded to a multiple of TS with decoupled identity rows.
+// Dense blocks are stored as lower-triangular arrays of column-major TSxTS tiles;
+// tile (i, j), i >= j, sits at tile index i*(i+1)/2 + j.
+struct SubInfo {
+  int32_t n_nodes;      // local nodes
+  int32_t n_ii, n_b;    // interior / constraint DOFs (without padding)
+  int32_t nt_i, nt_b, nt;
+  int32_t node_off;     // offset into local-node arrays
+  int32_t floating;     // has a rigid-body kernel
+  int32_t n_modes;      // kernel dimension used (0, 3..6)
+  int32_t coarse_off;   // first coarse index of this subdomain
+  int64_t tile_off;     // element offset into the factor arena
+  int64_t linv_off;     // element offset into the diagonal-inverse arena
+  int64_t x_off;        // element offset into the interface arenas (X, W, S)
+  int64_t full_off;     // offset of the local vector in full-space vectors
+  int64_t b_off;        // offset of the interface part in b-space vectors
+  int64_t part_off;     // offset into interface GEMV partial sums
+};
+
+// One work item of a batched tile kernel.
+struct Task {
+  int32_t sub, i, j, k0, k1;
+};
+
+struct HostPlan {
+  // ---- problem copy
+  int64_t n_nodes = 0, n_elems = 0, n_dof = 0;
+  int32_t n_sub = 0;
+  bool af = true;
+  int precond = 1;
+  bool mixed = false;
+  bool any_hgo = false;
+  std::vector<double> xyz;
+  std::vector<int64_t> hex8;
+  std::vector<int32_t> elem_sub, elem_mat;
+  std::vector<feti_material> mat;
+  std::vector<double> fibers, body_force;
+  std::vector<int64_t> pface;
+  double pressure = 0.0;
+  std::vector<uint8_t> dir_mask;        // [n_dof]
+  std::vector<double> dir_val;          // [n_dof]
+  std::vector<int64_t> dir_list;        // Dirichlet dofs, ascending
+
+  // ---- subdomains
+  std::vector<SubInfo> sub;
+  int64_t n_loc_nodes = 0;              // total local nodes
+  std::vector<int64_t> loc_node;        // [n_loc_nodes] global node
+  std::vector<int32_t> loc_pos;         // [3*n_loc_nodes] position in local full space, -1 eliminated
+  std::vector<int32_t> loc_ncopy;       // [n_loc_nodes] number of subdomain copies of the node
+  std::vector<int32_t> loc_sub;         // [n_loc_nodes] owning subdomain
+  std::vector<int32_t> fpos_lnode;      // [NF] local node of a full-space position (-1 padding)
+  std::vector<int8_t> fpos_comp;        // [NF] component of a full-space position
+  std::vector<int32_t> f_sub;           // [NF] subdomain of a full-space position
+  int64_t NF = 0, NB = 0;               // full-space and b-space lengths
+  int64_t n_tiles = 0, n_xtiles = 0, n_linv = 0, n_part = 0;
+
+  // ---- assembly gather (node pairs inside a subdomain)
+  std::vector<int32_t> ps_a, ps_b, ps_nbr, ps_c0, ps_c1;   // per pair slot (a,b: local-node index incl. node_off)
+  std::vector<int32_t> pc_e;            // contribution element
+  std::vector<int32_t> pc_ab;           // la | lb << 8
+  std::vector<int32_t> diag_slot;       // [n_loc_nodes] slot of (a, a)
+  std::vector<int32_t> ell_col;         // [NF*ELLW]  >=0 local pos, -1 empty, <=-2 Dirichlet dof -(g+2)
+
+  // ---- multipliers
+  int64_t n_lam = 0;
+  std::vector<int64_t> r_b0, r_b1;      // b-space index of the two entries (-1 if none)
+  std::vector<double> r_c0, r_c1, r_w;  // coefficients and multiplicity weight
+  std::vector<int64_t> r_gdof;          // Dirichlet dof of an AF Dirichlet row, else -1
+  std::vector<int32_t> g_ptr;           // [NB+1] multiplier rows touching each b entry
+  std::vector<int32_t> g_row;
+  std::vector<double> g_coef;
+  std::vector<int64_t> b2full;          // [NB]
+  std::vector<int32_t> b_sub;           // [NB]
+
+  // ---- recovery of global displacements
+  std::vector<int32_t> uc_ptr;          // [n_dof+1]
+  std::vector<int64_t> uc_idx;          // full-space index of each copy
+
+  // ---- pressure faces: per global node, (face*4+corner) list
+  std::vector<int32_t> pf_ptr, pf_ent;
+
+  // ---- coarse problem: neighbour pairs (s >= t) and their shared rows
+  std::vector<int32_t> qp_s, qp_t, qp_ptr;       // per pair, entries [qp_ptr[k], qp_ptr[k+1])
+  std::vector<int64_t> qe_bs, qe_bt;
+  std::vector<double> qe_c;                       // c_s * c_t
+
+  // ---- factor schedule (task lists, launched in order)
+  struct Launch { int kind; int32_t first, count; };
+  std::vector<Task> tasks;
+  std::vector<Launch> sched_interior;   // stage 1
+  Launch sched_schur{0, 0, 0};          // stage 2
+  std::vector<Launch> sched_iface;      // stage 4
+  std::vector<Launch> sched_trtri;      // stage 5
+  Launch sched_lauum{0, 0, 0};          // stage 6
+  Launch sched_xtiles{0, 0, 0};         // all interface lower tiles (sub, I, J)
+  Launch sched_alltiles{0, 0, 0};       // all factor tiles (sub, i, j)
+  int max_nt_i = 0, max_nt_b = 0;
+};
+
+enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4 };
+
+// Builds the plan; returns an empty string on success, else an error message.
+std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);
+
+// Appends the factor schedule of a batch of matrices described by `subs`
+// (interior/interface tile counts) into P-like containers.
+void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& tasks,
+                           std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
+                           std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
+                           HostPlan::Launch& lauum, HostPlan::Launch& xtiles,
+                           HostPlan::Launch& alltiles);
+
+}  // namespace feti

@@ -1,0 +1,590 @@
+// Element assembly, local gathers, right-hand sides, rigid-body kernels and
+// the coarse matrix G^T G.
+//
+// Element tangents: one wavefront per Q1 element, lane (a, b) computes the
+// 3x3 block K_ab over the 2x2x2 Gauss points.
+//   * isotropic linear elasticity (section 5.1);
+//   * Holzapfel-Gasser-Ogden (section 2: eqs. (isoaniso), (iso), (aniso_1),
+//     (aniso_2), stress split of eq. (additiveStress)) with the tangent of
+//     eq. (Tangent) and a pressure that is constant per element and condensed
+//     (section 3.2, P0 static condensation): mean dilatation Jbar = v_e/V_e,
+//     p = kappa (Jbar - 1), plus the rank-one term (kappa/V_e) g g^T.
+// The elasticity tensor, which the paper leaves to its references, is the
+// closed form of the HGO energy: C = C_iso + C_vol with
+//   C_iso = P:Cbar:P^T + 2/3 J^{-2/3} (Sbar:C) Ptilde - 2/3 (Cinv x S_iso + S_iso x Cinv),
+//   C_vol = J p (Cinv x Cinv - 2 Cinv (.) Cinv).
+// Gathers into the subdomain matrices sum the element blocks of every node pair
+// in a fixed order (no atomics), so assembly is deterministic.
+#include "feti_impl.h"
+#include "k_pcg.h"
+
+namespace feti {
+
+__device__ __forceinline__ int64_t tidx3(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+__device__ __forceinline__ double corner(int a, int k) { return (double)(2 * ((a >> k) & 1) - 1); }
+
+// dN_a/dxi_k at Gauss point gp (points at +-1/sqrt(3), ordered like the corners)
+__device__ __forceinline__ double dshape(int a, int k, int gp) {
+  const double g = 0.57735026918962576451;
+  double v = 0.125 * corner(a, k);
+  for (int d = 0; d < 3; ++d)
+    if (d != k) v *= 1.0 + corner(a, d) * corner(gp, d) * g;
+  return v;
+}
+__device__ __forceinline__ double shape(int a, int gp) {
+  const double g = 0.57735026918962576451;
+  double v = 0.125;
+  for (int d = 0; d < 3; ++d) v *= 1.0 + corner(a, d) * corner(gp, d) * g;
+  return v;
+}
+
+__device__ void inv3(const double* A, double* inv, double* det) {
+  const double c00 = A[4] * A[8] - A[5] * A[7];
+  const double c01 = -(A[3] * A[8] - A[5] * A[6]);
+  const double c02 = A[3] * A[7] - A[4] * A[6];
+  const double d = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  const double id = 1.0 / d;
+  inv[0] = c00 * id;
+  inv[3] = c01 * id;
+  inv[6] = c02 * id;
+  inv[1] = -(A[1] * A[8] - A[2] * A[7]) * id;
+  inv[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  inv[7] = -(A[0] * A[7] - A[1] * A[6]) * id;
+  inv[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  inv[5] = -(A[0] * A[5] - A[2] * A[3]) * id;
+  inv[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  *det = d;
+}
+
+__constant__ int VA[6] = {0, 1, 2, 0, 1, 0};
+__constant__ int VB[6] = {0, 1, 2, 1, 2, 2};
+
+// Per-Gauss-point HGO state: total S (sym 3x3), Voigt tangent, F.
+struct HgoPoint {
+  double S[9], CV[36], F[9];
+};
+
+// Closed-form isochoric + volumetric stress/tangent of the HGO model at C,
+// with the element pressure p (P0) and the element factor J of this point.
+__device__ void hgo_point(const double* F, double J, double p, const double* a1, const double* a2, double c,
+                          double k1, double k2, HgoPoint& out) {
+  double C[9];
+  for (int I = 0; I < 3; ++I)
+    for (int K = 0; K < 3; ++K) C[3 * I + K] = F[I] * F[K] + F[3 + I] * F[3 + K] + F[6 + I] * F[6 + K];
+  double Ci[9], detC;
+  inv3(C, Ci, &detC);
+  const double Jm23 = pow(J, -2.0 / 3.0);
+  const double* af[2] = {a1, a2};
+  double d1[2], d2[2], A[2][9], D[2][9];
+  for (int f = 0; f < 2; ++f) {
+    const double* a = af[f];
+    double aCa = 0.0, aCIa = 0.0;
+    for (int I = 0; I < 3; ++I)
+      for (int K = 0; K < 3; ++K) {
+        aCa += a[I] * C[3 * I + K] * a[K];
+        aCIa += a[I] * (C[3 * I + K] - (I == K ? 1.0 : 0.0)) * a[K];
+      }
+    // Ibar_4 - 1 for a unit fibre, exactly zero at C = I
+    const double E = Jm23 * aCIa + (Jm23 - 1.0);
+    if (E > 0.0) {   // fibres carry tension only
+      const double ex = exp(k2 * E * E);
+      d1[f] = k1 * E * ex;
+      d2[f] = k1 * (1.0 + 2.0 * k2 * E * E) * ex;
+    } else {
+      d1[f] = 0.0;
+      d2[f] = 0.0;
+    }
+    for (int I = 0; I < 3; ++I)
+      for (int K = 0; K < 3; ++K) A[f][3 * I + K] = a[I] * a[K];
+    for (int k = 0; k < 9; ++k) D[f][k] = A[f][k] - aCa / 3.0 * Ci[k];   // dev_C(A)
+  }
+  double Sb[9];
+  for (int k = 0; k < 9; ++k) Sb[k] = 2.0 * d1[0] * A[0][k] + 2.0 * d1[1] * A[1][k];
+  Sb[0] += c;
+  Sb[4] += c;
+  Sb[8] += c;
+  double SbC = 0.0;
+  for (int k = 0; k < 9; ++k) SbC += Sb[k] * C[k];
+  double Siso[9];
+  for (int k = 0; k < 9; ++k) Siso[k] = Jm23 * (Sb[k] - SbC / 3.0 * Ci[k]);
+  for (int k = 0; k < 9; ++k) {
+    out.S[k] = Siso[k] + J * p * Ci[k];
+    out.F[k] = F[k];
+  }
+  const double cbar0 = 4.0 * Jm23 * Jm23 * d2[0], cbar1 = 4.0 * Jm23 * Jm23 * d2[1];
+  const double tr23 = 2.0 / 3.0 * Jm23 * SbC;
+  for (int al = 0; al < 6; ++al) {
+    const int a = VA[al], b = VB[al];
+    for (int be = 0; be < 6; ++be) {
+      const int cc = VA[be], d = VB[be];
+      const double odot = 0.5 * (Ci[3 * a + cc] * Ci[3 * b + d] + Ci[3 * a + d] * Ci[3 * b + cc]);
+      const double oxo = Ci[3 * a + b] * Ci[3 * cc + d];
+      double v = cbar0 * D[0][3 * a + b] * D[0][3 * cc + d] + cbar1 * D[1][3 * a + b] * D[1][3 * cc + d];
+      v += tr23 * (odot - oxo / 3.0);
+      v -= 2.0 / 3.0 * (Ci[3 * a + b] * Siso[3 * cc + d] + Siso[3 * a + b] * Ci[3 * cc + d]);
+      v += J * p * (oxo - 2.0 * odot);
+      out.CV[6 * al + be] = v;
+    }
+  }
+}
+
+// One wavefront per element; 4 elements per 256-thread block.  Barriers are
+// block-wide and unconditional; per-wave work is guarded by its element's kind.
+__global__ __launch_bounds__(256) void k_elements(AsmArgs A) {
+  __shared__ double sX[4][24], sU[4][24], sInv[4][8][9], sDet[4][8], sdN[4][8][8][3];
+  __shared__ double sJ[4][8], sG[4][24], sFp[4][8][9], sF[4][8][8][3];
+  __shared__ HgoPoint sP[4][8];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + w;
+  const bool live = e < A.n_elems;
+  const double* m = live ? A.mat + 7 * A.elem_mat[e] : A.mat;
+  const int kind = live ? (int)m[0] : -1;
+  const bool hgo = kind == 1, lin = kind == 0;
+  if (live && l < 24) {
+    const int64_t nd = A.hex8[e * 8 + l / 3];
+    sX[w][l] = A.xyz[nd * 3 + l % 3];
+    sU[w][l] = A.U ? A.U[nd * 3 + l % 3] : 0.0;
+  }
+  __syncthreads();
+  if (live && l < 8) {
+    double Jm[9];
+    for (int d = 0; d < 3; ++d)
+      for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int a = 0; a < 8; ++a) s += sX[w][3 * a + d] * dshape(a, k, l);
+        Jm[3 * d + k] = s;
+      }
+    double det;
+    inv3(Jm, sInv[w][l], &det);
+    sDet[w][l] = det;
+  }
+  __syncthreads();
+  if (live) {
+    const int gp = l >> 3, a = l & 7;
+    for (int d = 0; d < 3; ++d) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += dshape(a, k, gp) * sInv[w][gp][3 * k + d];
+      sdN[w][gp][a][d] = s;
+    }
+  }
+  __syncthreads();
+  // HGO stage 1: deformation gradient and J at every Gauss point
+  if (hgo && l < 8) {
+    const int gp = l;
+    double F[9];
+    for (int i = 0; i < 3; ++i)
+      for (int J = 0; J < 3; ++J) {
+        double s = (i == J) ? 1.0 : 0.0;
+        for (int q = 0; q < 8; ++q) s += sU[w][3 * q + i] * sdN[w][gp][q][J];
+        F[3 * i + J] = s;
+      }
+    double Fi[9], detF;
+    inv3(F, Fi, &detF);
+    sJ[w][gp] = detF;
+    for (int k = 0; k < 9; ++k) sFp[w][gp][k] = F[k];
+  }
+  __syncthreads();
+  // HGO stage 2: element pressure, point stresses/tangents, g vector
+  double V = 0.0, p = 0.0;
+  if (hgo) {
+    double v = 0.0;
+    for (int gp = 0; gp < 8; ++gp) {
+      V += sDet[w][gp];
+      v += sDet[w][gp] * sJ[w][gp];
+    }
+    p = m[6] * (v / V - 1.0);
+    if (l < 8) {
+      const double* a1 = A.fibers + e * 6;
+      hgo_point(sFp[w][l], sJ[w][l], p, a1, a1 + 3, m[3], m[4], m[5], sP[w][l]);
+    }
+    if (l < 24) {   // g_a = int J F^{-T} grad N_a, node l/3, component l%3
+      const int q = l / 3, i = l % 3;
+      double s = 0.0;
+      for (int gp = 0; gp < 8; ++gp) {
+        double Fi[9], dF;
+        inv3(sFp[w][gp], Fi, &dF);
+        double t = 0.0;
+        for (int I = 0; I < 3; ++I) t += Fi[3 * I + i] * sdN[w][gp][q][I];
+        s += sDet[w][gp] * sJ[w][gp] * t;
+      }
+      sG[w][l] = s;
+    }
+  }
+  __syncthreads();
+  const int a = l >> 3, b = l & 7;
+  double K[9];
+  for (int k = 0; k < 9; ++k) K[k] = 0.0;
+  if (lin) {
+    const double E = m[1], nu = m[2];
+    const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+    for (int gp = 0; gp < 8; ++gp) {
+      const double* na = sdN[w][gp][a];
+      const double* nb = sdN[w][gp][b];
+      const double wt = sDet[w][gp];
+      const double dot = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          K[3 * i + j] += wt * (lam * na[i] * nb[j] + mu * (na[j] * nb[i] + (i == j ? dot : 0.0)));
+    }
+  } else if (hgo) {
+    for (int gp = 0; gp < 8; ++gp) {
+      const HgoPoint& P = sP[w][gp];
+      const double* na = sdN[w][gp][a];
+      const double* nb = sdN[w][gp][b];
+      const double wt = sDet[w][gp];
+      double geo = 0.0;
+      for (int I = 0; I < 3; ++I)
+        for (int J = 0; J < 3; ++J) geo += na[I] * P.S[3 * I + J] * nb[J];
+      double Ba[6][3], Bb[6][3];
+      for (int al = 0; al < 6; ++al) {
+        const int I = VA[al], J = VB[al];
+        for (int i = 0; i < 3; ++i) {
+          if (I == J) {
+            Ba[al][i] = P.F[3 * i + I] * na[I];
+            Bb[al][i] = P.F[3 * i + I] * nb[I];
+          } else {
+            Ba[al][i] = P.F[3 * i + I] * na[J] + P.F[3 * i + J] * na[I];
+            Bb[al][i] = P.F[3 * i + I] * nb[J] + P.F[3 * i + J] * nb[I];
+          }
+        }
+      }
+      for (int j = 0; j < 3; ++j) {
+        double cb[6];
+        for (int al = 0; al < 6; ++al) {
+          double s = 0.0;
+          for (int be = 0; be < 6; ++be) s += P.CV[6 * al + be] * Bb[be][j];
+          cb[al] = s;
+        }
+        for (int i = 0; i < 3; ++i) {
+          double s = 0.0;
+          for (int al = 0; al < 6; ++al) s += Ba[al][i] * cb[al];
+          K[3 * i + j] += wt * (s + (i == j ? geo : 0.0));
+        }
+      }
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) K[3 * i + j] += m[6] / V * sG[w][3 * a + i] * sG[w][3 * b + j];
+  }
+  if (live) {
+    double* out = A.Ke + e * 576 + (a * 8 + b) * 9;
+    for (int k = 0; k < 9; ++k) out[k] = K[k];
+  }
+  // internal force: linear K_e u_e (reduced over b through LDS); HGO int F S grad N_a
+  if (lin)
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j) s += K[3 * i + j] * sU[w][3 * b + j];
+      sF[w][a][b][i] = s;
+    }
+  __syncthreads();
+  if (live && b == 0) {
+    for (int i = 0; i < 3; ++i) {
+      double fb = 0.0, fi = 0.0;
+      if (A.body)
+        for (int gp = 0; gp < 8; ++gp) fb += sDet[w][gp] * shape(a, gp) * A.body[e * 3 + i];
+      if (lin) {
+        for (int q = 0; q < 8; ++q) fi += sF[w][a][q][i];
+      } else {
+        for (int gp = 0; gp < 8; ++gp) {
+          const HgoPoint& P = sP[w][gp];
+          double t = 0.0;
+          for (int J = 0; J < 3; ++J) {
+            double FS = 0.0;
+            for (int I = 0; I < 3; ++I) FS += P.F[3 * i + I] * P.S[3 * I + J];
+            t += FS * sdN[w][gp][a][J];
+          }
+          fi += sDet[w][gp] * t;
+        }
+      }
+      A.fbody[e * 24 + 3 * a + i] = fb;
+      A.fint[e * 24 + 3 * a + i] = fi;
+    }
+  }
+}
+
+void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s) {
+  (void)any_hgo;
+  if (a.n_elems) hipLaunchKernelGGL(k_elements, dim3((unsigned)((a.n_elems + 3) / 4)), dim3(256), 0, s, a);
+}
+
+// Node-pair gather: K_i[(a,i),(b,j)] = sum over shared elements (fixed order).
+template <typename T>
+__global__ void k_gather_local(GatherArgs G, T* arena) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= G.n_slots) return;
+  const int la = G.ps_a[sl], lb = G.ps_b[sl], nbr = G.ps_nbr[sl];
+  double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = G.ps_c0[sl]; c < G.ps_c1[sl]; ++c) {
+    const int e = G.pc_e[c], ab = G.pc_ab[c];
+    const double* src = G.Ke + (int64_t)e * 576 + ((ab & 255) * 8 + (ab >> 8)) * 9;
+    for (int k = 0; k < 9; ++k) K[k] += src[k];
+  }
+  const SubInfo s = G.subs[G.loc_sub[la]];
+  T* base = arena + s.tile_off;
+  for (int i = 0; i < 3; ++i) {
+    const int row = G.loc_pos[3 * la + i];
+    if (row < 0) continue;
+    double* ev = G.ell_val + (s.full_off + row) * ELLW + nbr * 3;
+    for (int j = 0; j < 3; ++j) {
+      ev[j] = K[3 * i + j];
+      const int col = G.loc_pos[3 * lb + j];
+      if (col >= 0 && row >= col) {
+        const int ti = row / TS, tj = col / TS;
+        base[tidx3(ti, tj) * TS2 + (col % TS) * TS + (row % TS)] = (T)K[3 * i + j];
+      }
+    }
+  }
+}
+
+template <typename T>
+void asm_gather(const GatherArgs& g, T* arena, hipStream_t s) {
+  if (g.n_slots) hipLaunchKernelGGL(k_gather_local<T>, dim3((unsigned)((g.n_slots + 255) / 256)), dim3(256), 0, s, g, arena);
+}
+template void asm_gather<double>(const GatherArgs&, double*, hipStream_t);
+template void asm_gather<float>(const GatherArgs&, float*, hipStream_t);
+
+// Local right-hand side: body_scale * f_body - int_scale * f_int + nodal share,
+// minus the coupling to eliminated Dirichlet DOFs (classical variant).
+__global__ void k_rhs(RhsArgs R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * R.n_loc_nodes) return;
+  const int64_t la = t / 3;
+  const int i = (int)(t % 3);
+  const int pos = R.loc_pos[t];
+  if (pos < 0) return;
+  const SubInfo s = R.subs[R.loc_sub[la]];
+  const int sl = R.diag_slot[la];
+  double fb = 0.0, fi = 0.0;
+  for (int c = R.ps_c0[sl]; c < R.ps_c1[sl]; ++c) {
+    const int e = R.pc_e[c], lq = R.pc_ab[c] & 255;
+    fb += R.fbody[(int64_t)e * 24 + 3 * lq + i];
+    if (R.int_scale != 0.0) fi += R.fint[(int64_t)e * 24 + 3 * lq + i];
+  }
+  double f = R.body_scale * fb - R.int_scale * fi;
+  const int64_t g = R.loc_node[la];
+  if (R.fnodal) f += R.nodal_scale * R.fnodal[3 * g + i] / R.loc_ncopy[la];
+  const int64_t row = s.full_off + pos;
+  for (int k = 0; k < ELLW; ++k) {
+    const int cc = R.ell_col[row * ELLW + k];
+    if (cc <= -2) f -= R.ell_val[row * ELLW + k] * R.dvals[-(cc + 2)];
+  }
+  R.f[row] = f;
+}
+
+void asm_rhs(const RhsArgs& r, hipStream_t s) {
+  if (r.n_loc_nodes) hipLaunchKernelGGL(k_rhs, dim3((unsigned)((3 * r.n_loc_nodes + 255) / 256)), dim3(256), 0, s, r);
+}
+
+// Follower pressure on the current surface: f_a = -p int N_a (x,1 x x,2) deta.
+__global__ void k_pressure(PressureArgs P) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P.n_nodes) return;
+  double f[3] = {0, 0, 0};
+  const double g = 0.57735026918962576451;
+  const double e1[4] = {-1, 1, 1, -1}, e2[4] = {-1, -1, 1, 1};
+  for (int k = P.pf_ptr[n]; k < P.pf_ptr[n + 1]; ++k) {
+    const int64_t fc = P.pf_ent[k];
+    const int64_t face = fc / 4;
+    const int cn = (int)(fc % 4);
+    double x[4][3];
+    for (int q = 0; q < 4; ++q) {
+      const int64_t nd = P.pface[face * 4 + q];
+      for (int d = 0; d < 3; ++d) x[q][d] = P.xyz[nd * 3 + d] + (P.U ? P.U[nd * 3 + d] : 0.0);
+    }
+    for (int g1 = 0; g1 < 2; ++g1)
+      for (int g2 = 0; g2 < 2; ++g2) {
+        const double h1 = g1 ? g : -g, h2 = g2 ? g : -g;
+        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
+        for (int q = 0; q < 4; ++q) {
+          const double d1 = 0.25 * e1[q] * (1 + e2[q] * h2), d2 = 0.25 * e2[q] * (1 + e1[q] * h1);
+          for (int d = 0; d < 3; ++d) {
+            t1[d] += x[q][d] * d1;
+            t2[d] += x[q][d] * d2;
+          }
+        }
+        const double nv[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],
+                              t1[0] * t2[1] - t1[1] * t2[0]};
+        const double N = 0.25 * (1 + e1[cn] * h1) * (1 + e2[cn] * h2);
+        for (int d = 0; d < 3; ++d) f[d] += -P.pressure * N * nv[d];
+      }
+  }
+  for (int d = 0; d < 3; ++d) P.fnodal[3 * n + d] = f[d];
+}
+
+void asm_pressure(const PressureArgs& p, hipStream_t s) {
+  if (p.n_nodes) hipLaunchKernelGGL(k_pressure, dim3((unsigned)((p.n_nodes + 255) / 256)), dim3(256), 0, s, p);
+}
+
+// ---------------------------------------------------------------------------
+// Rigid-body kernel of each floating subdomain: translations and rotations
+// about the current centroid (rotations kept only if K annihilates them, for
+// stressed tangents); Gram-Schmidt (two passes, FP64) on the interface rows
+// gives an orthonormal Rb = R_b T; the full basis R T is used for G, e and
+// the recovery of the displacements.
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
+  __shared__ double red[256];
+  __shared__ double cen[3], T[6][6];
+  __shared__ int sel[6], nsel;
+  const int sid = blockIdx.x;
+  const SubInfo s = M.subs[sid];
+  const int64_t n = (int64_t)s.nt * TS;
+  double* rf = M.rfull + s.full_off * 6;
+  double* W = M.work + s.full_off * 6;
+  const int tid = threadIdx.x;
+  if (!s.floating) {
+    for (int64_t p = tid; p < n * 6; p += 256) rf[p] = 0.0;
+    for (int64_t p = tid; p < (int64_t)s.nt_b * TS * 6; p += 256) M.rb[s.b_off * 6 + p] = 0.0;
+    if (tid == 0) M.n_modes[sid] = 0;
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    double acc = 0.0;
+    for (int q = tid; q < s.n_nodes; q += 256) {
+      const int64_t g = M.loc_node[s.node_off + q];
+      acc += M.xyz[g * 3 + d] + (M.U ? M.U[g * 3 + d] : 0.0);
+    }
+    const double tot = block_sum(acc, red);
+    if (tid == 0) cen[d] = tot / s.n_nodes;
+  }
+  __syncthreads();
+  for (int64_t p = tid; p < n; p += 256) {
+    const int ln = M.fpos_lnode[s.full_off + p];
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    if (ln >= 0) {
+      const int comp = M.fpos_comp[s.full_off + p];
+      const int64_t g = M.loc_node[ln];
+      double x[3];
+      for (int d = 0; d < 3; ++d) x[d] = M.xyz[g * 3 + d] + (M.U ? M.U[g * 3 + d] : 0.0) - cen[d];
+      r[comp] = 1.0;
+      // rotation about x: (0,-z,y); about y: (z,0,-x); about z: (-y,x,0)
+      if (comp == 0) { r[4] = x[2]; r[5] = -x[1]; }
+      if (comp == 1) { r[3] = -x[2]; r[5] = x[0]; }
+      if (comp == 2) { r[3] = x[1]; r[4] = -x[0]; }
+    }
+    for (int k = 0; k < 6; ++k) W[p * 6 + k] = r[k];
+  }
+  __syncthreads();
+  __shared__ int failed[3], nfail;
+  if (tid == 0) {
+    nsel = 3;
+    nfail = 0;
+    for (int k = 0; k < 3; ++k) sel[k] = k;
+  }
+  __syncthreads();
+  if (M.test_rotations) {
+    double kf = 0.0;
+    for (int64_t p = tid; p < n; p += 256)
+      for (int q = 0; q < ELLW; ++q) {
+        const double v = M.ell_val[(s.full_off + p) * ELLW + q];
+        if (M.ell_col[(s.full_off + p) * ELLW + q] >= 0) kf += v * v;
+      }
+    const double knorm = sqrt(block_sum(kf, red));
+    for (int k = 3; k < 6; ++k) {
+      double kr = 0.0, rr = 0.0;
+      for (int64_t p = tid; p < n; p += 256) {
+        double y = 0.0;
+        for (int q = 0; q < ELLW; ++q) {
+          const int c = M.ell_col[(s.full_off + p) * ELLW + q];
+          if (c >= 0) y += M.ell_val[(s.full_off + p) * ELLW + q] * W[(int64_t)c * 6 + k];
+        }
+        kr += y * y;
+        rr += W[p * 6 + k] * W[p * 6 + k];
+      }
+      const double nkr = sqrt(block_sum(kr, red)), nr = sqrt(block_sum(rr, red));
+      if (tid == 0) {
+        if (nkr <= M.kernel_tol * knorm * nr) sel[nsel++] = k;
+        else failed[nfail++] = k;
+      }
+      __syncthreads();
+    }
+    // kernel modes first, then the rotations the stressed tangent does not annihilate
+    if (tid == 0)
+      for (int q = 0; q < nfail; ++q) sel[nsel + q] = failed[q];
+    __syncthreads();
+  } else {
+    if (tid == 0) {
+      nsel = 6;
+      for (int k = 0; k < 6; ++k) sel[k] = k;
+    }
+    __syncthreads();
+  }
+  const int n_kernel = nsel;
+  const int m = 6;   // all six rigid modes regularise; the first n_kernel span the kernel
+  // two-pass classical Gram-Schmidt on the interface rows; Q kept in rb
+  const int64_t b0 = (int64_t)s.nt_i * TS, nb = (int64_t)s.nt_b * TS;
+  double* Q = M.rb + s.b_off * 6;
+  for (int64_t p = tid; p < nb * 6; p += 256) Q[p] = 0.0;
+  if (tid < 36) T[tid / 6][tid % 6] = (tid / 6 == tid % 6) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    for (int64_t p = tid; p < nb; p += 256) Q[p * 6 + k] = W[(b0 + p) * 6 + sel[k]];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = 0; j < k; ++j) {
+        double acc = 0.0;
+        for (int64_t p = tid; p < nb; p += 256) acc += Q[p * 6 + j] * Q[p * 6 + k];
+        const double cj = block_sum(acc, red);
+        for (int64_t p = tid; p < nb; p += 256) Q[p * 6 + k] -= cj * Q[p * 6 + j];
+        if (tid < 6) T[tid][k] -= cj * T[tid][j];
+        __syncthreads();
+      }
+    }
+    double acc = 0.0;
+    for (int64_t p = tid; p < nb; p += 256) acc += Q[p * 6 + k] * Q[p * 6 + k];
+    const double nrm = sqrt(block_sum(acc, red));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t p = tid; p < nb; p += 256) Q[p * 6 + k] *= inv;
+    if (tid < 6) T[tid][k] *= inv;
+    __syncthreads();
+  }
+  // full basis R T (columns m..5 zero)
+  for (int64_t p = tid; p < n; p += 256) {
+    for (int k = 0; k < 6; ++k) {
+      double acc = 0.0;
+      if (k < m)
+        for (int j = 0; j < m; ++j) acc += W[p * 6 + sel[j]] * T[j][k];
+      rf[p * 6 + k] = acc;
+    }
+  }
+  if (tid == 0) M.n_modes[sid] = n_kernel;
+}
+
+void asm_modes(const ModesArgs& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_modes, dim3(m.n_sub), dim3(256), 0, s, m);
+}
+
+// Coarse matrix Q = G^T G with G = [B_i Rb_i]: block (s, t), s >= t, sums
+// c_s c_t Rb_s[b_s] Rb_t[b_t]^T over the multiplier rows the two share (in
+// row order); written into the lower tiles of the dense coarse matrix.
+__global__ void k_coarse_q(CoarseArgs C) {
+  const int k = blockIdx.x;
+  const int s = C.qp_s[k], t = C.qp_t[k];
+  const SubInfo Ss = C.subs[s], St = C.subs[t];
+  const int a = threadIdx.x / 6, b = threadIdx.x % 6;
+  if (threadIdx.x >= 36 || a >= Ss.n_modes || b >= St.n_modes) return;
+  double acc = 0.0;
+  for (int q = C.qp_ptr[k]; q < C.qp_ptr[k + 1]; ++q)
+    acc += C.qe_c[q] * C.rb[C.qe_bs[q] * 6 + a] * C.rb[C.qe_bt[q] * 6 + b];
+  const int row = Ss.coarse_off + a, col = St.coarse_off + b;
+  if (row < col) return;
+  C.q[tidx3(row / TS, col / TS) * TS2 + (col % TS) * TS + (row % TS)] = acc;
+}
+
+void asm_coarse(const CoarseArgs& c, hipStream_t s) {
+  if (c.n_pairs) hipLaunchKernelGGL(k_coarse_q, dim3(c.n_pairs), dim3(64), 0, s, c);
+}
+
+}  // namespace feti

@@ -1,0 +1,510 @@
+// Batched dense tile kernels for the local generalised inverses (gfx950).
+//
+// Every subdomain matrix K_i is stored interior-first as a lower-triangular
+// array of 64x64 column-major tiles.  A blocked left-looking Cholesky runs over
+// all subdomains at once: each launch processes one tile column of every
+// subdomain that has it (a task list built on the host), so subdomains of
+// different sizes share launches.  The contractions run on 16x16x4 MFMA
+// (FP64 for the FP64 path, FP32 with FP32 accumulation for the mixed path).
+//
+// The factorisation realises the generalised inverse of the paper's
+// eq. (localSolutions) by interior-first elimination (section 4, eq.
+// (reordered) orders interior DOFs before coupling DOFs): after the interior
+// columns the trailing block is the Schur complement S_i of eq. (DirichletVK);
+// it is regularised on its rigid-body kernel, factored, and inverted
+// explicitly (X_i = S~_i^{-1}) so that every PCG iteration applies the local
+// pseudo-inverse restricted to the interface as one dense matrix-vector product.
+#include "feti_impl.h"
+
+namespace feti {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct V4;
+template <> struct V4<double> { typedef d4 type; };
+template <> struct V4<float> { typedef f4 type; };
+
+constexpr int LD = TS + 1;   // LDS leading dimension (odd: conflict-free transposed stores)
+
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of accumulator register r held by lane l (column is l & 15).
+__device__ __forceinline__ int out_row(double, int l, int r) { return 4 * r + (l >> 4); }
+__device__ __forceinline__ int out_row(float, int l, int r) { return 4 * (l >> 4) + r; }
+
+__device__ __forceinline__ int64_t tidx(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+// LDS operand layout: s[k*LD + m] holds op(A)(m, k) (or op(B)(k, m)).
+// direct: s[k][m] = g[k*TS + m]   (A not transposed, or B transposed)
+template <typename T>
+__device__ __forceinline__ void lds_direct(T* s, const T* __restrict__ g) {
+  for (int e = threadIdx.x; e < TS2; e += 256) s[(e >> 6) * LD + (e & 63)] = g[e];
+}
+// transposed: s[k][m] = g[m*TS + k]   (A transposed, or B not transposed)
+template <typename T>
+__device__ __forceinline__ void lds_trans(T* s, const T* __restrict__ g) {
+  for (int e = threadIdx.x; e < TS2; e += 256) s[(e & 63) * LD + (e >> 6)] = g[e];
+}
+
+template <typename T>
+struct Acc {
+  typename V4<T>::type c[2][2];
+  __device__ void zero() {
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y)
+        for (int r = 0; r < 4; ++r) c[x][y][r] = T(0);
+  }
+};
+
+// acc += opA * opB for one 64x64x64 product; wave w owns the 32x32 block (w>>1, w&1).
+template <typename T>
+__device__ __forceinline__ void mma64(Acc<T>& acc, const T* sA, const T* sB) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1, lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 4 * kk + lk;
+    const T a0 = sA[k * LD + 32 * wr + lr], a1 = sA[k * LD + 32 * wr + 16 + lr];
+    const T b0 = sB[k * LD + 32 * wc + lr], b1 = sB[k * LD + 32 * wc + 16 + lr];
+    acc.c[0][0] = mfma4(a0, b0, acc.c[0][0]);
+    acc.c[0][1] = mfma4(a0, b1, acc.c[0][1]);
+    acc.c[1][0] = mfma4(a1, b0, acc.c[1][0]);
+    acc.c[1][1] = mfma4(a1, b1, acc.c[1][1]);
+  }
+}
+
+// Scatter scale*acc into LDS.  colmajor: s[col*LD + row]; else s[row*LD + col].
+template <typename T>
+__device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, bool colmajor) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int r = 0; r < 4; ++r) {
+        const int row = 32 * wr + 16 * x + out_row(T(0), lane, r);
+        const int col = 32 * wc + 16 * y + (lane & 15);
+        s[colmajor ? col * LD + row : row * LD + col] = scale * acc.c[x][y][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// C_ij <- C_ij - sum_{k0<=k<k1} L_ik L_jk^T   (left-looking update)
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks,
+                                                const SubInfo* __restrict__ subs, T* arena) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  T* base = arena + subs[t.sub].tile_off;
+  Acc<T> acc;
+  acc.zero();
+  for (int k = t.k0; k < t.k1; ++k) {
+    lds_direct(sA, base + tidx(t.i, k) * TS2);
+    lds_direct(sB, base + tidx(t.j, k) * TS2);
+    __syncthreads();
+    mma64(acc, sA, sB);
+    __syncthreads();
+  }
+  acc_to_lds(sA, acc, T(-1), true);
+  __syncthreads();
+  T* C = base + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) C[e] += sA[(e >> 6) * LD + (e & 63)];
+}
+
+// Cholesky of the diagonal tile (j, j) in place (zeroing its upper part) and
+// its triangular inverse.  Computed in FP64 whatever the storage type.
+// A non-positive or non-finite pivot records the subdomain in err[0] (min).
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(const Task* __restrict__ tasks,
+                                              const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                              int* err) {
+  __shared__ double sL[TS * LD], sI[TS * LD];
+  __shared__ double red[4][TS];
+  __shared__ int bad;
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
+  T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TS2; e += 256) sL[(e >> 6) * LD + (e & 63)] = (double)C[e];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int c = 0; c < TS; ++c) {
+    if (tid == 0) {
+      double d = sL[c * LD + c];
+      if (!(d > 0.0) || !(d < 1e300)) {
+        bad = 1;
+        d = 1.0;
+      }
+      sL[c * LD + c] = sqrt(d);
+    }
+    __syncthreads();
+    if (tid > c && tid < TS) sL[c * LD + tid] /= sL[c * LD + c];
+    __syncthreads();
+    const int m = TS - 1 - c;
+    for (int e = tid; e < m * m; e += 256) {
+      const int cc = c + 1 + e / m, r = c + 1 + e % m;
+      if (r >= cc) sL[cc * LD + r] -= sL[c * LD + r] * sL[c * LD + cc];
+    }
+    __syncthreads();
+  }
+  // zero the upper triangle, clear the inverse
+  for (int e = tid; e < TS2; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    if (r < c) sL[c * LD + r] = 0.0;
+    sI[c * LD + r] = 0.0;
+  }
+  __syncthreads();
+  // forward substitution, all columns at once: X(i, j) for j <= i
+  const int j = tid & 63, part = tid >> 6;
+  for (int i = 0; i < TS; ++i) {
+    double acc = 0.0;
+    if (j < i)
+      for (int k = j + part; k < i; k += 4) acc += sL[k * LD + i] * sI[j * LD + k];
+    red[part][j] = acc;
+    __syncthreads();
+    if (part == 0 && j <= i) {
+      const double sum = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+      sI[j * LD + i] = ((i == j ? 1.0 : 0.0) - sum) / sL[i * LD + i];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < TS2; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    C[e] = (T)sL[c * LD + r];
+    Li[e] = (T)sI[c * LD + r];
+  }
+  if (tid == 0 && bad) atomicMin(err, t.sub);
+}
+
+// L_ij <- C_ij L_jj^{-T}   (panel solve by the explicit diagonal inverse)
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
+                                              const SubInfo* __restrict__ subs, T* arena,
+                                              const T* __restrict__ linv) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  T* C = arena + s.tile_off + tidx(t.i, t.j) * TS2;
+  lds_direct(sA, C);
+  lds_direct(sB, linv + s.linv_off + (int64_t)t.j * TS2);   // B(k,n) = Linv(n,k)
+  __syncthreads();
+  Acc<T> acc;
+  acc.zero();
+  mma64(acc, sA, sB);
+  __syncthreads();
+  acc_to_lds(sA, acc, T(1), true);
+  __syncthreads();
+  for (int e = threadIdx.x; e < TS2; e += 256) C[e] = sA[(e >> 6) * LD + (e & 63)];
+}
+
+// Inverse of the interface Cholesky factor, one block row per launch
+// (interface-local tile indices): W_ii = L_ii^{-1};
+// W_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik W_kj for j < i.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
+                                               const SubInfo* __restrict__ subs,
+                                               const T* __restrict__ arena,
+                                               const T* __restrict__ linv, T* W) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  const int ni = s.nt_i;
+  const T* Lbase = arena + s.tile_off;
+  T* Wbase = W + s.x_off;
+  T* out = Wbase + tidx(t.i, t.j) * TS2;
+  const T* Lii_inv = linv + s.linv_off + (int64_t)(ni + t.i) * TS2;
+  if (t.i == t.j) {
+    for (int e = threadIdx.x; e < TS2; e += 256) out[e] = Lii_inv[e];
+    return;
+  }
+  Acc<T> acc;
+  acc.zero();
+  for (int k = t.j; k < t.i; ++k) {
+    lds_direct(sA, Lbase + tidx(ni + t.i, ni + k) * TS2);
+    lds_trans(sB, Wbase + tidx(k, t.j) * TS2);
+    __syncthreads();
+    mma64(acc, sA, sB);
+    __syncthreads();
+  }
+  acc_to_lds(sB, acc, T(1), false);   // B(k, n) = acc(k, n)
+  lds_direct(sA, Lii_inv);            // A(m, k) = Linv(m, k)
+  __syncthreads();
+  Acc<T> acc2;
+  acc2.zero();
+  mma64(acc2, sA, sB);
+  __syncthreads();
+  acc_to_lds(sA, acc2, T(-1), true);
+  __syncthreads();
+  for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e >> 6) * LD + (e & 63)];
+}
+
+// X_IJ = sum_{k>=I} W_kI^T W_kJ  (I >= J): X = W^T W = (L L^T)^{-1}.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lauum(const Task* __restrict__ tasks,
+                                               const SubInfo* __restrict__ subs,
+                                               const T* __restrict__ W, T* X) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  const T* Wb = W + s.x_off;
+  Acc<T> acc;
+  acc.zero();
+  for (int k = t.k0; k < t.k1; ++k) {
+    lds_trans(sA, Wb + tidx(k, t.i) * TS2);
+    lds_trans(sB, Wb + tidx(k, t.j) * TS2);
+    __syncthreads();
+    mma64(acc, sA, sB);
+    __syncthreads();
+  }
+  acc_to_lds(sA, acc, T(1), true);
+  __syncthreads();
+  T* out = X + s.x_off + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e >> 6) * LD + (e & 63)];
+}
+
+// Copy of the interface Schur complement (for the Dirichlet preconditioner).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_iface(const Task* __restrict__ tasks,
+                                                    const SubInfo* __restrict__ subs,
+                                                    const T* __restrict__ arena, T* S) {
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  const T* src = arena + s.tile_off + tidx(s.nt_i + t.i, s.nt_i + t.j) * TS2;
+  T* dst = S + s.x_off + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) dst[e] = src[e];
+}
+
+// rho_s = mean of the diagonal of the interface Schur complement (real DOFs).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rho(const SubInfo* __restrict__ subs,
+                                             const T* __restrict__ arena, double* rho) {
+  __shared__ double red[256];
+  const SubInfo s = subs[blockIdx.x];
+  double acc = 0.0;
+  for (int d = threadIdx.x; d < s.n_b; d += 256) {
+    const int I = d / TS, r = d % TS;
+    acc += (double)arena[s.tile_off + tidx(s.nt_i + I, s.nt_i + I) * TS2 + r * TS + r];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rho[blockIdx.x] = s.n_b > 0 ? red[0] / s.n_b : 0.0;
+}
+
+// S~ = S + rho Rb Rb^T on the interface tiles of floating subdomains, with all
+// six rigid modes (rb: interface-space vectors, 6 interleaved orthonormal
+// columns, kernel modes first).  For a stressed tangent whose kernel holds
+// only some of them, the inverse is corrected afterwards (k_wb_*).
+template <typename T>
+__global__ __launch_bounds__(256) void k_regularise(const Task* __restrict__ tasks,
+                                                    const SubInfo* __restrict__ subs,
+                                                    const double* __restrict__ rb,
+                                                    const double* __restrict__ rho, T* arena) {
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  if (!s.floating) return;
+  const double r0 = rho[t.sub];
+  T* C = arena + s.tile_off + tidx(s.nt_i + t.i, s.nt_i + t.j) * TS2;
+  const double* Ri = rb + (s.b_off + (int64_t)t.i * TS) * 6;
+  const double* Rj = rb + (s.b_off + (int64_t)t.j * TS) * 6;
+  for (int e = threadIdx.x; e < TS2; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    double acc = 0.0;
+    for (int k = 0; k < 6; ++k) acc += Ri[r * 6 + k] * Rj[c * 6 + k];
+    C[e] = (T)((double)C[e] + r0 * acc);
+  }
+}
+
+// Exact generalised inverse for stressed floating subdomains.  With V the
+// regularised rigid modes that are not in ker K_i (columns n_modes..5 of rb),
+// S~_k = S + rho Rk Rk^T (kernel modes only) equals S~_6 - rho V V^T, so by the
+// Woodbury identity X_k = X_6 + Y M Y^T with Y = X_6 V and
+// M = (I/rho - V^T Y)^{-1}.  X_k is then a generalised inverse of S, as the
+// local solution formula (eq. (localSolutions)) requires.
+template <typename T>
+__device__ __forceinline__ double xsym(const T* X, int64_t x_off, int I, int J, int r, int c) {
+  if (I > J) return (double)X[x_off + tidx(I, J) * TS2 + c * TS + r];
+  if (I < J) return (double)X[x_off + tidx(J, I) * TS2 + r * TS + c];
+  return r >= c ? (double)X[x_off + tidx(I, I) * TS2 + c * TS + r] : (double)X[x_off + tidx(I, I) * TS2 + r * TS + c];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_wb_y(const SubInfo* __restrict__ subs, const T* __restrict__ X,
+                                              const double* __restrict__ rb, double* Y) {
+  __shared__ double red[4][TS][3];
+  const SubInfo s = subs[blockIdx.y];
+  const int I = blockIdx.x;
+  if (!s.floating || s.n_modes >= 6 || I >= s.nt_b) return;
+  const int mk = s.n_modes, mv = 6 - mk;
+  const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+  double acc[3] = {0, 0, 0};
+  for (int J = 0; J < s.nt_b; ++J)
+    for (int c = 16 * q; c < 16 * q + 16; ++c) {
+      const double x = xsym(X, s.x_off, I, J, r, c);
+      const double* v = rb + (s.b_off + (int64_t)J * TS + c) * 6 + mk;
+      for (int k = 0; k < mv; ++k) acc[k] += x * v[k];
+    }
+  for (int k = 0; k < 3; ++k) red[q][r][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < TS)
+    for (int k = 0; k < 3; ++k)
+      Y[(s.b_off + (int64_t)I * TS + r) * 3 + k] = red[0][r][k] + red[1][r][k] + red[2][r][k] + red[3][r][k];
+}
+
+__global__ __launch_bounds__(256) void k_wb_m(const SubInfo* __restrict__ subs, const double* __restrict__ rb,
+                                              const double* __restrict__ Y, const double* __restrict__ rho,
+                                              double* Mout) {
+  __shared__ double red[256];
+  __shared__ double Cm[3][3];
+  const SubInfo s = subs[blockIdx.x];
+  if (!s.floating || s.n_modes >= 6) return;
+  const int mk = s.n_modes, mv = 6 - mk;
+  const int64_t nb = (int64_t)s.nt_b * TS;
+  for (int k = 0; k < mv; ++k)
+    for (int l = 0; l < mv; ++l) {
+      double acc = 0.0;
+      for (int64_t b = threadIdx.x; b < nb; b += 256)
+        acc += rb[(s.b_off + b) * 6 + mk + k] * Y[(s.b_off + b) * 3 + l];
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) Cm[k][l] = (k == l ? 1.0 / rho[blockIdx.x] : 0.0) - red[0];
+      __syncthreads();
+    }
+  if (threadIdx.x == 0) {
+    // Gauss-Jordan inverse of the mv x mv capacitance matrix
+    double A[3][6];
+    for (int k = 0; k < mv; ++k)
+      for (int l = 0; l < 2 * mv; ++l) A[k][l] = l < mv ? Cm[k][l] : (l - mv == k ? 1.0 : 0.0);
+    for (int c = 0; c < mv; ++c) {
+      int piv = c;
+      for (int k = c + 1; k < mv; ++k)
+        if (fabs(A[k][c]) > fabs(A[piv][c])) piv = k;
+      for (int l = 0; l < 2 * mv; ++l) {
+        const double t = A[c][l];
+        A[c][l] = A[piv][l];
+        A[piv][l] = t;
+      }
+      const double d = A[c][c];
+      for (int l = 0; l < 2 * mv; ++l) A[c][l] /= d;
+      for (int k = 0; k < mv; ++k)
+        if (k != c) {
+          const double f = A[k][c];
+          for (int l = 0; l < 2 * mv; ++l) A[k][l] -= f * A[c][l];
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) Mout[blockIdx.x * 9 + 3 * k + l] = (k < mv && l < mv) ? A[k][mv + l] : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_wb_update(const Task* __restrict__ tasks, const SubInfo* __restrict__ subs,
+                                                   const double* __restrict__ Y, const double* __restrict__ Mm,
+                                                   T* X) {
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  if (!s.floating || s.n_modes >= 6) return;
+  const double* M = Mm + t.sub * 9;
+  T* C = X + s.x_off + tidx(t.i, t.j) * TS2;
+  const double* Yi = Y + (s.b_off + (int64_t)t.i * TS) * 3;
+  const double* Yj = Y + (s.b_off + (int64_t)t.j * TS) * 3;
+  for (int e = threadIdx.x; e < TS2; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    double acc = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double mk = 0.0;
+      for (int l = 0; l < 3; ++l) mk += M[3 * k + l] * Yj[c * 3 + l];
+      acc += Yi[r * 3 + k] * mk;
+    }
+    C[e] = (T)((double)C[e] + acc);
+  }
+}
+
+template <typename T>
+void launch_woodbury(int n_sub, int max_nt_b, const Task* xtasks, int xcount, const SubInfo* subs, T* X,
+                     const double* rb, const double* rho, double* Y, double* M, hipStream_t st) {
+  if (max_nt_b <= 0) return;
+  hipLaunchKernelGGL(k_wb_y<T>, dim3(max_nt_b, n_sub), dim3(256), 0, st, subs, (const T*)X, rb, Y);
+  hipLaunchKernelGGL(k_wb_m, dim3(n_sub), dim3(256), 0, st, subs, rb, (const double*)Y, rho, M);
+  if (xcount > 0) hipLaunchKernelGGL(k_wb_update<T>, dim3(xcount), dim3(256), 0, st, xtasks, subs, (const double*)Y, (const double*)M, X);
+}
+template void launch_woodbury<double>(int, int, const Task*, int, const SubInfo*, double*, const double*, const double*, double*, double*, hipStream_t);
+template void launch_woodbury<float>(int, int, const Task*, int, const SubInfo*, float*, const double*, const double*, double*, double*, hipStream_t);
+
+// Zero every factor tile, with unit diagonal on padding positions.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_arena(const Task* __restrict__ tasks,
+                                                    const SubInfo* __restrict__ subs, T* arena) {
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  T* C = arena + s.tile_off + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    T v = T(0);
+    if (t.i == t.j && r == c) {
+      const int p = t.i * TS + r;
+      const bool pad = (p >= s.n_ii && p < s.nt_i * TS) || (p >= s.nt_i * TS + s.n_b);
+      if (pad) v = T(1);
+    }
+    C[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+template <typename T>
+void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
+                  T* W, T* X, int* err, hipStream_t st) {
+  if (count <= 0) return;
+  switch (kind) {
+    case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena); break;
+    case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, linv, err); break;
+    case K_TRSM: hipLaunchKernelGGL(k_trsm<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, (const T*)linv); break;
+    case K_TRTRI: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W); break;
+    case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
+  }
+}
+template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t);
+template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t);
+
+template <typename T>
+void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_init_arena<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena);
+}
+template void launch_init_arena<double>(const Task*, int, const SubInfo*, double*, hipStream_t);
+template void launch_init_arena<float>(const Task*, int, const SubInfo*, float*, hipStream_t);
+
+template <typename T>
+void launch_copy_iface(const Task* tasks, int count, const SubInfo* subs, const T* arena, T* S, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_copy_iface<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, S);
+}
+template void launch_copy_iface<double>(const Task*, int, const SubInfo*, const double*, double*, hipStream_t);
+template void launch_copy_iface<float>(const Task*, int, const SubInfo*, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_rho(int n_sub, const SubInfo* subs, const T* arena, double* rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_rho<T>, dim3(n_sub), dim3(256), 0, st, subs, arena, rho);
+}
+template void launch_rho<double>(int, const SubInfo*, const double*, double*, hipStream_t);
+template void launch_rho<float>(int, const SubInfo*, const float*, double*, hipStream_t);
+
+template <typename T>
+void launch_regularise(const Task* tasks, int count, const SubInfo* subs, const double* rb,
+                       const double* rho, T* arena, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_regularise<T>, dim3(count), dim3(256), 0, st, tasks, subs, rb, rho, arena);
+}
+template void launch_regularise<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, hipStream_t);
+template void launch_regularise<float>(const Task*, int, const SubInfo*, const double*, const double*, float*, hipStream_t);
+
+}  // namespace feti

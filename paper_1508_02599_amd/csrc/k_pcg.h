@@ -1,0 +1,166 @@
+// Device-side PCG state and launchers of the dual-iteration and assembly kernels.
+#pragma once
+
+#include "feti_impl.h"
+
+namespace feti {
+
+constexpr int DOT_PARTS = 256;   // fixed partition of every dot product
+
+// Scalars of the projected PCG, resident on the device so that iterations can
+// be captured in a HIP graph and run without host synchronisation.
+struct PcgState {
+  double rho, alpha, beta, w0, wn, pq, rtol, atol;
+  int32_t it, max_it, done, status, hist_cap, pad_;
+};
+
+// Device index arrays used by the dual-space kernels.
+struct DevIdx {
+  int64_t NB = 0, NF = 0, n_lam = 0;
+  const int32_t *g_ptr = nullptr, *g_row = nullptr, *b_sub = nullptr, *f_sub = nullptr;
+  const double *g_coef = nullptr, *r_w = nullptr, *r_c0 = nullptr, *r_c1 = nullptr;
+  const int64_t *r_b0 = nullptr, *r_b1 = nullptr, *r_gdof = nullptr, *b2full = nullptr;
+};
+
+// --- dense factor kernels (k_dense.hip)
+template <typename T>
+void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv, T* W, T* X,
+                  int* err, hipStream_t st);
+template <typename T>
+void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st);
+template <typename T>
+void launch_copy_iface(const Task* tasks, int count, const SubInfo* subs, const T* arena, T* S, hipStream_t st);
+template <typename T>
+void launch_rho(int n_sub, const SubInfo* subs, const T* arena, double* rho, hipStream_t st);
+template <typename T>
+void launch_regularise(const Task* tasks, int count, const SubInfo* subs, const double* rb, const double* rho,
+                       T* arena, hipStream_t st);
+
+template <typename T>
+void launch_woodbury(int n_sub, int max_nt_b, const Task* xtasks, int xcount, const SubInfo* subs, T* X,
+                     const double* rb, const double* rho, double* Y, double* M, hipStream_t st);
+
+// --- dual iteration kernels (k_pcg.hip)
+void pcg_gather(const DevIdx& d, int weighted, const double* v, double* xb, const PcgState* st, hipStream_t s);
+void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* base, double sgn, double* out,
+                 const PcgState* st, hipStream_t s);
+template <typename T>
+void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s);
+void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
+             const PcgState* st, hipStream_t s);
+void pcg_alpha(const double* part, PcgState* st, hipStream_t s);
+void pcg_beta(const double* part, PcgState* st, int init, double* hist, hipStream_t s);
+void pcg_update_lr(int64_t n, double* lam, double* r, const double* sv, const double* q, const PcgState* st,
+                   hipStream_t s);
+void pcg_update_s(int64_t n, double* sv, const double* z, const PcgState* st, hipStream_t s);
+void pcg_coarse_gt(int n_sub, const SubInfo* subs, const double* rb, const double* xb, double* g,
+                   const PcgState* st, hipStream_t s);
+void pcg_coarse_gt_full(int n_sub, const SubInfo* subs, const double* rf, const double* xf, double* g,
+                        hipStream_t s);
+void pcg_coarse_expand(const DevIdx& d, const SubInfo* subs, const double* rb, const double* alpha, double* vb,
+                       const PcgState* st, hipStream_t s);
+void pcg_add_modes(int64_t NF, const int32_t* f_sub, const SubInfo* subs, const double* rf, const double* gamma,
+                   double* u, hipStream_t s);
+void pcg_lumped(const DevIdx& d, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
+                const double* xb, double* yb, const PcgState* st, hipStream_t s);
+void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s);
+void vec_add_b2f(const DevIdx& d, const double* b, double sgn, double* full, hipStream_t s);
+void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s);
+void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, const double* ufull,
+                const uint8_t* dmask, const double* dvals, double* out, int sum_mode, hipStream_t s);
+void vec_dirinc(int64_t n_dof, const uint8_t* dmask, const double* dirval, double tau, const double* U,
+                double* dvals, hipStream_t s);
+void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+void vec_fill(int64_t n, double v, double* y, hipStream_t s);
+void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s);
+void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
+template <typename T>
+void local_kpinv(int n_sub, const SubInfo* subs, const T* arena, const T* linv, const T* X, const double* g,
+                 double* z, double* w, hipStream_t s);
+
+// --- assembly kernels (k_assemble.hip)
+struct AsmArgs {
+  int64_t n_elems = 0;
+  const double* xyz = nullptr;        // [n_nodes*3]
+  const int64_t* hex8 = nullptr;      // [n_elems*8]
+  const int32_t* elem_mat = nullptr;
+  const double* mat = nullptr;        // [n_mat*7] kind,E,nu,c,k1,k2,kappa
+  const double* fibers = nullptr;     // [n_elems*6] or null
+  const double* body = nullptr;       // [n_elems*3] or null
+  const double* U = nullptr;          // [n_nodes*3] or null
+  double* Ke = nullptr;               // [n_elems*576]  layout [a][b][i][j]
+  double* fint = nullptr;             // [n_elems*24]
+  double* fbody = nullptr;            // [n_elems*24]
+};
+void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s);
+
+struct GatherArgs {
+  int64_t n_slots = 0;
+  const int32_t *ps_a = nullptr, *ps_b = nullptr, *ps_nbr = nullptr, *ps_c0 = nullptr, *ps_c1 = nullptr;
+  const int32_t *pc_e = nullptr, *pc_ab = nullptr;
+  const int32_t* loc_sub = nullptr;   // [n_loc_nodes] owning subdomain
+  const int32_t* loc_pos = nullptr;   // [3*n_loc_nodes]
+  const SubInfo* subs = nullptr;
+  const double* Ke = nullptr;
+  double* ell_val = nullptr;          // [NF*ELLW]
+};
+template <typename T>
+void asm_gather(const GatherArgs& g, T* arena, hipStream_t s);
+
+struct RhsArgs {
+  int64_t n_loc_nodes = 0;
+  const int32_t *diag_slot = nullptr, *ps_c0 = nullptr, *ps_c1 = nullptr, *pc_e = nullptr, *pc_ab = nullptr;
+  const int32_t *loc_sub = nullptr, *loc_pos = nullptr, *loc_ncopy = nullptr;
+  const int64_t* loc_node = nullptr;
+  const SubInfo* subs = nullptr;
+  const double *fbody = nullptr, *fint = nullptr, *fnodal = nullptr;   // fnodal [n_dof] or null
+  const int32_t* ell_col = nullptr;
+  const double* ell_val = nullptr;
+  const double* dvals = nullptr;      // [n_dof] prescribed values / increments
+  double body_scale = 1.0, int_scale = 0.0, nodal_scale = 0.0;
+  double* f = nullptr;                // [NF]
+};
+void asm_rhs(const RhsArgs& r, hipStream_t s);
+
+struct PressureArgs {
+  int64_t n_nodes = 0;
+  const double *xyz = nullptr, *U = nullptr;
+  const int64_t* pface = nullptr;
+  const int32_t *pf_ptr = nullptr, *pf_ent = nullptr;
+  double pressure = 0.0;
+  double* fnodal = nullptr;           // [n_dof]
+};
+void asm_pressure(const PressureArgs& p, hipStream_t s);
+
+struct ModesArgs {
+  int n_sub = 0;
+  const SubInfo* subs = nullptr;
+  const int64_t* loc_node = nullptr;
+  const int32_t* loc_pos = nullptr;
+  const int32_t* fpos_lnode = nullptr; // [NF] local-node index (incl. node_off) of a full position, -1 pad
+  const int8_t* fpos_comp = nullptr;   // [NF]
+  const double *xyz = nullptr, *U = nullptr;
+  const int32_t* ell_col = nullptr;
+  const double* ell_val = nullptr;
+  int test_rotations = 0;              // keep a rotation only if K annihilates it
+  double kernel_tol = 1e-12;
+  double* rfull = nullptr;             // [NF*6]
+  double* rb = nullptr;                // [NB*6]
+  int32_t* n_modes = nullptr;          // [n_sub] (output)
+  double* work = nullptr;              // [NF*6] scratch
+};
+void asm_modes(const ModesArgs& m, hipStream_t s);
+
+struct CoarseArgs {
+  int n_pairs = 0;
+  const int32_t *qp_s = nullptr, *qp_t = nullptr, *qp_ptr = nullptr;
+  const int64_t *qe_bs = nullptr, *qe_bt = nullptr;
+  const double* qe_c = nullptr;
+  const SubInfo* subs = nullptr;
+  const double* rb = nullptr;
+  double* q = nullptr;                 // lower tiles of the coarse matrix
+};
+void asm_coarse(const CoarseArgs& c, hipStream_t s);
+
+}  // namespace feti

@@ -1,0 +1,601 @@
+// Kernels of the dual iteration (paper section 4.3): the action of
+// F = sum_i B_i K_i^+ B_i^T through the jump operators, the projection
+// P = I - G (G^T G)^{-1} G^T, the multiplicity-scaled preconditioners of
+// section 4.4, deterministic dot products and the CG recurrences.
+//
+// All reductions use a fixed partition and a fixed summation order, so a
+// solve gives bit-identical results whatever else runs on the device.
+#include "feti_impl.h"
+#include "k_pcg.h"
+
+namespace feti {
+
+constexpr int LDV = TS + 1;
+
+__device__ __forceinline__ bool halted(const PcgState* st) { return st != nullptr && st->done != 0; }
+__device__ __forceinline__ int64_t tidx2(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+
+// xb[b] = sum_{rows r touching b} coef * (w_r if weighted) * v[r]
+__global__ void k_gather(int64_t NB, const int32_t* __restrict__ g_ptr, const int32_t* __restrict__ g_row,
+                         const double* __restrict__ g_coef, const double* __restrict__ w, int weighted,
+                         const double* __restrict__ v, double* __restrict__ xb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  double acc = 0.0;
+  for (int k = g_ptr[b]; k < g_ptr[b + 1]; ++k) {
+    const int r = g_row[k];
+    acc += g_coef[k] * (weighted ? w[r] : 1.0) * v[r];
+  }
+  xb[b] = acc;
+}
+
+// out[r] = base[r] + sgn * (w_r if weighted) * (c0 y[b0] + c1 y[b1])   (base may be NULL)
+__global__ void k_scatter(int64_t n_lam, const int64_t* __restrict__ b0, const double* __restrict__ c0,
+                          const int64_t* __restrict__ b1, const double* __restrict__ c1,
+                          const double* __restrict__ w, int weighted, const double* __restrict__ y,
+                          const double* __restrict__ base, double sgn, double* __restrict__ out,
+                          const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_lam) return;
+  double v = c0[r] * y[b0[r]];
+  if (b1[r] >= 0) v += c1[r] * y[b1[r]];
+  if (weighted) v *= w[r];
+  out[r] = (base ? base[r] : 0.0) + sgn * v;
+}
+
+// Symmetric tile matrix-vector product, phase 1: every stored lower tile
+// (I, J) of a symmetric matrix contributes M_IJ x_J to block row I and,
+// off the diagonal, M_IJ^T x_I to block row J.  Partial sums go to
+// part[part_off + (row*nt + col)*TS + .] and are summed in order afterwards.
+template <typename T>
+__global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tasks,
+                                                    const SubInfo* __restrict__ subs,
+                                                    const T* __restrict__ M,
+                                                    const double* __restrict__ xb, double* part,
+                                                    const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ T sM[TS * LDV];
+  __shared__ double xI[TS], xJ[TS];
+  __shared__ double red[4][TS], red2[4][TS];
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  const T* tile = M + s.x_off + tidx2(t.i, t.j) * TS2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TS2; e += 256) sM[(e >> 6) * LDV + (e & 63)] = tile[e];
+  if (tid < TS) {
+    xI[tid] = xb[s.b_off + (int64_t)t.i * TS + tid];
+    xJ[tid] = xb[s.b_off + (int64_t)t.j * TS + tid];
+  }
+  __syncthreads();
+  const int a = tid & 63, q = tid >> 6;
+  double s1 = 0.0, s2 = 0.0;
+  if (t.i != t.j) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 16 * q + k;
+      s1 += (double)sM[c * LDV + a] * xJ[c];     // (M x_J)[a]
+      s2 += (double)sM[a * LDV + c] * xI[c];     // (M^T x_I)[a], column a row c
+    }
+  } else {
+    // diagonal tile: only its lower triangle is meaningful; mirror it
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 16 * q + k;
+      const int hi = a > c ? a : c, lo = a > c ? c : a;
+      s1 += (double)sM[lo * LDV + hi] * xJ[c];
+    }
+  }
+  red[q][a] = s1;
+  red2[q][a] = s2;
+  __syncthreads();
+  if (tid < TS) {
+    const int nt = s.nt_b;
+    part[s.part_off + ((int64_t)t.i * nt + t.j) * TS + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (t.i != t.j)
+      part[s.part_off + ((int64_t)t.j * nt + t.i) * TS + tid] =
+          red2[0][tid] + red2[1][tid] + red2[2][tid] + red2[3][tid];
+  }
+}
+
+// Phase 2: yb[b] = sum_J part[row I of b][J] in order.
+__global__ void k_symv_reduce(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
+                              const double* __restrict__ part, double* __restrict__ yb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  const int64_t loc = b - s.b_off;
+  const int I = (int)(loc / TS), r = (int)(loc % TS);
+  const double* p = part + s.part_off + (int64_t)I * s.nt_b * TS + r;
+  double acc = 0.0;
+  for (int J = 0; J < s.nt_b; ++J) acc += p[(int64_t)J * TS];
+  yb[b] = acc;
+}
+
+// Block partial sums of up to two dot products over n entries (fixed partition).
+__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ d, double* part,
+                                                     const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ double r1[256], r2[256];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
+    s1 += a[k] * b[k];
+    if (c) s2 += c[k] * d[k];
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r1[0];
+    part[2 * blockIdx.x + 1] = r2[0];
+  }
+}
+
+__device__ void sum_parts(const double* part, int nparts, double* o1, double* o2) {
+  __shared__ double r1[256], r2[256];
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    s1 += part[2 * k];
+    s2 += part[2 * k + 1];
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  *o1 = r1[0];
+  *o2 = r2[0];
+}
+
+// alpha = rho / (s.q); breakdown if s.q <= 0.
+__global__ __launch_bounds__(256) void k_alpha(const double* part, int nparts, PcgState* st) {
+  if (st->done) return;
+  double pq, unused;
+  sum_parts(part, nparts, &pq, &unused);
+  if (threadIdx.x == 0) {
+    st->pq = pq;
+    if (!(pq > 0.0)) {
+      st->alpha = 0.0;
+      st->done = 1;
+      st->status = FETI_EBREAKDOWN;
+    } else {
+      st->alpha = st->rho / pq;
+    }
+  }
+}
+
+// lam += alpha s ; r -= alpha q
+__global__ void k_update_lr(int64_t n, double* lam, double* r, const double* __restrict__ s,
+                            const double* __restrict__ q, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double a = st->alpha;
+  lam[k] += a * s[k];
+  r[k] -= a * q[k];
+}
+
+// rho' = w.z, ||w||; beta = rho'/rho; convergence test on ||w|| <= rtol ||w0||.
+// init != 0: first evaluation (sets rho, w0, no beta).
+__global__ __launch_bounds__(256) void k_beta(const double* part, int nparts, PcgState* st, int init,
+                                              double* hist) {
+  if (st->done) return;
+  double wz, ww;
+  sum_parts(part, nparts, &wz, &ww);
+  if (threadIdx.x == 0) {
+    const double wn = sqrt(ww);
+    if (init) {
+      st->rho = wz;
+      st->w0 = wn;
+      st->wn = wn;
+      st->beta = 0.0;
+      st->it = 0;
+      if (!(wn > st->atol)) { st->done = 1; st->status = FETI_OK; }
+      return;
+    }
+    const int it = st->it;
+    if (hist && it < st->hist_cap) {
+      hist[2 * it] = st->alpha;
+      hist[2 * it + 1] = wz / st->rho;
+    }
+    st->beta = wz / st->rho;
+    st->rho = wz;
+    st->wn = wn;
+    st->it = it + 1;
+    if (wn <= st->rtol * st->w0 || !(wn > st->atol)) {
+      st->done = 1;
+      st->status = FETI_OK;
+    } else if (st->it >= st->max_it) {
+      st->done = 1;
+      st->status = FETI_ENOCONV;
+    }
+  }
+}
+
+// s = z + beta s
+__global__ void k_update_s(int64_t n, double* s, const double* __restrict__ z, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  s[k] = z[k] + st->beta * s[k];
+}
+
+// g[coarse_off + k] = rb_k . xb over the interface of every floating subdomain.
+__global__ __launch_bounds__(256) void k_coarse_gt(const SubInfo* __restrict__ subs, const double* __restrict__ rb,
+                                                   const double* __restrict__ xb, double* g,
+                                                   const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ double red[6][256];
+  const SubInfo s = subs[blockIdx.x];
+  if (s.n_modes == 0) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t n = (int64_t)s.nt_b * TS;
+  for (int64_t b = threadIdx.x; b < n; b += 256) {
+    const double x = xb[s.b_off + b];
+    const double* R = rb + (s.b_off + b) * 6;
+    for (int k = 0; k < 6; ++k) acc[k] += R[k] * x;
+  }
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < s.n_modes) g[s.coarse_off + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Same over the full local space (e_i = R_i^T f_i).
+__global__ __launch_bounds__(256) void k_coarse_gt_full(const SubInfo* __restrict__ subs,
+                                                        const double* __restrict__ rf,
+                                                        const double* __restrict__ xf, double* g) {
+  __shared__ double red[6][256];
+  const SubInfo s = subs[blockIdx.x];
+  if (s.n_modes == 0) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t n = (int64_t)s.nt * TS;
+  for (int64_t b = threadIdx.x; b < n; b += 256) {
+    const double x = xf[s.full_off + b];
+    const double* R = rf + (s.full_off + b) * 6;
+    for (int k = 0; k < 6; ++k) acc[k] += R[k] * x;
+  }
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < s.n_modes) g[s.coarse_off + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// vb = Rb alpha (zero on subdomains without kernel)
+__global__ void k_coarse_expand(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
+                                const double* __restrict__ rb, const double* __restrict__ alpha,
+                                double* vb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  double acc = 0.0;
+  for (int k = 0; k < s.n_modes; ++k) acc += rb[b * 6 + k] * alpha[s.coarse_off + k];
+  vb[b] = acc;
+}
+
+// u_full += R gamma on the full local space
+__global__ void k_add_modes(int64_t NF, const int32_t* __restrict__ f_sub, const SubInfo* __restrict__ subs,
+                            const double* __restrict__ rf, const double* __restrict__ gamma, double* u) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NF) return;
+  const SubInfo s = subs[f_sub[p]];
+  double acc = 0.0;
+  for (int k = 0; k < s.n_modes; ++k) acc += rf[p * 6 + k] * gamma[s.coarse_off + k];
+  u[p] += acc;
+}
+
+// Lumped preconditioner: yb = K_bb xb (sparse rows of the local stiffness).
+__global__ void k_lumped(int64_t NB, const int64_t* __restrict__ b2full, const int32_t* __restrict__ b_sub,
+                         const SubInfo* __restrict__ subs, const int32_t* __restrict__ ell_col,
+                         const double* __restrict__ ell_val, const double* __restrict__ xb,
+                         double* __restrict__ yb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  const int64_t row = b2full[b];
+  const int bstart = s.nt_i * TS;
+  double acc = 0.0;
+  for (int k = 0; k < ELLW; ++k) {
+    const int c = ell_col[row * ELLW + k];
+    if (c >= bstart) acc += ell_val[row * ELLW + k] * xb[s.b_off + (c - bstart)];
+  }
+  yb[b] = acc;
+}
+
+__global__ void k_copy_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ full,
+                           double* __restrict__ b) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < NB) b[k] = full[b2full[k]];
+}
+
+// full[b2full[k]] += sgn * b[k]
+__global__ void k_add_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ b,
+                          double sgn, double* full) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < NB) full[b2full[k]] += sgn * b[k];
+}
+
+// Multiplier right-hand side b: prescribed value of an all-floating Dirichlet row, else 0.
+__global__ void k_bvec(int64_t n_lam, const int64_t* __restrict__ gdof, const double* __restrict__ dvals,
+                       double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_lam) return;
+  out[r] = gdof[r] >= 0 ? dvals[gdof[r]] : 0.0;
+}
+
+// Global nodal result.  sum_mode 0: mean of the subdomain copies, Dirichlet
+// DOFs take dvals.  sum_mode 1: sum of the copies (assembled vector), zero on
+// Dirichlet DOFs.
+__global__ void k_global(int64_t n_dof, const int32_t* __restrict__ uc_ptr, const int64_t* __restrict__ uc_idx,
+                         const double* __restrict__ ufull, const uint8_t* __restrict__ dmask,
+                         const double* __restrict__ dvals, double* out, int sum_mode) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_dof) return;
+  if (dmask[g]) {
+    out[g] = sum_mode ? 0.0 : dvals[g];
+    return;
+  }
+  double acc = 0.0;
+  const int n = uc_ptr[g + 1] - uc_ptr[g];
+  for (int k = uc_ptr[g]; k < uc_ptr[g + 1]; ++k) acc += ufull[uc_idx[k]];
+  out[g] = sum_mode ? acc : (n ? acc / n : 0.0);
+}
+
+// Dirichlet data of a Newton step: dvals = tau u_D - U on Dirichlet DOFs (U may be NULL).
+__global__ void k_dirinc(int64_t n_dof, const uint8_t* __restrict__ dmask, const double* __restrict__ dirval,
+                         double tau, const double* __restrict__ U, double* dvals) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_dof) return;
+  dvals[g] = dmask[g] ? tau * dirval[g] - (U ? U[g] : 0.0) : 0.0;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = (b == 0.0) ? a * x[k] : a * x[k] + b * y[k];   // b == 0: y is not read
+}
+
+__global__ void k_copy_st(int64_t n, const double* __restrict__ x, double* __restrict__ y, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = x[k];
+}
+
+__global__ void k_fill(int64_t n, double v, double* y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = v;
+}
+
+__global__ void k_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap) {
+  st->rho = st->alpha = st->beta = st->w0 = st->wn = st->pq = 0.0;
+  st->rtol = rtol;
+  st->atol = atol;
+  st->it = 0;
+  st->max_it = max_it;
+  st->done = 0;
+  st->status = 0;
+  st->hist_cap = hist_cap;
+}
+
+// ---------------------------------------------------------------------------
+// Local generalised inverse z = K^+ g on the full local vector of each
+// subdomain (block formula of the interior-first elimination):
+//   w_I = L_II^{-1} g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,
+//   z_I = L_II^{-T} (w_I - L_bI^T z_b).
+// One workgroup per subdomain; tile products read coalesced columns.
+template <typename T>
+__device__ void tile_mv(const T* __restrict__ A, const double* x, double* y_acc, double* red, bool trans,
+                        double sgn) {
+  // y_acc[64] += sgn * op(A) x, A column-major 64x64.
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  if (!trans) {
+    const int r = tid & 63, q = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += (double)A[(16 * q + k) * TS + r] * x[16 * q + k];
+    red[q * TS + r] = s;
+  } else {
+    const int c = tid >> 2, q = tid & 3;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += (double)A[c * TS + 16 * q + k] * x[16 * q + k];
+    red[q * TS + c] = s;
+  }
+  __syncthreads();
+  if (tid < TS) {
+    if (!trans)
+      y_acc[tid] += sgn * (red[tid] + red[TS + tid] + red[2 * TS + tid] + red[3 * TS + tid]);
+    else
+      y_acc[tid] += sgn * (red[tid] + red[TS + tid] + red[2 * TS + tid] + red[3 * TS + tid]);
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kpinv(const SubInfo* __restrict__ subs, const T* __restrict__ arena,
+                                               const T* __restrict__ linv, const T* __restrict__ X,
+                                               const double* __restrict__ g, double* z, double* w) {
+  __shared__ double red[4 * TS];
+  __shared__ double acc[TS], xv[TS];
+  const SubInfo s = subs[blockIdx.x];
+  const T* L = arena + s.tile_off;
+  const int tid = threadIdx.x;
+  const double* gs = g + s.full_off;
+  double* ws = w + s.full_off;
+  double* zs = z + s.full_off;
+  // forward over the interior, and interface right-hand side
+  for (int I = 0; I < s.nt; ++I) {
+    if (tid < TS) acc[tid] = gs[I * TS + tid];
+    __syncthreads();
+    for (int J = 0; J < (I < s.nt_i ? I : s.nt_i); ++J) {
+      if (tid < TS) xv[tid] = ws[J * TS + tid];
+      __syncthreads();
+      tile_mv(L + tidx2(I, J) * TS2, xv, acc, red, false, -1.0);
+    }
+    if (I < s.nt_i) {
+      if (tid < TS) xv[tid] = acc[tid];
+      __syncthreads();
+      if (tid < TS) acc[tid] = 0.0;
+      __syncthreads();
+      tile_mv(linv + s.linv_off + (int64_t)I * TS2, xv, acc, red, false, 1.0);
+    }
+    if (tid < TS) ws[I * TS + tid] = acc[tid];
+    __syncthreads();
+  }
+  // z_b = X w_b (symmetric, lower tiles stored)
+  for (int I = 0; I < s.nt_b; ++I) {
+    if (tid < TS) acc[tid] = 0.0;
+    __syncthreads();
+    for (int J = 0; J < s.nt_b; ++J) {
+      if (tid < TS) xv[tid] = ws[(s.nt_i + J) * TS + tid];
+      __syncthreads();
+      if (J <= I)
+        tile_mv(X + s.x_off + tidx2(I, J) * TS2, xv, acc, red, false, 1.0);
+      else
+        tile_mv(X + s.x_off + tidx2(J, I) * TS2, xv, acc, red, true, 1.0);
+    }
+    if (tid < TS) zs[(s.nt_i + I) * TS + tid] = acc[tid];
+    __syncthreads();
+  }
+  // backward over the interior
+  for (int I = s.nt_i - 1; I >= 0; --I) {
+    if (tid < TS) acc[tid] = ws[I * TS + tid];
+    __syncthreads();
+    for (int J = I + 1; J < s.nt; ++J) {
+      if (tid < TS) xv[tid] = zs[J * TS + tid];
+      __syncthreads();
+      tile_mv(L + tidx2(J, I) * TS2, xv, acc, red, true, -1.0);
+    }
+    if (tid < TS) xv[tid] = acc[tid];
+    __syncthreads();
+    if (tid < TS) acc[tid] = 0.0;
+    __syncthreads();
+    tile_mv(linv + s.linv_off + (int64_t)I * TS2, xv, acc, red, true, 1.0);
+    if (tid < TS) zs[I * TS + tid] = acc[tid];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+void pcg_gather(const DevIdx& d, int weighted, const double* v, double* xb, const PcgState* st, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_gather, grid1(d.NB), dim3(256), 0, s, d.NB, d.g_ptr, d.g_row, d.g_coef, d.r_w, weighted, v, xb, st);
+}
+void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* base, double sgn, double* out,
+                 const PcgState* st, hipStream_t s) {
+  if (d.n_lam) hipLaunchKernelGGL(k_scatter, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, d.r_w, weighted, y, base, sgn, out, st);
+}
+template <typename T>
+void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st);
+  hipLaunchKernelGGL(k_symv_reduce, grid1(NB), dim3(256), 0, s, NB, b_sub, subs, (const double*)part, yb, st);
+}
+template void pcg_symv<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
+template void pcg_symv<float>(const Task*, int, const SubInfo*, const float*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
+
+void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
+             const PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_PARTS), dim3(256), 0, s, n, a, b, c, d, part, st);
+}
+void pcg_alpha(const double* part, PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(256), 0, s, part, DOT_PARTS, st);
+}
+void pcg_beta(const double* part, PcgState* st, int init, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_beta, dim3(1), dim3(256), 0, s, part, DOT_PARTS, st, init, hist);
+}
+void pcg_update_lr(int64_t n, double* lam, double* r, const double* sv, const double* q, const PcgState* st,
+                   hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_update_lr, grid1(n), dim3(256), 0, s, n, lam, r, sv, q, st);
+}
+void pcg_update_s(int64_t n, double* sv, const double* z, const PcgState* st, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_update_s, grid1(n), dim3(256), 0, s, n, sv, z, st);
+}
+void pcg_coarse_gt(int n_sub, const SubInfo* subs, const double* rb, const double* xb, double* g,
+                   const PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_gt, dim3(n_sub), dim3(256), 0, s, subs, rb, xb, g, st);
+}
+void pcg_coarse_gt_full(int n_sub, const SubInfo* subs, const double* rf, const double* xf, double* g,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_gt_full, dim3(n_sub), dim3(256), 0, s, subs, rf, xf, g);
+}
+void pcg_coarse_expand(const DevIdx& d, const SubInfo* subs, const double* rb, const double* alpha, double* vb,
+                       const PcgState* st, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_coarse_expand, grid1(d.NB), dim3(256), 0, s, d.NB, d.b_sub, subs, rb, alpha, vb, st);
+}
+void pcg_add_modes(int64_t NF, const int32_t* f_sub, const SubInfo* subs, const double* rf, const double* gamma,
+                   double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_modes, grid1(NF), dim3(256), 0, s, NF, f_sub, subs, rf, gamma, u);
+}
+void pcg_lumped(const DevIdx& d, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
+                const double* xb, double* yb, const PcgState* st, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_lumped, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, d.b_sub, subs, ell_col, ell_val, xb, yb, st);
+}
+void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_copy_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, full, b);
+}
+void vec_add_b2f(const DevIdx& d, const double* b, double sgn, double* full, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_add_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, sgn, full);
+}
+void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s) {
+  if (d.n_lam) hipLaunchKernelGGL(k_bvec, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_gdof, dvals, out);
+}
+void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, const double* ufull,
+                const uint8_t* dmask, const double* dvals, double* out, int sum_mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_global, grid1(n_dof), dim3(256), 0, s, n_dof, uc_ptr, uc_idx, ufull, dmask, dvals, out, sum_mode);
+}
+void vec_dirinc(int64_t n_dof, const uint8_t* dmask, const double* dirval, double tau, const double* U,
+                double* dvals, hipStream_t s) {
+  hipLaunchKernelGGL(k_dirinc, grid1(n_dof), dim3(256), 0, s, n_dof, dmask, dirval, tau, U, dvals);
+}
+void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_axpby, grid1(n), dim3(256), 0, s, n, a, x, b, y);
+}
+void vec_fill(int64_t n, double v, double* y, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill, grid1(n), dim3(256), 0, s, n, v, y);
+}
+void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_copy_st, grid1(n), dim3(256), 0, s, n, x, y, st);
+}
+void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, rtol, atol, max_it, hist_cap);
+}
+template <typename T>
+void local_kpinv(int n_sub, const SubInfo* subs, const T* arena, const T* linv, const T* X, const double* g,
+                 double* z, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_kpinv<T>, dim3(n_sub), dim3(256), 0, s, subs, arena, linv, X, g, z, w);
+}
+template void local_kpinv<double>(int, const SubInfo*, const double*, const double*, const double*, const double*, double*, double*, hipStream_t);
+template void local_kpinv<float>(int, const SubInfo*, const float*, const float*, const float*, const double*, double*, double*, hipStream_t);
+
+}  // namespace feti

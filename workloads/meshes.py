@@ -198,11 +198,12 @@ def random_box_cube(n_el=64, n_box_axis=8, seed=0, *, E=1.0, nu=0.3, lo=4, hi=12
 # is the paper's Table 1; the adventitia set and the layer thickness ratio are
 # part of the synthetic tube workload.
 MEDIA = dict(c=3.0, k1=2.3632, k2=0.8393, angle_deg=29.0)
+MMHG = 0.133322          # kPa per mmHg: stresses and moduli are in kPa, as in Table 1
 ADVENTITIA = dict(c=0.3, k1=0.562, k2=0.7112, angle_deg=62.0)
 
 
 def tube_mesh(nr=16, nth=128, nz=64, sub=(1, 16, 8), r_in=1.0, r_out=1.3, length=4.0,
-              r_layer=1.2, kappa_factor=1000.0, pressure=16.0) -> Mesh:
+              r_layer=1.2, kappa_factor=1000.0, pressure=16.0 * 0.133322) -> Mesh:
     """Two-layer thick-walled tube, periodic in the circumferential direction.
 
     Nodes sit at r_i = r_in + (r_out-r_in) i/nr, theta_j = 2 pi j/nth,
@@ -210,7 +211,8 @@ def tube_mesh(nr=16, nth=128, nz=64, sub=(1, 16, 8), r_in=1.0, r_out=1.3, length
     Elements whose centroid radius is below ``r_layer`` are media, the others
     adventitia.  Fibre families are cos(a) e_theta +/- sin(a) e_z at the
     element centroid.  Both ends (z=0 and z=length) are clamped.  The inner
-    surface carries a follower pressure.  Subdomains are boxes of the
+    surface carries a follower pressure, in kPa like the material moduli
+    (default 16 mmHg).  Subdomains are boxes of the
     (r, theta, z) element grid, id = br + Br*(bt + Bt*bz).
     """
     nrn, nthn, nzn = nr + 1, nth, nz + 1
