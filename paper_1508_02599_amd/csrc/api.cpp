@@ -68,7 +68,9 @@ struct feti_problem {
   // assembly / factor data
   double *d_Ke = nullptr, *d_fint = nullptr, *d_fbody = nullptr, *d_ell_val = nullptr, *d_U = nullptr;
   double *d_fnodal = nullptr;
-  void *d_arena = nullptr, *d_linv = nullptr, *d_W = nullptr, *d_X = nullptr, *d_S = nullptr;
+  void *d_arena = nullptr, *d_linv = nullptr, *d_W = nullptr, *d_X = nullptr, *d_S = nullptr, *d_Wi = nullptr;
+  double *d_t = nullptr, *d_kb1 = nullptr, *d_kb2 = nullptr, *d_bb_val = nullptr;
+  int32_t *d_bb_slot = nullptr, *d_bb_col = nullptr;
   double *d_rfull = nullptr, *d_rb = nullptr, *d_work = nullptr, *d_rho = nullptr, *d_wbm = nullptr;
   int32_t *d_nmodes = nullptr, *d_err = nullptr;
   // coarse
@@ -86,6 +88,10 @@ struct feti_problem {
   double *d_cg = nullptr, *d_calpha = nullptr, *d_gamma = nullptr, *d_e = nullptr;
   double *d_dvals = nullptr, *d_out = nullptr, *d_dots = nullptr, *d_hist = nullptr;
   PcgState* d_state = nullptr;
+  int* d_ticket = nullptr;
+  double *d_fpart = nullptr, *d_qdense = nullptr, *d_gpart = nullptr;
+  int32_t* d_bco = nullptr;
+  int ldg = 0;
   int hist_cap = 0;
   // graph
   hipGraphExec_t graph = nullptr;
@@ -166,13 +172,26 @@ void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, co
                      p->di.b_sub, yb, st, p->stream);
 }
 
+void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st);
+
+// z = K^+ g for every subdomain (full local vectors), see k_kp_tiles.
+template <typename T>
+void kpinv_t(feti_problem* p, const double* g, double* z) {
+  const HostPlan& P = p->P;
+  const T* A = (const T*)p->d_arena;
+  const T* Wi = (const T*)p->d_Wi;
+  hipStream_t st = p->stream;
+  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  vec_set_b2f(p->di, p->d_kb2, z, st);
+}
+
 void kpinv(feti_problem* p, const double* g, double* z) {
-  if (p->P.mixed)
-    local_kpinv<float>(p->P.n_sub, p->d_sub, (const float*)p->d_arena, (const float*)p->d_linv,
-                       (const float*)p->d_X, g, z, p->d_w, p->stream);
-  else
-    local_kpinv<double>(p->P.n_sub, p->d_sub, (const double*)p->d_arena, (const double*)p->d_linv,
-                        (const double*)p->d_X, g, z, p->d_w, p->stream);
+  if (p->P.mixed) kpinv_t<float>(p, g, z);
+  else kpinv_t<double>(p, g, z);
 }
 
 // alpha = Q^{-1} g on the coarse space (alpha = 0 without coarse space).
@@ -182,17 +201,18 @@ void coarse_solve(feti_problem* p, const double* g, double* alpha, const PcgStat
                    (int64_t)p->nq * TS, p->d_qbsub, alpha, st, p->stream);
 }
 
-// out = P in = in - G Q^{-1} G^T in
-void project(feti_problem* p, const double* in, double* out, const PcgState* st) {
-  if (p->n_coarse == 0) {
-    if (in != out) vec_copy_st(p->P.n_lam, in, out, st, p->stream);
-    return;
+// Projection by the fused kernels: g = Rb^T B^T x per subdomain, a = Q^{-1} g
+// (dense inverse), and per multiplier row out = x - G a (see k_proj_apply for
+// the modes: 0 plain, 1 with the r/lambda update, 2 with the PCG dot products).
+void project_fused(feti_problem* p, int mode, int init, double* x, double* out, const double* w, PcgState* st,
+                   double* hist) {
+  const int nc = p->n_coarse;
+  if (nc) {
+    pcg_proj_gt(p->P.n_sub, p->d_sub, p->di, p->d_rb, x, p->d_q, mode == 1, p->d_gpart, p->ldg, st, p->stream);
+    pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, p->stream);
   }
-  pcg_gather(p->di, 0, in, p->d_xb, st, p->stream);
-  pcg_coarse_gt(p->P.n_sub, p->d_sub, p->d_rb, p->d_xb, p->d_cg, st, p->stream);
-  coarse_solve(p, p->d_cg, p->d_calpha, st);
-  pcg_coarse_expand(p->di, p->d_sub, p->d_rb, p->d_calpha, p->d_vb, st, p->stream);
-  pcg_scatter(p->di, 0, p->d_vb, in, -1.0, out, st, p->stream);
+  pcg_proj_apply(mode, init, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, x, p->d_q, p->d_s, p->d_lam, out, w,
+                 p->d_fpart, p->d_ticket + 1, st, hist, p->stream);
 }
 
 // q = F v
@@ -207,7 +227,7 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
   pcg_gather(p->di, 1, w, p->d_xb, st, p->stream);
   const double* y = p->d_xb;
   if (p->P.precond == FETI_PREC_LUMPED) {
-    pcg_lumped(p->di, p->d_sub, p->d_ell_col, p->d_ell_val, p->d_xb, p->d_yb, st, p->stream);
+    pcg_lumped(p->di, p->P.w_bb, p->d_bb_col, p->d_bb_val, p->d_xb, p->d_yb, st, p->stream);
     y = p->d_yb;
   } else if (p->P.precond == FETI_PREC_DIRICHLET) {
     symv_local(p, p->d_S, p->d_xb, p->d_yb, st);
@@ -216,19 +236,17 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
   pcg_scatter(p->di, 1, y, nullptr, 1.0, out, st, p->stream);
 }
 
+// One PCG iteration (six to seven launches, all scalars on the device):
+//   q = F s (s = z + beta s formed on the fly), alpha;  r -= alpha q,
+//   lambda += alpha s, w = P r;  t = M^{-1} w;  z = P t, beta and the test.
 void pcg_iteration(feti_problem* p) {
   PcgState* st = p->d_state;
-  const int64_t n = p->P.n_lam;
-  apply_F(p, p->d_s, p->d_q, nullptr, 1.0, st);
-  pcg_dot(n, p->d_s, p->d_q, nullptr, nullptr, p->d_dots, st, p->stream);
-  pcg_alpha(p->d_dots, st, p->stream);
-  pcg_update_lr(n, p->d_lam, p->d_r, p->d_s, p->d_q, st, p->stream);
-  project(p, p->d_r, p->d_wv, st);
+  pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, p->stream);
+  symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
+  pcg_scatter_dot_alpha(p->di, p->d_yb, p->d_zv, p->d_s, p->d_q, p->d_fpart, p->d_ticket, st, p->stream);
+  project_fused(p, 1, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
   precondition(p, p->d_wv, p->d_tv, st);
-  project(p, p->d_tv, p->d_zv, st);
-  pcg_dot(n, p->d_wv, p->d_zv, p->d_wv, p->d_wv, p->d_dots, st, p->stream);
-  pcg_beta(p->d_dots, st, 0, p->d_hist, p->stream);
-  pcg_update_s(n, p->d_s, p->d_zv, st, p->stream);
+  project_fused(p, 2, 0, p->d_tv, p->d_zv, p->d_wv, st, p->d_hist);
 }
 
 // Condition estimate from the recorded (alpha, beta): extreme eigenvalues of
@@ -307,6 +325,11 @@ feti_status setup_device(feti_problem* p) {
   TRY(upload(p, p->d_pc_ab, P.pc_ab));
   TRY(upload(p, p->d_diag_slot, P.diag_slot));
   TRY(upload(p, p->d_ell_col, P.ell_col));
+  if (P.precond == FETI_PREC_LUMPED) {
+    TRY(upload(p, p->d_bb_slot, P.bb_slot));
+    TRY(upload(p, p->d_bb_col, P.bb_col));
+    TRY(dalloc(p, p->d_bb_val, P.bb_slot.size()));
+  }
   TRY(upload(p, p->d_fpos_lnode, P.fpos_lnode));
   TRY(upload(p, p->d_fpos_comp, P.fpos_comp));
   TRY(upload(p, p->d_f_sub, P.f_sub));
@@ -361,7 +384,9 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_U, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_fnodal, (size_t)P.n_dof));
   {
-    char *a, *l, *w, *x, *s = nullptr;
+    char *a, *l, *w, *x, *s = nullptr, *wi;
+    TRY(dalloc(p, wi, (size_t)P.n_witiles * e));
+    p->d_Wi = wi;
     TRY(dalloc(p, a, (size_t)P.n_tiles * e));
     TRY(dalloc(p, l, (size_t)P.n_linv * e));
     TRY(dalloc(p, w, (size_t)P.n_xtiles * e));
@@ -411,6 +436,9 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_w, (size_t)P.NF));
   TRY(dalloc(p, p->d_u, (size_t)P.NF));
   TRY(dalloc(p, p->d_gfull, (size_t)P.NF));
+  TRY(dalloc(p, p->d_t, (size_t)P.NF));
+  TRY(dalloc(p, p->d_kb1, (size_t)P.NB));
+  TRY(dalloc(p, p->d_kb2, (size_t)P.NB));
   TRY(dalloc(p, p->d_xb, (size_t)P.NB));
   TRY(dalloc(p, p->d_yb, (size_t)P.NB));
   TRY(dalloc(p, p->d_vb, (size_t)P.NB));
@@ -431,6 +459,13 @@ feti_status setup_device(feti_problem* p) {
   p->hist_cap = std::max(1, p->opt.max_it);
   TRY(dalloc(p, p->d_hist, 2 * (size_t)p->hist_cap));
   TRY(dalloc(p, p->d_state, 1));
+  TRY(dalloc(p, p->d_ticket, 4));
+  HIPCHK(hipMemsetAsync(p->d_ticket, 0, 4 * sizeof(int), p->stream));
+  TRY(dalloc(p, p->d_fpart, 2 * 256));
+  TRY(dalloc(p, p->d_qdense, (size_t)max_coarse * max_coarse));
+  p->ldg = max_coarse;
+  TRY(dalloc(p, p->d_gpart, (size_t)4 * max_coarse));
+  TRY(dalloc(p, p->d_bco, (size_t)P.NB));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
   HIPCHK(hipStreamSynchronize(p->stream));
   return FETI_OK;
@@ -474,6 +509,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   g.subs = p->d_sub;
   g.Ke = p->d_Ke;
   g.ell_val = p->d_ell_val;
+  g.NF = P.NF;
   if (P.mixed) asm_gather<float>(g, (float*)p->d_arena, st);
   else asm_gather<double>(g, (double*)p->d_arena, st);
   ModesArgs m;
@@ -487,12 +523,14 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.U = U_dev;
   m.ell_col = p->d_ell_col;
   m.ell_val = p->d_ell_val;
+  m.NF = P.NF;
   m.test_rotations = (P.any_hgo && U_dev) ? 1 : 0;
   m.rfull = p->d_rfull;
   m.rb = p->d_rb;
   m.n_modes = p->d_nmodes;
   m.work = p->d_work;
   asm_modes(m, st);
+  if (P.precond == FETI_PREC_LUMPED) lumped_fill(p->di, P.w_bb, p->d_bb_slot, p->d_ell_val, p->d_bb_val, st);
   HIPCHK(hipEventRecord(p->ev[1], st));
   // coarse layout from the kernel dimensions
   std::vector<int32_t> nm(P.n_sub);
@@ -507,10 +545,19 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   p->n_coarse = off;
   p->nq = (off + TS - 1) / TS;
   HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
+  fill_bco(p->di, p->d_sub, p->d_bco, st);
   // batched factorisation
   const int big = 0x7fffffff;
   HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
   for (const auto& L : P.sched_interior) dense(p, L);
+  for (const auto& L : P.sched_trtri_int) {
+    if (P.mixed)
+      launch_dense<float>(L.kind, p->d_tasks + L.first, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv,
+                          (float*)p->d_Wi, nullptr, p->d_err, st);
+    else
+      launch_dense<double>(L.kind, p->d_tasks + L.first, L.count, p->d_sub, (double*)p->d_arena,
+                           (double*)p->d_linv, (double*)p->d_Wi, nullptr, p->d_err, st);
+  }
   dense(p, P.sched_schur);
   const auto& XT = P.sched_xtiles;
   if (P.precond == FETI_PREC_DIRICHLET) {
@@ -587,6 +634,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     for (const auto& L : qf) qd(L);
     for (const auto& L : qr) qd(L);
     qd(qla);
+    coarse_to_dense(p->n_coarse, p->n_coarse, p->d_qX, p->d_qdense, st);
     HIPCHK(hipStreamSynchronize(st));   // task list upload must complete before qt goes out of scope
   }
   HIPCHK(hipEventRecord(p->ev[2], st));
@@ -635,12 +683,10 @@ feti_status solve_core(feti_problem* p, feti_stats* stats) {
     // r = d - F lambda ; w = P r ; z = P M w ; s = z
     apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
     pcg_init_state(p->d_state, p->opt.rtol, 0.0, p->opt.max_it, p->hist_cap, st);
-    project(p, p->d_r, p->d_wv, nullptr);
-    precondition(p, p->d_wv, p->d_tv, nullptr);
-    project(p, p->d_tv, p->d_zv, nullptr);
-    vec_axpby(n, 1.0, p->d_zv, 0.0, p->d_s, st);
-    pcg_dot(n, p->d_wv, p->d_zv, p->d_wv, p->d_wv, p->d_dots, nullptr, st);
-    pcg_beta(p->d_dots, p->d_state, 1, nullptr, st);
+    vec_fill(n, 0.0, p->d_s, st);   // s = z + 0 s in the first iteration
+    project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->d_state, nullptr);
+    precondition(p, p->d_wv, p->d_tv, p->d_state);
+    project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->d_state, nullptr);
     // graph of graph_block iterations
     const int gb = std::max(1, p->opt.graph_block);
     if (!p->graph || p->graph_iters != gb) {
@@ -882,6 +928,7 @@ feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stat
   r.fnodal = fn;
   r.ell_col = p->d_ell_col;
   r.ell_val = p->d_ell_val;
+  r.NF = P.NF;
   r.dvals = p->d_dvals;
   r.body_scale = load_factor;
   r.int_scale = 0.0;
@@ -949,6 +996,7 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
   r.fnodal = fn;
   r.ell_col = p->d_ell_col;
   r.ell_val = p->d_ell_val;
+  r.NF = P.NF;
   r.body_scale = tau;
   r.int_scale = 1.0;
   r.nodal_scale = tau;

@@ -298,7 +298,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   }
   // ---- interior-first positions
   P.loc_pos.assign(3 * P.n_loc_nodes, -1);
-  int64_t tile_off = 0, linv_off = 0, x_off = 0, full_off = 0, b_off = 0, part_off = 0;
+  int64_t tile_off = 0, linv_off = 0, x_off = 0, full_off = 0, b_off = 0, part_off = 0, wi_off = 0;
   for (int s = 0; s < ns; ++s) {
     SubInfo& si = P.sub[s];
     int n_ii = 0, n_b = 0;
@@ -334,6 +334,8 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     si.full_off = full_off;
     si.b_off = b_off;
     si.part_off = part_off;
+    si.wi_off = wi_off;
+    wi_off += (int64_t)si.nt_i * (si.nt_i + 1) / 2 * TS2;
     tile_off += (int64_t)si.nt * (si.nt + 1) / 2 * TS2;
     linv_off += (int64_t)si.nt * TS2;
     x_off += (int64_t)si.nt_b * (si.nt_b + 1) / 2 * TS2;
@@ -349,6 +351,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   P.NF = full_off;
   P.NB = b_off;
   P.n_part = part_off;
+  P.n_witiles = wi_off;
   if (P.NB >= ((int64_t)1 << 31) || P.n_lam >= ((int64_t)1 << 31)) return "problem too large";
   P.fpos_lnode.assign(P.NF, -1);
   P.fpos_comp.assign(P.NF, 0);
@@ -450,7 +453,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
               const int64_t ldb = 3 * (int64_t)(si.node_off + tup[t][0]) + j;
               const int col = P.loc_pos[ldb];
               const int64_t gb = 3 * P.loc_node[si.node_off + tup[t][0]] + j;
-              P.ell_col[(si.full_off + row) * ELLW + nbr * 3 + j] = col >= 0 ? col : (int32_t)(-(gb + 2));
+              P.ell_col[(int64_t)(nbr * 3 + j) * P.NF + si.full_off + row] = col >= 0 ? col : (int32_t)(-(gb + 2));
             }
           }
         }
@@ -459,6 +462,32 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
       }
       if (nbr >= 0) P.ps_c1.push_back((int32_t)P.pc_e.size());
     }
+  }
+  // ---- interface-interface block of every local stiffness (lumped preconditioner)
+  {
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(P.NB);
+    int32_t w = 0;
+    for (int s = 0; s < ns; ++s) {
+      const SubInfo& si = P.sub[s];
+      const int bstart = si.nt_i * TS;
+      for (int pb = 0; pb < si.n_b; ++pb) {
+        const int64_t row = si.full_off + bstart + pb;
+        auto& L = rows[si.b_off + pb];
+        for (int k = 0; k < ELLW; ++k) {
+          const int c = P.ell_col[(int64_t)k * P.NF + row];
+          if (c >= bstart) L.push_back({k, (int32_t)(si.b_off + c - bstart)});
+        }
+        w = std::max<int32_t>(w, (int32_t)L.size());
+      }
+    }
+    P.w_bb = w;
+    P.bb_slot.assign((size_t)w * P.NB, -1);
+    P.bb_col.assign((size_t)w * P.NB, 0);
+    for (int64_t b = 0; b < P.NB; ++b)
+      for (size_t k = 0; k < rows[b].size(); ++k) {
+        P.bb_slot[k * P.NB + b] = rows[b][k].first;
+        P.bb_col[k * P.NB + b] = rows[b][k].second;
+      }
   }
   // ---- copies of every global dof in the full local space
   P.uc_ptr.assign(P.n_dof + 1, 0);
@@ -528,6 +557,15 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   }
   build_factor_schedule(P.sub, P.tasks, P.sched_interior, P.sched_schur, P.sched_iface, P.sched_trtri,
                         P.sched_lauum, P.sched_xtiles, P.sched_alltiles);
+  // inverse of the interior factor, block row by block row
+  for (int ib = 0; ib < P.max_nt_i; ++ib) {
+    HostPlan::Launch L{K_TRTRI_INT, (int32_t)P.tasks.size(), 0};
+    for (int s = 0; s < ns; ++s)
+      if (P.sub[s].nt_i > ib)
+        for (int jb = 0; jb <= ib; ++jb) P.tasks.push_back({s, ib, jb, jb, ib});
+    L.count = (int32_t)P.tasks.size() - L.first;
+    P.sched_trtri_int.push_back(L);
+  }
   return "";
 }
 

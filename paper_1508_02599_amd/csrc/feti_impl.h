@@ -34,6 +34,7 @@ struct SubInfo {
   int64_t tile_off;     // element offset into the factor arena
   int64_t linv_off;     // element offset into the diagonal-inverse arena
   int64_t x_off;        // element offset into the interface arenas (X, W, S)
+  int64_t wi_off;       // element offset into the interior-inverse arena
   int64_t full_off;     // offset of the local vector in full-space vectors
   int64_t b_off;        // offset of the interface part in b-space vectors
   int64_t part_off;     // offset into interface GEMV partial sums
@@ -74,14 +75,17 @@ struct HostPlan {
   std::vector<int8_t> fpos_comp;        // [NF] component of a full-space position
   std::vector<int32_t> f_sub;           // [NF] subdomain of a full-space position
   int64_t NF = 0, NB = 0;               // full-space and b-space lengths
-  int64_t n_tiles = 0, n_xtiles = 0, n_linv = 0, n_part = 0;
+  int64_t n_tiles = 0, n_xtiles = 0, n_linv = 0, n_part = 0, n_witiles = 0;
 
   // ---- assembly gather (node pairs inside a subdomain)
   std::vector<int32_t> ps_a, ps_b, ps_nbr, ps_c0, ps_c1;   // per pair slot (a,b: local-node index incl. node_off)
   std::vector<int32_t> pc_e;            // contribution element
   std::vector<int32_t> pc_ab;           // la | lb << 8
   std::vector<int32_t> diag_slot;       // [n_loc_nodes] slot of (a, a)
-  std::vector<int32_t> ell_col;         // [NF*ELLW]  >=0 local pos, -1 empty, <=-2 Dirichlet dof -(g+2)
+  std::vector<int32_t> ell_col;         // [ELLW][NF] slot-major: >=0 local pos, -1 empty, <=-2 Dirichlet dof -(g+2)
+  int32_t w_bb = 0;                     // width of the interface-interface block K_bb in slots
+  std::vector<int32_t> bb_slot;         // [w_bb][NB] ELL slot of each K_bb entry (-1 none)
+  std::vector<int32_t> bb_col;          // [w_bb][NB] b-space column
 
   // ---- multipliers
   int64_t n_lam = 0;
@@ -113,13 +117,14 @@ struct HostPlan {
   Launch sched_schur{0, 0, 0};          // stage 2
   std::vector<Launch> sched_iface;      // stage 4
   std::vector<Launch> sched_trtri;      // stage 5
+  std::vector<Launch> sched_trtri_int;  // inverse of the interior factor
   Launch sched_lauum{0, 0, 0};          // stage 6
   Launch sched_xtiles{0, 0, 0};         // all interface lower tiles (sub, I, J)
   Launch sched_alltiles{0, 0, 0};       // all factor tiles (sub, i, j)
   int max_nt_i = 0, max_nt_b = 0;
 };
 
-enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4 };
+enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4, K_TRTRI_INT = 5 };
 
 // Builds the plan; returns an empty string on success, else an error message.
 std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);

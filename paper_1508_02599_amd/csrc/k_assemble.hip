@@ -325,9 +325,8 @@ __global__ void k_gather_local(GatherArgs G, T* arena) {
   for (int i = 0; i < 3; ++i) {
     const int row = G.loc_pos[3 * la + i];
     if (row < 0) continue;
-    double* ev = G.ell_val + (s.full_off + row) * ELLW + nbr * 3;
     for (int j = 0; j < 3; ++j) {
-      ev[j] = K[3 * i + j];
+      G.ell_val[(int64_t)(nbr * 3 + j) * G.NF + s.full_off + row] = K[3 * i + j];
       const int col = G.loc_pos[3 * lb + j];
       if (col >= 0 && row >= col) {
         const int ti = row / TS, tj = col / TS;
@@ -366,8 +365,8 @@ __global__ void k_rhs(RhsArgs R) {
   if (R.fnodal) f += R.nodal_scale * R.fnodal[3 * g + i] / R.loc_ncopy[la];
   const int64_t row = s.full_off + pos;
   for (int k = 0; k < ELLW; ++k) {
-    const int cc = R.ell_col[row * ELLW + k];
-    if (cc <= -2) f -= R.ell_val[row * ELLW + k] * R.dvals[-(cc + 2)];
+    const int cc = R.ell_col[k * R.NF + row];
+    if (cc <= -2) f -= R.ell_val[k * R.NF + row] * R.dvals[-(cc + 2)];
   }
   R.f[row] = f;
 }
@@ -488,8 +487,8 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
     double kf = 0.0;
     for (int64_t p = tid; p < n; p += 256)
       for (int q = 0; q < ELLW; ++q) {
-        const double v = M.ell_val[(s.full_off + p) * ELLW + q];
-        if (M.ell_col[(s.full_off + p) * ELLW + q] >= 0) kf += v * v;
+        const double v = M.ell_val[q * M.NF + s.full_off + p];
+        if (M.ell_col[q * M.NF + s.full_off + p] >= 0) kf += v * v;
       }
     const double knorm = sqrt(block_sum(kf, red));
     for (int k = 3; k < 6; ++k) {
@@ -497,8 +496,8 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
       for (int64_t p = tid; p < n; p += 256) {
         double y = 0.0;
         for (int q = 0; q < ELLW; ++q) {
-          const int c = M.ell_col[(s.full_off + p) * ELLW + q];
-          if (c >= 0) y += M.ell_val[(s.full_off + p) * ELLW + q] * W[(int64_t)c * 6 + k];
+          const int c = M.ell_col[q * M.NF + s.full_off + p];
+          if (c >= 0) y += M.ell_val[q * M.NF + s.full_off + p] * W[(int64_t)c * 6 + k];
         }
         kr += y * y;
         rr += W[p * 6 + k] * W[p * 6 + k];

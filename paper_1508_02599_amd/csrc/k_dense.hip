@@ -39,16 +39,39 @@ __device__ __forceinline__ int out_row(float, int l, int r) { return 4 * (l >> 4
 __device__ __forceinline__ int64_t tidx(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
 // LDS operand layout: s[k*LD + m] holds op(A)(m, k) (or op(B)(k, m)).
+// Tiles are read with 16-byte vector loads, all issued before any LDS store,
+// so that a workgroup keeps a whole 64x64 tile of loads in flight.
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+
+template <typename T, bool TRANS>
+__device__ __forceinline__ void lds_load(T* s, const T* __restrict__ g) {
+  typedef typename Vec16<T>::type V;
+  constexpr int EPV = Vec16<T>::n;
+  constexpr int NV = TS2 / EPV / 256;
+  const V* gv = reinterpret_cast<const V*>(g);
+  V v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = gv[threadIdx.x + 256 * i];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e0 = (threadIdx.x + 256 * i) * EPV;
+#pragma unroll
+    for (int u = 0; u < EPV; ++u) {
+      const int e = e0 + u;
+      const T x = reinterpret_cast<const T*>(&v[i])[u];
+      if (TRANS) s[(e & 63) * LD + (e >> 6)] = x;
+      else s[(e >> 6) * LD + (e & 63)] = x;
+    }
+  }
+}
 // direct: s[k][m] = g[k*TS + m]   (A not transposed, or B transposed)
 template <typename T>
-__device__ __forceinline__ void lds_direct(T* s, const T* __restrict__ g) {
-  for (int e = threadIdx.x; e < TS2; e += 256) s[(e >> 6) * LD + (e & 63)] = g[e];
-}
+__device__ __forceinline__ void lds_direct(T* s, const T* __restrict__ g) { lds_load<T, false>(s, g); }
 // transposed: s[k][m] = g[m*TS + k]   (A transposed, or B not transposed)
 template <typename T>
-__device__ __forceinline__ void lds_trans(T* s, const T* __restrict__ g) {
-  for (int e = threadIdx.x; e < TS2; e += 256) s[(e & 63) * LD + (e >> 6)] = g[e];
-}
+__device__ __forceinline__ void lds_trans(T* s, const T* __restrict__ g) { lds_load<T, true>(s, g); }
 
 template <typename T>
 struct Acc {
@@ -115,69 +138,74 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks,
 }
 
 // Cholesky of the diagonal tile (j, j) in place (zeroing its upper part) and
-// its triangular inverse.  Computed in FP64 whatever the storage type.
-// A non-positive or non-finite pivot records the subdomain in err[0] (min).
+// its triangular inverse, by one wavefront.  Lane r keeps row r of the tile in
+// registers (loops fully unrolled); column c of L is broadcast through LDS and
+// the trailing update is a register FMA per entry.  For the inverse, lane j
+// keeps column j of L^{-1} in registers and reads L by broadcast.
+// Computed in FP64 whatever the storage type.  A non-positive or non-finite
+// pivot records the subdomain in err[0] (min).
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag(const Task* __restrict__ tasks,
-                                              const SubInfo* __restrict__ subs, T* arena, T* linv,
-                                              int* err) {
+__global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
+                                             const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                             int* err) {
+  __shared__ double colv[TS];
   __shared__ double sL[TS * LD], sI[TS * LD];
-  __shared__ double red[4][TS];
-  __shared__ int bad;
   const Task t = tasks[blockIdx.x];
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
   T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < TS2; e += 256) sL[(e >> 6) * LD + (e & 63)] = (double)C[e];
-  if (tid == 0) bad = 0;
+  const int r = threadIdx.x;
+  for (int c0 = 0; c0 < TS; c0 += 16) {
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = C[(c0 + i) * TS + r];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sL[(c0 + i) * LD + r] = (double)v[i];
+  }
+  bool bad = false;
   __syncthreads();
   for (int c = 0; c < TS; ++c) {
-    if (tid == 0) {
-      double d = sL[c * LD + c];
-      if (!(d > 0.0) || !(d < 1e300)) {
-        bad = 1;
-        d = 1.0;
-      }
-      sL[c * LD + c] = sqrt(d);
-    }
+    const double d = sL[c * LD + c];
+    const bool ok = (d > 0.0) && (d < 1e300);
+    bad |= !ok;
+    const double sd = sqrt(ok ? d : 1.0);
+    const double l = r > c ? sL[c * LD + r] / sd : (r == c ? sd : 0.0);
     __syncthreads();
-    if (tid > c && tid < TS) sL[c * LD + tid] /= sL[c * LD + c];
+    colv[r] = l;
+    sL[c * LD + r] = l;
     __syncthreads();
-    const int m = TS - 1 - c;
-    for (int e = tid; e < m * m; e += 256) {
-      const int cc = c + 1 + e / m, r = c + 1 + e % m;
-      if (r >= cc) sL[cc * LD + r] -= sL[c * LD + r] * sL[c * LD + cc];
-    }
+    // trailing update of row r; colv is a separate array, so the row updates
+    // are independent and pipeline (entries above the diagonal are scratch)
+#pragma unroll 8
+    for (int cc = c + 1; cc < TS; ++cc) sL[cc * LD + r] -= l * colv[cc];
     __syncthreads();
   }
-  // zero the upper triangle, clear the inverse
-  for (int e = tid; e < TS2; e += 256) {
-    const int c = e >> 6, r = e & 63;
-    if (r < c) sL[c * LD + r] = 0.0;
-    sI[c * LD + r] = 0.0;
+  // zero the upper triangle and write L back
+  for (int c = 0; c < TS; ++c)
+    if (c > r) sL[c * LD + r] = 0.0;
+  __syncthreads();
+#pragma unroll 8
+  for (int c = 0; c < TS; ++c) C[c * TS + r] = (T)sL[c * LD + r];
+  // X = L^{-1}: lane j owns column j, kept in LDS (sI[j][.]):
+  // X(i,j) = (delta_ij - sum_{j<=k<i} L(i,k) X(k,j)) / L(i,i)
+  const int j = r;
+  for (int i = 0; i < TS; ++i) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int k = j;
+    for (; k + 3 < i; k += 4) {
+      acc0 += sL[k * LD + i] * sI[j * LD + k];
+      acc1 += sL[(k + 1) * LD + i] * sI[j * LD + k + 1];
+      acc2 += sL[(k + 2) * LD + i] * sI[j * LD + k + 2];
+      acc3 += sL[(k + 3) * LD + i] * sI[j * LD + k + 3];
+    }
+    for (; k < i; ++k) acc0 += sL[k * LD + i] * sI[j * LD + k];
+    const double acc = (acc0 + acc1) + (acc2 + acc3);
+    sI[j * LD + i] = i < j ? 0.0 : ((i == j ? 1.0 : 0.0) - acc) / sL[i * LD + i];
   }
   __syncthreads();
-  // forward substitution, all columns at once: X(i, j) for j <= i
-  const int j = tid & 63, part = tid >> 6;
-  for (int i = 0; i < TS; ++i) {
-    double acc = 0.0;
-    if (j < i)
-      for (int k = j + part; k < i; k += 4) acc += sL[k * LD + i] * sI[j * LD + k];
-    red[part][j] = acc;
-    __syncthreads();
-    if (part == 0 && j <= i) {
-      const double sum = red[0][j] + red[1][j] + red[2][j] + red[3][j];
-      sI[j * LD + i] = ((i == j ? 1.0 : 0.0) - sum) / sL[i * LD + i];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < TS2; e += 256) {
-    const int c = e >> 6, r = e & 63;
-    C[e] = (T)sL[c * LD + r];
-    Li[e] = (T)sI[c * LD + r];
-  }
-  if (tid == 0 && bad) atomicMin(err, t.sub);
+#pragma unroll 8
+  for (int c = 0; c < TS; ++c) Li[c * TS + r] = (T)sI[c * LD + r];
+  if (bad) atomicMin(err, t.sub);
 }
 
 // L_ij <- C_ij L_jj^{-T}   (panel solve by the explicit diagonal inverse)
@@ -208,13 +236,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
                                                const SubInfo* __restrict__ subs,
                                                const T* __restrict__ arena,
-                                               const T* __restrict__ linv, T* W) {
+                                               const T* __restrict__ linv, T* W, int interior) {
   __shared__ T sA[TS * LD], sB[TS * LD];
   const Task t = tasks[blockIdx.x];
   const SubInfo s = subs[t.sub];
-  const int ni = s.nt_i;
+  const int ni = interior ? 0 : s.nt_i;
   const T* Lbase = arena + s.tile_off;
-  T* Wbase = W + s.x_off;
+  T* Wbase = W + (interior ? s.wi_off : s.x_off);
   T* out = Wbase + tidx(t.i, t.j) * TS2;
   const T* Lii_inv = linv + s.linv_off + (int64_t)(ni + t.i) * TS2;
   if (t.i == t.j) {
@@ -469,9 +497,10 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
   if (count <= 0) return;
   switch (kind) {
     case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena); break;
-    case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, linv, err); break;
+    case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(64), 0, st, tasks, subs, arena, linv, err); break;
     case K_TRSM: hipLaunchKernelGGL(k_trsm<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, (const T*)linv); break;
-    case K_TRTRI: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W); break;
+    case K_TRTRI: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W, 0); break;
+    case K_TRTRI_INT: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W, 1); break;
     case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
   }
 }

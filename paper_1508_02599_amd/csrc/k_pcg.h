@@ -62,8 +62,10 @@ void pcg_coarse_expand(const DevIdx& d, const SubInfo* subs, const double* rb, c
                        const PcgState* st, hipStream_t s);
 void pcg_add_modes(int64_t NF, const int32_t* f_sub, const SubInfo* subs, const double* rf, const double* gamma,
                    double* u, hipStream_t s);
-void pcg_lumped(const DevIdx& d, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                const double* xb, double* yb, const PcgState* st, hipStream_t s);
+void pcg_lumped(const DevIdx& d, int w_bb, const int32_t* bb_col, const double* bb_val, const double* xb,
+                double* yb, const PcgState* st, hipStream_t s);
+void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double* ell_val, double* bb_val,
+                 hipStream_t s);
 void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s);
 void vec_add_b2f(const DevIdx& d, const double* b, double sgn, double* full, hipStream_t s);
 void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s);
@@ -76,8 +78,23 @@ void vec_fill(int64_t n, double v, double* y, hipStream_t s);
 void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s);
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
 template <typename T>
-void local_kpinv(int n_sub, const SubInfo* subs, const T* arena, const T* linv, const T* X, const double* g,
-                 double* z, double* w, hipStream_t s);
+void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const T* arena, const T* Wi,
+                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s);
+void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s);
+// fused iteration kernels
+void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,
+                  hipStream_t s);
+void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
+                           int* ticket, PcgState* st, hipStream_t s);
+void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* rbv, const double* x,
+                 const double* q, int with_update, double* gpart, int ldg, const PcgState* st, hipStream_t s);
+void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int ldg, double* a, const PcgState* st,
+                      hipStream_t s);
+void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int32_t* bco, const double* rbv,
+                    const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
+                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s);
+void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, hipStream_t s);
+void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s);
 
 // --- assembly kernels (k_assemble.hip)
 struct AsmArgs {
@@ -103,7 +120,8 @@ struct GatherArgs {
   const int32_t* loc_pos = nullptr;   // [3*n_loc_nodes]
   const SubInfo* subs = nullptr;
   const double* Ke = nullptr;
-  double* ell_val = nullptr;          // [NF*ELLW]
+  double* ell_val = nullptr;          // [ELLW][NF] slot-major
+  int64_t NF = 0;
 };
 template <typename T>
 void asm_gather(const GatherArgs& g, T* arena, hipStream_t s);
@@ -115,8 +133,9 @@ struct RhsArgs {
   const int64_t* loc_node = nullptr;
   const SubInfo* subs = nullptr;
   const double *fbody = nullptr, *fint = nullptr, *fnodal = nullptr;   // fnodal [n_dof] or null
-  const int32_t* ell_col = nullptr;
+  const int32_t* ell_col = nullptr;   // [ELLW][NF] slot-major
   const double* ell_val = nullptr;
+  int64_t NF = 0;
   const double* dvals = nullptr;      // [n_dof] prescribed values / increments
   double body_scale = 1.0, int_scale = 0.0, nodal_scale = 0.0;
   double* f = nullptr;                // [NF]
@@ -141,8 +160,9 @@ struct ModesArgs {
   const int32_t* fpos_lnode = nullptr; // [NF] local-node index (incl. node_off) of a full position, -1 pad
   const int8_t* fpos_comp = nullptr;   // [NF]
   const double *xyz = nullptr, *U = nullptr;
-  const int32_t* ell_col = nullptr;
+  const int32_t* ell_col = nullptr;   // [ELLW][NF] slot-major
   const double* ell_val = nullptr;
+  int64_t NF = 0;
   int test_rotations = 0;              // keep a rotation only if K annihilates it
   double kernel_tol = 1e-12;
   double* rfull = nullptr;             // [NF*6]

@@ -63,7 +63,16 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tas
   const SubInfo s = subs[t.sub];
   const T* tile = M + s.x_off + tidx2(t.i, t.j) * TS2;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TS2; e += 256) sM[(e >> 6) * LDV + (e & 63)] = tile[e];
+  {
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = tile[tid + 256 * i];   // all loads in flight first
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = tid + 256 * i;
+      sM[(e >> 6) * LDV + (e & 63)] = v[i];
+    }
+  }
   if (tid < TS) {
     xI[tid] = xb[s.b_off + (int64_t)t.i * TS + tid];
     xJ[tid] = xb[s.b_off + (int64_t)t.j * TS + tid];
@@ -313,23 +322,29 @@ __global__ void k_add_modes(int64_t NF, const int32_t* __restrict__ f_sub, const
   u[p] += acc;
 }
 
-// Lumped preconditioner: yb = K_bb xb (sparse rows of the local stiffness).
-__global__ void k_lumped(int64_t NB, const int64_t* __restrict__ b2full, const int32_t* __restrict__ b_sub,
-                         const SubInfo* __restrict__ subs, const int32_t* __restrict__ ell_col,
-                         const double* __restrict__ ell_val, const double* __restrict__ xb,
+// Lumped preconditioner: yb = K_bb xb with the interface-interface block of
+// every local stiffness stored slot-major (consecutive interface DOFs coalesce).
+__global__ void k_lumped(int64_t NB, int w_bb, const int32_t* __restrict__ bb_col,
+                         const double* __restrict__ bb_val, const double* __restrict__ xb,
                          double* __restrict__ yb, const PcgState* st) {
   if (halted(st)) return;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= NB) return;
-  const SubInfo s = subs[b_sub[b]];
-  const int64_t row = b2full[b];
-  const int bstart = s.nt_i * TS;
   double acc = 0.0;
-  for (int k = 0; k < ELLW; ++k) {
-    const int c = ell_col[row * ELLW + k];
-    if (c >= bstart) acc += ell_val[row * ELLW + k] * xb[s.b_off + (c - bstart)];
-  }
+  for (int k = 0; k < w_bb; ++k) acc += bb_val[k * NB + b] * xb[bb_col[k * NB + b]];
   yb[b] = acc;
+}
+
+// K_bb values from the assembled rows (after every factorisation).
+__global__ void k_bb_fill(int64_t NB, int64_t NF, int w_bb, const int32_t* __restrict__ bb_slot,
+                          const int64_t* __restrict__ b2full, const double* __restrict__ ell_val,
+                          double* __restrict__ bb_val) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NB * w_bb) return;
+  const int64_t b = t % NB;
+  const int k = (int)(t / NB);
+  const int sl = bb_slot[t];
+  bb_val[t] = sl >= 0 ? ell_val[(int64_t)sl * NF + b2full[b]] : 0.0;
 }
 
 __global__ void k_copy_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ full,
@@ -407,101 +422,327 @@ __global__ void k_init_state(PcgState* st, double rtol, double atol, int max_it,
 }
 
 // ---------------------------------------------------------------------------
-// Local generalised inverse z = K^+ g on the full local vector of each
-// subdomain (block formula of the interior-first elimination):
-//   w_I = L_II^{-1} g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,
-//   z_I = L_II^{-T} (w_I - L_bI^T z_b).
-// One workgroup per subdomain; tile products read coalesced columns.
-template <typename T>
-__device__ void tile_mv(const T* __restrict__ A, const double* x, double* y_acc, double* red, bool trans,
-                        double sgn) {
-  // y_acc[64] += sgn * op(A) x, A column-major 64x64.
-  const int tid = threadIdx.x;
-  double s = 0.0;
-  if (!trans) {
-    const int r = tid & 63, q = tid >> 6;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) s += (double)A[(16 * q + k) * TS + r] * x[16 * q + k];
-    red[q * TS + r] = s;
-  } else {
-    const int c = tid >> 2, q = tid & 3;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) s += (double)A[c * TS + 16 * q + k] * x[16 * q + k];
-    red[q * TS + c] = s;
+// Fused kernels of one PCG iteration (section 4.3 CG on P^T F with the
+// projection P = I - G Q^{-1} G^T).  The search direction s = z + beta s is
+// formed on the fly where it is read and written back by the per-row kernel
+// that owns each multiplier; the dot products finish in the last workgroup to
+// arrive (fixed partition and summation order, so results are deterministic).
+
+// last-arriving block of a grid: thread 0 publishes the block's partial sums,
+// fences and takes a ticket; the block that draws the last ticket reduces.
+__device__ bool last_block(int* ticket) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int t = atomicAdd(ticket, 1);
+    last = (t == (int)gridDim.x - 1);
   }
   __syncthreads();
-  if (tid < TS) {
-    if (!trans)
-      y_acc[tid] += sgn * (red[tid] + red[TS + tid] + red[2 * TS + tid] + red[3 * TS + tid]);
-    else
-      y_acc[tid] += sgn * (red[tid] + red[TS + tid] + red[2 * TS + tid] + red[3 * TS + tid]);
-  }
-  __syncthreads();
+  if (last) __threadfence();
+  return last;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of a and b over a 256-thread block (fixed order); result valid in every thread.
+__device__ void block_reduce2(double& a, double& b, double* ra, double* rb) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    ra[w] = a;
+    rb[w] = b;
+  }
+  __syncthreads();
+  a = (ra[0] + ra[1]) + (ra[2] + ra[3]);
+  b = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+}
+
+// xb = B^T (z + beta s)
+__global__ void k_gather_s(int64_t NB, const int32_t* __restrict__ g_ptr, const int32_t* __restrict__ g_row,
+                           const double* __restrict__ g_coef, const double* __restrict__ z,
+                           const double* __restrict__ sv, double* __restrict__ xb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const double beta = st->beta;
+  double acc = 0.0;
+  for (int k = g_ptr[b]; k < g_ptr[b + 1]; ++k) {
+    const int r = g_row[k];
+    acc += g_coef[k] * (z[r] + beta * sv[r]);
+  }
+  xb[b] = acc;
+}
+
+// q = B yb ; s <- z + beta s ; alpha = rho / (s.q)  (breakdown if s.q <= 0)
+__global__ __launch_bounds__(256) void k_scatter_dot_alpha(
+    int64_t n, const int64_t* __restrict__ b0, const double* __restrict__ c0, const int64_t* __restrict__ b1,
+    const double* __restrict__ c1, const double* __restrict__ yb, const double* __restrict__ z, double* sv,
+    double* q, double* part, int* ticket, PcgState* st) {
+  if (st->done) return;
+  __shared__ double ra[256], rb[256];
+  double acc = 0.0, unused = 0.0;
+  const double beta = st->beta;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+    double v = c0[r] * yb[b0[r]];
+    if (b1[r] >= 0) v += c1[r] * yb[b1[r]];
+    const double sn = z[r] + beta * sv[r];
+    sv[r] = sn;
+    q[r] = v;
+    acc += sn * v;
+  }
+  block_reduce2(acc, unused, ra, rb);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (!last_block(ticket)) return;
+  double pq = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += 256) pq += part[k];
+  block_reduce2(pq, unused, ra, rb);
+  if (threadIdx.x == 0) {
+    *ticket = 0;
+    st->pq = pq;
+    if (!(pq > 0.0)) {
+      st->alpha = 0.0;
+      st->done = 1;
+      st->status = FETI_EBREAKDOWN;
+    } else {
+      st->alpha = st->rho / pq;
+    }
+  }
+}
+
+// Partial g = Rb^T B^T x per floating subdomain, in GT_CHUNKS chunks of its
+// interface (gpart[chunk][coarse index]); with_update: x is r - alpha q
+// (formed on the fly).
+constexpr int GT_CHUNKS = 4;
+__global__ __launch_bounds__(256) void k_proj_gt(const SubInfo* __restrict__ subs, const int32_t* __restrict__ g_ptr,
+                                                 const int32_t* __restrict__ g_row, const double* __restrict__ g_coef,
+                                                 const double* __restrict__ rbv, const double* __restrict__ x,
+                                                 const double* __restrict__ q, int with_update, double* gpart,
+                                                 int ldg, const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ double red[6][4];
+  const SubInfo s = subs[blockIdx.y];
+  if (s.n_modes == 0) return;
+  const double alpha = with_update ? st->alpha : 0.0;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t nb = (int64_t)s.nt_b * TS;
+  const int64_t lo = nb * blockIdx.x / GT_CHUNKS, hi = nb * (blockIdx.x + 1) / GT_CHUNKS;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
+    const int64_t b = s.b_off + k;
+    double xv = 0.0;
+    for (int e = g_ptr[b]; e < g_ptr[b + 1]; ++e) {
+      const int r = g_row[e];
+      xv += g_coef[e] * (with_update ? x[r] - alpha * q[r] : x[r]);
+    }
+    const double* R = rbv + b * 6;
+    for (int m = 0; m < 6; ++m) acc[m] += R[m] * xv;
+  }
+  for (int m = 0; m < 6; ++m) acc[m] = wave_sum(acc[m]);
+  if ((threadIdx.x & 63) == 0)
+    for (int m = 0; m < 6; ++m) red[m][threadIdx.x >> 6] = acc[m];
+  __syncthreads();
+  if (threadIdx.x < s.n_modes) {
+    const int m = threadIdx.x;
+    gpart[(int64_t)blockIdx.x * ldg + s.coarse_off + m] = (red[m][0] + red[m][1]) + (red[m][2] + red[m][3]);
+  }
+}
+
+// alpha_c = Qinv g with the dense symmetric inverse (column-major, leading dim
+// ld); g is summed from its GT_CHUNKS partials.  16 rows per block, the
+// columns split 16 ways and reduced in a fixed order.
+__global__ __launch_bounds__(256) void k_coarse_dense(int nc, int ld, const double* __restrict__ Qi,
+                                                      const double* __restrict__ gpart, int ldg,
+                                                      double* __restrict__ a, const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ double red[16][17];
+  const int rl = threadIdx.x & 15, cq = threadIdx.x >> 4;
+  const int row = blockIdx.x * 16 + rl;
+  double acc = 0.0;
+  if (row < nc)
+    for (int j = cq; j < nc; j += 16) {
+      double g = 0.0;
+      for (int c = 0; c < GT_CHUNKS; ++c) g += gpart[(int64_t)c * ldg + j];
+      acc += Qi[(int64_t)j * ld + row] * g;
+    }
+  red[cq][rl] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16 && row < nc) {
+    double v = 0.0;
+    for (int k = 0; k < 16; ++k) v += red[k][threadIdx.x];
+    a[row] = v;
+  }
+}
+
+// (G a)_r contribution of one row entry: Rb[b] . a[coarse block of b's subdomain]
+__device__ __forceinline__ double g_alpha(int64_t b, const int32_t* bco, const double* rbv, const double* ac) {
+  const int co = bco[b];
+  if (co < 0) return 0.0;
+  const int nm = co & 7, off = co >> 3;
+  double v = 0.0;
+  for (int m = 0; m < nm; ++m) v += rbv[b * 6 + m] * ac[off + m];
+  return v;
+}
+
+// bco[b] = coarse_off << 3 | n_modes of b's subdomain, or -1 without kernel
+__global__ void k_fill_bco(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
+                           int32_t* bco) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  bco[b] = s.n_modes > 0 ? ((s.coarse_off << 3) | s.n_modes) : -1;
+}
+
+// Per multiplier row:
+//  mode 0: out = x - G ac
+//  mode 1: r <- r - alpha q, lam <- lam + alpha s, out = r - G ac
+//  mode 2: out = x - G ac, then rho' = w.out, ||w||, beta, convergence (init: first evaluation)
+__global__ __launch_bounds__(256) void k_proj_apply(
+    int mode, int init, int64_t n, int coarse, const int64_t* __restrict__ b0, const double* __restrict__ c0,
+    const int64_t* __restrict__ b1, const double* __restrict__ c1, const int32_t* __restrict__ bco,
+    const double* __restrict__ rbv, const double* __restrict__ ac, double* x,
+    const double* __restrict__ q, const double* __restrict__ sv, double* lam, double* out,
+    const double* __restrict__ w, double* part, int* ticket, PcgState* st, double* hist) {
+  if (st->done) return;
+  __shared__ double ra[256], rb[256];
+  const double alpha = mode == 1 ? st->alpha : 0.0;
+  double d1 = 0.0, d2 = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+    double xr = x[r];
+    if (mode == 1) {
+      xr -= alpha * q[r];
+      x[r] = xr;
+      lam[r] += alpha * sv[r];
+    }
+    double ga = 0.0;
+    if (coarse) {
+      ga = c0[r] * g_alpha(b0[r], bco, rbv, ac);
+      if (b1[r] >= 0) ga += c1[r] * g_alpha(b1[r], bco, rbv, ac);
+    }
+    const double o = xr - ga;
+    out[r] = o;
+    if (mode == 2) {
+      d1 += w[r] * o;
+      d2 += w[r] * w[r];
+    }
+  }
+  if (mode != 2) return;
+  block_reduce2(d1, d2, ra, rb);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = d1;
+    part[2 * blockIdx.x + 1] = d2;
+  }
+  if (!last_block(ticket)) return;
+  double wz = 0.0, ww = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += 256) {
+    wz += part[2 * k];
+    ww += part[2 * k + 1];
+  }
+  block_reduce2(wz, ww, ra, rb);
+  if (threadIdx.x == 0) {
+    *ticket = 0;
+    const double wn = sqrt(ww);
+    if (init) {
+      st->rho = wz;
+      st->w0 = wn;
+      st->wn = wn;
+      st->beta = 0.0;
+      st->it = 0;
+      if (!(wn > st->atol)) { st->done = 1; st->status = FETI_OK; }
+    } else {
+      const int it = st->it;
+      if (hist && it < st->hist_cap) {
+        hist[2 * it] = st->alpha;
+        hist[2 * it + 1] = wz / st->rho;
+      }
+      st->beta = wz / st->rho;
+      st->rho = wz;
+      st->wn = wn;
+      st->it = it + 1;
+      if (wn <= st->rtol * st->w0 || !(wn > st->atol)) {
+        st->done = 1;
+        st->status = FETI_OK;
+      } else if (st->it >= st->max_it) {
+        st->done = 1;
+        st->status = FETI_ENOCONV;
+      }
+    }
+  }
+}
+
+// Dense column-major copy of a symmetric matrix stored as lower tiles (coarse inverse).
+__global__ void k_tiles_to_dense(int nc, int ld, const double* __restrict__ tiles, double* __restrict__ D) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nc * nc) return;
+  const int i = (int)(t % nc), j = (int)(t / nc);
+  const int hi = i > j ? i : j, lo = i > j ? j : i;
+  D[(int64_t)j * ld + i] = tiles[tidx2(hi / TS, lo / TS) * TS2 + (lo % TS) * TS + (hi % TS)];
+}
+
+// ---------------------------------------------------------------------------
+// Local generalised inverse z = K^+ g on the full local vector of each
+// subdomain, by the block formula of the interior-first elimination with the
+// explicit inverse Wi = L_II^{-1} of the interior factor:
+//   w_I = Wi g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,  t_I = w_I - L_bI^T z_b,
+//   z_I = Wi^T t_I.
+// Each launch runs one workgroup per (tile row or column, subdomain); tile
+// reads are coalesced columns and each workgroup reduces once at the end.
+//   mode 0: y_I = sum_{J<=I} Wi(I,J) x_J                 (rows I < nt_i)
+//   mode 1: yb_I = base_b - sum_{J<nt_i} L(nt_i+I, J) x_J   (rows I < nt_b)
+//   mode 2: y_I = base_I - sum_{J<nt_b} L(nt_i+J, I)^T xb_J (cols I < nt_i)
+//   mode 3: y_I = sum_{J>=I} Wi(J,I)^T x_J               (cols I < nt_i)
 template <typename T>
-__global__ __launch_bounds__(256) void k_kpinv(const SubInfo* __restrict__ subs, const T* __restrict__ arena,
-                                               const T* __restrict__ linv, const T* __restrict__ X,
-                                               const double* __restrict__ g, double* z, double* w) {
-  __shared__ double red[4 * TS];
-  __shared__ double acc[TS], xv[TS];
-  const SubInfo s = subs[blockIdx.x];
-  const T* L = arena + s.tile_off;
+__global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __restrict__ subs,
+                                                  const T* __restrict__ arena, const T* __restrict__ Wi,
+                                                  const double* __restrict__ x, const double* __restrict__ xb,
+                                                  const double* __restrict__ base, double* y, double* yb) {
+  __shared__ double red[4][TS];
+  const SubInfo s = subs[blockIdx.y];
+  const int I = blockIdx.x;
+  if (I >= (mode == 1 ? s.nt_b : s.nt_i)) return;
   const int tid = threadIdx.x;
-  const double* gs = g + s.full_off;
-  double* ws = w + s.full_off;
-  double* zs = z + s.full_off;
-  // forward over the interior, and interface right-hand side
-  for (int I = 0; I < s.nt; ++I) {
-    if (tid < TS) acc[tid] = gs[I * TS + tid];
-    __syncthreads();
-    for (int J = 0; J < (I < s.nt_i ? I : s.nt_i); ++J) {
-      if (tid < TS) xv[tid] = ws[J * TS + tid];
-      __syncthreads();
-      tile_mv(L + tidx2(I, J) * TS2, xv, acc, red, false, -1.0);
+  const bool trans = mode >= 2;
+  const int a = trans ? (tid >> 2) : (tid & 63);   // output row/column handled
+  const int q = trans ? (tid & 3) : (tid >> 6);     // quarter of the reduction index
+  double acc = 0.0;
+  int j0, j1;
+  if (mode == 0) { j0 = 0; j1 = I + 1; }
+  else if (mode == 1) { j0 = 0; j1 = s.nt_i; }
+  else if (mode == 2) { j0 = 0; j1 = s.nt_b; }
+  else { j0 = I; j1 = s.nt_i; }
+  for (int J = j0; J < j1; ++J) {
+    const T* tile;
+    const double* xs;
+    if (mode == 0) { tile = Wi + s.wi_off + tidx2(I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
+    else if (mode == 1) { tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
+    else if (mode == 2) { tile = arena + s.tile_off + tidx2(s.nt_i + J, I) * TS2; xs = xb + s.b_off + (int64_t)J * TS; }
+    else { tile = Wi + s.wi_off + tidx2(J, I) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
+    if (!trans) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += (double)tile[(16 * q + k) * TS + a] * xs[16 * q + k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += (double)tile[a * TS + 16 * q + k] * xs[16 * q + k];
     }
-    if (I < s.nt_i) {
-      if (tid < TS) xv[tid] = acc[tid];
-      __syncthreads();
-      if (tid < TS) acc[tid] = 0.0;
-      __syncthreads();
-      tile_mv(linv + s.linv_off + (int64_t)I * TS2, xv, acc, red, false, 1.0);
-    }
-    if (tid < TS) ws[I * TS + tid] = acc[tid];
-    __syncthreads();
   }
-  // z_b = X w_b (symmetric, lower tiles stored)
-  for (int I = 0; I < s.nt_b; ++I) {
-    if (tid < TS) acc[tid] = 0.0;
-    __syncthreads();
-    for (int J = 0; J < s.nt_b; ++J) {
-      if (tid < TS) xv[tid] = ws[(s.nt_i + J) * TS + tid];
-      __syncthreads();
-      if (J <= I)
-        tile_mv(X + s.x_off + tidx2(I, J) * TS2, xv, acc, red, false, 1.0);
-      else
-        tile_mv(X + s.x_off + tidx2(J, I) * TS2, xv, acc, red, true, 1.0);
-    }
-    if (tid < TS) zs[(s.nt_i + I) * TS + tid] = acc[tid];
-    __syncthreads();
+  red[q][a] = acc;
+  __syncthreads();
+  if (tid < TS) {
+    const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (mode == 0 || mode == 3) y[s.full_off + (int64_t)I * TS + tid] = v;
+    else if (mode == 1) yb[s.b_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)(s.nt_i + I) * TS + tid] - v;
+    else y[s.full_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)I * TS + tid] - v;
   }
-  // backward over the interior
-  for (int I = s.nt_i - 1; I >= 0; --I) {
-    if (tid < TS) acc[tid] = ws[I * TS + tid];
-    __syncthreads();
-    for (int J = I + 1; J < s.nt; ++J) {
-      if (tid < TS) xv[tid] = zs[J * TS + tid];
-      __syncthreads();
-      tile_mv(L + tidx2(J, I) * TS2, xv, acc, red, true, -1.0);
-    }
-    if (tid < TS) xv[tid] = acc[tid];
-    __syncthreads();
-    if (tid < TS) acc[tid] = 0.0;
-    __syncthreads();
-    tile_mv(linv + s.linv_off + (int64_t)I * TS2, xv, acc, red, true, 1.0);
-    if (tid < TS) zs[I * TS + tid] = acc[tid];
-    __syncthreads();
-  }
+}
+
+// full[b2full[k]] = b[k]
+__global__ void k_set_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ b,
+                          double* full) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < NB) full[b2full[k]] = b[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -557,9 +798,13 @@ void pcg_add_modes(int64_t NF, const int32_t* f_sub, const SubInfo* subs, const 
                    double* u, hipStream_t s) {
   hipLaunchKernelGGL(k_add_modes, grid1(NF), dim3(256), 0, s, NF, f_sub, subs, rf, gamma, u);
 }
-void pcg_lumped(const DevIdx& d, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                const double* xb, double* yb, const PcgState* st, hipStream_t s) {
-  if (d.NB) hipLaunchKernelGGL(k_lumped, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, d.b_sub, subs, ell_col, ell_val, xb, yb, st);
+void pcg_lumped(const DevIdx& d, int w_bb, const int32_t* bb_col, const double* bb_val, const double* xb,
+                double* yb, const PcgState* st, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_lumped, grid1(d.NB), dim3(256), 0, s, d.NB, w_bb, bb_col, bb_val, xb, yb, st);
+}
+void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double* ell_val, double* bb_val,
+                 hipStream_t s) {
+  if (d.NB && w_bb) hipLaunchKernelGGL(k_bb_fill, grid1(d.NB * w_bb), dim3(256), 0, s, d.NB, d.NF, w_bb, bb_slot, d.b2full, ell_val, bb_val);
 }
 void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_copy_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, full, b);
@@ -590,12 +835,45 @@ void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipS
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, rtol, atol, max_it, hist_cap);
 }
-template <typename T>
-void local_kpinv(int n_sub, const SubInfo* subs, const T* arena, const T* linv, const T* X, const double* g,
-                 double* z, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_kpinv<T>, dim3(n_sub), dim3(256), 0, s, subs, arena, linv, X, g, z, w);
+constexpr int FUSE_BLOCKS = 256;
+void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,
+                  hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_gather_s, grid1(d.NB), dim3(256), 0, s, d.NB, d.g_ptr, d.g_row, d.g_coef, z, sv, xb, st);
 }
-template void local_kpinv<double>(int, const SubInfo*, const double*, const double*, const double*, const double*, double*, double*, hipStream_t);
-template void local_kpinv<float>(int, const SubInfo*, const float*, const float*, const float*, const double*, double*, double*, hipStream_t);
+void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
+                           int* ticket, PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_dot_alpha, dim3(FUSE_BLOCKS), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, yb, z, sv, q, part, ticket, st);
+}
+void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* rbv, const double* x,
+                 const double* q, int with_update, double* gpart, int ldg, const PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_proj_gt, dim3(GT_CHUNKS, n_sub), dim3(256), 0, s, subs, d.g_ptr, d.g_row, d.g_coef, rbv, x, q, with_update, gpart, ldg, st);
+}
+void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int ldg, double* a, const PcgState* st,
+                      hipStream_t s) {
+  if (nc) hipLaunchKernelGGL(k_coarse_dense, dim3((nc + 15) / 16), dim3(256), 0, s, nc, ld, Qi, gpart, ldg, a, st);
+}
+void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int32_t* bco, const double* rbv,
+                    const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
+                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, bco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist);
+}
+void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_fill_bco, grid1(d.NB), dim3(256), 0, s, d.NB, d.b_sub, subs, bco);
+}
+void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s) {
+  if (nc) hipLaunchKernelGGL(k_tiles_to_dense, grid1((int64_t)nc * nc), dim3(256), 0, s, nc, ld, tiles, D);
+}
+
+template <typename T>
+void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const T* arena, const T* Wi,
+                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s) {
+  if (max_rows > 0)
+    hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, arena, Wi, x, xb, base, y, yb);
+}
+template void local_kp_tiles<double>(int, int, int, const SubInfo*, const double*, const double*, const double*, const double*, const double*, double*, double*, hipStream_t);
+template void local_kp_tiles<float>(int, int, int, const SubInfo*, const float*, const float*, const double*, const double*, const double*, double*, double*, hipStream_t);
+void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s) {
+  if (d.NB) hipLaunchKernelGGL(k_set_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, full);
+}
 
 }  // namespace feti
