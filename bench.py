@@ -11,9 +11,19 @@ subdomains of 8^3 elements (2187 DOFs each), E = 1, nu per subdomain from
 U[0.25, 0.35] (seed 0), body force (0, 0, -1), u = 0 on the boundary,
 lumped preconditioner.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+The JSON line carries a roofline object for the dominant kernel (the one with
+the larger device time per solve among the dual-operator interface GEMV and
+the factor's tile update), timed live with HIP events on the library stream in
+a second timed pass of the same steps (PCG iterations launched one by one
+there, since events inside a replayed HIP graph cannot be timed), and the CPU
+oracle timed on the host.
+
+Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+  python bench.py --copy-calibration     # plain 1 GiB device copy (HBM counter scale)
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,56 +34,119 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per solve, used for the roofline line:
-# the dominant kernel is the batched left-looking tile update of the local
-# Cholesky factorisation (MFMA FP64 / FP32).
-
-
-def factor_flops(mesh_subs):
-    """Sum over subdomains of n^3/3 (dense Cholesky) + 2 n_b^3/3 (interface inverse)."""
-    tot = 0.0
-    for n, nb in mesh_subs:
-        tot += n ** 3 / 3.0 + 2.0 * nb ** 3 / 3.0
-    return tot
-
-
-def sub_sizes(mesh, variant="af"):
-    """(n_i, n_b) per subdomain, from the mesh (host-side counting only)."""
-    sizes = []
-    node_subs = {}
-    for e in range(mesh.n_elems):
-        pass
-    n_nodes = mesh.n_nodes
-    copies = np.zeros(n_nodes, dtype=np.int64)
-    sub_nodes = []
-    for s in range(mesh.n_sub):
-        nodes = np.unique(mesh.hex8[mesh.elem_sub == s])
-        sub_nodes.append(nodes)
-        copies[nodes] += 1
-    dmask = np.zeros(mesh.n_dofs, dtype=bool)
-    dmask[mesh.dir_dof] = True
-    dnode = dmask.reshape(-1, 3).any(axis=1)
-    for nodes in sub_nodes:
-        iface = (copies[nodes] > 1) | (dnode[nodes] if variant == "af" else False)
-        nb = 3 * int(iface.sum())
-        sizes.append((3 * len(nodes), nb))
-    return sizes
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # dense FP64 / FP32 matrix peaks
 
 
 def cpu_baseline(mesh, budget_s=20.0):
-    """Oracle (monolithic sparse direct FP64 solve) timed on the host."""
+    """The oracle (monolithic sparse direct FP64 solve) on the host, one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import monolithic
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        monolithic.solve_linear(mesh)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 20:
-            break
-    dt = (time.perf_counter() - t0) / n
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            monolithic.solve_linear(mesh)
+            n += 1
+            if time.perf_counter() - t0 > budget_s or n >= 20:
+                break
+        dt = (time.perf_counter() - t0) / n
     return dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{n} full monolithic solves of the same workload (assembly + SuperLU "
-                       f"factor + solve, single-threaded), {dt:.2f} s each")
+                sample=f"{n} complete monolithic solves of the benchmark workload (NumPy assembly, "
+                       f"SuperLU symmetric-mode factor and solve), {dt:.2f} s each")
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, launches_bytes):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    try:
+        rec = json.load(open(f)).get(kernel)
+        if not rec:
+            return None
+        src = os.path.join(ROOT, rec["source"])
+        if source_sha(src) != rec["source_sha"]:
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 27   # 128 Mi doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
+
+
+def run(args, precision, profile=True):
+    import torch
+    from workloads import config_mesh
+    from paper_1508_02599_amd.feti import Problem
+
+    mesh = config_mesh(args.config)
+    p = Problem(mesh, variant=args.variant, precond=args.precond, precision=precision, rtol=1e-8,
+                device_ptrs=True, profile=profile)
+    u = torch.empty(mesh.n_dofs, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        p.factor()
+        p.solve(out=u)
+    torch.cuda.synchronize()
+    lat, st_all = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        p.factor()
+        _, st = p.solve(out=u)
+        lat.append(time.perf_counter() - a)
+        st_all.append(st)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    # PCG-only throughput with the factors resident
+    p.factor()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        p.solve(out=u)
+    torch.cuda.synchronize()
+    pcg_total = time.perf_counter() - t1
+    p.close()
+    return mesh, total, pcg_total, lat, st_all
+
+
+def roofline(st_all, precision):
+    """Roofline of the dominant kernel from the live HIP-event timings."""
+    g_ms = np.mean([s["kernel_gemv_ms"] for s in st_all])
+    g_n = np.mean([s["kernel_gemv_launches"] for s in st_all])
+    u_ms = np.mean([s["kernel_update_ms"] for s in st_all])
+    u_n = np.mean([s["kernel_update_launches"] for s in st_all])
+    gemv = {"kernel": "k_symv_tiles", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "achieved": st_all[-1]["gemv_bytes"] / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None,
+            "avg_launch_ms": g_ms, "launches_per_solve": g_n,
+            "algorithmic_bytes_per_launch": st_all[-1]["gemv_bytes"]}
+    upd = {"kernel": "k_update", "bound": "mfma", "unit": "TFLOP/s",
+           "peak": MFMA_PEAK_TFLOPS[precision],
+           "achieved": st_all[-1]["update_flops"] / max(u_n, 1) / (u_ms * 1e-3) / 1e12 if u_ms > 0 else None,
+           "avg_launch_ms": u_ms, "launches_per_solve": u_n,
+           "algorithmic_flops_per_launch": st_all[-1]["update_flops"] / max(u_n, 1)}
+    for r in (gemv, upd):
+        r["frac"] = r["achieved"] / r["peak"] if r["achieved"] else None
+        r["device_ms_per_solve"] = r["avg_launch_ms"] * r["launches_per_solve"]
+    dom, other = (gemv, upd) if gemv["device_ms_per_solve"] >= upd["device_ms_per_solve"] else (upd, gemv)
+    t = traffic_from_profiles(dom["kernel"] + ("_f32" if precision == "mixed" else ""), None)
+    dom["traffic"] = t
+    return dom, other
 
 
 def main():
@@ -86,49 +159,27 @@ def main():
     ap.add_argument("--precond", default="lumped")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
+              "the method is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
     import torch
-    from workloads import config_mesh
-    from paper_1508_02599_amd.feti import Problem
-
     torch.cuda.set_device(0)
-    mesh = config_mesh(args.config)
-    stream = torch.cuda.current_stream()
-    p = Problem(mesh, variant=args.variant, precond=args.precond, precision=args.precision,
-                rtol=1e-8, device_ptrs=True, hip_stream=stream.cuda_stream)
-    u = torch.empty(mesh.n_dofs, dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
-        p.factor()
-        p.solve(out=u)
-    torch.cuda.synchronize()
-    lat = []
-    stats = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        p.factor()
-        _, stats = p.solve(out=u)
-        lat.append(time.perf_counter() - a)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    # PCG-only throughput with the factors resident
-    p.factor()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        p.solve(out=u)
-    torch.cuda.synchronize()
-    pcg_total = time.perf_counter() - t1
-    value = args.steps / total
-    sizes = sub_sizes(mesh, args.variant)
-    fl = factor_flops(sizes)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    mesh, total, pcg_total, lat, st_all = run(args, args.precision, profile=False)
+    st = st_all[-1]
+    # roofline pass: same workload, events around the dominant kernels' launches
+    _, ptotal, _, _, pst = run(args, args.precision, profile=True)
+    dom, other = roofline(pst, args.precision)
+    dom["profiled_pass_ms_per_step"] = 1e3 * ptotal / args.steps
     line = {
         "metric": "FETI PCG solves/s at 1e-8 residual (FP64 vs mixed); p50/p99 solve latency",
-        "value": value,
+        "value": args.steps / total,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -139,16 +190,36 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-local/f64-global",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: unit cube 32^3 Q1, 4x4x4 subdomains of 8^3 elements "
-                               f"(2187 DOFs each), {args.variant}, {args.precond}, rtol 1e-8",
-                   "subdomains": mesh.n_sub, "global_dofs": mesh.n_dofs},
+        "config": {"workload": f"{args.config}: unit cube 32^3 Q1 elements in 4x4x4 "
+                               f"{'all-floating' if args.variant == 'af' else 'classical'} subdomains "
+                               f"of 8^3 elements (2187 DOFs each), nu per subdomain ~ U[0.25,0.35] "
+                               f"(seed 0), {args.precond} preconditioner, rtol 1e-8",
+                   "subdomains": mesh.n_sub, "global_dofs": mesh.n_dofs,
+                   "multipliers": st["n_lambda"], "coarse_dim": st["n_coarse"]},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "pcg_only_solves_per_s": args.steps / pcg_total,
-        "iters": stats["iters"],
-        "phase_s": {k: stats[k] for k in ("t_assemble", "t_factor", "t_pcg", "t_total")},
-        "factor_flops": fl,
+        "iters": st["iters"],
+        "phase_ms": {k: 1e3 * st[k] for k in ("t_assemble", "t_factor", "t_pcg")},
+        "roofline": {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_kernel": {k: v for k, v in dom.items()
+                            if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_secondary": other,
     }
+    if args.precision == "fp64" and not args.no_mixed:
+        try:
+            _, tm, pm, lm, sm = run(args, "mixed", profile=False)
+            _, _, _, _, smp = run(args, "mixed", profile=True)
+            d2, o2 = roofline(smp, "mixed")
+            line["mixed"] = {"value": args.steps / tm, "unit": "solves/s",
+                             "latency_ms": {"p50": 1e3 * float(np.percentile(lm, 50)),
+                                            "p99": 1e3 * float(np.percentile(lm, 99))},
+                             "pcg_only_solves_per_s": args.steps / pm, "iters": sm[-1]["iters"],
+                             "ir_sweeps": sm[-1]["ir_sweeps"],
+                             "phase_ms": {k: 1e3 * sm[-1][k] for k in ("t_assemble", "t_factor", "t_pcg")},
+                             "roofline": d2, "roofline_secondary": o2}
+        except Exception as e:   # mixed precision reported as unavailable, never as a number
+            line["mixed"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh)
     print(json.dumps(line))

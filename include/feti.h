@@ -108,6 +108,8 @@ typedef struct {
 } feti_mesh;
 
 #define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */
+#define FETI_PROFILE 0x2ull     /* time the dual-operator GEMV and factor-update launches with
+                                   HIP events (reported in feti_stats.kernel_*)              */
 
 typedef struct {
   feti_variant variant;
@@ -117,7 +119,7 @@ typedef struct {
   int32_t max_it;              /* PCG iteration cap (0 => 1000)                           */
   double ir_tol;               /* mixed: relative FP64 residual target of the outer
                                   refinement (0 => 1e-10)                                 */
-  int32_t ir_max;              /* mixed: max refinement sweeps (0 => 6)                   */
+  int32_t ir_max;              /* mixed: max correction sweeps (negative => 6)            */
   int32_t graph_block;         /* PCG iterations captured per HIP graph (0 => 8)          */
   void* hip_stream;            /* hipStream_t to run on, or NULL for a library stream    */
   void* (*dev_alloc)(size_t bytes, void* stream, void* ctx);   /* optional allocator     */
@@ -136,6 +138,13 @@ typedef struct {
   double kappa_est;            /* Lanczos estimate of the preconditioned condition number */
   double t_assemble, t_factor, t_pcg, t_total;   /* seconds, from HIP events              */
   size_t device_bytes;         /* device memory held by the problem                       */
+  /* with FETI_PROFILE: launches and mean duration (ms, HIP events on the problem's
+     stream) of the interface GEMV of F (per PCG iteration) and of the factor's
+     tile-update kernel, since the last feti_factor; algorithmic bytes of one GEMV
+     launch and flops of all update launches of one factorisation */
+  int32_t kernel_gemv_launches, kernel_update_launches;
+  double kernel_gemv_ms, kernel_update_ms;
+  double gemv_bytes, update_flops;
 } feti_stats;
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */

@@ -87,6 +87,7 @@ struct feti_problem {
   double *d_tv = nullptr, *d_d = nullptr, *d_bv = nullptr;
   double *d_cg = nullptr, *d_calpha = nullptr, *d_gamma = nullptr, *d_e = nullptr;
   double *d_dvals = nullptr, *d_out = nullptr, *d_dots = nullptr, *d_hist = nullptr;
+  double *d_f0 = nullptr, *d_uglob = nullptr, *d_zero = nullptr;
   PcgState* d_state = nullptr;
   int* d_ticket = nullptr;
   double *d_fpart = nullptr, *d_qdense = nullptr, *d_gpart = nullptr;
@@ -97,6 +98,13 @@ struct feti_problem {
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   hipEvent_t ev[6] = {};
+  // FETI_PROFILE: event pairs around the F GEMV of every captured iteration and
+  // around every factor-update launch
+  bool profile = false;
+  std::vector<hipEvent_t> ev_gemv, ev_upd;
+  int n_upd_recorded = 0;
+  double prof_gemv_ms = 0.0, prof_upd_ms = 0.0, upd_flops = 0.0, gemv_bytes = 0.0;
+  int prof_gemv_n = 0, prof_upd_n = 0;
 };
 
 namespace {
@@ -154,12 +162,16 @@ size_t elt(const feti_problem* p) { return p->P.mixed ? sizeof(float) : sizeof(d
 // Dense launches on the subdomain batch in the working precision.
 void dense(feti_problem* p, const HostPlan::Launch& L) {
   const Task* t = p->d_tasks + L.first;
+  const bool timed = p->profile && L.kind == K_UPDATE && L.count > 0 &&
+                     2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
+  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], p->stream);
   if (p->P.mixed)
     launch_dense<float>(L.kind, t, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)p->d_W,
                         (float*)p->d_X, p->d_err, p->stream);
   else
     launch_dense<double>(L.kind, t, L.count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv,
                          (double*)p->d_W, (double*)p->d_X, p->d_err, p->stream);
+  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], p->stream);
 }
 
 void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st) {
@@ -239,10 +251,12 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
 // One PCG iteration (six to seven launches, all scalars on the device):
 //   q = F s (s = z + beta s formed on the fly), alpha;  r -= alpha q,
 //   lambda += alpha s, w = P r;  t = M^{-1} w;  z = P t, beta and the test.
-void pcg_iteration(feti_problem* p) {
+void pcg_iteration(feti_problem* p, int slot) {
   PcgState* st = p->d_state;
   pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, p->stream);
+  if (p->profile) (void)hipEventRecord(p->ev_gemv[2 * slot], p->stream);
   symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
+  if (p->profile) (void)hipEventRecord(p->ev_gemv[2 * slot + 1], p->stream);
   pcg_scatter_dot_alpha(p->di, p->d_yb, p->d_zv, p->d_s, p->d_q, p->d_fpart, p->d_ticket, st, p->stream);
   project_fused(p, 1, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
   precondition(p, p->d_wv, p->d_tv, st);
@@ -455,6 +469,12 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bv, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
+  if (P.mixed) {
+    TRY(dalloc(p, p->d_f0, (size_t)P.NF));
+    TRY(dalloc(p, p->d_uglob, (size_t)P.n_dof));
+    TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
+    vec_fill(P.n_dof, 0.0, p->d_zero, p->stream);
+  }
   TRY(dalloc(p, p->d_dots, 2 * DOT_PARTS));
   p->hist_cap = std::max(1, p->opt.max_it);
   TRY(dalloc(p, p->d_hist, 2 * (size_t)p->hist_cap));
@@ -467,6 +487,41 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_gpart, (size_t)4 * max_coarse));
   TRY(dalloc(p, p->d_bco, (size_t)P.NB));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
+  p->profile = (p->opt.flags & FETI_PROFILE) != 0;
+  if (p->profile) {
+    p->ev_gemv.resize(2 * 64);
+    for (auto& ev : p->ev_gemv) HIPCHK(hipEventCreate(&ev));
+    p->ev_upd.resize(2 * (P.sched_interior.size() + P.sched_iface.size() + 2));
+    for (auto& ev : p->ev_upd) HIPCHK(hipEventCreate(&ev));
+  }
+  // algorithmic work: bytes of the packed symmetric interface inverses read by
+  // one GEMV, and flops of the tile updates counted on real (unpadded) rows,
+  // lower triangle only for diagonal tiles
+  {
+    const double es = (double)elt(p);
+    double bytes = 0.0, fl = 0.0;
+    for (const auto& si : P.sub) bytes += 0.5 * si.n_b * (si.n_b + 1.0) * es;
+    auto real = [&](const SubInfo& si, int t) -> double {
+      if (t < si.nt_i) return std::min(TS, si.n_ii - t * TS);
+      return std::min(TS, si.n_b - (t - si.nt_i) * TS);
+    };
+    auto add = [&](const HostPlan::Launch& L) {
+      if (L.kind != K_UPDATE) return;
+      for (int k = 0; k < L.count; ++k) {
+        const Task& t = P.tasks[L.first + k];
+        const SubInfo& si = P.sub[t.sub];
+        double inner = 0.0;
+        for (int q = t.k0; q < t.k1; ++q) inner += real(si, q);
+        const double ri = real(si, t.i), rj = real(si, t.j);
+        fl += (t.i == t.j ? ri * (ri + 1.0) : 2.0 * ri * rj) * inner;
+      }
+    };
+    for (const auto& L : P.sched_interior) add(L);
+    for (const auto& L : P.sched_iface) add(L);
+    add(P.sched_schur);
+    p->gemv_bytes = bytes;
+    p->upd_flops = fl;
+  }
   HIPCHK(hipStreamSynchronize(p->stream));
   return FETI_OK;
 }
@@ -547,6 +602,11 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
   fill_bco(p->di, p->d_sub, p->d_bco, st);
   // batched factorisation
+  p->n_upd_recorded = 0;
+  p->prof_upd_ms = 0.0;
+  p->prof_upd_n = 0;
+  p->prof_gemv_ms = 0.0;
+  p->prof_gemv_n = 0;
   const int big = 0x7fffffff;
   HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
   for (const auto& L : P.sched_interior) dense(p, L);
@@ -641,6 +701,15 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   int errs[2] = {0x7fffffff, 0x7fffffff};
   HIPCHK(hipMemcpyAsync(errs, p->d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < p->n_upd_recorded; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev_upd[2 * k], p->ev_upd[2 * k + 1]) == hipSuccess) {
+      p->prof_upd_ms += ms;
+      p->prof_upd_n++;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
   if (errs[0] != 0x7fffffff) {
     p->err = "non-positive pivot in the local factor of subdomain " + std::to_string(errs[0]);
     p->factored = false;
@@ -656,12 +725,14 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
 }
 
 // Dual solve for the local right-hand sides already in d_f and the Dirichlet
-// data in d_dvals; writes the local displacements to d_u.
-feti_status solve_core(feti_problem* p, feti_stats* stats) {
+// data in d_dvals; writes the local displacements to d_u.  A correction solve
+// (first = false) leaves the start event of the PCG phase where the first
+// solve put it.
+feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool first = true) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
   const int64_t n = P.n_lam;
-  HIPCHK(hipEventRecord(p->ev[3], st));
+  if (first) HIPCHK(hipEventRecord(p->ev[3], st));
   // e = R^T f ; d = B K^+ f - b
   if (p->n_coarse) pcg_coarse_gt_full(P.n_sub, p->d_sub, p->d_rfull, p->d_f, p->d_e, st);
   kpinv(p, p->d_f, p->d_z);
@@ -682,32 +753,59 @@ feti_status solve_core(feti_problem* p, feti_stats* stats) {
     }
     // r = d - F lambda ; w = P r ; z = P M w ; s = z
     apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
-    pcg_init_state(p->d_state, p->opt.rtol, 0.0, p->opt.max_it, p->hist_cap, st);
+    pcg_init_state(p->d_state, rtol, 0.0, p->opt.max_it, p->hist_cap, st);
     vec_fill(n, 0.0, p->d_s, st);   // s = z + 0 s in the first iteration
     project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->d_state, nullptr);
     precondition(p, p->d_wv, p->d_tv, p->d_state);
     project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->d_state, nullptr);
     // graph of graph_block iterations
     const int gb = std::max(1, p->opt.graph_block);
-    if (!p->graph || p->graph_iters != gb) {
+    if (!p->profile && (!p->graph || p->graph_iters != gb)) {
       if (p->graph) {
         (void)hipGraphExecDestroy(p->graph);
         p->graph = nullptr;
       }
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < gb; ++k) pcg_iteration(p);
+      for (int k = 0; k < gb; ++k) pcg_iteration(p, k);
       HIPCHK(hipStreamEndCapture(st, &gr));
       HIPCHK(hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0));
       (void)hipGraphDestroy(gr);
       p->graph_iters = gb;
     }
     PcgState hs{};
+    int it_before = 0;
+    bool replayed = false;
     for (;;) {
       HIPCHK(hipMemcpyAsync(&hs, p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      if (p->profile && replayed) {
+        // iterations that ran in this replay: it advanced, plus the one that set done
+        // the GEMV ran in every iteration that advanced the count, and in one
+        // that stopped at a breakdown before advancing it
+        int ran = hs.it - it_before + (hs.status == FETI_EBREAKDOWN ? 1 : 0);
+        ran = std::min(ran, gb);
+        for (int k = 0; k < ran; ++k) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, p->ev_gemv[2 * k], p->ev_gemv[2 * k + 1]) == hipSuccess) {
+            p->prof_gemv_ms += ms;
+            p->prof_gemv_n++;
+          } else {
+            (void)hipGetLastError();
+          }
+        }
+      }
       if (hs.done) break;
-      HIPCHK(hipGraphLaunch(p->graph, st));
+      it_before = hs.it;
+      if (p->profile) {
+        // same kernels and launch configuration, launched one by one so that the
+        // events around the GEMV can be timed (events recorded inside a captured
+        // graph cannot)
+        for (int k = 0; k < gb; ++k) pcg_iteration(p, k);
+      } else {
+        HIPCHK(hipGraphLaunch(p->graph, st));
+      }
+      replayed = true;
     }
     iters = hs.it;
     status = hs.status;
@@ -735,6 +833,12 @@ feti_status solve_core(feti_problem* p, feti_stats* stats) {
   }
   HIPCHK(hipEventRecord(p->ev[4], st));
   if (stats) {
+    stats->kernel_gemv_launches = p->prof_gemv_n;
+    stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
+    stats->kernel_update_launches = p->prof_upd_n;
+    stats->kernel_update_ms = p->prof_upd_n ? p->prof_upd_ms / p->prof_upd_n : 0.0;
+    stats->gemv_bytes = p->gemv_bytes;
+    stats->update_flops = p->upd_flops;
     stats->iters = iters;
     stats->converged = status == FETI_OK ? 1 : 0;
     stats->rel_res = rel;
@@ -754,10 +858,79 @@ feti_status solve_core(feti_problem* p, feti_stats* stats) {
   return FETI_OK;
 }
 
+// ||v||_2 of a device vector (deterministic partition, host finish).
+feti_status dev_norm(feti_problem* p, const double* v, int64_t n, double* out) {
+  pcg_dot(n, v, v, nullptr, nullptr, p->d_dots, nullptr, p->stream);
+  std::vector<double> parts(2 * DOT_PARTS);
+  HIPCHK(hipMemcpyAsync(parts.data(), p->d_dots, parts.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double s2 = 0.0;
+  for (int k = 0; k < DOT_PARTS; ++k) s2 += parts[2 * k];
+  *out = std::sqrt(s2);
+  return FETI_OK;
+}
+
+// Solve for the local right-hand sides in d_f and the Dirichlet data in
+// d_dvals; the global result goes to d_uglob (mixed) or stays in d_u.
+// FP64: one dual solve.  Mixed (FP32 local factors): iterative refinement on
+// the assembled problem -- the FP64 residual f - K u of the current global
+// displacement is computed from the FP64 sparse local stiffnesses and the
+// correction solves K du = r (zero Dirichlet data) with the FP32 factors, the
+// assembled r split evenly over the subdomain copies of each node (a torn
+// residual would carry the full interface forces into the correction, whose
+// dual error then scales with them rather than with r),
+// until ||r|| <= ir_tol ||f|| or ir_max corrections.
+feti_status solve_refined(feti_problem* p, feti_stats* stats) {
+  HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  feti_status s = solve_core(p, stats, p->opt.rtol);
+  if (!P.mixed || (s != FETI_OK && s != FETI_ENOCONV)) return s;
+  int iters = stats ? stats->iters : 0;
+  const int64_t nd = P.n_dof;
+  vec_axpby(P.NF, 1.0, p->d_f, 0.0, p->d_f0, st);
+  vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
+  double fnorm = 0.0, rnorm = 0.0;
+  vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
+  TRY(dev_norm(p, p->d_out, nd, &fnorm));
+  int sweeps = 0;
+  const double inner_rtol = std::max(p->opt.rtol, 1e-5);
+  for (;;) {
+    local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
+                   p->d_ell_val, p->d_dmask, p->d_uglob, p->d_f0, p->d_f, st);
+    vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
+    TRY(dev_norm(p, p->d_out, nd, &rnorm));
+    if (!(rnorm > p->opt.ir_tol * fnorm) || sweeps >= p->opt.ir_max) break;
+    // correction: the assembled residual, split evenly over the subdomain
+    // copies of each node, as loads; homogeneous Dirichlet data
+    vec_distribute(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->d_uc_ptr, p->d_dmask, p->d_out,
+                   p->d_f, st);
+    HIPCHK(hipMemcpyAsync(p->d_dvals, p->d_zero, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    feti_stats cs{};
+    s = solve_core(p, &cs, inner_rtol, false);
+    if (s != FETI_OK && s != FETI_ENOCONV) return s;
+    iters += cs.iters;
+    vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_zero, p->d_out, 0, st);
+    vec_axpby(nd, 1.0, p->d_out, 1.0, p->d_uglob, st);
+    ++sweeps;
+  }
+  if (stats) {
+    stats->iters = iters;
+    stats->ir_sweeps = sweeps;
+  }
+  if (!(rnorm <= p->opt.ir_tol * fnorm)) {
+    p->err = "mixed-precision refinement did not reach ir_tol within ir_max corrections";
+    return FETI_ENOCONV;
+  }
+  return FETI_OK;
+}
+
 feti_status write_output(feti_problem* p, double* out, int sum_mode) {
   HostPlan& P = p->P;
   double* dst = (p->opt.flags & FETI_DEVICE_PTRS) ? out : p->d_out;
-  vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, dst, sum_mode, p->stream);
+  if (P.mixed)
+    HIPCHK(hipMemcpyAsync(dst, p->d_uglob, P.n_dof * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  else
+    vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, dst, sum_mode, p->stream);
   if (!(p->opt.flags & FETI_DEVICE_PTRS))
     HIPCHK(hipMemcpyAsync(out, p->d_out, P.n_dof * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -812,9 +985,9 @@ feti_status feti_setup(const feti_mesh* mesh, const feti_options* opts, feti_pro
   if (p->opt.rtol <= 0) p->opt.rtol = 1e-8;
   if (p->opt.max_it <= 0) p->opt.max_it = 1000;
   if (p->opt.ir_tol <= 0) p->opt.ir_tol = 1e-10;
-  if (p->opt.ir_max <= 0) p->opt.ir_max = 6;
+  if (p->opt.ir_max < 0) p->opt.ir_max = 6;
   if (p->opt.graph_block <= 0) p->opt.graph_block = 8;
-  p->opt.graph_block = std::min(p->opt.graph_block, 64);
+  p->opt.graph_block = std::min(p->opt.graph_block, 64);   // also bounds the profiling event slots
   if (p->opt.variant != FETI_CLASSICAL && p->opt.variant != FETI_ALL_FLOATING) {
     g_setup_error = "bad variant";
     return FETI_EINVAL;
@@ -935,7 +1108,7 @@ feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stat
   r.nodal_scale = load_factor;
   r.f = p->d_f;
   asm_rhs(r, st);
-  feti_status s = solve_core(p, stats);
+  feti_status s = solve_refined(p, stats);
   if (s != FETI_OK && s != FETI_ENOCONV) return s;
   feti_status s2 = write_output(p, u, 0);
   if (s2 != FETI_OK) return s2;
@@ -944,7 +1117,6 @@ feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stat
     stats->t_total = ev_ms(p->ev[5], p->ev[4]) * 1e-3;
     stats->t_assemble = ev_ms(p->ev[0], p->ev[1]) * 1e-3;
     stats->t_factor = ev_ms(p->ev[1], p->ev[2]) * 1e-3;
-    stats->ir_sweeps = 0;
   }
   return s;
 }
@@ -1020,7 +1192,7 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
   r.dvals = p->d_dvals;
   r.f = p->d_f;
   asm_rhs(r, st);
-  feti_status s = solve_core(p, stats);
+  feti_status s = solve_refined(p, stats);
   if (s != FETI_OK && s != FETI_ENOCONV) return s;
   feti_status s2 = write_output(p, dU, 0);
   if (s2 != FETI_OK) return s2;
@@ -1029,7 +1201,6 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
     stats->t_assemble = ev_ms(p->ev[0], p->ev[1]) * 1e-3;
     stats->t_factor = ev_ms(p->ev[1], p->ev[2]) * 1e-3;
     stats->t_total = stats->t_assemble + stats->t_factor + ev_ms(p->ev[5], p->ev[4]) * 1e-3;
-    stats->ir_sweeps = 0;
   }
   return s;
 }
@@ -1044,6 +1215,10 @@ void feti_destroy(feti_problem* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   for (auto& ev : p->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : p->ev_gemv)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : p->ev_upd)
     if (ev) (void)hipEventDestroy(ev);
   for (void* a : p->allocs) {
     if (p->da.fr) p->da.fr(a, p->da.ctx);

@@ -683,6 +683,57 @@ __global__ void k_tiles_to_dense(int nc, int ld, const double* __restrict__ tile
 }
 
 // ---------------------------------------------------------------------------
+// FP64 residual of the assembled problem for the mixed-precision refinement:
+// the global displacement is restricted to every subdomain, the local residual
+// f_i - K_i u_i is formed with the FP64 sparse rows of the local stiffness
+// (free columns only: Dirichlet lifting is already in f_i), and summed over
+// the subdomain copies afterwards.
+__global__ void k_local_residual(int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
+                                 const int64_t* __restrict__ loc_node, const int32_t* __restrict__ f_sub,
+                                 const SubInfo* __restrict__ subs, const int32_t* __restrict__ ell_col,
+                                 const double* __restrict__ ell_val, const uint8_t* __restrict__ dmask,
+                                 const double* __restrict__ uglob, const double* __restrict__ f,
+                                 double* __restrict__ r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NF) return;
+  // padding, and constrained DOFs (their residual is a reaction, absorbed by
+  // the multipliers; the correction has zero Dirichlet data there)
+  if (fpos_lnode[p] < 0 || dmask[loc_node[fpos_lnode[p]] * 3 + fpos_comp[p]]) {
+    r[p] = 0.0;
+    return;
+  }
+  const SubInfo s = subs[f_sub[p]];
+  double acc = f[p];
+  for (int k = 0; k < ELLW; ++k) {
+    const int c = ell_col[k * NF + p];
+    if (c >= 0) {
+      const int64_t q = s.full_off + c;
+      const int64_t g = loc_node[fpos_lnode[q]] * 3 + fpos_comp[q];
+      acc -= ell_val[k * NF + p] * uglob[g];
+    }
+  }
+  r[p] = acc;
+}
+
+// Assembled vector back to the subdomains, split evenly over the copies of each
+// node: r_p = rg[g(p)] / (number of subdomains holding g).  Padding and
+// constrained DOFs get 0.  Used for the loads of a refinement correction, whose
+// interface forces then scale with the assembled residual.
+__global__ void k_distribute(int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
+                             const int64_t* __restrict__ loc_node, const int32_t* __restrict__ uc_ptr,
+                             const uint8_t* __restrict__ dmask, const double* __restrict__ rg, double* __restrict__ r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NF) return;
+  if (fpos_lnode[p] < 0) {
+    r[p] = 0.0;
+    return;
+  }
+  const int64_t g = loc_node[fpos_lnode[p]] * 3 + fpos_comp[p];
+  const int n = uc_ptr[g + 1] - uc_ptr[g];
+  r[p] = (dmask[g] || n == 0) ? 0.0 : rg[g] / n;
+}
+
+// ---------------------------------------------------------------------------
 // Local generalised inverse z = K^+ g on the full local vector of each
 // subdomain, by the block formula of the interior-first elimination with the
 // explicit inverse Wi = L_II^{-1} of the interior factor:
@@ -834,6 +885,15 @@ void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipS
 }
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, rtol, atol, max_it, hist_cap);
+}
+void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
+                    const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
+                    const uint8_t* dmask, const double* uglob, const double* f, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_residual, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, f_sub, subs, ell_col, ell_val, dmask, uglob, f, r);
+}
+void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
+                    const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_distribute, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, uc_ptr, dmask, rg, r);
 }
 constexpr int FUSE_BLOCKS = 256;
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,

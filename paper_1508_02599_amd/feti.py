@@ -25,6 +25,7 @@ VARIANTS = {"classical": 0, "af": 1, "all_floating": 1}
 PRECONDS = {"identity": 0, "lumped": 1, "dirichlet": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FETI_DEVICE_PTRS = 1
+FETI_PROFILE = 2
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -58,7 +59,10 @@ class feti_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("ir_sweeps", C.c_int32),
                 ("n_coarse", C.c_int32), ("n_lambda", C.c_int64), ("rel_res", C.c_double),
                 ("kappa_est", C.c_double), ("t_assemble", C.c_double), ("t_factor", C.c_double),
-                ("t_pcg", C.c_double), ("t_total", C.c_double), ("device_bytes", C.c_size_t)]
+                ("t_pcg", C.c_double), ("t_total", C.c_double), ("device_bytes", C.c_size_t),
+                ("kernel_gemv_launches", C.c_int32), ("kernel_update_launches", C.c_int32),
+                ("kernel_gemv_ms", C.c_double), ("kernel_update_ms", C.c_double),
+                ("gemv_bytes", C.c_double), ("update_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,10 +159,10 @@ def _check(lib, handle, status):
 
 def feti_setup(mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-               torch_allocator=False):
+               torch_allocator=False, profile=False):
     """Create a problem handle (see :class:`Problem`)."""
     return Problem(mesh, variant, precond, precision, rtol, max_it, graph_block, ir_tol, ir_max,
-                   hip_stream, device_ptrs, torch_allocator)
+                   hip_stream, device_ptrs, torch_allocator, profile)
 
 
 class Problem:
@@ -166,7 +170,7 @@ class Problem:
 
     def __init__(self, mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                  graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-                 torch_allocator=False):
+                 torch_allocator=False, profile=False):
         self.lib = load_library()
         self.n_dof = 3 * int(np.asarray(mesh.xyz).shape[0])
         keep = []
@@ -181,7 +185,7 @@ class Problem:
         o.ir_max = ir_max
         o.graph_block = graph_block
         o.hip_stream = hip_stream
-        o.flags = FETI_DEVICE_PTRS if device_ptrs else 0
+        o.flags = (FETI_DEVICE_PTRS if device_ptrs else 0) | (FETI_PROFILE if profile else 0)
         self._cb = None
         if torch_allocator:
             import torch

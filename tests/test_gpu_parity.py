@@ -199,3 +199,39 @@ def test_newton_step_midsize_tube():
         print(f"tube 4x32x16 newton {variant}: it={st['iters']} err={err:.3e}")
         assert abs(rn - rn_ref) <= 1e-10 * rn_ref
         assert err <= 1e-9
+
+
+# ---------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("variant,precond", [("af", "lumped"), ("classical", "dirichlet"),
+                                             ("af", "dirichlet")])
+def test_mixed_precision_cube8(variant, precond):
+    """FP32 local factors and solves, FP64 dual iteration and coarse problem,
+    accuracy recovered by refinement against FP64 residuals: <= 1e-8."""
+    m, ref = _oracle("cube8_s2")
+    u, st = _solve(m, variant=variant, precond=precond, precision="mixed", rtol=1e-8)
+    err = _rel(u, ref)
+    print(f"mixed cube8 {variant} {precond}: it={st['iters']} sweeps={st['ir_sweeps']} err={err:.3e}")
+    assert err <= 1e-8
+
+
+def test_mixed_precision_cube32_full_size():
+    m, ref = _oracle("cube32_s4")
+    u, st = _solve(m, variant="af", precond="lumped", precision="mixed", rtol=1e-8)
+    err = _rel(u, ref)
+    u64, st64 = _solve(m, variant="af", precond="lumped", rtol=1e-8)
+    err64 = _rel(u64, ref)
+    print(f"cube32 mixed: it={st['iters']} sweeps={st['ir_sweeps']} err={err:.3e}; fp64 at rtol 1e-8: "
+          f"it={st64['iters']} err={err64:.3e}")
+    assert err <= 1e-8
+
+
+def test_mixed_precision_newton_step():
+    m = _small_tube()
+    U = _converged(m, 0.1)
+    dU_ref, _ = monolithic.newton_increment(m, U, 0.2)
+    with _problem(m, variant="af", precond="dirichlet", precision="mixed", rtol=1e-8,
+                  ir_tol=1e-12, ir_max=10) as p:
+        dU, rn, st = p.newton_step(U, 0.2)
+    err = _rel(dU, dU_ref)
+    print(f"tube newton mixed: it={st['iters']} sweeps={st['ir_sweeps']} err={err:.3e}")
+    assert err <= 1e-8
