@@ -14,9 +14,12 @@ lumped preconditioner.
 The JSON line carries a roofline object for the dominant kernel (the one with
 the larger device time per solve among the dual-operator interface GEMV and
 the factor's tile update), timed live with HIP events on the library stream in
-a second timed pass of the same steps (PCG iterations launched one by one
-there, since events inside a replayed HIP graph cannot be timed), and the CPU
-oracle timed on the host.
+a second timed pass of the same steps, and the CPU oracle timed on the host.
+
+The mixed-precision path (FP32 local factors and GEMV values, FP64 dual
+iteration and coarse problem) is reported beside it at the same accuracy: its
+first dual solve stops at --mixed-rtol, and the outer refinement runs until
+the FP64 residual ||f - K u|| / ||f|| is no larger than the FP64 path's.
 
 Usage:
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
@@ -61,7 +64,7 @@ def source_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, launches_bytes):
+def traffic_from_profiles(kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
     f = os.path.join(ROOT, "profiles", "traffic.json")
@@ -90,14 +93,14 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
 
 
-def run(args, precision, profile=True):
+def run(args, precision, profile=True, rtol=1e-8, ir_tol=0.0):
     import torch
     from workloads import config_mesh
     from paper_1508_02599_amd.feti import Problem
 
     mesh = config_mesh(args.config)
-    p = Problem(mesh, variant=args.variant, precond=args.precond, precision=precision, rtol=1e-8,
-                device_ptrs=True, profile=profile)
+    p = Problem(mesh, variant=args.variant, precond=args.precond, precision=precision, rtol=rtol,
+                ir_tol=ir_tol, device_ptrs=True, profile=profile)
     u = torch.empty(mesh.n_dofs, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         p.factor()
@@ -126,26 +129,32 @@ def run(args, precision, profile=True):
 
 
 def roofline(st_all, precision):
-    """Roofline of the dominant kernel from the live HIP-event timings."""
-    g_ms = np.mean([s["kernel_gemv_ms"] for s in st_all])
-    g_n = np.mean([s["kernel_gemv_launches"] for s in st_all])
-    u_ms = np.mean([s["kernel_update_ms"] for s in st_all])
-    u_n = np.mean([s["kernel_update_launches"] for s in st_all])
+    """Roofline of the dominant kernel from the live HIP-event timings: the F
+    GEMV (mean of a back-to-back burst after each solve) and the factor's tile
+    update (events around each launch)."""
+    g_ms = float(np.mean([s["kernel_gemv_ms"] for s in st_all]))
+    g_n = float(np.mean([s["kernel_gemv_launches"] for s in st_all]))
+    u_ms = float(np.mean([s["kernel_update_ms"] for s in st_all]))
+    u_n = float(np.mean([s["kernel_update_launches"] for s in st_all]))
+    gb = st_all[-1]["gemv_bytes"]
     gemv = {"kernel": "k_symv_tiles", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-            "achieved": st_all[-1]["gemv_bytes"] / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None,
+            "achieved": gb / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None,
             "avg_launch_ms": g_ms, "launches_per_solve": g_n,
-            "algorithmic_bytes_per_launch": st_all[-1]["gemv_bytes"]}
+            "algorithmic_bytes_per_launch": gb}
+    uf = st_all[-1]["update_flops"] / max(u_n, 1)
     upd = {"kernel": "k_update", "bound": "mfma", "unit": "TFLOP/s",
            "peak": MFMA_PEAK_TFLOPS[precision],
-           "achieved": st_all[-1]["update_flops"] / max(u_n, 1) / (u_ms * 1e-3) / 1e12 if u_ms > 0 else None,
+           "achieved": uf / (u_ms * 1e-3) / 1e12 if u_ms > 0 else None,
            "avg_launch_ms": u_ms, "launches_per_solve": u_n,
-           "algorithmic_flops_per_launch": st_all[-1]["update_flops"] / max(u_n, 1)}
+           "algorithmic_flops_per_launch": uf}
     for r in (gemv, upd):
         r["frac"] = r["achieved"] / r["peak"] if r["achieved"] else None
         r["device_ms_per_solve"] = r["avg_launch_ms"] * r["launches_per_solve"]
     dom, other = (gemv, upd) if gemv["device_ms_per_solve"] >= upd["device_ms_per_solve"] else (upd, gemv)
-    t = traffic_from_profiles(dom["kernel"] + ("_f32" if precision == "mixed" else ""), None)
-    dom["traffic"] = t
+    suffix = "_f32" if precision == "mixed" else ""
+    for r in (dom, other):
+        t = traffic_from_profiles(r["kernel"] + suffix)
+        r["traffic"] = t
     return dom, other
 
 
@@ -158,6 +167,11 @@ def main():
     ap.add_argument("--variant", default="af")
     ap.add_argument("--precond", default="lumped")
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--mixed-rtol", type=float, default=1e-6,
+                    help="PCG tolerance of the first dual solve of the mixed path")
+    ap.add_argument("--ir-tol", type=float, default=0.0,
+                    help="--precision mixed: refinement target (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -171,12 +185,17 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    mesh, total, pcg_total, lat, st_all = run(args, args.precision, profile=False)
+    mesh, total, pcg_total, lat, st_all = run(args, args.precision, profile=False,
+                                              rtol=args.rtol if args.precision == "fp64" else args.mixed_rtol,
+                                              ir_tol=args.ir_tol)
     st = st_all[-1]
-    # roofline pass: same workload, events around the dominant kernels' launches
-    _, ptotal, _, _, pst = run(args, args.precision, profile=True)
+    # roofline pass: same workload, kernel timings with HIP events
+    _, ptotal, _, _, pst = run(args, args.precision, profile=True,
+                               rtol=args.rtol if args.precision == "fp64" else args.mixed_rtol,
+                               ir_tol=args.ir_tol)
     dom, other = roofline(pst, args.precision)
     dom["profiled_pass_ms_per_step"] = 1e3 * ptotal / args.steps
+    res64 = pst[-1]["res_primal"]
     line = {
         "metric": "FETI PCG solves/s at 1e-8 residual (FP64 vs mixed); p50/p99 solve latency",
         "value": args.steps / total,
@@ -193,33 +212,44 @@ def main():
         "config": {"workload": f"{args.config}: unit cube 32^3 Q1 elements in 4x4x4 "
                                f"{'all-floating' if args.variant == 'af' else 'classical'} subdomains "
                                f"of 8^3 elements (2187 DOFs each), nu per subdomain ~ U[0.25,0.35] "
-                               f"(seed 0), {args.precond} preconditioner, rtol 1e-8",
+                               f"(seed 0), {args.precond} preconditioner, PCG rtol {args.rtol:g}",
                    "subdomains": mesh.n_sub, "global_dofs": mesh.n_dofs,
                    "multipliers": st["n_lambda"], "coarse_dim": st["n_coarse"]},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "pcg_only_solves_per_s": args.steps / pcg_total,
         "iters": st["iters"],
+        "res_primal": res64,
         "phase_ms": {k: 1e3 * st[k] for k in ("t_assemble", "t_factor", "t_pcg")},
         "roofline": {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": {k: v for k, v in dom.items()
                             if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_secondary": other,
     }
+    tm = None
     if args.precision == "fp64" and not args.no_mixed:
+        # mixed precision at the same accuracy: FP32 local factors, first dual
+        # solve to mixed_rtol, then refinement until the FP64 residual is no
+        # larger than the FP64 path's
+        ir_tol = max(res64, 1e-14)
         try:
-            _, tm, pm, lm, sm = run(args, "mixed", profile=False)
-            _, _, _, _, smp = run(args, "mixed", profile=True)
-            d2, o2 = roofline(smp, "mixed")
-            line["mixed"] = {"value": args.steps / tm, "unit": "solves/s",
-                             "latency_ms": {"p50": 1e3 * float(np.percentile(lm, 50)),
-                                            "p99": 1e3 * float(np.percentile(lm, 99))},
-                             "pcg_only_solves_per_s": args.steps / pm, "iters": sm[-1]["iters"],
-                             "ir_sweeps": sm[-1]["ir_sweeps"],
-                             "phase_ms": {k: 1e3 * sm[-1][k] for k in ("t_assemble", "t_factor", "t_pcg")},
-                             "roofline": d2, "roofline_secondary": o2}
-        except Exception as e:   # mixed precision reported as unavailable, never as a number
+            _, tm, pm, lm, sm = run(args, "mixed", profile=False, rtol=args.mixed_rtol, ir_tol=ir_tol)
+            _, _, _, _, smp = run(args, "mixed", profile=True, rtol=args.mixed_rtol, ir_tol=ir_tol)
+        except Exception as e:   # reported as unavailable, never as a number
             line["mixed"] = {"error": str(e)}
+            tm = None
+    if args.precision == "fp64" and not args.no_mixed and tm is not None:
+        d2, o2 = roofline(smp, "mixed")
+        line["mixed"] = {"value": args.steps / tm, "unit": "solves/s",
+                         "speedup_vs_fp64": (args.steps / tm) / line["value"],
+                         "first_solve_rtol": args.mixed_rtol, "ir_tol": ir_tol,
+                         "res_primal": sm[-1]["res_primal"],
+                         "latency_ms": {"p50": 1e3 * float(np.percentile(lm, 50)),
+                                        "p99": 1e3 * float(np.percentile(lm, 99))},
+                         "pcg_only_solves_per_s": args.steps / pm, "iters": sm[-1]["iters"],
+                         "ir_sweeps": sm[-1]["ir_sweeps"],
+                         "phase_ms": {k: 1e3 * sm[-1][k] for k in ("t_assemble", "t_factor", "t_pcg")},
+                         "roofline": d2, "roofline_secondary": o2}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh)
     print(json.dumps(line))

@@ -108,7 +108,7 @@ typedef struct {
 } feti_mesh;
 
 #define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */
-#define FETI_PROFILE 0x2ull     /* time the dual-operator GEMV and factor-update launches with
+#define FETI_PROFILE 0x2ull     /* time the dual-operator GEMV and factor-update kernels with
                                    HIP events (reported in feti_stats.kernel_*)              */
 
 typedef struct {
@@ -117,8 +117,9 @@ typedef struct {
   feti_precision precision;
   double rtol;                 /* PCG stop: ||P r_k||_2 <= rtol ||P r_0||_2 (0 => 1e-8)  */
   int32_t max_it;              /* PCG iteration cap (0 => 1000)                           */
-  double ir_tol;               /* mixed: relative FP64 residual target of the outer
-                                  refinement (0 => 1e-10)                                 */
+  double ir_tol;               /* mixed: target of the outer refinement,
+                                  ||f - K u||_2 <= ir_tol ||f||_2 over free DOFs, FP64,
+                                  assembled (0 => 1e-10)                                  */
   int32_t ir_max;              /* mixed: max correction sweeps (negative => 6)            */
   int32_t graph_block;         /* PCG iterations captured per HIP graph (0 => 8)          */
   void* hip_stream;            /* hipStream_t to run on, or NULL for a library stream    */
@@ -138,13 +139,20 @@ typedef struct {
   double kappa_est;            /* Lanczos estimate of the preconditioned condition number */
   double t_assemble, t_factor, t_pcg, t_total;   /* seconds, from HIP events              */
   size_t device_bytes;         /* device memory held by the problem                       */
-  /* with FETI_PROFILE: launches and mean duration (ms, HIP events on the problem's
-     stream) of the interface GEMV of F (per PCG iteration) and of the factor's
-     tile-update kernel, since the last feti_factor; algorithmic bytes of one GEMV
-     launch and flops of all update launches of one factorisation */
+  /* kernel_gemv_launches: interface GEMV launches of F in this solve (one per PCG
+     iteration and one for the initial residual, over all refinement sweeps);
+     kernel_update_launches: tile-update launches of the last feti_factor.
+     With FETI_PROFILE: mean duration (ms, HIP events on the problem's stream) of
+     one GEMV launch, from back-to-back launches after the solve, and of one
+     update launch, from events around each launch of the last factorisation.
+     gemv_bytes: algorithmic bytes of one GEMV launch (packed symmetric interface
+     inverses); update_flops: flops of all update launches of one factorisation */
   int32_t kernel_gemv_launches, kernel_update_launches;
   double kernel_gemv_ms, kernel_update_ms;
   double gemv_bytes, update_flops;
+  double res_primal;           /* ||f - K u||_2 / ||f||_2 of the returned u (FP64, assembled,
+                                  free DOFs): always for FETI_MIXED, with FETI_PROFILE for
+                                  FETI_FP64, else 0                                         */
 } feti_stats;
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */

@@ -101,7 +101,7 @@ struct feti_problem {
   // FETI_PROFILE: event pairs around the F GEMV of every captured iteration and
   // around every factor-update launch
   bool profile = false;
-  std::vector<hipEvent_t> ev_gemv, ev_upd;
+  std::vector<hipEvent_t> ev_gemv, ev_upd;   // burst start/end; pairs around update launches
   int n_upd_recorded = 0;
   double prof_gemv_ms = 0.0, prof_upd_ms = 0.0, upd_flops = 0.0, gemv_bytes = 0.0;
   int prof_gemv_n = 0, prof_upd_n = 0;
@@ -251,12 +251,10 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
 // One PCG iteration (six to seven launches, all scalars on the device):
 //   q = F s (s = z + beta s formed on the fly), alpha;  r -= alpha q,
 //   lambda += alpha s, w = P r;  t = M^{-1} w;  z = P t, beta and the test.
-void pcg_iteration(feti_problem* p, int slot) {
+void pcg_iteration(feti_problem* p) {
   PcgState* st = p->d_state;
   pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, p->stream);
-  if (p->profile) (void)hipEventRecord(p->ev_gemv[2 * slot], p->stream);
   symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
-  if (p->profile) (void)hipEventRecord(p->ev_gemv[2 * slot + 1], p->stream);
   pcg_scatter_dot_alpha(p->di, p->d_yb, p->d_zv, p->d_s, p->d_q, p->d_fpart, p->d_ticket, st, p->stream);
   project_fused(p, 1, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
   precondition(p, p->d_wv, p->d_tv, st);
@@ -469,7 +467,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bv, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
-  if (P.mixed) {
+  if (P.mixed || (p->opt.flags & FETI_PROFILE)) {   // refinement / residual report
     TRY(dalloc(p, p->d_f0, (size_t)P.NF));
     TRY(dalloc(p, p->d_uglob, (size_t)P.n_dof));
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
@@ -489,10 +487,11 @@ feti_status setup_device(feti_problem* p) {
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
-    p->ev_gemv.resize(2 * 64);
+    p->ev_gemv.resize(2);
     for (auto& ev : p->ev_gemv) HIPCHK(hipEventCreate(&ev));
+    // no system-scope fence at these events: they bracket single launches
     p->ev_upd.resize(2 * (P.sched_interior.size() + P.sched_iface.size() + 2));
-    for (auto& ev : p->ev_upd) HIPCHK(hipEventCreate(&ev));
+    for (auto& ev : p->ev_upd) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
   }
   // algorithmic work: bytes of the packed symmetric interface inverses read by
   // one GEMV, and flops of the tile updates counted on real (unpadded) rows,
@@ -760,52 +759,25 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->d_state, nullptr);
     // graph of graph_block iterations
     const int gb = std::max(1, p->opt.graph_block);
-    if (!p->profile && (!p->graph || p->graph_iters != gb)) {
+    if (!p->graph || p->graph_iters != gb) {
       if (p->graph) {
         (void)hipGraphExecDestroy(p->graph);
         p->graph = nullptr;
       }
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < gb; ++k) pcg_iteration(p, k);
+      for (int k = 0; k < gb; ++k) pcg_iteration(p);
       HIPCHK(hipStreamEndCapture(st, &gr));
       HIPCHK(hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0));
       (void)hipGraphDestroy(gr);
       p->graph_iters = gb;
     }
     PcgState hs{};
-    int it_before = 0;
-    bool replayed = false;
     for (;;) {
       HIPCHK(hipMemcpyAsync(&hs, p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      if (p->profile && replayed) {
-        // iterations that ran in this replay: it advanced, plus the one that set done
-        // the GEMV ran in every iteration that advanced the count, and in one
-        // that stopped at a breakdown before advancing it
-        int ran = hs.it - it_before + (hs.status == FETI_EBREAKDOWN ? 1 : 0);
-        ran = std::min(ran, gb);
-        for (int k = 0; k < ran; ++k) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, p->ev_gemv[2 * k], p->ev_gemv[2 * k + 1]) == hipSuccess) {
-            p->prof_gemv_ms += ms;
-            p->prof_gemv_n++;
-          } else {
-            (void)hipGetLastError();
-          }
-        }
-      }
       if (hs.done) break;
-      it_before = hs.it;
-      if (p->profile) {
-        // same kernels and launch configuration, launched one by one so that the
-        // events around the GEMV can be timed (events recorded inside a captured
-        // graph cannot)
-        for (int k = 0; k < gb; ++k) pcg_iteration(p, k);
-      } else {
-        HIPCHK(hipGraphLaunch(p->graph, st));
-      }
-      replayed = true;
+      HIPCHK(hipGraphLaunch(p->graph, st));
     }
     iters = hs.it;
     status = hs.status;
@@ -833,7 +805,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
   }
   HIPCHK(hipEventRecord(p->ev[4], st));
   if (stats) {
-    stats->kernel_gemv_launches = p->prof_gemv_n;
+    stats->kernel_gemv_launches = n > 0 ? iters + 1 : 0;
     stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
     stats->kernel_update_launches = p->prof_upd_n;
     stats->kernel_update_ms = p->prof_upd_n ? p->prof_upd_ms / p->prof_upd_n : 0.0;
@@ -870,6 +842,31 @@ feti_status dev_norm(feti_problem* p, const double* v, int64_t n, double* out) {
   return FETI_OK;
 }
 
+// FETI_PROFILE: mean duration of the dual-operator GEMV (tile phase), from
+// back-to-back launches on the problem's stream after the solve, on the last
+// gathered interface vector (nothing reads the partial sums afterwards).
+feti_status profile_gemv(feti_problem* p) {
+  constexpr int kBurst = 20;
+  if (!p->profile || p->P.n_lam == 0) return FETI_OK;
+  const HostPlan::Launch& L = p->P.sched_xtiles;
+  HIPCHK(hipEventRecord(p->ev_gemv[0], p->stream));
+  for (int r = 0; r < kBurst; ++r) {
+    if (p->P.mixed)
+      pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)p->d_X, p->d_xb, p->d_part,
+                      p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream);
+    else
+      pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)p->d_X, p->d_xb, p->d_part,
+                       p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream);
+  }
+  HIPCHK(hipEventRecord(p->ev_gemv[1], p->stream));
+  HIPCHK(hipEventSynchronize(p->ev_gemv[1]));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, p->ev_gemv[0], p->ev_gemv[1]));
+  p->prof_gemv_ms = ms;
+  p->prof_gemv_n = kBurst;
+  return FETI_OK;
+}
+
 // Solve for the local right-hand sides in d_f and the Dirichlet data in
 // d_dvals; the global result goes to d_uglob (mixed) or stays in d_u.
 // FP64: one dual solve.  Mixed (FP32 local factors): iterative refinement on
@@ -884,8 +881,28 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
   feti_status s = solve_core(p, stats, p->opt.rtol);
-  if (!P.mixed || (s != FETI_OK && s != FETI_ENOCONV)) return s;
+  if (!P.mixed || (s != FETI_OK && s != FETI_ENOCONV)) {
+    if ((s == FETI_OK || s == FETI_ENOCONV) && p->profile) {
+      TRY(profile_gemv(p));
+      // FP64 residual of the result, for comparison with the mixed path
+      const int64_t nd = P.n_dof;
+      double fnorm = 0.0, rnorm = 0.0;
+      vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
+      local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
+                     p->d_ell_val, p->d_dmask, p->d_uglob, p->d_f, p->d_f0, st);
+      vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
+      TRY(dev_norm(p, p->d_out, nd, &rnorm));
+      vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
+      TRY(dev_norm(p, p->d_out, nd, &fnorm));
+      if (stats) {
+        stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
+        stats->res_primal = fnorm > 0 ? rnorm / fnorm : 0.0;
+      }
+    }
+    return s;
+  }
   int iters = stats ? stats->iters : 0;
+  int launches = stats ? stats->kernel_gemv_launches : 0;
   const int64_t nd = P.n_dof;
   vec_axpby(P.NF, 1.0, p->d_f, 0.0, p->d_f0, st);
   vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
@@ -893,7 +910,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
   TRY(dev_norm(p, p->d_out, nd, &fnorm));
   int sweeps = 0;
-  const double inner_rtol = std::max(p->opt.rtol, 1e-5);
+  double amp = 10.0, eta = 1.0, rprev = 0.0;
   for (;;) {
     local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
                    p->d_ell_val, p->d_dmask, p->d_uglob, p->d_f0, p->d_f, st);
@@ -901,21 +918,34 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     TRY(dev_norm(p, p->d_out, nd, &rnorm));
     if (!(rnorm > p->opt.ir_tol * fnorm) || sweeps >= p->opt.ir_max) break;
     // correction: the assembled residual, split evenly over the subdomain
-    // copies of each node, as loads; homogeneous Dirichlet data
+    // copies of each node, as loads; homogeneous Dirichlet data.  The dual
+    // solve only has to remove the part of the residual above the target.
+    // A dual reduction eta has reduced the primal residual by about
+    // amp * eta; amp is learnt from the sweeps so far (start: 10), with a
+    // margin of 2, and eta stays within [rtol, 0.1].
+    if (sweeps > 0) amp = std::max(1.0, (rnorm / rprev) / eta);
     vec_distribute(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->d_uc_ptr, p->d_dmask, p->d_out,
                    p->d_f, st);
     HIPCHK(hipMemcpyAsync(p->d_dvals, p->d_zero, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const double need = p->opt.ir_tol * fnorm / rnorm;
+    eta = std::min(0.1, std::max(p->opt.rtol, 0.5 * need / amp));
+    rprev = rnorm;
     feti_stats cs{};
-    s = solve_core(p, &cs, inner_rtol, false);
+    s = solve_core(p, &cs, eta, false);
     if (s != FETI_OK && s != FETI_ENOCONV) return s;
     iters += cs.iters;
+    launches += cs.kernel_gemv_launches;
     vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_zero, p->d_out, 0, st);
     vec_axpby(nd, 1.0, p->d_out, 1.0, p->d_uglob, st);
     ++sweeps;
   }
+  TRY(profile_gemv(p));
   if (stats) {
     stats->iters = iters;
     stats->ir_sweeps = sweeps;
+    stats->kernel_gemv_launches = launches;
+    stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
+    stats->res_primal = fnorm > 0 ? rnorm / fnorm : 0.0;
   }
   if (!(rnorm <= p->opt.ir_tol * fnorm)) {
     p->err = "mixed-precision refinement did not reach ir_tol within ir_max corrections";

@@ -119,6 +119,8 @@ static bool finite(double v) { return std::isfinite(v); }
 std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   if (!m) return "mesh is NULL";
   if (m->n_nodes <= 0 || m->n_elems <= 0 || m->n_sub <= 0 || m->n_mat <= 0) return "empty mesh";
+  // the coarse vector (6 per subdomain) of a projection is staged in 64 KiB of LDS
+  if (m->n_sub > kMaxSub) return "more than " + std::to_string(kMaxSub) + " subdomains";
   if (!m->xyz || !m->hex8 || !m->elem_sub || !m->mat || !m->elem_mat) return "missing mesh array";
   if (m->n_dir < 0 || (m->n_dir > 0 && (!m->dir_dof || !m->dir_val))) return "bad Dirichlet arrays";
   if (m->n_pfaces < 0 || (m->n_pfaces > 0 && !m->pface)) return "bad pressure faces";

@@ -17,6 +17,9 @@ constexpr int TS = 64;
 constexpr int TS2 = TS * TS;
 // Maximum number of nonzeros in one row of a Q1 stiffness (27 nodes x 3 dofs).
 constexpr int ELLW = 81;
+// Maximum number of subdomains: the coarse vector (6 entries per subdomain)
+// of one projection fits in 64 KiB of LDS.
+constexpr int kMaxSub = 1365;
 
 // Per-subdomain layout, copied to the device as a plain struct array.
 // A subdomain's local DOFs are ordered interior first, constraint ("b") DOFs

@@ -44,6 +44,9 @@ void launch_woodbury(int n_sub, int max_nt_b, const Task* xtasks, int xcount, co
 void pcg_gather(const DevIdx& d, int weighted, const double* v, double* xb, const PcgState* st, hipStream_t s);
 void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* base, double sgn, double* out,
                  const PcgState* st, hipStream_t s);
+// Packed symmetric GEMV over the interface tiles of every subdomain: tile
+// partial sums into part, then their ordered sum into yb (yb NULL: the tile
+// phase only).
 template <typename T>
 void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
               int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s);

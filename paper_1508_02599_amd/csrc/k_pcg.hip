@@ -45,84 +45,6 @@ __global__ void k_scatter(int64_t n_lam, const int64_t* __restrict__ b0, const d
   out[r] = (base ? base[r] : 0.0) + sgn * v;
 }
 
-// Symmetric tile matrix-vector product, phase 1: every stored lower tile
-// (I, J) of a symmetric matrix contributes M_IJ x_J to block row I and,
-// off the diagonal, M_IJ^T x_I to block row J.  Partial sums go to
-// part[part_off + (row*nt + col)*TS + .] and are summed in order afterwards.
-template <typename T>
-__global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tasks,
-                                                    const SubInfo* __restrict__ subs,
-                                                    const T* __restrict__ M,
-                                                    const double* __restrict__ xb, double* part,
-                                                    const PcgState* st) {
-  if (halted(st)) return;
-  __shared__ T sM[TS * LDV];
-  __shared__ double xI[TS], xJ[TS];
-  __shared__ double red[4][TS], red2[4][TS];
-  const Task t = tasks[blockIdx.x];
-  const SubInfo s = subs[t.sub];
-  const T* tile = M + s.x_off + tidx2(t.i, t.j) * TS2;
-  const int tid = threadIdx.x;
-  {
-    T v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = tile[tid + 256 * i];   // all loads in flight first
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int e = tid + 256 * i;
-      sM[(e >> 6) * LDV + (e & 63)] = v[i];
-    }
-  }
-  if (tid < TS) {
-    xI[tid] = xb[s.b_off + (int64_t)t.i * TS + tid];
-    xJ[tid] = xb[s.b_off + (int64_t)t.j * TS + tid];
-  }
-  __syncthreads();
-  const int a = tid & 63, q = tid >> 6;
-  double s1 = 0.0, s2 = 0.0;
-  if (t.i != t.j) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int c = 16 * q + k;
-      s1 += (double)sM[c * LDV + a] * xJ[c];     // (M x_J)[a]
-      s2 += (double)sM[a * LDV + c] * xI[c];     // (M^T x_I)[a], column a row c
-    }
-  } else {
-    // diagonal tile: only its lower triangle is meaningful; mirror it
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int c = 16 * q + k;
-      const int hi = a > c ? a : c, lo = a > c ? c : a;
-      s1 += (double)sM[lo * LDV + hi] * xJ[c];
-    }
-  }
-  red[q][a] = s1;
-  red2[q][a] = s2;
-  __syncthreads();
-  if (tid < TS) {
-    const int nt = s.nt_b;
-    part[s.part_off + ((int64_t)t.i * nt + t.j) * TS + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    if (t.i != t.j)
-      part[s.part_off + ((int64_t)t.j * nt + t.i) * TS + tid] =
-          red2[0][tid] + red2[1][tid] + red2[2][tid] + red2[3][tid];
-  }
-}
-
-// Phase 2: yb[b] = sum_J part[row I of b][J] in order.
-__global__ void k_symv_reduce(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
-                              const double* __restrict__ part, double* __restrict__ yb, const PcgState* st) {
-  if (halted(st)) return;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= NB) return;
-  const SubInfo s = subs[b_sub[b]];
-  const int64_t loc = b - s.b_off;
-  const int I = (int)(loc / TS), r = (int)(loc % TS);
-  const double* p = part + s.part_off + (int64_t)I * s.nt_b * TS + r;
-  double acc = 0.0;
-  for (int J = 0; J < s.nt_b; ++J) acc += p[(int64_t)J * TS];
-  yb[b] = acc;
-}
-
 // Block partial sums of up to two dot products over n entries (fixed partition).
 __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __restrict__ a,
                                                      const double* __restrict__ b,
@@ -324,14 +246,32 @@ __global__ void k_add_modes(int64_t NF, const int32_t* __restrict__ f_sub, const
 
 // Lumped preconditioner: yb = K_bb xb with the interface-interface block of
 // every local stiffness stored slot-major (consecutive interface DOFs coalesce).
-__global__ void k_lumped(int64_t NB, int w_bb, const int32_t* __restrict__ bb_col,
-                         const double* __restrict__ bb_val, const double* __restrict__ xb,
-                         double* __restrict__ yb, const PcgState* st) {
+// Lumped preconditioner block y = K_bb x over the compact slot-major ELL of
+// K_bb.  The slots of a row are taken in chunks of LUMP_CHUNK whose index and
+// value loads are all issued before their x gathers, so a row costs a few
+// memory round trips rather than one per slot.
+constexpr int LUMP_CHUNK = 10;
+__global__ __launch_bounds__(256) void k_lumped(int64_t NB, int w_bb, const int32_t* __restrict__ bb_col,
+                                                const double* __restrict__ bb_val, const double* __restrict__ xb,
+                                                double* __restrict__ yb, const PcgState* st) {
   if (halted(st)) return;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= NB) return;
   double acc = 0.0;
-  for (int k = 0; k < w_bb; ++k) acc += bb_val[k * NB + b] * xb[bb_col[k * NB + b]];
+  for (int k0 = 0; k0 < w_bb; k0 += LUMP_CHUNK) {
+    int c[LUMP_CHUNK];
+    double v[LUMP_CHUNK], x[LUMP_CHUNK];
+#pragma unroll
+    for (int i = 0; i < LUMP_CHUNK; ++i) {
+      const bool in = k0 + i < w_bb;
+      c[i] = in ? bb_col[(int64_t)(k0 + i) * NB + b] : 0;
+      v[i] = in ? bb_val[(int64_t)(k0 + i) * NB + b] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < LUMP_CHUNK; ++i) x[i] = xb[c[i]];
+#pragma unroll
+    for (int i = 0; i < LUMP_CHUNK; ++i) acc += v[i] * x[i];
+  }
   yb[b] = acc;
 }
 
@@ -551,30 +491,37 @@ __global__ __launch_bounds__(256) void k_proj_gt(const SubInfo* __restrict__ sub
   }
 }
 
-// alpha_c = Qinv g with the dense symmetric inverse (column-major, leading dim
-// ld); g is summed from its GT_CHUNKS partials.  16 rows per block, the
-// columns split 16 ways and reduced in a fixed order.
+// alpha_c = Qinv g with the dense symmetric inverse (leading dim ld); g is the
+// sum of its GT_CHUNKS partials, formed once per block in LDS.  One wave per
+// row: Qinv is symmetric, so row i is read as the contiguous column i; the
+// lanes take columns lane, lane+64, ... and the wave sum fixes the order.
 __global__ __launch_bounds__(256) void k_coarse_dense(int nc, int ld, const double* __restrict__ Qi,
                                                       const double* __restrict__ gpart, int ldg,
                                                       double* __restrict__ a, const PcgState* st) {
   if (halted(st)) return;
-  __shared__ double red[16][17];
-  const int rl = threadIdx.x & 15, cq = threadIdx.x >> 4;
-  const int row = blockIdx.x * 16 + rl;
-  double acc = 0.0;
-  if (row < nc)
-    for (int j = cq; j < nc; j += 16) {
-      double g = 0.0;
-      for (int c = 0; c < GT_CHUNKS; ++c) g += gpart[(int64_t)c * ldg + j];
-      acc += Qi[(int64_t)j * ld + row] * g;
-    }
-  red[cq][rl] = acc;
-  __syncthreads();
-  if (threadIdx.x < 16 && row < nc) {
+  extern __shared__ double g[];
+  for (int j = threadIdx.x; j < nc; j += 256) {
     double v = 0.0;
-    for (int k = 0; k < 16; ++k) v += red[k][threadIdx.x];
-    a[row] = v;
+#pragma unroll
+    for (int c = 0; c < GT_CHUNKS; ++c) v += gpart[(int64_t)c * ldg + j];
+    g[j] = v;
   }
+  __syncthreads();
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= nc) return;
+  const double* q = Qi + (int64_t)row * ld;
+  double acc = 0.0;
+  int j = lane;
+  for (; j + 192 < nc; j += 256) {
+    const double q0 = q[j], q1 = q[j + 64], q2 = q[j + 128], q3 = q[j + 192];
+    acc += q0 * g[j];
+    acc += q1 * g[j + 64];
+    acc += q2 * g[j + 128];
+    acc += q3 * g[j + 192];
+  }
+  for (; j < nc; j += 64) acc += q[j] * g[j];
+  acc = wave_sum(acc);
+  if (lane == 0) a[row] = acc;
 }
 
 // (G a)_r contribution of one row entry: Rb[b] . a[coarse block of b's subdomain]
@@ -806,16 +753,6 @@ void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* b
                  const PcgState* st, hipStream_t s) {
   if (d.n_lam) hipLaunchKernelGGL(k_scatter, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, d.r_w, weighted, y, base, sgn, out, st);
 }
-template <typename T>
-void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
-              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s) {
-  if (count <= 0) return;
-  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st);
-  hipLaunchKernelGGL(k_symv_reduce, grid1(NB), dim3(256), 0, s, NB, b_sub, subs, (const double*)part, yb, st);
-}
-template void pcg_symv<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
-template void pcg_symv<float>(const Task*, int, const SubInfo*, const float*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
-
 void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
              const PcgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial, dim3(DOT_PARTS), dim3(256), 0, s, n, a, b, c, d, part, st);
@@ -910,7 +847,7 @@ void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* 
 }
 void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int ldg, double* a, const PcgState* st,
                       hipStream_t s) {
-  if (nc) hipLaunchKernelGGL(k_coarse_dense, dim3((nc + 15) / 16), dim3(256), 0, s, nc, ld, Qi, gpart, ldg, a, st);
+  if (nc) hipLaunchKernelGGL(k_coarse_dense, dim3((nc + 3) / 4), dim3(256), nc * sizeof(double), s, nc, ld, Qi, gpart, ldg, a, st);
 }
 void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int32_t* bco, const double* rbv,
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,

@@ -1,0 +1,114 @@
+// Packed-symmetric tile GEMV y = M x over the interface blocks of all
+// subdomains: the per-iteration action of the local interface inverses in the
+// dual operator F = sum_i B_i K_i^+ B_i^T (paper section 4.3, eq.
+// (classicalFetiF)), and the Dirichlet preconditioner's Schur complements
+// (section 4.4, eq. (DirichletVK)).  HBM-bound: every stored tile is read once
+// per launch.
+#include "feti_impl.h"
+#include "k_pcg.h"
+
+namespace feti {
+
+constexpr int LDV = TS + 1;
+
+__device__ __forceinline__ bool halted(const PcgState* st) { return st != nullptr && st->done != 0; }
+__device__ __forceinline__ int64_t tidx2(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
+static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+// Symmetric tile matrix-vector product, phase 1: every stored lower tile
+// (I, J) of a symmetric matrix contributes M_IJ x_J to block row I and,
+// off the diagonal, M_IJ^T x_I to block row J.  Partial sums go to
+// part[part_off + (row*nt + col)*TS + .] and are summed in order afterwards.
+template <typename T>
+__global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tasks,
+                                                    const SubInfo* __restrict__ subs,
+                                                    const T* __restrict__ M,
+                                                    const double* __restrict__ xb, double* part,
+                                                    const PcgState* st) {
+  if (halted(st)) return;
+  __shared__ T sM[TS * LDV];
+  __shared__ double xI[TS], xJ[TS];
+  __shared__ double red[4][TS], red2[4][TS];
+  const Task t = tasks[blockIdx.x];
+  const SubInfo s = subs[t.sub];
+  const T* tile = M + s.x_off + tidx2(t.i, t.j) * TS2;
+  const int tid = threadIdx.x;
+  {
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = tile[tid + 256 * i];   // all loads in flight first
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = tid + 256 * i;
+      sM[(e >> 6) * LDV + (e & 63)] = v[i];
+    }
+  }
+  if (tid < TS) {
+    xI[tid] = xb[s.b_off + (int64_t)t.i * TS + tid];
+    xJ[tid] = xb[s.b_off + (int64_t)t.j * TS + tid];
+  }
+  __syncthreads();
+  const int a = tid & 63, q = tid >> 6;
+  double s1 = 0.0, s2 = 0.0;
+  if (t.i != t.j) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 16 * q + k;
+      s1 += (double)sM[c * LDV + a] * xJ[c];     // (M x_J)[a]
+      s2 += (double)sM[a * LDV + c] * xI[c];     // (M^T x_I)[a], column a row c
+    }
+  } else {
+    // diagonal tile: only its lower triangle is meaningful; mirror it
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 16 * q + k;
+      const int hi = a > c ? a : c, lo = a > c ? c : a;
+      s1 += (double)sM[lo * LDV + hi] * xJ[c];
+    }
+  }
+  red[q][a] = s1;
+  red2[q][a] = s2;
+  __syncthreads();
+  if (tid < TS) {
+    const int nt = s.nt_b;
+    part[s.part_off + ((int64_t)t.i * nt + t.j) * TS + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    if (t.i != t.j)
+      part[s.part_off + ((int64_t)t.j * nt + t.i) * TS + tid] =
+          red2[0][tid] + red2[1][tid] + red2[2][tid] + red2[3][tid];
+  }
+}
+
+// Phase 2: yb[b] = sum_J part[row I of b][J] in order (loads of a chunk of
+// eight partials in flight together).
+__global__ void k_symv_reduce(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
+                              const double* __restrict__ part, double* __restrict__ yb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  const int64_t loc = b - s.b_off;
+  const int I = (int)(loc / TS), r = (int)(loc % TS);
+  const double* p = part + s.part_off + (int64_t)I * s.nt_b * TS + r;
+  const int nt = s.nt_b;
+  double acc = 0.0;
+  for (int J0 = 0; J0 < nt; J0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = J0 + k < nt ? p[(int64_t)(J0 + k) * TS] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  yb[b] = acc;
+}
+
+template <typename T>
+void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st);
+  if (yb) hipLaunchKernelGGL(k_symv_reduce, grid1(NB), dim3(256), 0, s, NB, b_sub, subs, (const double*)part, yb, st);
+}
+template void pcg_symv<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
+template void pcg_symv<float>(const Task*, int, const SubInfo*, const float*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
+
+}  // namespace feti

@@ -62,7 +62,7 @@ class feti_stats(C.Structure):
                 ("t_pcg", C.c_double), ("t_total", C.c_double), ("device_bytes", C.c_size_t),
                 ("kernel_gemv_launches", C.c_int32), ("kernel_update_launches", C.c_int32),
                 ("kernel_gemv_ms", C.c_double), ("kernel_update_ms", C.c_double),
-                ("gemv_bytes", C.c_double), ("update_flops", C.c_double)]
+                ("gemv_bytes", C.c_double), ("update_flops", C.c_double), ("res_primal", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
