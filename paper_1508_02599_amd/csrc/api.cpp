@@ -248,17 +248,37 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
   pcg_scatter(p->di, 1, y, nullptr, 1.0, out, st, p->stream);
 }
 
-// One PCG iteration (six to seven launches, all scalars on the device):
-//   q = F s (s = z + beta s formed on the fly), alpha;  r -= alpha q,
-//   lambda += alpha s, w = P r;  t = M^{-1} w;  z = P t, beta and the test.
+// One PCG iteration (ten or eleven launches, all scalars on the device):
+//   xb = B^T s with s = z + beta s formed on the fly;  y = X xb (tile phase,
+//   ordered reduction);  q = B y, alpha, and G^T q from y;  a = Q^{-1} G^T q;
+//   r -= alpha q, lambda += alpha s, w -= alpha (q - G a);
+//   t = M^{-1} w with G^T t from the preconditioner's interface output;
+//   a = Q^{-1} G^T t;  z = t - G a, beta and the stopping test.
 void pcg_iteration(feti_problem* p) {
   PcgState* st = p->d_state;
-  pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, p->stream);
+  hipStream_t s = p->stream;
+  const int nc = p->n_coarse;
+  pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, s);
   symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
-  pcg_scatter_dot_alpha(p->di, p->d_yb, p->d_zv, p->d_s, p->d_q, p->d_fpart, p->d_ticket, st, p->stream);
-  project_fused(p, 1, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
-  precondition(p, p->d_wv, p->d_tv, st);
-  project_fused(p, 2, 0, p->d_tv, p->d_zv, p->d_wv, st, p->d_hist);
+  pcg_scatter_dot_alpha_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, p->d_yb, p->d_zv, p->d_s, p->d_q,
+                           p->d_fpart, p->d_ticket, st, p->d_gpart, p->ldg, s);
+  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
+  pcg_proj_apply(1, 0, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, p->d_r, p->d_q, p->d_s, p->d_lam, p->d_wv,
+                 nullptr, p->d_fpart, p->d_ticket + 1, st, nullptr, s);
+  // preconditioner
+  pcg_gather(p->di, 1, p->d_wv, p->d_xb, st, s);
+  const double* y = p->d_xb;
+  if (p->P.precond == FETI_PREC_LUMPED) {
+    pcg_lumped(p->di, p->P.w_bb, p->d_bb_col, p->d_bb_val, p->d_xb, p->d_yb, st, s);
+    y = p->d_yb;
+  } else if (p->P.precond == FETI_PREC_DIRICHLET) {
+    symv_local(p, p->d_S, p->d_xb, p->d_yb, st);
+    y = p->d_yb;
+  }
+  pcg_scatter_w_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, y, p->d_tv, st, p->d_gpart, p->ldg, s);
+  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
+  pcg_proj_apply(2, 0, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, p->d_tv, p->d_q, p->d_s, p->d_lam, p->d_zv,
+                 p->d_wv, p->d_fpart, p->d_ticket + 1, st, p->d_hist, s);
 }
 
 // Condition estimate from the recorded (alpha, beta): extreme eigenvalues of
@@ -386,6 +406,16 @@ feti_status setup_device(feti_problem* p) {
     p->di.r_b1 = r1;
     p->di.r_gdof = rg;
     p->di.b2full = b2f;
+    int32_t *cp, *cc;
+    double *cv0, *cv1;
+    TRY(upload(p, cp, P.c_ptr));
+    TRY(upload(p, cc, P.c_col));
+    TRY(upload(p, cv0, P.c_v0));
+    TRY(upload(p, cv1, P.c_v1));
+    p->di.c_ptr = cp;
+    p->di.c_col = cc;
+    p->di.c_v0 = cv0;
+    p->di.c_v1 = cv1;
   }
   // working memory
   const size_t e = elt(p);

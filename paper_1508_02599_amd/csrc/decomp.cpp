@@ -402,6 +402,39 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
       }
     }
   }
+  // ---- copy coupling C = B^T B and C~ = B^T diag(w) B: entry (b, b') sums
+  // c_{r,b} c_{r,b'} (times w_r) over the rows r holding both, so that
+  // B^T (B v) is one gather from v; columns ascending
+  P.c_ptr.assign(P.NB + 1, 0);
+  P.c_col.clear();
+  P.c_v0.clear();
+  P.c_v1.clear();
+  {
+    std::vector<std::pair<int64_t, std::pair<double, double>>> ent;
+    for (int64_t b = 0; b < P.NB; ++b) {
+      ent.clear();
+      for (int32_t k = P.g_ptr[b]; k < P.g_ptr[b + 1]; ++k) {
+        const int64_t r = P.g_row[k];
+        const double c = P.g_coef[k], w = P.r_w[r];
+        ent.push_back({P.r_b0[r], {c * P.r_c0[r], c * P.r_c0[r] * w}});
+        if (P.r_b1[r] >= 0) ent.push_back({P.r_b1[r], {c * P.r_c1[r], c * P.r_c1[r] * w}});
+      }
+      std::sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+      for (size_t i = 0; i < ent.size();) {
+        size_t j = i;
+        double v0 = 0.0, v1 = 0.0;
+        for (; j < ent.size() && ent[j].first == ent[i].first; ++j) {
+          v0 += ent[j].second.first;
+          v1 += ent[j].second.second;
+        }
+        P.c_col.push_back((int32_t)ent[i].first);
+        P.c_v0.push_back(v0);
+        P.c_v1.push_back(v1);
+        i = j;
+      }
+      P.c_ptr[b + 1] = (int32_t)P.c_col.size();
+    }
+  }
   P.b2full.resize(P.NB);
   P.b_sub.resize(P.NB);
   for (int s = 0; s < ns; ++s) {

@@ -98,6 +98,8 @@ struct HostPlan {
   std::vector<int32_t> g_ptr;           // [NB+1] multiplier rows touching each b entry
   std::vector<int32_t> g_row;
   std::vector<double> g_coef;
+  std::vector<int32_t> c_ptr, c_col;    // copy coupling B^T B in CSR over b-space
+  std::vector<double> c_v0, c_v1;       // values of B^T B and of B^T diag(w) B
   std::vector<int64_t> b2full;          // [NB]
   std::vector<int32_t> b_sub;           // [NB]
 

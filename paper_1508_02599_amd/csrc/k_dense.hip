@@ -137,74 +137,80 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks,
   for (int e = threadIdx.x; e < TS2; e += 256) C[e] += sA[(e >> 6) * LD + (e & 63)];
 }
 
-// Cholesky of the diagonal tile (j, j) in place (zeroing its upper part) and
-// its triangular inverse, by one wavefront.  Lane r keeps row r of the tile in
-// registers (loops fully unrolled); column c of L is broadcast through LDS and
-// the trailing update is a register FMA per entry.  For the inverse, lane j
-// keeps column j of L^{-1} in registers and reads L by broadcast.
-// Computed in FP64 whatever the storage type.  A non-positive or non-finite
-// pivot records the subdomain in err[0] (min).
+// Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
+// and the explicit inverse L_jj^{-1}.  One wave per tile with the tile in
+// registers (lane r holds row r, loops fully unrolled).  Each elimination
+// step broadcasts its pivot and then its column of L through LDS (single-wave
+// barriers), so a trailing update costs one broadcast LDS read and one
+// register FMA per entry.  The inverse (lane j holds column j) reads L back
+// from LDS by broadcast.  A non-positive or non-finite pivot records the
+// subdomain in *err.
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
                                              const SubInfo* __restrict__ subs, T* arena, T* linv,
                                              int* err) {
-  __shared__ double colv[TS];
-  __shared__ double sL[TS * LD], sI[TS * LD];
+  __shared__ double piv[TS], colv[TS];
+  __shared__ double sL[TS * LD];
   const Task t = tasks[blockIdx.x];
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
   T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
   const int r = threadIdx.x;
-  for (int c0 = 0; c0 < TS; c0 += 16) {
-    T v[16];
+  double a[TS];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = C[(c0 + i) * TS + r];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) sL[(c0 + i) * LD + r] = (double)v[i];
-  }
+  for (int c = 0; c < TS; ++c) a[c] = (double)C[c * TS + r];
   bool bad = false;
-  __syncthreads();
+  // right-looking elimination: a[cc] of lane r is A(r, cc); its lower part is kept
+#pragma unroll
   for (int c = 0; c < TS; ++c) {
-    const double d = sL[c * LD + c];
+    piv[r] = a[c];   // every lane stores (a store under a lane condition makes the compiler spill)
+    __syncthreads();
+    const double d = piv[c];
     const bool ok = (d > 0.0) && (d < 1e300);
     bad |= !ok;
     const double sd = sqrt(ok ? d : 1.0);
-    const double l = r > c ? sL[c * LD + r] / sd : (r == c ? sd : 0.0);
-    __syncthreads();
+    // two plain selects (a nested conditional here makes the compiler spill)
+    double l = a[c] / sd;
+    l = r > c ? l : 0.0;
+    l = r == c ? sd : l;
+    a[c] = l;
     colv[r] = l;
-    sL[c * LD + r] = l;
     __syncthreads();
-    // trailing update of row r; colv is a separate array, so the row updates
-    // are independent and pipeline (entries above the diagonal are scratch)
-#pragma unroll 8
-    for (int cc = c + 1; cc < TS; ++cc) sL[cc * LD + r] -= l * colv[cc];
+#pragma unroll
+    for (int cc = c + 1; cc < TS; ++cc) a[cc] -= l * colv[cc];
     __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
   }
-  // zero the upper triangle and write L back
-  for (int c = 0; c < TS; ++c)
-    if (c > r) sL[c * LD + r] = 0.0;
+#pragma unroll
+  for (int c = 0; c < TS; ++c) {
+    double v = a[c];
+    v = c > r ? 0.0 : v;
+    C[c * TS + r] = (T)v;
+    sL[c * LD + r] = v;
+  }
   __syncthreads();
-#pragma unroll 8
-  for (int c = 0; c < TS; ++c) C[c * TS + r] = (T)sL[c * LD + r];
-  // X = L^{-1}: lane j owns column j, kept in LDS (sI[j][.]):
-  // X(i,j) = (delta_ij - sum_{j<=k<i} L(i,k) X(k,j)) / L(i,i)
+  // X = L^{-1} with lane j holding column j:
+  // X(i, j) = (delta_ij - sum_{k<i} L(i, k) X(k, j)) / L(i, i), X(k, j) = 0 for k < j
   const int j = r;
+  double x[TS];
+#pragma unroll
   for (int i = 0; i < TS; ++i) {
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int k = j;
-    for (; k + 3 < i; k += 4) {
-      acc0 += sL[k * LD + i] * sI[j * LD + k];
-      acc1 += sL[(k + 1) * LD + i] * sI[j * LD + k + 1];
-      acc2 += sL[(k + 2) * LD + i] * sI[j * LD + k + 2];
-      acc3 += sL[(k + 3) * LD + i] * sI[j * LD + k + 3];
-    }
-    for (; k < i; ++k) acc0 += sL[k * LD + i] * sI[j * LD + k];
-    const double acc = (acc0 + acc1) + (acc2 + acc3);
-    sI[j * LD + i] = i < j ? 0.0 : ((i == j ? 1.0 : 0.0) - acc) / sL[i * LD + i];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < i; ++k) acc[k & 3] += sL[k * LD + i] * x[k];
+    const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    double xi = ((i == j ? 1.0 : 0.0) - sum) / sL[i * LD + i];
+    x[i] = i < j ? 0.0 : xi;
+    // keep the loads of later rows from being hoisted (register pressure)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < TS; ++i) sL[j * LD + i] = x[i];
+  __syncthreads();
 #pragma unroll 8
-  for (int c = 0; c < TS; ++c) Li[c * TS + r] = (T)sI[c * LD + r];
+  for (int c = 0; c < TS; ++c) Li[c * TS + r] = (T)sL[c * LD + r];
   if (bad) atomicMin(err, t.sub);
 }
 

@@ -20,6 +20,8 @@ struct DevIdx {
   const int32_t *g_ptr = nullptr, *g_row = nullptr, *b_sub = nullptr, *f_sub = nullptr;
   const double *g_coef = nullptr, *r_w = nullptr, *r_c0 = nullptr, *r_c1 = nullptr;
   const int64_t *r_b0 = nullptr, *r_b1 = nullptr, *r_gdof = nullptr, *b2full = nullptr;
+  const int32_t *c_ptr = nullptr, *c_col = nullptr;   // copy coupling B^T B (CSR over b)
+  const double *c_v0 = nullptr, *c_v1 = nullptr;      // B^T B, B^T diag(w) B
 };
 
 // --- dense factor kernels (k_dense.hip)
@@ -89,6 +91,13 @@ void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb
                   hipStream_t s);
 void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
                            int* ticket, PcgState* st, hipStream_t s);
+// Fused scatters that also form the coarse right-hand side of the next
+// projection from the interface vector (coarse = 0: no coarse space).
+void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
+                              const double* yb, const double* z, double* sv, double* q, double* part, int* ticket,
+                              PcgState* st, double* gpart, int ldg, hipStream_t s);
+void pcg_scatter_w_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
+                      const double* y, double* out, const PcgState* st, double* gpart, int ldg, hipStream_t s);
 void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* rbv, const double* x,
                  const double* q, int with_update, double* gpart, int ldg, const PcgState* st, hipStream_t s);
 void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int ldg, double* a, const PcgState* st,

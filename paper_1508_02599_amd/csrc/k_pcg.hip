@@ -5,6 +5,8 @@
 //
 // All reductions use a fixed partition and a fixed summation order, so a
 // solve gives bit-identical results whatever else runs on the device.
+#include <algorithm>
+
 #include "feti_impl.h"
 #include "k_pcg.h"
 
@@ -370,12 +372,13 @@ __global__ void k_init_state(PcgState* st, double rtol, double atol, int max_it,
 
 // last-arriving block of a grid: thread 0 publishes the block's partial sums,
 // fences and takes a ticket; the block that draws the last ticket reduces.
-__device__ bool last_block(int* ticket) {
+__device__ bool last_block(int* ticket, int nblocks = -1) {
   __shared__ bool last;
+  if (nblocks < 0) nblocks = (int)gridDim.x;
   if (threadIdx.x == 0) {
     __threadfence();
     const int t = atomicAdd(ticket, 1);
-    last = (t == (int)gridDim.x - 1);
+    last = (t == nblocks - 1);
   }
   __syncthreads();
   if (last) __threadfence();
@@ -400,6 +403,41 @@ __device__ void block_reduce2(double& a, double& b, double* ra, double* rb) {
   __syncthreads();
   a = (ra[0] + ra[1]) + (ra[2] + ra[3]);
   b = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+}
+
+constexpr int GT_CHUNKS = 4;
+
+// One chunk of g = Rb^T (C v) for subdomain `sub`, with C a copy coupling
+// (B^T B or B^T diag(w) B, CSR over b-space): the coarse right-hand side
+// G^T (B v) straight from an interface vector v, without the row vector.
+// Writes gpart[chunk][coarse_off + m].  Called by a whole block.
+__device__ void gt_chunk(int sub, int chunk, const SubInfo* __restrict__ subs, const int32_t* __restrict__ c_ptr,
+                         const int32_t* __restrict__ c_col, const double* __restrict__ cv,
+                         const double* __restrict__ rbv, const double* __restrict__ v, double* gpart, int ldg) {
+  __shared__ double red[6][4];
+  const SubInfo s = subs[sub];
+  if (s.n_modes == 0) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t nb = (int64_t)s.nt_b * TS;
+  const int64_t lo = nb * chunk / GT_CHUNKS, hi = nb * (chunk + 1) / GT_CHUNKS;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
+    const int64_t b = s.b_off + k;
+    const int e0 = c_ptr[b], e1 = c_ptr[b + 1];
+    double u = 0.0;
+    for (int e = e0; e < e1; ++e) u += cv[e] * v[c_col[e]];
+    const double* R = rbv + b * 6;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc[m] += R[m] * u;
+  }
+#pragma unroll
+  for (int m = 0; m < 6; ++m) acc[m] = wave_sum(acc[m]);
+  if ((threadIdx.x & 63) == 0)
+    for (int m = 0; m < 6; ++m) red[m][threadIdx.x >> 6] = acc[m];
+  __syncthreads();
+  if (threadIdx.x < s.n_modes) {
+    const int m = threadIdx.x;
+    gpart[(int64_t)chunk * ldg + s.coarse_off + m] = (red[m][0] + red[m][1]) + (red[m][2] + red[m][3]);
+  }
 }
 
 // xb = B^T (z + beta s)
@@ -454,10 +492,75 @@ __global__ __launch_bounds__(256) void k_scatter_dot_alpha(
   }
 }
 
+// Fused: blocks [0, nrow_blocks) do q = B yb, s <- z + beta s and
+// alpha = rho / (s.q) (breakdown if s.q <= 0); the blocks after them form the
+// coarse right-hand side G^T q = Rb^T (B^T B) yb by subdomain chunks.
+__global__ __launch_bounds__(256) void k_scatter_dot_alpha_gt(
+    int64_t n, int nrow_blocks, const int64_t* __restrict__ b0, const double* __restrict__ c0,
+    const int64_t* __restrict__ b1, const double* __restrict__ c1, const double* __restrict__ yb,
+    const double* __restrict__ z, double* sv, double* q, double* part, int* ticket, PcgState* st,
+    const SubInfo* __restrict__ subs, const int32_t* __restrict__ c_ptr, const int32_t* __restrict__ c_col,
+    const double* __restrict__ cv, const double* __restrict__ rbv, double* gpart, int ldg) {
+  if (st->done) return;
+  if ((int)blockIdx.x >= nrow_blocks) {
+    const int g = blockIdx.x - nrow_blocks;
+    gt_chunk(g / GT_CHUNKS, g % GT_CHUNKS, subs, c_ptr, c_col, cv, rbv, yb, gpart, ldg);
+    return;
+  }
+  __shared__ double ra[256], rb[256];
+  double acc = 0.0, unused = 0.0;
+  const double beta = st->beta;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)nrow_blocks * 256) {
+    double v = c0[r] * yb[b0[r]];
+    if (b1[r] >= 0) v += c1[r] * yb[b1[r]];
+    const double sn = z[r] + beta * sv[r];
+    sv[r] = sn;
+    q[r] = v;
+    acc += sn * v;
+  }
+  block_reduce2(acc, unused, ra, rb);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (!last_block(ticket, nrow_blocks)) return;
+  double pq = 0.0;
+  for (int k = threadIdx.x; k < nrow_blocks; k += 256) pq += part[k];
+  block_reduce2(pq, unused, ra, rb);
+  if (threadIdx.x == 0) {
+    *ticket = 0;
+    st->pq = pq;
+    if (!(pq > 0.0)) {
+      st->alpha = 0.0;
+      st->done = 1;
+      st->status = FETI_EBREAKDOWN;
+    } else {
+      st->alpha = st->rho / pq;
+    }
+  }
+}
+
+// Fused: blocks [0, nrow_blocks) do the weighted scatter t = diag(w) B y;
+// the blocks after them form G^T t = Rb^T (B^T diag(w) B) y by subdomain chunks.
+__global__ __launch_bounds__(256) void k_scatter_w_gt(
+    int64_t n, int nrow_blocks, const int64_t* __restrict__ b0, const double* __restrict__ c0,
+    const int64_t* __restrict__ b1, const double* __restrict__ c1, const double* __restrict__ w,
+    const double* __restrict__ y, double* __restrict__ out, const PcgState* st, const SubInfo* __restrict__ subs,
+    const int32_t* __restrict__ c_ptr, const int32_t* __restrict__ c_col, const double* __restrict__ cv,
+    const double* __restrict__ rbv, double* gpart, int ldg) {
+  if (halted(st)) return;
+  if ((int)blockIdx.x >= nrow_blocks) {
+    const int g = blockIdx.x - nrow_blocks;
+    gt_chunk(g / GT_CHUNKS, g % GT_CHUNKS, subs, c_ptr, c_col, cv, rbv, y, gpart, ldg);
+    return;
+  }
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)nrow_blocks * 256) {
+    double v = c0[r] * y[b0[r]];
+    if (b1[r] >= 0) v += c1[r] * y[b1[r]];
+    out[r] = w[r] * v;
+  }
+}
+
 // Partial g = Rb^T B^T x per floating subdomain, in GT_CHUNKS chunks of its
 // interface (gpart[chunk][coarse index]); with_update: x is r - alpha q
 // (formed on the fly).
-constexpr int GT_CHUNKS = 4;
 __global__ __launch_bounds__(256) void k_proj_gt(const SubInfo* __restrict__ subs, const int32_t* __restrict__ g_ptr,
                                                  const int32_t* __restrict__ g_row, const double* __restrict__ g_coef,
                                                  const double* __restrict__ rbv, const double* __restrict__ x,
@@ -545,7 +648,9 @@ __global__ void k_fill_bco(int64_t NB, const int32_t* __restrict__ b_sub, const 
 
 // Per multiplier row:
 //  mode 0: out = x - G ac
-//  mode 1: r <- r - alpha q, lam <- lam + alpha s, out = r - G ac
+//  mode 1: r <- r - alpha q, lam <- lam + alpha s, w <- w - alpha (q - G ac) with
+//          ac = Q^{-1} G^T q: the projected residual w = P r follows r (x is r,
+//          out is w)
 //  mode 2: out = x - G ac, then rho' = w.out, ||w||, beta, convergence (init: first evaluation)
 __global__ __launch_bounds__(256) void k_proj_apply(
     int mode, int init, int64_t n, int coarse, const int64_t* __restrict__ b0, const double* __restrict__ c0,
@@ -558,18 +663,20 @@ __global__ __launch_bounds__(256) void k_proj_apply(
   const double alpha = mode == 1 ? st->alpha : 0.0;
   double d1 = 0.0, d2 = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
-    double xr = x[r];
-    if (mode == 1) {
-      xr -= alpha * q[r];
-      x[r] = xr;
-      lam[r] += alpha * sv[r];
-    }
     double ga = 0.0;
     if (coarse) {
       ga = c0[r] * g_alpha(b0[r], bco, rbv, ac);
       if (b1[r] >= 0) ga += c1[r] * g_alpha(b1[r], bco, rbv, ac);
     }
-    const double o = xr - ga;
+    double o;
+    if (mode == 1) {
+      const double qr = q[r];
+      x[r] -= alpha * qr;
+      lam[r] += alpha * sv[r];
+      o = out[r] - alpha * (qr - ga);
+    } else {
+      o = x[r] - ga;
+    }
     out[r] = o;
     if (mode == 2) {
       d1 += w[r] * o;
@@ -840,6 +947,20 @@ void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb
 void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
                            int* ticket, PcgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter_dot_alpha, dim3(FUSE_BLOCKS), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, yb, z, sv, q, part, ticket, st);
+}
+void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
+                              const double* yb, const double* z, double* sv, double* q, double* part, int* ticket,
+                              PcgState* st, double* gpart, int ldg, hipStream_t s) {
+  const int nb = FUSE_BLOCKS + (coarse ? GT_CHUNKS * n_sub : 0);
+  hipLaunchKernelGGL(k_scatter_dot_alpha_gt, dim3(nb), dim3(256), 0, s, d.n_lam, FUSE_BLOCKS, d.r_b0, d.r_c0, d.r_b1,
+                     d.r_c1, yb, z, sv, q, part, ticket, st, subs, d.c_ptr, d.c_col, d.c_v0, rbv, gpart, ldg);
+}
+void pcg_scatter_w_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
+                      const double* y, double* out, const PcgState* st, double* gpart, int ldg, hipStream_t s) {
+  const int nrow = (int)std::min<int64_t>(FUSE_BLOCKS, (d.n_lam + 255) / 256);
+  const int nb = nrow + (coarse ? GT_CHUNKS * n_sub : 0);
+  if (nb) hipLaunchKernelGGL(k_scatter_w_gt, dim3(nb), dim3(256), 0, s, d.n_lam, nrow, d.r_b0, d.r_c0, d.r_b1, d.r_c1,
+                             d.r_w, y, out, st, subs, d.c_ptr, d.c_col, d.c_v1, rbv, gpart, ldg);
 }
 void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* rbv, const double* x,
                  const double* q, int with_update, double* gpart, int ldg, const PcgState* st, hipStream_t s) {
