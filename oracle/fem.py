@@ -282,17 +282,20 @@ def _elem_material(mesh):
     return m
 
 
-def element_matrices(mesh, U=None, chunk=4096):
-    """Element tangents and internal forces for every element of ``mesh``.
+def element_matrices(mesh, U=None, chunk=4096, elems=None):
+    """Element tangents and internal forces for every element of ``mesh``
+    (or the elements listed in ``elems``).
 
     Linear material: K_e = int B^T D B and f_int = K_e u_e.  HGO: exact tangent
     and internal force at displacement U (global [n_nodes,3] or None = 0).
     """
     from workloads.meshes import MAT_HGO
-    ne = mesh.n_elems
-    Xe = mesh.xyz[mesh.hex8]
-    Ue = np.zeros_like(Xe) if U is None else np.asarray(U).reshape(-1, 3)[mesh.hex8]
-    m = _elem_material(mesh)
+    el = np.arange(mesh.n_elems) if elems is None else np.asarray(elems)
+    ne = el.size
+    hex8 = mesh.hex8[el]
+    Xe = mesh.xyz[hex8]
+    Ue = np.zeros_like(Xe) if U is None else np.asarray(U).reshape(-1, 3)[hex8]
+    m = _elem_material(mesh)[el]
     Ke = np.empty((ne, 24, 24))
     fe = np.zeros((ne, 24))
     hgo = m[:, 0] == MAT_HGO
@@ -309,8 +312,8 @@ def element_matrices(mesh, U=None, chunk=4096):
         for s in range(0, idx.size, chunk):
             ii = idx[s:s + chunk]
             mm = m[ii]
-            a1 = mesh.fibers[ii, 0]
-            a2 = mesh.fibers[ii, 1]
+            a1 = mesh.fibers[el[ii], 0]
+            a2 = mesh.fibers[el[ii], 1]
             K, f = hgo_element_tangent(Xe[ii], Ue[ii], a1, a2, mm[:, 3], mm[:, 4], mm[:, 5],
                                        mm[:, 6])
             Ke[ii] = K
@@ -343,3 +346,58 @@ def assemble(mesh, U=None, tau=1.0):
         pd = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).ravel()
         f_ext += np.bincount(pd, weights=fp.ravel(), minlength=n)
     return K, f_int, tau * f_ext
+
+
+def nodal_residual(mesh, nodes, u, U=None, tau=1.0):
+    """Rows of the linear(ised) system at sampled nodes, from the elements and
+    pressure faces around them only.
+
+    The system is K'(U) u = tau f_ext(U) - f_int(U) (U = None: the linear
+    problem K u = tau f_ext).  Returns (res, scale), both [len(nodes), 3]:
+    res = tau f_ext - f_int - K' u on each DOF of the nodes, and scale = the
+    sum of the magnitudes of the element and load terms of that row, so that
+    |res| / scale is a componentwise relative residual.  Rows of Dirichlet
+    DOFs are returned as 0 with scale 1.
+    """
+    nodes = np.asarray(nodes, dtype=np.int64)
+    u = np.asarray(u, dtype=np.float64).reshape(-1, 3)
+    elems = np.nonzero(np.isin(mesh.hex8, nodes).any(axis=1))[0]
+    Ke, fe = element_matrices(mesh, U, elems=elems)
+    hex8 = mesh.hex8[elems]
+    ue = u[hex8].reshape(-1, 24)
+    Ku = np.einsum("eij,ej->ei", Ke, ue)
+    pos = {int(n): k for k, n in enumerate(nodes)}
+    res = np.zeros((nodes.size, 3))
+    scale = np.zeros((nodes.size, 3))
+    loc = np.array([[pos.get(int(n), -1) for n in row] for row in hex8])
+    fb = None
+    if mesh.body_force is not None:
+        fb = body_force_vector(mesh.xyz[hex8], mesh.body_force[elems])
+    for e in range(elems.size):
+        for a in range(8):
+            k = loc[e, a]
+            if k < 0:
+                continue
+            sl = slice(3 * a, 3 * a + 3)
+            res[k] -= Ku[e, sl] + (0.0 if U is None else fe[e, sl])
+            scale[k] += np.abs(Ke[e, sl, :]) @ np.abs(ue[e]) + (0.0 if U is None else np.abs(fe[e, sl]))
+            if fb is not None:
+                res[k] += tau * fb[e, sl]
+                scale[k] += np.abs(tau * fb[e, sl])
+    if mesh.pface is not None and mesh.pressure != 0.0:
+        faces = np.nonzero(np.isin(mesh.pface, nodes).any(axis=1))[0]
+        if faces.size:
+            x = mesh.xyz + (0.0 if U is None else np.asarray(U).reshape(-1, 3))
+            fp = pressure_face_load(x[mesh.pface[faces]], mesh.pressure)
+            for q, f in enumerate(faces):
+                for a in range(4):
+                    k = pos.get(int(mesh.pface[f, a]), -1)
+                    if k >= 0:
+                        res[k] += tau * fp[q, a]
+                        scale[k] += np.abs(tau * fp[q, a])
+    dmask = np.zeros(mesh.n_dofs, dtype=bool)
+    dmask[mesh.dir_dof] = True
+    dm = dmask.reshape(-1, 3)[nodes]
+    res[dm] = 0.0
+    scale[dm] = 1.0
+    return res, scale

@@ -1,0 +1,295 @@
+"""Serving loop: FETI solves and Newton steps of different meshes on one GPU.
+
+Requests arrive over time (open loop).  A request is admitted as soon as a
+worker slot is free and the device memory it needs fits the budget: an idle
+problem of the same mesh is reused (its device-resident decomposition, and for
+linear problems its factors, are kept between requests); otherwise a new
+problem is set up, after evicting idle problems of other meshes
+(least recently used first) if the budget requires it.  Admitted requests run
+concurrently, each problem on its own HIP stream, so work arriving while
+others are on the GPU overlaps with them.  Every reduction of the library has a
+fixed order and each problem owns its buffers, so a request's result does not
+depend on what else runs.
+
+    python -m paper_1508_02599_amd.serve [--requests 64] [--rates 0.5,1,2]
+                                         [--precision fp64|mixed] [--workers 4]
+
+prints one JSON line per arrival rate: throughput (requests/s), p50/p99
+latency from arrival to result, and the mix of work served.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import threading
+import time
+from collections import OrderedDict
+
+import numpy as np
+
+from .feti import Problem
+
+
+class Request:
+    def __init__(self, rid, key, kind, param, arrival):
+        self.rid, self.key, self.kind, self.param, self.arrival = rid, key, kind, param, arrival
+        self.result = None
+        self.error = None
+        self.t_start = self.t_done = None
+        self.iters = 0
+        self.done = threading.Event()
+
+    @property
+    def latency(self):
+        return self.t_done - self.arrival
+
+
+class _Slot:
+    """A set-up problem of one mesh: device memory held until evicted."""
+
+    def __init__(self, key, problem, footprint):
+        self.key, self.p, self.bytes = key, problem, footprint
+        self.factored_linear = False
+        self.busy = False
+
+
+class Server:
+    """Admission by slots and device memory; see the module docstring.
+
+    mesh_fn(key) builds the mesh of a request key; options are passed to every
+    problem (variant, precond, precision, rtol, ...)."""
+
+    def __init__(self, mesh_fn, workers=4, hbm_budget=200 << 30, options_for=None, **options):
+        self.mesh_fn = mesh_fn
+        self.options = dict(variant="af", precond="lumped", rtol=1e-8, max_it=10000)
+        self.options.update(options)
+        self.options_for = options_for     # key -> overrides of the problem options
+        self.budget = int(hbm_budget)
+        self.held = 0
+        self.slots: list[_Slot] = []
+        self.lru: OrderedDict = OrderedDict()   # idle slots, oldest first
+        self.meshes = {}
+        self.est = {}                            # key -> footprint of a problem of that mesh
+        self.pending: list[Request] = []
+        self.lock = threading.Condition()
+        self.closed = False
+        self.nworkers = workers
+        self.free_workers = workers
+        self.jobs: list = []
+        self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(workers)]
+        for t in self.threads:
+            t.start()
+
+    # ------------------------------------------------------------------ public
+    def submit(self, req: Request):
+        with self.lock:
+            self.pending.append(req)
+            self._admit()
+            self.lock.notify_all()
+
+    def close(self):
+        with self.lock:
+            self.closed = True
+            self.lock.notify_all()
+        for t in self.threads:
+            t.join()
+        for s in self.slots:
+            s.p.close()
+        self.slots.clear()
+
+    def mesh(self, key):
+        if key not in self.meshes:
+            self.meshes[key] = self.mesh_fn(key)
+        return self.meshes[key]
+
+    # ---------------------------------------------------------------- internal
+    def _estimate(self, key):
+        """Device bytes of a new problem of this mesh: measured once a problem
+        of it exists, else a bound from its subdomain sizes (dense tile arenas
+        for the factor, the interior and interface inverses, plus 20%)."""
+        if key in self.est:
+            return self.est[key]
+        m = self.mesh(key)
+        sub_nodes = np.zeros(m.n_sub)
+        for s in range(m.n_sub):
+            sub_nodes[s] = np.unique(m.hex8[m.elem_sub == s]).size
+        nt = np.ceil(3 * sub_nodes / 64) + 2
+        tiles = (nt * (nt + 1) / 2).sum()
+        elt = 4 if self.options.get("precision") == "mixed" else 8
+        # factor arena, plus interior and interface inverses (about half of it),
+        # plus sparse rows (81 entries of value and index per local DOF)
+        return int(2.0 * tiles * 64 * 64 * elt + 81 * 12 * 3 * sub_nodes.sum())
+
+    def _admit(self):
+        """Start pending requests (in arrival order) while slots and memory allow."""
+        i = 0
+        while i < len(self.pending) and self.free_workers > 0:
+            req = self.pending[i]
+            slot = next((s for s in self.slots if s.key == req.key and not s.busy), None)
+            need = 0 if slot else self._estimate(req.key)
+            if slot is None and self.held + need > self.budget:
+                # evict idle problems of other meshes, least recently used first
+                for s in list(self.lru.values()):
+                    if self.held + need <= self.budget:
+                        break
+                    if s.key != req.key:
+                        self._evict(s)
+            if slot is None and self.held + need > self.budget:
+                if self.slots or self.held > 0:
+                    i += 1      # wait for memory; later requests of resident meshes may still run
+                    continue
+                # nothing resident: try it (the measured footprint decides after setup)
+                need = min(need, self.budget)
+            self.pending.pop(i)
+            if slot is not None:
+                slot.busy = True
+                self.lru.pop(id(slot), None)
+            else:
+                self.held += need
+            self.free_workers -= 1
+            self.jobs.append((req, slot, need))
+            self.lock.notify_all()
+
+    def _evict(self, s: _Slot):
+        self.lru.pop(id(s), None)
+        self.slots.remove(s)
+        self.held -= s.bytes
+        s.p.close()
+
+    def _worker(self):
+        while True:
+            with self.lock:
+                while not self.jobs and not self.closed:
+                    self.lock.wait()
+                if not self.jobs:
+                    return
+                req, slot, reserved = self.jobs.pop(0)
+            req.t_start = time.perf_counter()
+            try:
+                if slot is None:
+                    opts = dict(self.options)
+                    if self.options_for is not None:
+                        opts.update(self.options_for(req.key))
+                    p = Problem(self.mesh(req.key), **opts)
+                    fp = p.footprint()
+                    if fp > self.budget:
+                        p.close()
+                        with self.lock:
+                            self.est[req.key] = fp
+                        raise MemoryError(f"problem needs {fp} bytes, budget {self.budget}")
+                    slot = _Slot(req.key, p, fp)
+                    slot.busy = True
+                    with self.lock:
+                        self.est[req.key] = fp
+                        self.held += fp - reserved
+                        self.slots.append(slot)
+                self._run(req, slot)
+            except Exception as e:   # reported on the request
+                req.error = f"{type(e).__name__}: {e}"
+            req.t_done = time.perf_counter()
+            with self.lock:
+                if slot is not None and slot in self.slots:
+                    slot.busy = False
+                    self.lru[id(slot)] = slot
+                elif slot is None:
+                    self.held -= reserved
+                self.free_workers += 1
+                self._admit()
+                self.lock.notify_all()
+            req.done.set()
+
+    def _run(self, req: Request, slot: _Slot):
+        p = slot.p
+        if req.kind == "solve":
+            if not slot.factored_linear:
+                p.factor()
+                slot.factored_linear = True
+            u, st = p.solve(load_factor=req.param)
+        else:
+            U = np.zeros(p.n_dof)
+            u, _, st = p.newton_step(U, req.param)
+            slot.factored_linear = False
+        req.result = u
+        req.iters = st["iters"]
+
+
+def run_stream(server: Server, stream, t0=None):
+    """Submit the requests of `stream` at their arrival times (relative to
+    t0) and wait for all; returns the Request objects."""
+    t0 = time.perf_counter() if t0 is None else t0
+    reqs = []
+    for k, r in enumerate(stream):
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        req = Request(k, r["key"], r["kind"], r["param"], t0 + r["t"])
+        reqs.append(req)
+        server.submit(req)
+    for r in reqs:
+        r.done.wait()
+    return reqs
+
+
+def summary(reqs, wall):
+    ok = [r for r in reqs if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    return {"requests": len(reqs), "failed": len(reqs) - len(ok),
+            "throughput_req_per_s": len(ok) / wall if wall > 0 else None,
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                           "p99": 1e3 * float(np.percentile(lat, 99)),
+                           "mean": 1e3 * float(lat.mean())},
+            "solves": sum(r.kind == "solve" for r in ok),
+            "newton_steps": sum(r.kind == "newton" for r in ok),
+            "pcg_iterations": int(sum(r.iters for r in ok)),
+            "errors": sorted({r.error for r in reqs if r.error})[:3]}
+
+
+def tube_dirichlet(key):
+    """Tube requests (nearly incompressible HGO) use the Dirichlet preconditioner."""
+    return dict(precond="dirichlet") if key[0].startswith("tube") else {}
+
+
+def main():
+    from workloads import request_mesh, request_stream
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rates", default="0.5,1,2,4", help="arrival rates, requests/s")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--budget-gib", type=float, default=200.0)
+    ap.add_argument("--cube-k", default="2,8")
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    ck = tuple(int(x) for x in a.cube_k.split(","))
+    kw = dict(precision=a.precision)
+    if a.precision == "mixed":
+        kw.update(rtol=1e-6, ir_tol=1e-8)
+    srv = Server(request_mesh, workers=a.workers, hbm_budget=int(a.budget_gib * 2**30),
+                 options_for=tube_dirichlet, **kw)
+    try:
+        # warm-up (not timed): one request per distinct mesh sets up its problem
+        seen = {}
+        for rate in (float(x) for x in a.rates.split(",")):
+            for r in request_stream(a.requests, rate, seed=a.seed, cube_k=ck):
+                seen.setdefault(r["key"], dict(r, t=0.0))
+        t0 = time.perf_counter()
+        run_stream(srv, list(seen.values()))
+        print(json.dumps({"warmup_meshes": len(seen), "warmup_s": time.perf_counter() - t0,
+                          "held_gib": srv.held / 2**30}), flush=True)
+        for rate in (float(x) for x in a.rates.split(",")):
+            stream = request_stream(a.requests, rate, seed=a.seed, cube_k=ck)
+            t0 = time.perf_counter()
+            reqs = run_stream(srv, stream, t0)
+            wall = max(r.t_done for r in reqs) - t0
+            line = {"metric": "served FETI requests", "precision": a.precision, "arrival_rate": rate,
+                    "workers": a.workers, "budget_gib": a.budget_gib, "wall_s": wall}
+            line.update(summary(reqs, wall))
+            print(json.dumps(line), flush=True)
+    finally:
+        srv.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,59 @@
+"""Served mix of FETI solves and Newton steps (different meshes and subdomain
+counts, running concurrently on their own streams): every result equals the
+result of the same request run alone, and admission under a small device
+memory budget (evicting idle problems) serves every request."""
+import numpy as np
+import pytest
+
+from workloads import request_mesh, request_stream
+
+pytestmark = pytest.mark.gpu
+
+KEYS = [("cube", 2), ("cube", 3), ("tube_small", 4), ("tube_small", 8)]
+
+
+def _stream(n=12, seed=1):
+    s = request_stream(n, rate=1e6, seed=seed, cube_k=(2, 3), tube_subs=(4, 8), tube_kind="tube_small")
+    return s
+
+
+def _alone(stream, fps=None):
+    from paper_1508_02599_amd.feti import Problem
+    from paper_1508_02599_amd.serve import tube_dirichlet
+    out = []
+    for r in stream:
+        opts = dict(variant="af", precond="lumped", rtol=1e-8, max_it=10000)
+        opts.update(tube_dirichlet(r["key"]))
+        with Problem(request_mesh(r["key"]), **opts) as p:
+            if fps is not None:
+                fps.append(p.footprint())
+            if r["kind"] == "solve":
+                p.factor()
+                u, _ = p.solve(load_factor=r["param"])
+            else:
+                u, _, _ = p.newton_step(np.zeros(p.n_dof), r["param"])
+        out.append(u)
+    return out
+
+
+@pytest.mark.parametrize("tight", [False, True])
+def test_served_results_equal_alone(tight):
+    """tight: the budget holds the largest problem with 20% to spare, so
+    requests of other meshes wait and idle problems are evicted."""
+    from paper_1508_02599_amd.serve import Server, run_stream, summary, tube_dirichlet
+    stream = _stream()
+    fps = []
+    ref = _alone(stream, fps)
+    budget = int(1.2 * max(fps)) if tight else 64 << 30
+    srv = Server(request_mesh, workers=3, hbm_budget=budget, options_for=tube_dirichlet)
+    try:
+        reqs = run_stream(srv, stream)
+        held_max = srv.held
+    finally:
+        srv.close()
+    s = summary(reqs, max(r.t_done for r in reqs) - min(r.arrival for r in reqs))
+    print(f"budget {budget / 2**30:.3f} GiB: {s}")
+    assert s["failed"] == 0, s["errors"]
+    for r, u in zip(reqs, ref):
+        d = float(np.abs(r.result - u).max() / np.abs(u).max())
+        assert d <= 1e-12, (r.key, r.kind, d)

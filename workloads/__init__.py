@@ -7,7 +7,7 @@ forces and pressure faces.  It contains none of the solver's arithmetic
 and the GPU path can both consume its output without sharing any method code.
 """
 from .meshes import (Mesh, cube_mesh, random_box_cube, tube_mesh, box_partition,
-                     kelvin_displacement, config_mesh, CONFIGS)
+                     kelvin_displacement, config_mesh, CONFIGS, request_mesh, request_stream)
 
 __all__ = ["Mesh", "cube_mesh", "random_box_cube", "tube_mesh", "box_partition",
-           "kelvin_displacement", "config_mesh", "CONFIGS"]
+           "kelvin_displacement", "config_mesh", "CONFIGS", "request_mesh", "request_stream"]

@@ -297,3 +297,46 @@ def config_mesh(name: str, **over) -> Mesh:
     if kind == "random":
         return random_box_cube(**cfg)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# served request stream
+# ---------------------------------------------------------------------------
+TUBE_SUBS = {64: (1, 8, 8), 128: (1, 16, 8), 256: (1, 16, 16)}
+
+
+def request_mesh(key):
+    """Mesh of a served request: ("cube", k) = unit cube of (8k)^3 Q1 elements
+    in k^3 boxes of 8^3 with nu per box from seed 0; ("tube", p) = the
+    16x128x64 two-layer tube in p subdomains; ("tube_small", p) = a 2x16x8
+    tube in 1 x p/2 x 2 subdomains (tests)."""
+    kind, n = key
+    if kind == "cube":
+        return config_mesh("cube32_s4", n_el=8 * n, n_sub_axis=n)
+    if kind == "tube":
+        return tube_mesh(16, 128, 64, sub=TUBE_SUBS[n])
+    if kind == "tube_small":
+        return tube_mesh(2, 16, 8, sub=(1, n // 2, 2))
+    raise KeyError(key)
+
+
+def request_stream(n, rate, seed=0, cube_k=(2, 8), tube_subs=(64, 128, 256), tube_kind="tube"):
+    """n requests with Poisson arrivals of the given rate (per second): half
+    cube linear solves with k^3 subdomains, k uniform in cube_k (inclusive),
+    and a load factor uniform in [0.5, 2]; half tube Newton steps from rest at
+    load factor tau = s/10, s uniform in 1..10, on one of tube_subs
+    subdomain counts.  Returns a list of dicts (arrival time in s, key, kind,
+    parameter)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for k in range(n):
+        if rng.random() < 0.5:
+            kk = int(rng.integers(cube_k[0], cube_k[1] + 1))
+            out.append(dict(t=float(t[k]), key=("cube", kk), kind="solve",
+                            param=float(rng.uniform(0.5, 2.0))))
+        else:
+            p = int(rng.choice(tube_subs))
+            out.append(dict(t=float(t[k]), key=(tube_kind, p), kind="newton",
+                            param=float(rng.integers(1, 11)) / 10.0))
+    return out
