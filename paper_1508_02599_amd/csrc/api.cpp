@@ -92,6 +92,7 @@ struct feti_problem {
   int* d_ticket = nullptr;
   double *d_fpart = nullptr, *d_qdense = nullptr, *d_gpart = nullptr;
   int32_t* d_bco = nullptr;
+  int2* d_rco = nullptr;     // per multiplier row: coarse codes of its two entries
   int ldg = 0;
   int hist_cap = 0;
   // graph
@@ -160,17 +161,21 @@ feti_status upload(feti_problem* p, T*& out, const std::vector<T>& v) {
 size_t elt(const feti_problem* p) { return p->P.mixed ? sizeof(float) : sizeof(double); }
 
 // Dense launches on the subdomain batch in the working precision.
+bool is_update(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI || kind == K_UPD_TRTRI_INT; }
+
 void dense(feti_problem* p, const HostPlan::Launch& L) {
   const Task* t = p->d_tasks + L.first;
-  const bool timed = p->profile && L.kind == K_UPDATE && L.count > 0 &&
+  const bool timed = p->profile && is_update(L.kind) && L.count > 0 &&
                      2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
+  // the interior inverse goes to its own arena
+  void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], p->stream);
   if (p->P.mixed)
-    launch_dense<float>(L.kind, t, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)p->d_W,
-                        (float*)p->d_X, p->d_err, p->stream);
+    launch_dense<float>(L.kind, t, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
+                        (float*)p->d_X, p->d_err, p->stream, L.split);
   else
-    launch_dense<double>(L.kind, t, L.count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv,
-                         (double*)p->d_W, (double*)p->d_X, p->d_err, p->stream);
+    launch_dense<double>(L.kind, t, L.count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
+                         (double*)p->d_X, p->d_err, p->stream, L.split);
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], p->stream);
 }
 
@@ -223,7 +228,7 @@ void project_fused(feti_problem* p, int mode, int init, double* x, double* out, 
     pcg_proj_gt(p->P.n_sub, p->d_sub, p->di, p->d_rb, x, p->d_q, mode == 1, p->d_gpart, p->ldg, st, p->stream);
     pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, p->stream);
   }
-  pcg_proj_apply(mode, init, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, x, p->d_q, p->d_s, p->d_lam, out, w,
+  pcg_proj_apply(mode, init, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, x, p->d_q, p->d_s, p->d_lam, out, w,
                  p->d_fpart, p->d_ticket + 1, st, hist, p->stream);
 }
 
@@ -263,7 +268,7 @@ void pcg_iteration(feti_problem* p) {
   pcg_scatter_dot_alpha_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, p->d_yb, p->d_zv, p->d_s, p->d_q,
                            p->d_fpart, p->d_ticket, st, p->d_gpart, p->ldg, s);
   if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
-  pcg_proj_apply(1, 0, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, p->d_r, p->d_q, p->d_s, p->d_lam, p->d_wv,
+  pcg_proj_apply(1, 0, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, p->d_r, p->d_q, p->d_s, p->d_lam, p->d_wv,
                  nullptr, p->d_fpart, p->d_ticket + 1, st, nullptr, s);
   // preconditioner
   pcg_gather(p->di, 1, p->d_wv, p->d_xb, st, s);
@@ -277,7 +282,7 @@ void pcg_iteration(feti_problem* p) {
   }
   pcg_scatter_w_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, y, p->d_tv, st, p->d_gpart, p->ldg, s);
   if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
-  pcg_proj_apply(2, 0, p->di, nc > 0, p->d_bco, p->d_rb, p->d_calpha, p->d_tv, p->d_q, p->d_s, p->d_lam, p->d_zv,
+  pcg_proj_apply(2, 0, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, p->d_tv, p->d_q, p->d_s, p->d_lam, p->d_zv,
                  p->d_wv, p->d_fpart, p->d_ticket + 1, st, p->d_hist, s);
 }
 
@@ -514,6 +519,7 @@ feti_status setup_device(feti_problem* p) {
   p->ldg = max_coarse;
   TRY(dalloc(p, p->d_gpart, (size_t)4 * max_coarse));
   TRY(dalloc(p, p->d_bco, (size_t)P.NB));
+  TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
@@ -524,8 +530,9 @@ feti_status setup_device(feti_problem* p) {
     for (auto& ev : p->ev_upd) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
   }
   // algorithmic work: bytes of the packed symmetric interface inverses read by
-  // one GEMV, and flops of the tile updates counted on real (unpadded) rows,
-  // lower triangle only for diagonal tiles
+  // one GEMV, and flops of the update launches counted on real (unpadded)
+  // rows: tile updates (lower triangle only for diagonal tiles) and the rows
+  // of the factor inverses fused into them
   {
     const double es = (double)elt(p);
     double bytes = 0.0, fl = 0.0;
@@ -535,14 +542,25 @@ feti_status setup_device(feti_problem* p) {
       return std::min(TS, si.n_b - (t - si.nt_i) * TS);
     };
     auto add = [&](const HostPlan::Launch& L) {
-      if (L.kind != K_UPDATE) return;
+      if (!is_update(L.kind)) return;
+      const int nupd = L.kind == K_UPDATE ? L.count : L.split;
       for (int k = 0; k < L.count; ++k) {
         const Task& t = P.tasks[L.first + k];
         const SubInfo& si = P.sub[t.sub];
-        double inner = 0.0;
-        for (int q = t.k0; q < t.k1; ++q) inner += real(si, q);
-        const double ri = real(si, t.i), rj = real(si, t.j);
-        fl += (t.i == t.j ? ri * (ri + 1.0) : 2.0 * ri * rj) * inner;
+        if (k < nupd) {
+          double inner = 0.0;
+          for (int q = t.k0; q < t.k1; ++q) inner += real(si, q);
+          const double ri = real(si, t.i), rj = real(si, t.j);
+          fl += (t.i == t.j ? ri * (ri + 1.0) : 2.0 * ri * rj) * inner;
+        } else if (t.i != t.j) {
+          // inverse row: sum_k L_ik W_kj, then L_ii^{-1} times it (tile indices
+          // local to the interior or the interface block)
+          const int off = L.kind == K_UPD_TRTRI_INT ? 0 : si.nt_i;
+          const double ri = real(si, off + t.i), rj = real(si, off + t.j);
+          double inner = 0.0;
+          for (int q = t.j; q < t.i; ++q) inner += real(si, off + q);
+          fl += 2.0 * ri * rj * inner + 2.0 * ri * ri * rj;
+        }
       }
     };
     for (const auto& L : P.sched_interior) add(L);
@@ -629,7 +647,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   p->n_coarse = off;
   p->nq = (off + TS - 1) / TS;
   HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
-  fill_bco(p->di, p->d_sub, p->d_bco, st);
+  fill_bco(p->di, p->d_sub, p->d_bco, p->d_rco, st);
   // batched factorisation
   p->n_upd_recorded = 0;
   p->prof_upd_ms = 0.0;
@@ -639,14 +657,6 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   const int big = 0x7fffffff;
   HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
   for (const auto& L : P.sched_interior) dense(p, L);
-  for (const auto& L : P.sched_trtri_int) {
-    if (P.mixed)
-      launch_dense<float>(L.kind, p->d_tasks + L.first, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv,
-                          (float*)p->d_Wi, nullptr, p->d_err, st);
-    else
-      launch_dense<double>(L.kind, p->d_tasks + L.first, L.count, p->d_sub, (double*)p->d_arena,
-                           (double*)p->d_linv, (double*)p->d_Wi, nullptr, p->d_err, st);
-  }
   dense(p, P.sched_schur);
   const auto& XT = P.sched_xtiles;
   if (P.precond == FETI_PREC_DIRICHLET) {
@@ -716,7 +726,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     asm_coarse(c, st);
     auto qd = [&](const HostPlan::Launch& L) {
       launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
-                           p->d_qX, p->d_err + 1, st);
+                           p->d_qX, p->d_err + 1, st, L.split);
     };
     const int big2 = 0x7fffffff;
     HIPCHK(hipMemcpyAsync(p->d_err + 1, &big2, sizeof(int), hipMemcpyHostToDevice, st));

@@ -23,7 +23,8 @@ static int32_t ceil_tiles(int64_t n) { return (int32_t)((n + TS - 1) / TS); }
 void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& tasks,
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
-                           HostPlan::Launch& lauum, HostPlan::Launch& xtiles, HostPlan::Launch& alltiles) {
+                           HostPlan::Launch& lauum, HostPlan::Launch& xtiles, HostPlan::Launch& alltiles,
+                           bool interior_inverse) {
   const int ns = (int)subs.size();
   int max_i = 0, max_b = 0;
   for (const auto& s : subs) {
@@ -32,6 +33,24 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   }
   auto begin = [&](int kind) { return HostPlan::Launch{kind, (int32_t)tasks.size(), 0}; };
   auto finish = [&](HostPlan::Launch& L) { L.count = (int32_t)tasks.size() - L.first; };
+  // block row ib of the inverse of the interior (or interface) factor, for the
+  // subdomains that have it: tasks (ib, jb), jb <= ib
+  auto inverse_row = [&](int ib, bool interior_part) {
+    for (int s = 0; s < ns; ++s)
+      if ((interior_part ? subs[s].nt_i : subs[s].nt_b) > ib)
+        for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
+  };
+  // update launch of a column step, with the previous block row of the
+  // inverse appended (its inputs are final once that column step is done)
+  auto fused = [&](HostPlan::Launch& L, int kind_fused, int row, bool interior_part) {
+    const int32_t nupd = (int32_t)tasks.size() - L.first;
+    inverse_row(row, interior_part);
+    finish(L);
+    if (L.count > nupd) {
+      L.kind = kind_fused;
+      L.split = nupd;
+    }
+  };
   // stage 1: interior columns, left-looking (rows run over every tile row below)
   for (int j = 0; j < max_i; ++j) {
     if (j > 0) {
@@ -39,7 +58,8 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_i > j)
           for (int i = j; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
-      finish(L);
+      if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
+      else finish(L);
       interior.push_back(L);
     }
     auto D = begin(K_DIAG);
@@ -54,14 +74,17 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     finish(T);
     interior.push_back(T);
   }
-  // stage 2: Schur complement of the interior on every interface tile
+  // stage 2: Schur complement of the interior on every interface tile (with
+  // the last block row of the interior inverse)
   schur = begin(K_UPDATE);
   for (int s = 0; s < ns; ++s)
     if (subs[s].nt_i > 0)
       for (int I = subs[s].nt_i; I < subs[s].nt; ++I)
         for (int J = subs[s].nt_i; J <= I; ++J) tasks.push_back({s, I, J, 0, subs[s].nt_i});
-  finish(schur);
-  // stage 4: interface columns (updates only over interface columns)
+  if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
+  else finish(schur);
+  // stage 4: interface columns (updates only over interface columns), each
+  // update launch carrying the previous block row of the interface inverse
   for (int jb = 0; jb < max_b; ++jb) {
     if (jb > 0) {
       auto L = begin(K_UPDATE);
@@ -70,7 +93,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
           const int j = subs[s].nt_i + jb;
           for (int i = j; i < subs[s].nt; ++i) tasks.push_back({s, i, j, subs[s].nt_i, j});
         }
-      finish(L);
+      fused(L, K_UPD_TRTRI, jb - 1, false);
       iface.push_back(L);
     }
     auto D = begin(K_DIAG);
@@ -87,12 +110,10 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     finish(T);
     if (T.count) iface.push_back(T);
   }
-  // stage 5: inverse of the interface factor, block row by block row
-  for (int ib = 0; ib < max_b; ++ib) {
+  // stage 5: the last block row of the interface inverse
+  if (max_b > 0) {
     auto L = begin(K_TRTRI);
-    for (int s = 0; s < ns; ++s)
-      if (subs[s].nt_b > ib)
-        for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
+    inverse_row(max_b - 1, false);
     finish(L);
     trtri.push_back(L);
   }
@@ -591,16 +612,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     P.qp_ptr.push_back((int32_t)P.qe_bs.size());
   }
   build_factor_schedule(P.sub, P.tasks, P.sched_interior, P.sched_schur, P.sched_iface, P.sched_trtri,
-                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles);
-  // inverse of the interior factor, block row by block row
-  for (int ib = 0; ib < P.max_nt_i; ++ib) {
-    HostPlan::Launch L{K_TRTRI_INT, (int32_t)P.tasks.size(), 0};
-    for (int s = 0; s < ns; ++s)
-      if (P.sub[s].nt_i > ib)
-        for (int jb = 0; jb <= ib; ++jb) P.tasks.push_back({s, ib, jb, jb, ib});
-    L.count = (int32_t)P.tasks.size() - L.first;
-    P.sched_trtri_int.push_back(L);
-  }
+                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles, true);
   return "";
 }
 

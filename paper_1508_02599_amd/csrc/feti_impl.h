@@ -116,30 +116,33 @@ struct HostPlan {
   std::vector<double> qe_c;                       // c_s * c_t
 
   // ---- factor schedule (task lists, launched in order)
-  struct Launch { int kind; int32_t first, count; };
+  // split: for a fused update + inverse-row launch, the number of update tasks
+  struct Launch { int kind; int32_t first, count; int32_t split = 0; };
   std::vector<Task> tasks;
   std::vector<Launch> sched_interior;   // stage 1
   Launch sched_schur{0, 0, 0};          // stage 2
   std::vector<Launch> sched_iface;      // stage 4
   std::vector<Launch> sched_trtri;      // stage 5
-  std::vector<Launch> sched_trtri_int;  // inverse of the interior factor
   Launch sched_lauum{0, 0, 0};          // stage 6
   Launch sched_xtiles{0, 0, 0};         // all interface lower tiles (sub, I, J)
   Launch sched_alltiles{0, 0, 0};       // all factor tiles (sub, i, j)
   int max_nt_i = 0, max_nt_b = 0;
 };
 
-enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4, K_TRTRI_INT = 5 };
+enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4, K_TRTRI_INT = 5,
+                  K_UPD_TRTRI = 6, K_UPD_TRTRI_INT = 7 };   // update tasks, then rows of the inverse
 
 // Builds the plan; returns an empty string on success, else an error message.
 std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);
 
 // Appends the factor schedule of a batch of matrices described by `subs`
 // (interior/interface tile counts) into P-like containers.
+// interior_inverse: also compute the inverse of the interior factor, its
+// block rows fused into the interior updates.
 void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& tasks,
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
                            HostPlan::Launch& lauum, HostPlan::Launch& xtiles,
-                           HostPlan::Launch& alltiles);
+                           HostPlan::Launch& alltiles, bool interior_inverse = false);
 
 }  // namespace feti

@@ -117,10 +117,8 @@ __device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, boo
 // ---------------------------------------------------------------------------
 // C_ij <- C_ij - sum_{k0<=k<k1} L_ik L_jk^T   (left-looking update)
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks,
-                                                const SubInfo* __restrict__ subs, T* arena) {
-  __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+__device__ __forceinline__ void update_tile(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* sA,
+                                            T* sB) {
   T* base = arena + subs[t.sub].tile_off;
   Acc<T> acc;
   acc.zero();
@@ -135,6 +133,24 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks,
   __syncthreads();
   T* C = base + tidx(t.i, t.j) * TS2;
   for (int e = threadIdx.x; e < TS2; e += 256) C[e] += sA[(e >> 6) * LD + (e & 63)];
+}
+
+template <typename T>
+__device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
+                           const T* __restrict__ linv, T* W, int interior, T* sA, T* sB);
+
+// Tile updates of a column step (blocks below n_upd); the blocks after them,
+// if any, compute one block row of the inverse of the factor (trtri_tile),
+// whose inputs are complete once the previous column step is done.  Fusing the
+// two keeps the serial chain of launches short.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, int n_upd,
+                                                const SubInfo* __restrict__ subs, T* arena,
+                                                const T* __restrict__ linv, T* W, int interior) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  if ((int)blockIdx.x < n_upd) update_tile<T>(t, subs, arena, sA, sB);
+  else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
 }
 
 // Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
@@ -235,16 +251,12 @@ __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
   for (int e = threadIdx.x; e < TS2; e += 256) C[e] = sA[(e >> 6) * LD + (e & 63)];
 }
 
-// Inverse of the interface Cholesky factor, one block row per launch
-// (interface-local tile indices): W_ii = L_ii^{-1};
-// W_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik W_kj for j < i.
+// One tile of the inverse W of a Cholesky factor (interface, or interior with
+// `interior`), block row i given rows < i (tile indices local to the block):
+// W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik W_kj for j < i.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
-                                               const SubInfo* __restrict__ subs,
-                                               const T* __restrict__ arena,
-                                               const T* __restrict__ linv, T* W, int interior) {
-  __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+__device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
+                           const T* __restrict__ linv, T* W, int interior, T* sA, T* sB) {
   const SubInfo s = subs[t.sub];
   const int ni = interior ? 0 : s.nt_i;
   const T* Lbase = arena + s.tile_off;
@@ -274,6 +286,17 @@ __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
   acc_to_lds(sA, acc2, T(-1), true);
   __syncthreads();
   for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e >> 6) * LD + (e & 63)];
+}
+
+// One block row of the inverse per launch (the rows not fused into updates).
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
+                                               const SubInfo* __restrict__ subs,
+                                               const T* __restrict__ arena,
+                                               const T* __restrict__ linv, T* W, int interior) {
+  __shared__ T sA[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
 }
 
 // X_IJ = sum_{k>=I} W_kI^T W_kJ  (I >= J): X = W^T W = (L L^T)^{-1}.
@@ -499,10 +522,12 @@ __global__ __launch_bounds__(256) void k_init_arena(const Task* __restrict__ tas
 // launchers
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
-                  T* W, T* X, int* err, hipStream_t st) {
+                  T* W, T* X, int* err, hipStream_t st, int split) {
   if (count <= 0) return;
   switch (kind) {
-    case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena); break;
+    case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, count, subs, arena, (const T*)linv, W, 0); break;
+    case K_UPD_TRTRI: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, split, subs, arena, (const T*)linv, W, 0); break;
+    case K_UPD_TRTRI_INT: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, split, subs, arena, (const T*)linv, W, 1); break;
     case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(64), 0, st, tasks, subs, arena, linv, err); break;
     case K_TRSM: hipLaunchKernelGGL(k_trsm<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, (const T*)linv); break;
     case K_TRTRI: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W, 0); break;
@@ -510,8 +535,8 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
     case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
   }
 }
-template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t);
-template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t);
+template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int);
+template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t, int);
 
 template <typename T>
 void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st) {

@@ -27,7 +27,7 @@ struct DevIdx {
 // --- dense factor kernels (k_dense.hip)
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv, T* W, T* X,
-                  int* err, hipStream_t st);
+                  int* err, hipStream_t st, int split = 0);
 template <typename T>
 void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st);
 template <typename T>
@@ -102,10 +102,10 @@ void pcg_proj_gt(int n_sub, const SubInfo* subs, const DevIdx& d, const double* 
                  const double* q, int with_update, double* gpart, int ldg, const PcgState* st, hipStream_t s);
 void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int ldg, double* a, const PcgState* st,
                       hipStream_t s);
-void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int32_t* bco, const double* rbv,
+void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int2* rco, const double* rbv,
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
                     const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s);
-void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, hipStream_t s);
+void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hipStream_t s);
 void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s);
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,

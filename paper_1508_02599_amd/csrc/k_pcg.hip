@@ -249,32 +249,40 @@ __global__ void k_add_modes(int64_t NF, const int32_t* __restrict__ f_sub, const
 // Lumped preconditioner: yb = K_bb xb with the interface-interface block of
 // every local stiffness stored slot-major (consecutive interface DOFs coalesce).
 // Lumped preconditioner block y = K_bb x over the compact slot-major ELL of
-// K_bb.  The slots of a row are taken in chunks of LUMP_CHUNK whose index and
-// value loads are all issued before their x gathers, so a row costs a few
-// memory round trips rather than one per slot.
-constexpr int LUMP_CHUNK = 10;
+// K_bb.  Four lanes share a row (lane q takes slots q, q+4, ...), so the
+// launch has enough waves to hide the memory latency of the slot loads and
+// the x gathers; the four partial sums are combined in a fixed order.
+constexpr int LUMP_LANES = 4;
 __global__ __launch_bounds__(256) void k_lumped(int64_t NB, int w_bb, const int32_t* __restrict__ bb_col,
                                                 const double* __restrict__ bb_val, const double* __restrict__ xb,
                                                 double* __restrict__ yb, const PcgState* st) {
   if (halted(st)) return;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= NB) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = t / LUMP_LANES;
+  const int q = (int)(t % LUMP_LANES);
   double acc = 0.0;
-  for (int k0 = 0; k0 < w_bb; k0 += LUMP_CHUNK) {
-    int c[LUMP_CHUNK];
-    double v[LUMP_CHUNK], x[LUMP_CHUNK];
+  if (b < NB) {
+    constexpr int C = 4;   // slots per lane in flight
+    for (int k0 = q; k0 < w_bb; k0 += C * LUMP_LANES) {
+      int c[C];
+      double v[C], x[C];
 #pragma unroll
-    for (int i = 0; i < LUMP_CHUNK; ++i) {
-      const bool in = k0 + i < w_bb;
-      c[i] = in ? bb_col[(int64_t)(k0 + i) * NB + b] : 0;
-      v[i] = in ? bb_val[(int64_t)(k0 + i) * NB + b] : 0.0;
+      for (int i = 0; i < C; ++i) {
+        const int k = k0 + i * LUMP_LANES;
+        const bool in = k < w_bb;
+        c[i] = in ? bb_col[(int64_t)k * NB + b] : 0;
+        v[i] = in ? bb_val[(int64_t)k * NB + b] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < C; ++i) x[i] = xb[c[i]];
+#pragma unroll
+      for (int i = 0; i < C; ++i) acc += v[i] * x[i];
     }
-#pragma unroll
-    for (int i = 0; i < LUMP_CHUNK; ++i) x[i] = xb[c[i]];
-#pragma unroll
-    for (int i = 0; i < LUMP_CHUNK; ++i) acc += v[i] * x[i];
   }
-  yb[b] = acc;
+  // lanes 4r..4r+3 of a wave hold row r's partial sums: ((q0 + q1) + (q2 + q3))
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (b < NB && q == 0) yb[b] = acc;
 }
 
 // K_bb values from the assembled rows (after every factorisation).
@@ -627,9 +635,9 @@ __global__ __launch_bounds__(256) void k_coarse_dense(int nc, int ld, const doub
   if (lane == 0) a[row] = acc;
 }
 
-// (G a)_r contribution of one row entry: Rb[b] . a[coarse block of b's subdomain]
-__device__ __forceinline__ double g_alpha(int64_t b, const int32_t* bco, const double* rbv, const double* ac) {
-  const int co = bco[b];
+// (G a)_r contribution of one row entry: Rb[b] . a[coarse block of b's
+// subdomain], with co = coarse_off << 3 | n_modes of that subdomain (or -1)
+__device__ __forceinline__ double g_alpha(int64_t b, int co, const double* rbv, const double* ac) {
   if (co < 0) return 0.0;
   const int nm = co & 7, off = co >> 3;
   double v = 0.0;
@@ -646,6 +654,14 @@ __global__ void k_fill_bco(int64_t NB, const int32_t* __restrict__ b_sub, const 
   bco[b] = s.n_modes > 0 ? ((s.coarse_off << 3) | s.n_modes) : -1;
 }
 
+// rco[r] = (bco of the row's first entry, bco of its second entry or -1)
+__global__ void k_fill_rco(int64_t n, const int64_t* __restrict__ b0, const int64_t* __restrict__ b1,
+                           const int32_t* __restrict__ bco, int2* rco) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  rco[r] = make_int2(bco[b0[r]], b1[r] >= 0 ? bco[b1[r]] : -1);
+}
+
 // Per multiplier row:
 //  mode 0: out = x - G ac
 //  mode 1: r <- r - alpha q, lam <- lam + alpha s, w <- w - alpha (q - G ac) with
@@ -654,7 +670,7 @@ __global__ void k_fill_bco(int64_t NB, const int32_t* __restrict__ b_sub, const 
 //  mode 2: out = x - G ac, then rho' = w.out, ||w||, beta, convergence (init: first evaluation)
 __global__ __launch_bounds__(256) void k_proj_apply(
     int mode, int init, int64_t n, int coarse, const int64_t* __restrict__ b0, const double* __restrict__ c0,
-    const int64_t* __restrict__ b1, const double* __restrict__ c1, const int32_t* __restrict__ bco,
+    const int64_t* __restrict__ b1, const double* __restrict__ c1, const int2* __restrict__ rco,
     const double* __restrict__ rbv, const double* __restrict__ ac, double* x,
     const double* __restrict__ q, const double* __restrict__ sv, double* lam, double* out,
     const double* __restrict__ w, double* part, int* ticket, PcgState* st, double* hist) {
@@ -665,8 +681,9 @@ __global__ __launch_bounds__(256) void k_proj_apply(
   for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
     double ga = 0.0;
     if (coarse) {
-      ga = c0[r] * g_alpha(b0[r], bco, rbv, ac);
-      if (b1[r] >= 0) ga += c1[r] * g_alpha(b1[r], bco, rbv, ac);
+      const int2 co = rco[r];
+      ga = c0[r] * g_alpha(b0[r], co.x, rbv, ac);
+      if (co.y >= 0) ga += c1[r] * g_alpha(b1[r], co.y, rbv, ac);
     }
     double o;
     if (mode == 1) {
@@ -895,7 +912,7 @@ void pcg_add_modes(int64_t NF, const int32_t* f_sub, const SubInfo* subs, const 
 }
 void pcg_lumped(const DevIdx& d, int w_bb, const int32_t* bb_col, const double* bb_val, const double* xb,
                 double* yb, const PcgState* st, hipStream_t s) {
-  if (d.NB) hipLaunchKernelGGL(k_lumped, grid1(d.NB), dim3(256), 0, s, d.NB, w_bb, bb_col, bb_val, xb, yb, st);
+  if (d.NB) hipLaunchKernelGGL(k_lumped, grid1(d.NB * LUMP_LANES), dim3(256), 0, s, d.NB, w_bb, bb_col, bb_val, xb, yb, st);
 }
 void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double* ell_val, double* bb_val,
                  hipStream_t s) {
@@ -970,13 +987,14 @@ void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int
                       hipStream_t s) {
   if (nc) hipLaunchKernelGGL(k_coarse_dense, dim3((nc + 3) / 4), dim3(256), nc * sizeof(double), s, nc, ld, Qi, gpart, ldg, a, st);
 }
-void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int32_t* bco, const double* rbv,
+void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int2* rco, const double* rbv,
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
                     const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, bco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist);
+  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, rco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist);
 }
-void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, hipStream_t s) {
+void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_fill_bco, grid1(d.NB), dim3(256), 0, s, d.NB, d.b_sub, subs, bco);
+  if (d.n_lam) hipLaunchKernelGGL(k_fill_rco, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_b1, bco, rco);
 }
 void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s) {
   if (nc) hipLaunchKernelGGL(k_tiles_to_dense, grid1((int64_t)nc * nc), dim3(256), 0, s, nc, ld, tiles, D);
