@@ -211,6 +211,23 @@ void kpinv(feti_problem* p, const double* g, double* z) {
   else kpinv_t<double>(p, g, z);
 }
 
+// Interface part only, zb = (K^+ g)_b = X (g_b - L_bI L_II^{-1} g_I), as a
+// b-space vector: the interior back substitution is not needed for B K^+ g.
+template <typename T>
+void kpinv_b_t(feti_problem* p, const double* g, double* zb) {
+  const HostPlan& P = p->P;
+  const T* A = (const T*)p->d_arena;
+  const T* Wi = (const T*)p->d_Wi;
+  hipStream_t st = p->stream;
+  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  symv_local(p, p->d_X, p->d_kb1, zb, nullptr);
+}
+void kpinv_b(feti_problem* p, const double* g, double* zb) {
+  if (p->P.mixed) kpinv_b_t<float>(p, g, zb);
+  else kpinv_b_t<double>(p, g, zb);
+}
+
 // alpha = Q^{-1} g on the coarse space (alpha = 0 without coarse space).
 void coarse_solve(feti_problem* p, const double* g, double* alpha, const PcgState* st) {
   if (p->n_coarse == 0) return;
@@ -774,11 +791,10 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
   if (first) HIPCHK(hipEventRecord(p->ev[3], st));
   // e = R^T f ; d = B K^+ f - b
   if (p->n_coarse) pcg_coarse_gt_full(P.n_sub, p->d_sub, p->d_rfull, p->d_f, p->d_e, st);
-  kpinv(p, p->d_f, p->d_z);
   int iters = 0, status = FETI_OK;
   double rel = 0.0, kappa = 1.0;
   if (n > 0) {
-    vec_copy_b2f(p->di, p->d_z, p->d_yb, st);
+    kpinv_b(p, p->d_f, p->d_yb);
     vec_bvec(p->di, p->d_dvals, p->d_bv, st);
     pcg_scatter(p->di, 0, p->d_yb, p->d_bv, 1.0, p->d_d, nullptr, st);
     vec_axpby(n, -2.0, p->d_bv, 1.0, p->d_d, st);   // (b + B y) - 2 b = B y - b
@@ -841,7 +857,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
       pcg_add_modes(P.NF, p->di.f_sub, p->d_sub, p->d_rfull, p->d_gamma, p->d_u, st);
     }
   } else {
-    vec_axpby(P.NF, 1.0, p->d_z, 0.0, p->d_u, st);
+    kpinv(p, p->d_f, p->d_u);
   }
   HIPCHK(hipEventRecord(p->ev[4], st));
   if (stats) {

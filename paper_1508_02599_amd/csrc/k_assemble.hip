@@ -566,24 +566,37 @@ void asm_modes(const ModesArgs& m, hipStream_t s) {
 }
 
 // Coarse matrix Q = G^T G with G = [B_i Rb_i]: block (s, t), s >= t, sums
-// c_s c_t Rb_s[b_s] Rb_t[b_t]^T over the multiplier rows the two share (in
-// row order); written into the lower tiles of the dense coarse matrix.
-__global__ void k_coarse_q(CoarseArgs C) {
+// c_s c_t Rb_s[b_s] Rb_t[b_t]^T over the multiplier rows the two share
+// (interleaved over seven thread groups, then summed in group order); written
+// into the lower tiles of the dense coarse matrix.
+__global__ __launch_bounds__(256) void k_coarse_q(CoarseArgs C) {
+  // 36 entries (a, b) of the 6x6 block of one subdomain pair, each summed by
+  // QGROUPS threads over interleaved shared rows, then in a fixed order
+  constexpr int QGROUPS = 7;
+  __shared__ double part[QGROUPS][36];
   const int k = blockIdx.x;
   const int s = C.qp_s[k], t = C.qp_t[k];
   const SubInfo Ss = C.subs[s], St = C.subs[t];
-  const int a = threadIdx.x / 6, b = threadIdx.x % 6;
-  if (threadIdx.x >= 36 || a >= Ss.n_modes || b >= St.n_modes) return;
+  const int ab = threadIdx.x % 36, g = threadIdx.x / 36;
+  const int a = ab / 6, b = ab % 6;
   double acc = 0.0;
-  for (int q = C.qp_ptr[k]; q < C.qp_ptr[k + 1]; ++q)
-    acc += C.qe_c[q] * C.rb[C.qe_bs[q] * 6 + a] * C.rb[C.qe_bt[q] * 6 + b];
+  if (g < QGROUPS && a < Ss.n_modes && b < St.n_modes) {
+    const int q0 = C.qp_ptr[k], q1 = C.qp_ptr[k + 1];
+    for (int q = q0 + g; q < q1; q += QGROUPS)
+      acc += C.qe_c[q] * C.rb[C.qe_bs[q] * 6 + a] * C.rb[C.qe_bt[q] * 6 + b];
+  }
+  if (g < QGROUPS) part[g][ab] = acc;
+  __syncthreads();
+  if (threadIdx.x >= 36 || a >= Ss.n_modes || b >= St.n_modes) return;
+  double v = 0.0;
+  for (int h = 0; h < QGROUPS; ++h) v += part[h][ab];
   const int row = Ss.coarse_off + a, col = St.coarse_off + b;
   if (row < col) return;
-  C.q[tidx3(row / TS, col / TS) * TS2 + (col % TS) * TS + (row % TS)] = acc;
+  C.q[tidx3(row / TS, col / TS) * TS2 + (col % TS) * TS + (row % TS)] = v;
 }
 
 void asm_coarse(const CoarseArgs& c, hipStream_t s) {
-  if (c.n_pairs) hipLaunchKernelGGL(k_coarse_q, dim3(c.n_pairs), dim3(64), 0, s, c);
+  if (c.n_pairs) hipLaunchKernelGGL(k_coarse_q, dim3(c.n_pairs), dim3(256), 0, s, c);
 }
 
 }  // namespace feti

@@ -66,6 +66,35 @@ __device__ __forceinline__ void lds_load(T* s, const T* __restrict__ g) {
     }
   }
 }
+// A tile held in registers between its global load and its LDS store, so the
+// load of the next k-step's tiles can be in flight during this step's MFMAs.
+template <typename T>
+struct TileRegs {
+  typedef typename Vec16<T>::type V;
+  static constexpr int EPV = Vec16<T>::n;
+  static constexpr int NV = TS2 / EPV / 256;
+  V v[NV];
+  __device__ __forceinline__ void fetch(const T* __restrict__ g) {
+    const V* gv = reinterpret_cast<const V*>(g);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = gv[threadIdx.x + 256 * i];
+  }
+  template <bool TRANS>
+  __device__ __forceinline__ void store(T* s) const {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e0 = (threadIdx.x + 256 * i) * EPV;
+#pragma unroll
+      for (int u = 0; u < EPV; ++u) {
+        const int e = e0 + u;
+        const T x = reinterpret_cast<const T*>(&v[i])[u];
+        if (TRANS) s[(e & 63) * LD + (e >> 6)] = x;
+        else s[(e >> 6) * LD + (e & 63)] = x;
+      }
+    }
+  }
+};
+
 // direct: s[k][m] = g[k*TS + m]   (A not transposed, or B transposed)
 template <typename T>
 __device__ __forceinline__ void lds_direct(T* s, const T* __restrict__ g) { lds_load<T, false>(s, g); }
@@ -88,7 +117,9 @@ template <typename T>
 __device__ __forceinline__ void mma64(Acc<T>& acc, const T* sA, const T* sB) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1, lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
+  // fully unrolled, so the LDS reads of later k-slices issue ahead of the
+  // MFMAs that consume earlier ones
+#pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int k = 4 * kk + lk;
     const T a0 = sA[k * LD + 32 * wr + lr], a1 = sA[k * LD + 32 * wr + 16 + lr];
@@ -122,10 +153,20 @@ __device__ __forceinline__ void update_tile(const Task& t, const SubInfo* __rest
   T* base = arena + subs[t.sub].tile_off;
   Acc<T> acc;
   acc.zero();
+  // software pipeline: the tiles of step k+1 load while step k multiplies
+  TileRegs<T> ra, rb;
+  if (t.k0 < t.k1) {
+    ra.fetch(base + tidx(t.i, t.k0) * TS2);
+    rb.fetch(base + tidx(t.j, t.k0) * TS2);
+  }
   for (int k = t.k0; k < t.k1; ++k) {
-    lds_direct(sA, base + tidx(t.i, k) * TS2);
-    lds_direct(sB, base + tidx(t.j, k) * TS2);
+    ra.template store<false>(sA);
+    rb.template store<false>(sB);
     __syncthreads();
+    if (k + 1 < t.k1) {
+      ra.fetch(base + tidx(t.i, k + 1) * TS2);
+      rb.fetch(base + tidx(t.j, k + 1) * TS2);
+    }
     mma64(acc, sA, sB);
     __syncthreads();
   }
@@ -269,10 +310,17 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   }
   Acc<T> acc;
   acc.zero();
+  TileRegs<T> ra, rb;
+  ra.fetch(Lbase + tidx(ni + t.i, ni + t.j) * TS2);
+  rb.fetch(Wbase + tidx(t.j, t.j) * TS2);
   for (int k = t.j; k < t.i; ++k) {
-    lds_direct(sA, Lbase + tidx(ni + t.i, ni + k) * TS2);
-    lds_trans(sB, Wbase + tidx(k, t.j) * TS2);
+    ra.template store<false>(sA);
+    rb.template store<true>(sB);
     __syncthreads();
+    if (k + 1 < t.i) {
+      ra.fetch(Lbase + tidx(ni + t.i, ni + k + 1) * TS2);
+      rb.fetch(Wbase + tidx(k + 1, t.j) * TS2);
+    }
     mma64(acc, sA, sB);
     __syncthreads();
   }
@@ -310,10 +358,19 @@ __global__ __launch_bounds__(256) void k_lauum(const Task* __restrict__ tasks,
   const T* Wb = W + s.x_off;
   Acc<T> acc;
   acc.zero();
+  TileRegs<T> ra, rb;
+  if (t.k0 < t.k1) {
+    ra.fetch(Wb + tidx(t.k0, t.i) * TS2);
+    rb.fetch(Wb + tidx(t.k0, t.j) * TS2);
+  }
   for (int k = t.k0; k < t.k1; ++k) {
-    lds_trans(sA, Wb + tidx(k, t.i) * TS2);
-    lds_trans(sB, Wb + tidx(k, t.j) * TS2);
+    ra.template store<true>(sA);
+    rb.template store<true>(sB);
     __syncthreads();
+    if (k + 1 < t.k1) {
+      ra.fetch(Wb + tidx(k + 1, t.i) * TS2);
+      rb.fetch(Wb + tidx(k + 1, t.j) * TS2);
+    }
     mma64(acc, sA, sB);
     __syncthreads();
   }
