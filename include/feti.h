@@ -110,6 +110,9 @@ typedef struct {
 #define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */
 #define FETI_PROFILE 0x2ull     /* time the dual-operator GEMV and factor-update kernels with
                                    HIP events (reported in feti_stats.kernel_*)              */
+#define FETI_AUTOTUNE 0x4ull    /* pick the output shape of each factor-update launch (64x64 or
+                                   128x64 tiles per workgroup) by timing both in the first two
+                                   factorisations; the factors do not depend on the choice   */
 
 typedef struct {
   feti_variant variant;
@@ -126,7 +129,7 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* stream, void* ctx);   /* optional allocator     */
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
-  uint64_t flags;              /* FETI_DEVICE_PTRS                                        */
+  uint64_t flags;              /* FETI_DEVICE_PTRS | FETI_PROFILE | FETI_AUTOTUNE          */
 } feti_options;
 
 typedef struct {
@@ -153,6 +156,8 @@ typedef struct {
   double res_primal;           /* ||f - K u||_2 / ||f||_2 of the returned u (FP64, assembled,
                                   free DOFs): always for FETI_MIXED, with FETI_PROFILE for
                                   FETI_FP64, else 0                                         */
+  int32_t autotune_wide;       /* FETI_AUTOTUNE: update launches that use 128x64 tiles once
+                                  tuned; -1 while tuning or without FETI_AUTOTUNE          */
 } feti_stats;
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */

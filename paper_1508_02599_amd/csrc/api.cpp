@@ -104,6 +104,17 @@ struct feti_problem {
   bool profile = false;
   std::vector<hipEvent_t> ev_gemv, ev_upd;   // burst start/end; pairs around update launches
   int n_upd_recorded = 0;
+  // autotuner of the update launches (FETI_AUTOTUNE): the first factorisation
+  // times the 64x64 form of every update launch, the second the 128x64 form;
+  // from then on each launch uses the faster.  Both forms give identical
+  // factors.  Launches are identified by the first task of their 64x64 form.
+  bool autotune = false;
+  int tune_phase = 0;                          // 0, 1: measuring; 2: decided
+  std::vector<int32_t> upd_first;              // update launches, by first task
+  std::vector<float> t_tile, t_wide;
+  std::vector<uint8_t> use_wide;
+  std::vector<hipEvent_t> ev_tune;
+  int n_wide = -1;
   double prof_gemv_ms = 0.0, prof_upd_ms = 0.0, upd_flops = 0.0, gemv_bytes = 0.0;
   int prof_gemv_n = 0, prof_upd_n = 0;
 };
@@ -163,20 +174,53 @@ size_t elt(const feti_problem* p) { return p->P.mixed ? sizeof(float) : sizeof(d
 // Dense launches on the subdomain batch in the working precision.
 bool is_update(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI || kind == K_UPD_TRTRI_INT; }
 
+int update_index(const feti_problem* p, const HostPlan::Launch& L) {
+  const auto it = std::lower_bound(p->upd_first.begin(), p->upd_first.end(), L.first);
+  return (it != p->upd_first.end() && *it == L.first) ? (int)(it - p->upd_first.begin()) : -1;
+}
+
 void dense(feti_problem* p, const HostPlan::Launch& L) {
-  const Task* t = p->d_tasks + L.first;
-  const bool timed = p->profile && is_update(L.kind) && L.count > 0 &&
-                     2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
+  const bool upd = is_update(L.kind) && L.count > 0;
+  const bool timed = p->profile && upd && 2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
   // the interior inverse goes to its own arena
   void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
+  int wide = 0, idx = -1;
+  if (upd && p->autotune && (idx = update_index(p, L)) >= 0 && L.wcount > 0)
+    wide = p->tune_phase == 0 ? 0 : p->tune_phase == 1 ? 1 : p->use_wide[idx];
+  const bool tuning = idx >= 0 && p->tune_phase < 2;
+  const Task* t = p->d_tasks + (wide ? L.wfirst : L.first);
+  const int count = wide ? L.wcount : L.count, split = wide ? L.wsplit : L.split;
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], p->stream);
+  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], p->stream);
   if (p->P.mixed)
-    launch_dense<float>(L.kind, t, L.count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
-                        (float*)p->d_X, p->d_err, p->stream, L.split);
+    launch_dense<float>(L.kind, t, count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
+                        (float*)p->d_X, p->d_err, p->stream, split, wide);
   else
-    launch_dense<double>(L.kind, t, L.count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
-                         (double*)p->d_X, p->d_err, p->stream, L.split);
+    launch_dense<double>(L.kind, t, count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
+                         (double*)p->d_X, p->d_err, p->stream, split, wide);
+  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], p->stream);
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], p->stream);
+}
+
+// After a factorisation: collect the autotuner's timings and advance it.
+void autotune_step(feti_problem* p) {
+  if (!p->autotune || p->tune_phase >= 2) return;
+  auto& dst = p->tune_phase == 0 ? p->t_tile : p->t_wide;
+  for (size_t k = 0; k < p->upd_first.size(); ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev_tune[2 * k], p->ev_tune[2 * k + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 0.f;
+    }
+    dst[k] = ms;
+  }
+  if (++p->tune_phase == 2) {
+    p->n_wide = 0;
+    for (size_t k = 0; k < p->upd_first.size(); ++k) {
+      p->use_wide[k] = p->t_wide[k] > 0.f && p->t_wide[k] < p->t_tile[k];
+      p->n_wide += p->use_wide[k];
+    }
+  }
 }
 
 void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st) {
@@ -546,6 +590,22 @@ feti_status setup_device(feti_problem* p) {
     p->ev_upd.resize(2 * (P.sched_interior.size() + P.sched_iface.size() + 2));
     for (auto& ev : p->ev_upd) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
   }
+  p->autotune = (p->opt.flags & FETI_AUTOTUNE) != 0;
+  if (p->autotune) {
+    auto reg = [&](const HostPlan::Launch& L) {
+      if (is_update(L.kind) && L.count > 0 && L.wcount > 0) p->upd_first.push_back(L.first);
+    };
+    for (const auto& L : P.sched_interior) reg(L);
+    reg(P.sched_schur);
+    for (const auto& L : P.sched_iface) reg(L);
+    std::sort(p->upd_first.begin(), p->upd_first.end());
+    const size_t nl = p->upd_first.size();
+    p->t_tile.assign(nl, 0.f);
+    p->t_wide.assign(nl, 0.f);
+    p->use_wide.assign(nl, 0);
+    p->ev_tune.resize(2 * nl);
+    for (auto& ev : p->ev_tune) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+  }
   // algorithmic work: bytes of the packed symmetric interface inverses read by
   // one GEMV, and flops of the update launches counted on real (unpadded)
   // rows: tile updates (lower triangle only for diagonal tiles) and the rows
@@ -766,6 +826,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
       (void)hipGetLastError();
     }
   }
+  autotune_step(p);
   if (errs[0] != 0x7fffffff) {
     p->err = "non-positive pivot in the local factor of subdomain " + std::to_string(errs[0]);
     p->factored = false;
@@ -874,6 +935,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     stats->n_coarse = p->n_coarse;
     stats->n_lambda = n;
     stats->device_bytes = p->bytes;
+    stats->autotune_wide = p->n_wide;
   }
   if (status == FETI_EBREAKDOWN) {
     p->err = "PCG breakdown (s.Fs <= 0)";
@@ -1305,6 +1367,8 @@ void feti_destroy(feti_problem* p) {
   for (auto& ev : p->ev_gemv)
     if (ev) (void)hipEventDestroy(ev);
   for (auto& ev : p->ev_upd)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : p->ev_tune)
     if (ev) (void)hipEventDestroy(ev);
   for (void* a : p->allocs) {
     if (p->da.fr) p->da.fr(a, p->da.ctx);

@@ -40,6 +40,33 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
       if ((interior_part ? subs[s].nt_i : subs[s].nt_b) > ib)
         for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
   };
+  // the wide form of an update launch: consecutive tasks of one subdomain and
+  // column with adjacent rows become one two-tile task; the inverse-row tasks
+  // follow unchanged
+  auto widen = [&](HostPlan::Launch& L) {
+    const int32_t nupd = L.kind == K_UPDATE ? L.count : L.split;
+    std::vector<Task> w;
+    for (int32_t k = 0; k < nupd;) {
+      Task a = tasks[L.first + k];
+      if (k + 1 < nupd) {
+        const Task& b = tasks[L.first + k + 1];
+        if (b.sub == a.sub && b.j == a.j && b.k0 == a.k0 && b.k1 == a.k1 && b.i == a.i + 1) {
+          a.n = 2;
+          w.push_back(a);
+          k += 2;
+          continue;
+        }
+      }
+      w.push_back(a);
+      ++k;
+    }
+    const int32_t nw = (int32_t)w.size();
+    for (int32_t k = nupd; k < L.count; ++k) w.push_back(tasks[L.first + k]);
+    L.wfirst = (int32_t)tasks.size();
+    L.wcount = (int32_t)w.size();
+    L.wsplit = nw;
+    tasks.insert(tasks.end(), w.begin(), w.end());
+  };
   // update launch of a column step, with the previous block row of the
   // inverse appended (its inputs are final once that column step is done)
   auto fused = [&](HostPlan::Launch& L, int kind_fused, int row, bool interior_part) {
@@ -50,6 +77,11 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
       L.kind = kind_fused;
       L.split = nupd;
     }
+    widen(L);
+  };
+  auto plain = [&](HostPlan::Launch& L) {
+    finish(L);
+    widen(L);
   };
   // stage 1: interior columns, left-looking (rows run over every tile row below)
   for (int j = 0; j < max_i; ++j) {
@@ -59,7 +91,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         if (subs[s].nt_i > j)
           for (int i = j; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
       if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
-      else finish(L);
+      else plain(L);
       interior.push_back(L);
     }
     auto D = begin(K_DIAG);
@@ -79,10 +111,10 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   schur = begin(K_UPDATE);
   for (int s = 0; s < ns; ++s)
     if (subs[s].nt_i > 0)
-      for (int I = subs[s].nt_i; I < subs[s].nt; ++I)
-        for (int J = subs[s].nt_i; J <= I; ++J) tasks.push_back({s, I, J, 0, subs[s].nt_i});
+      for (int J = subs[s].nt_i; J < subs[s].nt; ++J)
+        for (int I = J; I < subs[s].nt; ++I) tasks.push_back({s, I, J, 0, subs[s].nt_i});
   if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
-  else finish(schur);
+  else plain(schur);
   // stage 4: interface columns (updates only over interface columns), each
   // update launch carrying the previous block row of the interface inverse
   for (int jb = 0; jb < max_b; ++jb) {

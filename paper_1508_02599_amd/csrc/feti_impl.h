@@ -46,6 +46,7 @@ struct SubInfo {
 // One work item of a batched tile kernel.
 struct Task {
   int32_t sub, i, j, k0, k1;
+  int32_t n = 1;   // wide tile updates: output tiles (i, j) .. (i + n - 1, j)
 };
 
 struct HostPlan {
@@ -116,8 +117,15 @@ struct HostPlan {
   std::vector<double> qe_c;                       // c_s * c_t
 
   // ---- factor schedule (task lists, launched in order)
-  // split: for a fused update + inverse-row launch, the number of update tasks
-  struct Launch { int kind; int32_t first, count; int32_t split = 0; };
+  // split: for a fused update + inverse-row launch, the number of update tasks.
+  // wfirst/wcount/wsplit: the same launch with the tile updates paired into
+  // 128x64 outputs (wcount = 0: no such form).
+  struct Launch {
+    int kind;
+    int32_t first, count;
+    int32_t split = 0;
+    int32_t wfirst = 0, wcount = 0, wsplit = 0;
+  };
   std::vector<Task> tasks;
   std::vector<Launch> sched_interior;   // stage 1
   Launch sched_schur{0, 0, 0};          // stage 2

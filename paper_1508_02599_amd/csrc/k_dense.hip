@@ -194,6 +194,96 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, 
   else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
 }
 
+// Wide form: one block updates output tiles (i, j) and (i+1, j) (t.n = 2;
+// t.n = 1: only (i, j)), sharing the column panel L_jk.  Each wave computes 32
+// rows x 64 columns (8 accumulators), so a k-slice takes 6 LDS reads for 8
+// MFMAs, and a k-step stages three tiles for twice the work of the 64x64
+// form.  Every output element sums the same products in the same order as in
+// update_tile, so both forms give bit-identical factors.
+template <typename T>
+__device__ __forceinline__ void update_tile_wide(const Task& t, const SubInfo* __restrict__ subs, T* arena,
+                                                 T* sA0, T* sA1, T* sB) {
+  T* base = arena + subs[t.sub].tile_off;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int h = w >> 1;            // output tile i + h
+  const int r0 = 32 * (w & 1);     // first row of this wave within that tile
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool two = t.n == 2;
+  const bool active = h == 0 || two;
+  typename V4<T>::type acc[2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[x][y][r] = T(0);
+  TileRegs<T> ra0, ra1, rb;
+  if (t.k0 < t.k1) {
+    ra0.fetch(base + tidx(t.i, t.k0) * TS2);
+    if (two) ra1.fetch(base + tidx(t.i + 1, t.k0) * TS2);
+    rb.fetch(base + tidx(t.j, t.k0) * TS2);
+  }
+  for (int k = t.k0; k < t.k1; ++k) {
+    ra0.template store<false>(sA0);
+    if (two) ra1.template store<false>(sA1);
+    rb.template store<false>(sB);
+    __syncthreads();
+    if (k + 1 < t.k1) {
+      ra0.fetch(base + tidx(t.i, k + 1) * TS2);
+      if (two) ra1.fetch(base + tidx(t.i + 1, k + 1) * TS2);
+      rb.fetch(base + tidx(t.j, k + 1) * TS2);
+    }
+    if (active) {
+      const T* sA = h ? sA1 : sA0;
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int kr = 4 * kk + lk;
+        const T a0 = sA[kr * LD + r0 + lr], a1 = sA[kr * LD + r0 + 16 + lr];
+        T b[4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) b[y] = sB[kr * LD + 16 * y + lr];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          acc[0][y] = mfma4(a0, b[y], acc[0][y]);
+          acc[1][y] = mfma4(a1, b[y], acc[1][y]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // -acc into LDS (column-major, tile h), then added to C
+  if (active) {
+    T* sC = h ? sA1 : sA0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * x + out_row(T(0), lane, r);
+          const int col = 16 * y + lr;
+          sC[col * LD + row] = -acc[x][y][r];
+        }
+  }
+  __syncthreads();
+  T* C0 = base + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) C0[e] += sA0[(e >> 6) * LD + (e & 63)];
+  if (two) {
+    T* C1 = base + tidx(t.i + 1, t.j) * TS2;
+    for (int e = threadIdx.x; e < TS2; e += 256) C1[e] += sA1[(e >> 6) * LD + (e & 63)];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_wide(const Task* __restrict__ tasks, int n_upd,
+                                                     const SubInfo* __restrict__ subs, T* arena,
+                                                     const T* __restrict__ linv, T* W, int interior) {
+  __shared__ T sA0[TS * LD], sA1[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
+  if ((int)blockIdx.x < n_upd) update_tile_wide<T>(t, subs, arena, sA0, sA1, sB);
+  else trtri_tile<T>(t, subs, arena, linv, W, interior, sA0, sB);
+}
+
 // Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
 // and the explicit inverse L_jj^{-1}.  One wave per tile with the tile in
 // registers (lane r holds row r, loops fully unrolled).  Each elimination
@@ -579,8 +669,15 @@ __global__ __launch_bounds__(256) void k_init_arena(const Task* __restrict__ tas
 // launchers
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
-                  T* W, T* X, int* err, hipStream_t st, int split) {
+                  T* W, T* X, int* err, hipStream_t st, int split, int wide) {
   if (count <= 0) return;
+  if (wide) {   // update launches only: the task list is the wide form
+    const int nupd = kind == K_UPDATE ? count : split;
+    const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
+    hipLaunchKernelGGL(k_update_wide<T>, dim3(count), dim3(256), 0, st, tasks, nupd, subs, arena, (const T*)linv, W,
+                       interior);
+    return;
+  }
   switch (kind) {
     case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, count, subs, arena, (const T*)linv, W, 0); break;
     case K_UPD_TRTRI: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, split, subs, arena, (const T*)linv, W, 0); break;
@@ -592,8 +689,8 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
     case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
   }
 }
-template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int);
-template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t, int);
+template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int, int);
+template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t, int, int);
 
 template <typename T>
 void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st) {

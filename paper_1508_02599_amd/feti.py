@@ -26,6 +26,7 @@ PRECONDS = {"identity": 0, "lumped": 1, "dirichlet": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FETI_DEVICE_PTRS = 1
 FETI_PROFILE = 2
+FETI_AUTOTUNE = 4
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -62,7 +63,8 @@ class feti_stats(C.Structure):
                 ("t_pcg", C.c_double), ("t_total", C.c_double), ("device_bytes", C.c_size_t),
                 ("kernel_gemv_launches", C.c_int32), ("kernel_update_launches", C.c_int32),
                 ("kernel_gemv_ms", C.c_double), ("kernel_update_ms", C.c_double),
-                ("gemv_bytes", C.c_double), ("update_flops", C.c_double), ("res_primal", C.c_double)]
+                ("gemv_bytes", C.c_double), ("update_flops", C.c_double), ("res_primal", C.c_double),
+                ("autotune_wide", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -159,10 +161,10 @@ def _check(lib, handle, status):
 
 def feti_setup(mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-               torch_allocator=False, profile=False):
+               torch_allocator=False, profile=False, autotune=True):
     """Create a problem handle (see :class:`Problem`)."""
     return Problem(mesh, variant, precond, precision, rtol, max_it, graph_block, ir_tol, ir_max,
-                   hip_stream, device_ptrs, torch_allocator, profile)
+                   hip_stream, device_ptrs, torch_allocator, profile, autotune)
 
 
 class Problem:
@@ -170,7 +172,7 @@ class Problem:
 
     def __init__(self, mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                  graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-                 torch_allocator=False, profile=False):
+                 torch_allocator=False, profile=False, autotune=True):
         self.lib = load_library()
         self.n_dof = 3 * int(np.asarray(mesh.xyz).shape[0])
         keep = []
@@ -185,7 +187,8 @@ class Problem:
         o.ir_max = ir_max
         o.graph_block = graph_block
         o.hip_stream = hip_stream
-        o.flags = (FETI_DEVICE_PTRS if device_ptrs else 0) | (FETI_PROFILE if profile else 0)
+        o.flags = ((FETI_DEVICE_PTRS if device_ptrs else 0) | (FETI_PROFILE if profile else 0)
+                   | (FETI_AUTOTUNE if autotune else 0))
         self._cb = None
         if torch_allocator:
             import torch

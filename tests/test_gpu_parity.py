@@ -235,3 +235,24 @@ def test_mixed_precision_newton_step():
     err = _rel(dU, dU_ref)
     print(f"tube newton mixed: it={st['iters']} sweeps={st['ir_sweeps']} err={err:.3e}")
     assert err <= 1e-8
+
+
+# ---------------------------------------------------------------- autotuned update shapes
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_update_forms_identical(precision):
+    """The first factorisation uses 64x64 update tiles, the second 128x64, later
+    ones the faster per launch: the displacements are bit-identical throughout
+    (same products, same order) and match the oracle."""
+    m, ref = _oracle("cube32_s4")
+    kw = dict(rtol=1e-10) if precision == "fp64" else dict(rtol=1e-8, ir_tol=1e-12)
+    outs, wide = [], []
+    with _problem(m, variant="af", precond="lumped", precision=precision, autotune=True, **kw) as p:
+        for _ in range(3):
+            p.factor()
+            u, st = p.solve()
+            outs.append(u)
+            wide.append(st["autotune_wide"])
+    print(f"autotune {precision}: wide launches per factorisation after tuning = {wide}")
+    assert wide[0] == -1 and wide[2] >= 0
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    assert _rel(outs[2], ref) <= 1e-9
