@@ -162,6 +162,128 @@ def roofline(st_all, precision):
     return dom, other
 
 
+def tube_load_path(args):
+    """The HGO tube under its inner-pressure ramp to 16 mmHg: tau = s/n,
+    s = 1..n (n = --load-steps, default 40: 0.4 mmHg per load step; with 10
+    steps of 1.6 mmHg Newton stalls on this mesh, as the oracle's Newton does
+    on the 4x32x16 tube), each load step solved by Newton from the previous
+    equilibrium, every Newton step one FETI solve (factor at U_k + dual PCG).
+    A load step ends when the residual norm at U_k is at most newton_tol
+    times its value at the start of the load step.
+
+    Kernels: all six rigid modes for every floating subdomain, as in the paper
+    (FETI_KERNEL6): away from U = 0 the stressed local tangents of this mesh
+    are indefinite in rotation directions (compressive stress), so each
+    Newton step solves that approximate tangent system (an inexact Newton
+    step; --exact-steps refines it against the exact sparse tangent).  The
+    residual, and so the equilibrium reached, is exact either way.
+
+    Damping (not in the paper's scheme): with kappa = 1000 c the first
+    linearised step of a load step can overshoot into states where the
+    tangent is indefinite (a non-positive pivot, or a PCG breakdown).  A trial point U + a dU (a = 1, 1/2, ...) is
+    accepted when its FETI solve succeeds and its residual is smaller; that
+    solve's increment is then the next Newton step, so an accepted full step
+    costs no extra solve.  Every solve, rejected trials included, counts as a
+    step of the metric.  Returns the JSON line."""
+    import torch
+    from workloads import config_mesh
+    from paper_1508_02599_amd.feti import Problem, FetiError
+
+    mesh = config_mesh(args.config)
+    n = mesh.n_dofs
+    rtol = args.rtol if args.precision == "fp64" else args.mixed_rtol
+    p = Problem(mesh, variant=args.variant, precond="dirichlet", precision=args.precision, rtol=rtol,
+                ir_tol=args.ir_tol if args.ir_tol > 0 else 1e-10, ir_max=20 if args.exact_steps else 0,
+                max_it=3000, device_ptrs=True, kernel6=True)
+    U = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for _ in range(2):      # autotuning factorisations (untimed)
+        p.factor(U)
+    lat, its, res_hist = [], [], []
+    newton_per_load, rejected = [], 0
+
+    def step(Ux, tau):
+        d = torch.empty_like(Ux)
+        a = time.perf_counter()
+        try:
+            _, rn, st = p.newton_step(Ux, tau, out=d)
+            ok = True
+        except FetiError as e:
+            # an indefinite tangent (non-positive pivot, or s.Fs <= 0 in the
+            # dual iteration) or a dual iteration that does not converge
+            # rejects a trial point
+            if e.status not in (-4, -5, -7):
+                raise
+            rn, st, ok = float("inf"), {"iters": 0}, False
+        lat.append(time.perf_counter() - a)
+        its.append(st["iters"])
+        print(f"tau={tau:.3f} solve {len(lat)}: ok={ok} res={rn:.3e} pcg_it={st['iters']} "
+              f"sweeps={st.get('ir_sweeps', 0)} {1e3 * lat[-1]:.0f} ms", file=sys.stderr, flush=True)
+        return ok, d, rn
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    failed = None
+    nload = args.load_steps
+    for s in range(1, nload + 1):
+        tau = s / nload
+        ok, dU, rn = step(U, tau)
+        if not ok:
+            failed = f"tangent not SPD at the start of load step {s}"
+            break
+        tol = args.newton_tol * rn
+        k = 0
+        while rn > tol and k < 30:
+            if time.perf_counter() - t0 > args.time_budget:
+                failed = f"time budget of {args.time_budget:g} s spent in load step {s}"
+                break
+            k += 1
+            a = 1.0
+            while True:
+                Ut = U + a * dU
+                ok_t, dUt, rn_t = step(Ut, tau)
+                if ok_t and rn_t < rn:
+                    U, dU, rn = Ut, dUt, rn_t
+                    break
+                rejected += 1
+                a *= 0.5
+                if a < 1.0 / 256:
+                    failed = f"no descent in load step {s}"
+                    break
+            if failed:
+                break
+        res_hist.append(rn)
+        newton_per_load.append(k)
+        if failed:
+            break
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    p.close()
+    nsteps = len(lat)
+    line = {
+        "metric": "FETI Newton steps/s on the HGO tube load path (each step one FETI solve)",
+        "value": nsteps / total, "unit": "newton_steps/s", "n_gpus": 1, "steps": nsteps, "warmup": 0,
+        "ms_per_step": 1e3 * total / nsteps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-local/f64-global",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: two-layer HGO tube, 16x128x64 Q1-P0 elements in "
+                               f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, six-mode "
+                               f"kernels), "
+                               f"inner pressure 16 mmHg x s/{nload}, s = 1..{nload}, damped "
+                               f"{'exact' if args.exact_steps else 'inexact'} Newton to "
+                               f"|r| <= {args.newton_tol:g} |r_0| per load step",
+                   "global_dofs": n},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
+        "load_steps_done": len(res_hist) - (1 if failed else 0), "load_steps": nload,
+        "newton_steps_per_load_step": newton_per_load,
+        "rejected_trials": rejected,
+        "pcg_iterations": {"mean": float(np.mean(its)), "max": int(np.max(its))},
+        "final_residuals": res_hist,
+    }
+    if failed:
+        line["error"] = failed
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +298,14 @@ def main():
                     help="PCG tolerance of the first dual solve of the mixed path")
     ap.add_argument("--ir-tol", type=float, default=0.0,
                     help="--precision mixed: refinement target (0: library default)")
+    ap.add_argument("--newton-tol", type=float, default=1e-4,
+                    help="tube load path: residual reduction (relative to the start of a load step) "
+                         "that ends it")
+    ap.add_argument("--load-steps", type=int, default=40, help="tube load path: load increments to 16 mmHg")
+    ap.add_argument("--exact-steps", action="store_true",
+                    help="tube load path: refine each Newton step against the exact tangent")
+    ap.add_argument("--time-budget", type=float, default=240.0,
+                    help="tube load path: wall-clock limit (s); a partial path is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -188,6 +318,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.config.startswith("tube"):
+        print(json.dumps(tube_load_path(args)))
         return
     mesh, total, pcg_total, lat, st_all = run(args, args.precision, profile=False,
                                               rtol=args.rtol if args.precision == "fp64" else args.mixed_rtol,

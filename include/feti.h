@@ -113,6 +113,16 @@ typedef struct {
 #define FETI_AUTOTUNE 0x4ull    /* pick the output shape of each factor-update launch (64x64 or
                                    128x64 tiles per workgroup) by timing both in the first two
                                    factorisations; the factors do not depend on the choice   */
+#define FETI_KERNEL6 0x8ull     /* take all six rigid-body modes as the kernel of every floating
+                                   subdomain, as the paper does (section 4.3).  Exact for
+                                   stress-free tangents.  For stressed ones (Newton steps away
+                                   from U = 0) the dual solve is of an approximate tangent,
+                                   which stays definite where compressive stress makes a local
+                                   tangent indefinite, and the result is refined against the
+                                   exact sparse tangent (corrections as for FETI_MIXED, up to
+                                   ir_tol / ir_max).  Default: translations, plus each rotation
+                                   that passes the exactness test
+                                   ||K r|| <= 1e-12 ||K||_F ||r|| (a direct exact solve)     */
 
 typedef struct {
   feti_variant variant;
@@ -123,13 +133,15 @@ typedef struct {
   double ir_tol;               /* mixed: target of the outer refinement,
                                   ||f - K u||_2 <= ir_tol ||f||_2 over free DOFs, FP64,
                                   assembled (0 => 1e-10)                                  */
-  int32_t ir_max;              /* mixed: max correction sweeps (negative => 6)            */
+  int32_t ir_max;              /* max correction sweeps of the refinement (negative => 6);
+                                  0: none (the residual is still reported in res_primal)  */
   int32_t graph_block;         /* PCG iterations captured per HIP graph (0 => 8)          */
   void* hip_stream;            /* hipStream_t to run on, or NULL for a library stream    */
   void* (*dev_alloc)(size_t bytes, void* stream, void* ctx);   /* optional allocator     */
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
-  uint64_t flags;              /* FETI_DEVICE_PTRS | FETI_PROFILE | FETI_AUTOTUNE          */
+  uint64_t flags;              /* FETI_DEVICE_PTRS | FETI_PROFILE | FETI_AUTOTUNE |
+                                  FETI_KERNEL6                                            */
 } feti_options;
 
 typedef struct {

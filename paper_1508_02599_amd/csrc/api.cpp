@@ -44,6 +44,11 @@ struct feti_problem {
   size_t bytes = 0;
   bool factored = false;
   bool factored_linear = false;
+  // FETI_KERNEL6 at a stressed state: the dual solve is of an approximate
+  // tangent, and the outer refinement against the exact sparse tangent
+  // (as for mixed precision) recovers the exact step
+  bool approx_tangent = false;
+  bool refined_out = false;     // the last result is in d_uglob
   int n_coarse = 0;
   int nq = 0;   // coarse tiles
   DevIdx di;
@@ -563,7 +568,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bv, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
-  if (P.mixed || (p->opt.flags & FETI_PROFILE)) {   // refinement / residual report
+  if (P.mixed || (p->opt.flags & (FETI_PROFILE | FETI_KERNEL6))) {   // refinement / residual report
     TRY(dalloc(p, p->d_f0, (size_t)P.NF));
     TRY(dalloc(p, p->d_uglob, (size_t)P.n_dof));
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
@@ -703,7 +708,8 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.ell_col = p->d_ell_col;
   m.ell_val = p->d_ell_val;
   m.NF = P.NF;
-  m.test_rotations = (P.any_hgo && U_dev) ? 1 : 0;
+  m.test_rotations = (P.any_hgo && U_dev && !(p->opt.flags & FETI_KERNEL6)) ? 1 : 0;
+  p->approx_tangent = P.any_hgo && U_dev && (p->opt.flags & FETI_KERNEL6);
   m.rfull = p->d_rfull;
   m.rb = p->d_rb;
   m.n_modes = p->d_nmodes;
@@ -999,7 +1005,9 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
   feti_status s = solve_core(p, stats, p->opt.rtol);
-  if (!P.mixed || (s != FETI_OK && s != FETI_ENOCONV)) {
+  const bool refine = P.mixed || p->approx_tangent;
+  p->refined_out = false;
+  if (!refine || (s != FETI_OK && s != FETI_ENOCONV)) {
     if ((s == FETI_OK || s == FETI_ENOCONV) && p->profile) {
       TRY(profile_gemv(p));
       // FP64 residual of the result, for comparison with the mixed path
@@ -1057,6 +1065,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     vec_axpby(nd, 1.0, p->d_out, 1.0, p->d_uglob, st);
     ++sweeps;
   }
+  p->refined_out = true;
   TRY(profile_gemv(p));
   if (stats) {
     stats->iters = iters;
@@ -1065,8 +1074,8 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
     stats->res_primal = fnorm > 0 ? rnorm / fnorm : 0.0;
   }
-  if (!(rnorm <= p->opt.ir_tol * fnorm)) {
-    p->err = "mixed-precision refinement did not reach ir_tol within ir_max corrections";
+  if (p->opt.ir_max > 0 && !(rnorm <= p->opt.ir_tol * fnorm)) {
+    p->err = "refinement did not reach ir_tol within ir_max corrections";
     return FETI_ENOCONV;
   }
   return FETI_OK;
@@ -1075,7 +1084,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
 feti_status write_output(feti_problem* p, double* out, int sum_mode) {
   HostPlan& P = p->P;
   double* dst = (p->opt.flags & FETI_DEVICE_PTRS) ? out : p->d_out;
-  if (P.mixed)
+  if (p->refined_out)
     HIPCHK(hipMemcpyAsync(dst, p->d_uglob, P.n_dof * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   else
     vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, dst, sum_mode, p->stream);
