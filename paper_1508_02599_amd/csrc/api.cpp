@@ -96,6 +96,7 @@ struct feti_problem {
   PcgState* d_state = nullptr;
   int* d_ticket = nullptr;
   double *d_fpart = nullptr, *d_qdense = nullptr, *d_gpart = nullptr;
+  double* d_apart = nullptr;   // block partials of s.q (alpha)
   int32_t* d_bco = nullptr;
   int2* d_rco = nullptr;     // per multiplier row: coarse codes of its two entries
   int ldg = 0;
@@ -332,10 +333,10 @@ void pcg_iteration(feti_problem* p) {
   pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, s);
   symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
   pcg_scatter_dot_alpha_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, p->d_yb, p->d_zv, p->d_s, p->d_q,
-                           p->d_fpart, p->d_ticket, st, p->d_gpart, p->ldg, s);
+                           p->d_apart, st, p->d_gpart, p->ldg, s);
   if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
   pcg_proj_apply(1, 0, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, p->d_r, p->d_q, p->d_s, p->d_lam, p->d_wv,
-                 nullptr, p->d_fpart, p->d_ticket + 1, st, nullptr, s);
+                 nullptr, p->d_fpart, p->d_ticket + 1, st, nullptr, s, p->d_apart);
   // preconditioner
   pcg_gather(p->di, 1, p->d_wv, p->d_xb, st, s);
   const double* y = p->d_xb;
@@ -581,6 +582,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_ticket, 4));
   HIPCHK(hipMemsetAsync(p->d_ticket, 0, 4 * sizeof(int), p->stream));
   TRY(dalloc(p, p->d_fpart, 2 * 256));
+  TRY(dalloc(p, p->d_apart, 256));
   TRY(dalloc(p, p->d_qdense, (size_t)max_coarse * max_coarse));
   p->ldg = max_coarse;
   TRY(dalloc(p, p->d_gpart, (size_t)4 * max_coarse));

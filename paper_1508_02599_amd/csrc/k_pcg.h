@@ -94,7 +94,7 @@ void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, d
 // Fused scatters that also form the coarse right-hand side of the next
 // projection from the interface vector (coarse = 0: no coarse space).
 void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
-                              const double* yb, const double* z, double* sv, double* q, double* part, int* ticket,
+                              const double* yb, const double* z, double* sv, double* q, double* part,
                               PcgState* st, double* gpart, int ldg, hipStream_t s);
 void pcg_scatter_w_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
                       const double* y, double* out, const PcgState* st, double* gpart, int ldg, hipStream_t s);
@@ -104,7 +104,8 @@ void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int
                       hipStream_t s);
 void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int2* rco, const double* rbv,
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
-                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s);
+                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s,
+                    const double* apart = nullptr);
 void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hipStream_t s);
 void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s);
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,

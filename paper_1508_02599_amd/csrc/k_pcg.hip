@@ -500,13 +500,14 @@ __global__ __launch_bounds__(256) void k_scatter_dot_alpha(
   }
 }
 
-// Fused: blocks [0, nrow_blocks) do q = B yb, s <- z + beta s and
-// alpha = rho / (s.q) (breakdown if s.q <= 0); the blocks after them form the
-// coarse right-hand side G^T q = Rb^T (B^T B) yb by subdomain chunks.
+// Fused: blocks [0, nrow_blocks) do q = B yb, s <- z + beta s and the block
+// partial sums of s.q (part[block]; alpha = rho / s.q is formed by the next
+// kernel from them); the blocks after them form the coarse right-hand side
+// G^T q = Rb^T (B^T B) yb by subdomain chunks.
 __global__ __launch_bounds__(256) void k_scatter_dot_alpha_gt(
     int64_t n, int nrow_blocks, const int64_t* __restrict__ b0, const double* __restrict__ c0,
     const int64_t* __restrict__ b1, const double* __restrict__ c1, const double* __restrict__ yb,
-    const double* __restrict__ z, double* sv, double* q, double* part, int* ticket, PcgState* st,
+    const double* __restrict__ z, double* sv, double* q, double* part, const PcgState* st,
     const SubInfo* __restrict__ subs, const int32_t* __restrict__ c_ptr, const int32_t* __restrict__ c_col,
     const double* __restrict__ cv, const double* __restrict__ rbv, double* gpart, int ldg) {
   if (st->done) return;
@@ -528,21 +529,6 @@ __global__ __launch_bounds__(256) void k_scatter_dot_alpha_gt(
   }
   block_reduce2(acc, unused, ra, rb);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
-  if (!last_block(ticket, nrow_blocks)) return;
-  double pq = 0.0;
-  for (int k = threadIdx.x; k < nrow_blocks; k += 256) pq += part[k];
-  block_reduce2(pq, unused, ra, rb);
-  if (threadIdx.x == 0) {
-    *ticket = 0;
-    st->pq = pq;
-    if (!(pq > 0.0)) {
-      st->alpha = 0.0;
-      st->done = 1;
-      st->status = FETI_EBREAKDOWN;
-    } else {
-      st->alpha = st->rho / pq;
-    }
-  }
 }
 
 // Fused: blocks [0, nrow_blocks) do the weighted scatter t = diag(w) B y;
@@ -673,10 +659,31 @@ __global__ __launch_bounds__(256) void k_proj_apply(
     const int64_t* __restrict__ b1, const double* __restrict__ c1, const int2* __restrict__ rco,
     const double* __restrict__ rbv, const double* __restrict__ ac, double* x,
     const double* __restrict__ q, const double* __restrict__ sv, double* lam, double* out,
-    const double* __restrict__ w, double* part, int* ticket, PcgState* st, double* hist) {
+    const double* __restrict__ w, double* part, int* ticket, PcgState* st, double* hist,
+    const double* __restrict__ apart, int napart) {
   if (st->done) return;
   __shared__ double ra[256], rb[256];
-  const double alpha = mode == 1 ? st->alpha : 0.0;
+  double alpha = 0.0;
+  if (mode == 1) {
+    // alpha = rho / s.q from the scatter's block partials, summed in the same
+    // order by every block; block 0 records it (or the breakdown)
+    double pq = threadIdx.x < napart ? apart[threadIdx.x] : 0.0, unused = 0.0;
+    block_reduce2(pq, unused, ra, rb);
+    if (!(pq > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = 0.0;
+        st->status = FETI_EBREAKDOWN;
+        st->done = 1;
+      }
+      return;
+    }
+    alpha = st->rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->pq = pq;
+      st->alpha = alpha;
+    }
+  }
   double d1 = 0.0, d2 = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
     double ga = 0.0;
@@ -966,11 +973,11 @@ void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, d
   hipLaunchKernelGGL(k_scatter_dot_alpha, dim3(FUSE_BLOCKS), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, yb, z, sv, q, part, ticket, st);
 }
 void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
-                              const double* yb, const double* z, double* sv, double* q, double* part, int* ticket,
+                              const double* yb, const double* z, double* sv, double* q, double* part,
                               PcgState* st, double* gpart, int ldg, hipStream_t s) {
   const int nb = FUSE_BLOCKS + (coarse ? GT_CHUNKS * n_sub : 0);
   hipLaunchKernelGGL(k_scatter_dot_alpha_gt, dim3(nb), dim3(256), 0, s, d.n_lam, FUSE_BLOCKS, d.r_b0, d.r_c0, d.r_b1,
-                     d.r_c1, yb, z, sv, q, part, ticket, st, subs, d.c_ptr, d.c_col, d.c_v0, rbv, gpart, ldg);
+                     d.r_c1, yb, z, sv, q, part, st, subs, d.c_ptr, d.c_col, d.c_v0, rbv, gpart, ldg);
 }
 void pcg_scatter_w_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
                       const double* y, double* out, const PcgState* st, double* gpart, int ldg, hipStream_t s) {
@@ -989,8 +996,9 @@ void pcg_coarse_dense(int nc, int ld, const double* Qi, const double* gpart, int
 }
 void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int2* rco, const double* rbv,
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
-                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, rco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist);
+                    const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s,
+                    const double* apart) {
+  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, rco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist, apart, FUSE_BLOCKS);
 }
 void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_fill_bco, grid1(d.NB), dim3(256), 0, s, d.NB, d.b_sub, subs, bco);

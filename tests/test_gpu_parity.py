@@ -256,3 +256,23 @@ def test_autotune_update_forms_identical(precision):
     assert wide[0] == -1 and wide[2] >= 0
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
     assert _rel(outs[2], ref) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_six_mode_kernel_refined_to_exact_step(precision):
+    """FETI_KERNEL6 at a stressed state: the dual solve uses all six rigid
+    modes as local kernels (an approximate tangent), and the refinement
+    against the exact sparse tangent recovers the exact Newton step."""
+    m = _small_tube()
+    U = _converged(m, 0.1)
+    dU_ref, rn_ref = monolithic.newton_increment(m, U, 0.2)
+    ir_tol, bar = (1e-12, 1e-9) if precision == "fp64" else (1e-10, 1e-8)
+    with _problem(m, variant="af", precond="dirichlet", precision=precision, rtol=1e-8, ir_tol=ir_tol,
+                  ir_max=80, kernel6=True) as p:
+        dU, rn, st = p.newton_step(U, 0.2)
+    err = _rel(dU, dU_ref)
+    print(f"six-mode kernel {precision}: it={st['iters']} sweeps={st['ir_sweeps']} coarse={st['n_coarse']} "
+          f"err={err:.3e}")
+    assert st["n_coarse"] == 6 * m.n_sub
+    assert abs(rn - rn_ref) <= 1e-9 * rn_ref
+    assert err <= bar
