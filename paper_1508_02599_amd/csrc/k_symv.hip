@@ -34,9 +34,19 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tas
   const T* tile = M + s.x_off + tidx2(t.i, t.j) * TS2;
   const int tid = threadIdx.x;
   {
+    // only the stored entries that take part are read: rows beyond the last
+    // real interface DOF (the padding of the last tile row meets zero inputs
+    // and its outputs are dropped) and the upper half of a diagonal tile (the
+    // lower half is mirrored) are not fetched
+    const int rows = t.i == s.nt_b - 1 ? s.n_b - TS * (s.nt_b - 1) : TS;
+    const int row = tid & 63;
     T v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = tile[tid + 256 * i];   // all loads in flight first
+    for (int i = 0; i < 16; ++i) {
+      const int col = (tid >> 6) + 4 * i;
+      const bool need = row < rows && (t.i != t.j || row >= col);
+      v[i] = need ? tile[tid + 256 * i] : T(0);   // all loads in flight first
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int e = tid + 256 * i;
