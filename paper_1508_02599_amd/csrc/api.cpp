@@ -39,6 +39,11 @@ struct feti_problem {
   feti_options opt{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream of the factorisation (diagonal tiles of a column step,
+  // concurrent with the rest of its updates) and its fork/join events
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool forked = false;
   DeviceAlloc da;
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -186,7 +191,20 @@ int update_index(const feti_problem* p, const HostPlan::Launch& L) {
 }
 
 void dense(feti_problem* p, const HostPlan::Launch& L) {
-  const bool upd = is_update(L.kind) && L.count > 0;
+  hipStream_t stream = p->stream;
+  if (L.side) {
+    if (!p->forked) {
+      (void)hipEventRecord(p->ev_fork, p->stream);
+      (void)hipStreamWaitEvent(p->stream2, p->ev_fork, 0);
+      p->forked = true;
+    }
+    stream = p->stream2;
+  } else if (L.join && p->forked) {
+    (void)hipEventRecord(p->ev_join, p->stream2);
+    (void)hipStreamWaitEvent(p->stream, p->ev_join, 0);
+    p->forked = false;
+  }
+  const bool upd = is_update(L.kind) && L.count > 0 && !L.side;
   const bool timed = p->profile && upd && 2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
   // the interior inverse goes to its own arena
   void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
@@ -196,16 +214,16 @@ void dense(feti_problem* p, const HostPlan::Launch& L) {
   const bool tuning = idx >= 0 && p->tune_phase < 2;
   const Task* t = p->d_tasks + (wide ? L.wfirst : L.first);
   const int count = wide ? L.wcount : L.count, split = wide ? L.wsplit : L.split;
-  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], p->stream);
-  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], p->stream);
+  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], stream);
+  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], stream);
   if (p->P.mixed)
     launch_dense<float>(L.kind, t, count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
-                        (float*)p->d_X, p->d_err, p->stream, split, wide);
+                        (float*)p->d_X, p->d_err, stream, split, wide);
   else
     launch_dense<double>(L.kind, t, count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
-                         (double*)p->d_X, p->d_err, p->stream, split, wide);
-  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], p->stream);
-  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], p->stream);
+                         (double*)p->d_X, p->d_err, stream, split, wide);
+  if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], stream);
+  if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], stream);
 }
 
 // After a factorisation: collect the autotuner's timings and advance it.
@@ -589,6 +607,9 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bco, (size_t)P.NB));
   TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
+  HIPCHK(hipStreamCreateWithFlags(&p->stream2, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
     p->ev_gemv.resize(2);
@@ -626,7 +647,7 @@ feti_status setup_device(feti_problem* p) {
       return std::min(TS, si.n_b - (t - si.nt_i) * TS);
     };
     auto add = [&](const HostPlan::Launch& L) {
-      if (!is_update(L.kind)) return;
+      if (!is_update(L.kind) || L.side) return;   // side launches are not timed
       const int nupd = L.kind == K_UPDATE ? L.count : L.split;
       for (int k = 0; k < L.count; ++k) {
         const Task& t = P.tasks[L.first + k];
@@ -1385,6 +1406,12 @@ void feti_destroy(feti_problem* p) {
     if (p->da.fr) p->da.fr(a, p->da.ctx);
     else (void)hipFree(a);
   }
+  if (p->stream2) {
+    (void)hipStreamSynchronize(p->stream2);
+    (void)hipStreamDestroy(p->stream2);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }

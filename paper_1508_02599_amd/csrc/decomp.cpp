@@ -83,27 +83,41 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     finish(L);
     widen(L);
   };
-  // stage 1: interior columns, left-looking (rows run over every tile row below)
+  // stage 1: interior columns, left-looking (rows run over every tile row
+  // below).  A column step j > 0 forks: the update of the diagonal tiles and
+  // their factorisation run on the second stream while the main one updates
+  // the tiles below; the panel solve joins them.
   for (int j = 0; j < max_i; ++j) {
-    if (j > 0) {
-      auto L = begin(K_UPDATE);
+    const bool fork = j > 0;
+    if (fork) {
+      auto Ld = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_i > j)
-          for (int i = j; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
-      if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
-      else plain(L);
-      interior.push_back(L);
+        if (subs[s].nt_i > j) tasks.push_back({s, j, j, 0, j});
+      finish(Ld);
+      Ld.side = 1;
+      interior.push_back(Ld);
     }
     auto D = begin(K_DIAG);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_i > j) tasks.push_back({s, j, j, 0, 0});
     finish(D);
+    D.side = fork;
     interior.push_back(D);
+    if (fork) {
+      auto L = begin(K_UPDATE);
+      for (int s = 0; s < ns; ++s)
+        if (subs[s].nt_i > j)
+          for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
+      if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
+      else plain(L);
+      interior.push_back(L);
+    }
     auto T = begin(K_TRSM);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_i > j)
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
     finish(T);
+    T.join = fork;
     interior.push_back(T);
   }
   // stage 2: Schur complement of the interior on every interface tile (with
@@ -118,21 +132,31 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   // stage 4: interface columns (updates only over interface columns), each
   // update launch carrying the previous block row of the interface inverse
   for (int jb = 0; jb < max_b; ++jb) {
-    if (jb > 0) {
-      auto L = begin(K_UPDATE);
+    const bool fork = jb > 0;
+    if (fork) {
+      auto Ld = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_b > jb) {
-          const int j = subs[s].nt_i + jb;
-          for (int i = j; i < subs[s].nt; ++i) tasks.push_back({s, i, j, subs[s].nt_i, j});
-        }
-      fused(L, K_UPD_TRTRI, jb - 1, false);
-      iface.push_back(L);
+        if (subs[s].nt_b > jb) tasks.push_back({s, subs[s].nt_i + jb, subs[s].nt_i + jb, subs[s].nt_i, subs[s].nt_i + jb});
+      finish(Ld);
+      Ld.side = 1;
+      iface.push_back(Ld);
     }
     auto D = begin(K_DIAG);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_b > jb) tasks.push_back({s, subs[s].nt_i + jb, subs[s].nt_i + jb, 0, 0});
     finish(D);
+    D.side = fork;
     iface.push_back(D);
+    if (fork) {
+      auto L = begin(K_UPDATE);
+      for (int s = 0; s < ns; ++s)
+        if (subs[s].nt_b > jb) {
+          const int j = subs[s].nt_i + jb;
+          for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, subs[s].nt_i, j});
+        }
+      fused(L, K_UPD_TRTRI, jb - 1, false);
+      iface.push_back(L);
+    }
     auto T = begin(K_TRSM);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_b > jb) {
@@ -140,7 +164,8 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
       }
     finish(T);
-    if (T.count) iface.push_back(T);
+    T.join = fork;
+    iface.push_back(T);
   }
   // stage 5: the last block row of the interface inverse
   if (max_b > 0) {

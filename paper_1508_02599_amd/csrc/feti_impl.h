@@ -120,11 +120,15 @@ struct HostPlan {
   // split: for a fused update + inverse-row launch, the number of update tasks.
   // wfirst/wcount/wsplit: the same launch with the tile updates paired into
   // 128x64 outputs (wcount = 0: no such form).
+  // side: runs on the second stream, forked from the main one (the update of
+  // the diagonal tile and its factorisation, concurrent with the rest of the
+  // column's updates); join: the main stream waits for the second before it.
   struct Launch {
     int kind;
     int32_t first, count;
     int32_t split = 0;
     int32_t wfirst = 0, wcount = 0, wsplit = 0;
+    int32_t side = 0, join = 0;
   };
   std::vector<Task> tasks;
   std::vector<Launch> sched_interior;   // stage 1

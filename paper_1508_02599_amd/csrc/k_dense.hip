@@ -147,29 +147,37 @@ __device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, boo
 
 // ---------------------------------------------------------------------------
 // C_ij <- C_ij - sum_{k0<=k<k1} L_ik L_jk^T   (left-looking update)
+// acc = sum_{k0<=k<k1} L_ik L_jk^T, software-pipelined: the tiles of step k+1
+// load while step k multiplies
+template <typename T>
+__device__ __forceinline__ void accumulate_tile(Acc<T>& acc, const T* __restrict__ base, int i, int j, int k0,
+                                                int k1, T* sA,
+                                                T* sB) {
+  acc.zero();
+  TileRegs<T> ra, rb;
+  if (k0 < k1) {
+    ra.fetch(base + tidx(i, k0) * TS2);
+    rb.fetch(base + tidx(j, k0) * TS2);
+  }
+  for (int k = k0; k < k1; ++k) {
+    ra.template store<false>(sA);
+    rb.template store<false>(sB);
+    __syncthreads();
+    if (k + 1 < k1) {
+      ra.fetch(base + tidx(i, k + 1) * TS2);
+      rb.fetch(base + tidx(j, k + 1) * TS2);
+    }
+    mma64(acc, sA, sB);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void update_tile(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* sA,
                                             T* sB) {
   T* base = arena + subs[t.sub].tile_off;
   Acc<T> acc;
-  acc.zero();
-  // software pipeline: the tiles of step k+1 load while step k multiplies
-  TileRegs<T> ra, rb;
-  if (t.k0 < t.k1) {
-    ra.fetch(base + tidx(t.i, t.k0) * TS2);
-    rb.fetch(base + tidx(t.j, t.k0) * TS2);
-  }
-  for (int k = t.k0; k < t.k1; ++k) {
-    ra.template store<false>(sA);
-    rb.template store<false>(sB);
-    __syncthreads();
-    if (k + 1 < t.k1) {
-      ra.fetch(base + tidx(t.i, k + 1) * TS2);
-      rb.fetch(base + tidx(t.j, k + 1) * TS2);
-    }
-    mma64(acc, sA, sB);
-    __syncthreads();
-  }
+  accumulate_tile(acc, base, t.i, t.j, t.k0, t.k1, sA, sB);
   acc_to_lds(sA, acc, T(-1), true);
   __syncthreads();
   T* C = base + tidx(t.i, t.j) * TS2;
