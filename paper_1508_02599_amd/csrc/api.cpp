@@ -43,6 +43,9 @@ struct feti_problem {
   // concurrent with the rest of its updates) and its fork/join events
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // pinned copies of the PCG state after the two replays in flight
+  PcgState* h_state = nullptr;
+  hipEvent_t ev_rep[2] = {nullptr, nullptr};
   bool forked = false;
   DeviceAlloc da;
   std::vector<void*> allocs;
@@ -608,6 +611,8 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
   HIPCHK(hipStreamCreateWithFlags(&p->stream2, hipStreamNonBlocking));
+  HIPCHK(hipHostMalloc((void**)&p->h_state, 2 * sizeof(PcgState), hipHostMallocDefault));
+  for (auto& ev : p->ev_rep) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
@@ -918,13 +923,27 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
       (void)hipGraphDestroy(gr);
       p->graph_iters = gb;
     }
+    // Two replays in flight: the host checks the state copied after one while
+    // the next already runs (kernels of a replay after convergence return at
+    // once), so the GPU does not wait for the host between replays.
     PcgState hs{};
-    for (;;) {
-      HIPCHK(hipMemcpyAsync(&hs, p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpyAsync(&p->h_state[0], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(p->ev_rep[0], st));
+    HIPCHK(hipGraphLaunch(p->graph, st));
+    HIPCHK(hipMemcpyAsync(&p->h_state[1], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(p->ev_rep[1], st));
+    for (int k = 0;; ++k) {
+      const int slot = k & 1;
+      HIPCHK(hipEventSynchronize(p->ev_rep[slot]));
+      hs = p->h_state[slot];
       if (hs.done) break;
       HIPCHK(hipGraphLaunch(p->graph, st));
+      HIPCHK(hipMemcpyAsync(&p->h_state[slot], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipEventRecord(p->ev_rep[slot], st));
     }
+    HIPCHK(hipStreamSynchronize(st));
+    hs = p->h_state[0].done ? p->h_state[0] : p->h_state[1];
+    if (p->h_state[0].done && p->h_state[1].done && p->h_state[1].it > hs.it) hs = p->h_state[1];
     iters = hs.it;
     status = hs.status;
     rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
@@ -1411,6 +1430,9 @@ void feti_destroy(feti_problem* p) {
     (void)hipStreamDestroy(p->stream2);
   }
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  for (auto& ev : p->ev_rep)
+    if (ev) (void)hipEventDestroy(ev);
+  if (p->h_state) (void)hipHostFree(p->h_state);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
