@@ -68,22 +68,22 @@ __device__ __forceinline__ void lds_load(T* s, const T* __restrict__ g) {
 }
 // A tile held in registers between its global load and its LDS store, so the
 // load of the next k-step's tiles can be in flight during this step's MFMAs.
-template <typename T>
+template <typename T, int NT = 256>
 struct TileRegs {
   typedef typename Vec16<T>::type V;
   static constexpr int EPV = Vec16<T>::n;
-  static constexpr int NV = TS2 / EPV / 256;
+  static constexpr int NV = TS2 / EPV / NT;
   V v[NV];
   __device__ __forceinline__ void fetch(const T* __restrict__ g) {
     const V* gv = reinterpret_cast<const V*>(g);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = gv[threadIdx.x + 256 * i];
+    for (int i = 0; i < NV; ++i) v[i] = gv[threadIdx.x + NT * i];
   }
   template <bool TRANS>
   __device__ __forceinline__ void store(T* s) const {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const int e0 = (threadIdx.x + 256 * i) * EPV;
+      const int e0 = (threadIdx.x + NT * i) * EPV;
 #pragma unroll
       for (int u = 0; u < EPV; ++u) {
         const int e = e0 + u;
@@ -114,8 +114,8 @@ struct Acc {
 
 // acc += opA * opB for one 64x64x64 product; wave w owns the 32x32 block (w>>1, w&1).
 template <typename T>
-__device__ __forceinline__ void mma64(Acc<T>& acc, const T* sA, const T* sB) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ void mma64w(Acc<T>& acc, const T* sA, const T* sB, int w) {
+  const int lane = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1, lr = lane & 15, lk = lane >> 4;
   // fully unrolled, so the LDS reads of later k-slices issue ahead of the
   // MFMAs that consume earlier ones
@@ -131,10 +131,15 @@ __device__ __forceinline__ void mma64(Acc<T>& acc, const T* sA, const T* sB) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ void mma64(Acc<T>& acc, const T* sA, const T* sB) {
+  mma64w(acc, sA, sB, (int)(threadIdx.x >> 6));
+}
+
 // Scatter scale*acc into LDS.  colmajor: s[col*LD + row]; else s[row*LD + col].
 template <typename T>
-__device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, bool colmajor) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ void acc_to_lds_w(T* s, const Acc<T>& acc, T scale, bool colmajor, int w) {
+  const int lane = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1;
   for (int x = 0; x < 2; ++x)
     for (int y = 0; y < 2; ++y)
@@ -143,6 +148,10 @@ __device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, boo
         const int col = 32 * wc + 16 * y + (lane & 15);
         s[colmajor ? col * LD + row : row * LD + col] = scale * acc.c[x][y][r];
       }
+}
+template <typename T>
+__device__ __forceinline__ void acc_to_lds(T* s, const Acc<T>& acc, T scale, bool colmajor) {
+  acc_to_lds_w(s, acc, scale, colmajor, (int)(threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------------------
@@ -202,30 +211,26 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, 
   else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
 }
 
-// Wide form: one block updates output tiles (i, j) and (i+1, j) (t.n = 2;
-// t.n = 1: only (i, j)), sharing the column panel L_jk.  Each wave computes 32
-// rows x 64 columns (8 accumulators), so a k-slice takes 6 LDS reads for 8
-// MFMAs, and a k-step stages three tiles for twice the work of the 64x64
-// form.  Every output element sums the same products in the same order as in
-// update_tile, so both forms give bit-identical factors.
+// Wide form: one workgroup of eight waves updates output tiles (i, j) and
+// (i+1, j) (t.n = 2; t.n = 1: only (i, j)), sharing the column panel L_jk:
+// three tiles staged per k-step for two tiles of output, 27% less memory
+// traffic per flop than the 64x64 form, with two waves per SIMD.  Waves 0-3
+// compute tile i, waves 4-7 tile i+1, each a 32x32 block as in mma64, so every
+// output element sums the same products in the same order as in update_tile:
+// both forms give bit-identical factors.
 template <typename T>
-__device__ __forceinline__ void update_tile_wide(const Task& t, const SubInfo* __restrict__ subs, T* arena,
-                                                 T* sA0, T* sA1, T* sB) {
+__global__ __launch_bounds__(512) void k_update_wide(const Task* __restrict__ tasks,
+                                                     const SubInfo* __restrict__ subs, T* arena) {
+  __shared__ T sA0[TS * LD], sA1[TS * LD], sB[TS * LD];
+  const Task t = tasks[blockIdx.x];
   T* base = arena + subs[t.sub].tile_off;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int h = w >> 1;            // output tile i + h
-  const int r0 = 32 * (w & 1);     // first row of this wave within that tile
-  const int lr = lane & 15, lk = lane >> 4;
+  const int w = threadIdx.x >> 6;
+  const int h = w >> 2, wl = w & 3;
   const bool two = t.n == 2;
   const bool active = h == 0 || two;
-  typename V4<T>::type acc[2][4];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[x][y][r] = T(0);
-  TileRegs<T> ra0, ra1, rb;
+  Acc<T> acc;
+  acc.zero();
+  TileRegs<T, 512> ra0, ra1, rb;
   if (t.k0 < t.k1) {
     ra0.fetch(base + tidx(t.i, t.k0) * TS2);
     if (two) ra1.fetch(base + tidx(t.i + 1, t.k0) * TS2);
@@ -241,55 +246,17 @@ __device__ __forceinline__ void update_tile_wide(const Task& t, const SubInfo* _
       if (two) ra1.fetch(base + tidx(t.i + 1, k + 1) * TS2);
       rb.fetch(base + tidx(t.j, k + 1) * TS2);
     }
-    if (active) {
-      const T* sA = h ? sA1 : sA0;
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int kr = 4 * kk + lk;
-        const T a0 = sA[kr * LD + r0 + lr], a1 = sA[kr * LD + r0 + 16 + lr];
-        T b[4];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) b[y] = sB[kr * LD + 16 * y + lr];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          acc[0][y] = mfma4(a0, b[y], acc[0][y]);
-          acc[1][y] = mfma4(a1, b[y], acc[1][y]);
-        }
-      }
-    }
+    if (active) mma64w(acc, h ? sA1 : sA0, sB, wl);
     __syncthreads();
   }
-  // -acc into LDS (column-major, tile h), then added to C
-  if (active) {
-    T* sC = h ? sA1 : sA0;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + 16 * x + out_row(T(0), lane, r);
-          const int col = 16 * y + lr;
-          sC[col * LD + row] = -acc[x][y][r];
-        }
-  }
+  if (active) acc_to_lds_w(h ? sA1 : sA0, acc, T(-1), true, wl);
   __syncthreads();
   T* C0 = base + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 256) C0[e] += sA0[(e >> 6) * LD + (e & 63)];
+  for (int e = threadIdx.x; e < TS2; e += 512) C0[e] += sA0[(e >> 6) * LD + (e & 63)];
   if (two) {
     T* C1 = base + tidx(t.i + 1, t.j) * TS2;
-    for (int e = threadIdx.x; e < TS2; e += 256) C1[e] += sA1[(e >> 6) * LD + (e & 63)];
+    for (int e = threadIdx.x; e < TS2; e += 512) C1[e] += sA1[(e >> 6) * LD + (e & 63)];
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_update_wide(const Task* __restrict__ tasks, int n_upd,
-                                                     const SubInfo* __restrict__ subs, T* arena,
-                                                     const T* __restrict__ linv, T* W, int interior) {
-  __shared__ T sA0[TS * LD], sA1[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
-  if ((int)blockIdx.x < n_upd) update_tile_wide<T>(t, subs, arena, sA0, sA1, sB);
-  else trtri_tile<T>(t, subs, arena, linv, W, interior, sA0, sB);
 }
 
 // Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
@@ -679,11 +646,13 @@ template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
                   T* W, T* X, int* err, hipStream_t st, int split, int wide) {
   if (count <= 0) return;
-  if (wide) {   // update launches only: the task list is the wide form
+  if (wide) {   // update launches only: the task list is the wide form, then the inverse rows
     const int nupd = kind == K_UPDATE ? count : split;
     const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
-    hipLaunchKernelGGL(k_update_wide<T>, dim3(count), dim3(256), 0, st, tasks, nupd, subs, arena, (const T*)linv, W,
-                       interior);
+    if (nupd > 0) hipLaunchKernelGGL(k_update_wide<T>, dim3(nupd), dim3(512), 0, st, tasks, subs, arena);
+    if (count > nupd)
+      hipLaunchKernelGGL(k_trtri<T>, dim3(count - nupd), dim3(256), 0, st, tasks + nupd, subs, (const T*)arena,
+                         (const T*)linv, W, interior);
     return;
   }
   switch (kind) {
