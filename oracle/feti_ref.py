@@ -25,8 +25,11 @@ Readings where the paper is silent (stated in the design notes):
 * generalised inverse: interior-first block elimination; the interface Schur
   complement S_i is regularised as S_i + rho Rb Rb^T with Rb an orthonormal
   basis of the kernel restricted to the interface and rho = mean(diag S_i);
-* multiplicity of a DOF = number of subdomain copies, +1 for a Dirichlet DOF
-  in the all-floating variant; row weight = 1 / multiplicity;
+* scaled jump rows B_D: a gluing row of a DOF with m subdomain copies has
+  weight 1/m; at a Dirichlet DOF of the all-floating variant the Dirichlet
+  rows have weight 1 and the gluing rows weight 0 (the fixed boundary value is
+  the neighbour that takes the whole jump).  Both choices give
+  B B_D^T B = B, the defining property of a scaled jump operator;
 * stopping rule ||P r_k|| <= rtol ||P r_0||;
 * kernel of a stressed tangent: the three translations, plus each rotation
   about the current positions that K_i annihilates to 1e-12 relative.
@@ -107,7 +110,12 @@ class TornProblem:
             isdir = dir_mask[g]
             if variant == "classical" and isdir:
                 continue
-            mult = len(cs) + (1 if (variant == "af" and isdir) else 0)
+            # weights of the scaled rows B_D (eq. (feti_preconditioner)): 1/m on
+            # gluing rows of a DOF with m copies; at an all-floating Dirichlet
+            # DOF the fixed boundary value is the neighbour that takes the whole
+            # jump: weight 1 on its rows, 0 on the gluing rows of that DOF
+            afdir = variant == "af" and isdir
+            w_glue = 0.0 if afdir else 1.0 / len(cs)
             if len(cs) >= 2:
                 for a in range(len(cs)):
                     for b in range(a + 1, len(cs)):
@@ -115,12 +123,12 @@ class TornProblem:
                         rows.append([(sa, self.subs[sa]["loc_of_gdof"][g], 1.0),
                                      (sb, self.subs[sb]["loc_of_gdof"][g], -1.0)])
                         bvals.append(0.0)
-                        wts.append(1.0 / mult)
+                        wts.append(w_glue)
             if variant == "af" and isdir:
                 for sa in cs:
                     rows.append([(sa, self.subs[sa]["loc_of_gdof"][g], 1.0)])
                     bvals.append(dir_value[g])
-                    wts.append(1.0 / mult)
+                    wts.append(1.0)
         self.rows = rows
         self.b = np.array(bvals)
         self.w = np.array(wts)

@@ -6,7 +6,7 @@
 // and coupling DOFs (section 4, eqs. (decomposition), (skeleton), (reordered));
 // jump operators B_i with entries in {0, +1, -1} (section 4.1), "fully
 // redundant" gluing (Fig. 3); all-floating Dirichlet rows B_D,i with right-hand
-// side b (section 4.2, eq. (jumpoperatorAF)); multiplicity-scaled rows for the
+// side b (section 4.2, eq. (jumpoperatorAF)); scaled rows B_D for the
 // preconditioner (eq. (feti_preconditioner)).
 #include <algorithm>
 #include <array>
@@ -351,14 +351,20 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     const int nc = nc_ptr[nd + 1] - nc_ptr[nd];
     const bool isdir = P.dir_mask[g];
     if (!P.af && isdir) continue;
-    const int mult = nc + ((P.af && isdir) ? 1 : 0);
+    // Scaled rows of B_D (eq. (feti_preconditioner)): 1/multiplicity on the
+    // gluing rows.  At a Dirichlet DOF of the all-floating variant the
+    // boundary is a neighbour whose value is fixed: its row carries the whole
+    // jump of each copy (weight 1) and the gluing rows between the copies
+    // carry none, which keeps B B_D^T B = B (B_D^T B a projection).
+    const bool afdir = P.af && isdir;
+    const double w_glue = afdir ? 0.0 : 1.0 / nc;
     for (int a = 0; a < nc; ++a)
       for (int b = a + 1; b < nc; ++b) {
         re0.push_back(3 * (int64_t)nc_loc[nc_ptr[nd] + a] + comp);
         re1.push_back(3 * (int64_t)nc_loc[nc_ptr[nd] + b] + comp);
         P.r_c0.push_back(1.0);
         P.r_c1.push_back(-1.0);
-        P.r_w.push_back(1.0 / mult);
+        P.r_w.push_back(w_glue);
         P.r_gdof.push_back(-1);
       }
     if (P.af && isdir)
@@ -367,7 +373,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
         re1.push_back(-1);
         P.r_c0.push_back(1.0);
         P.r_c1.push_back(0.0);
-        P.r_w.push_back(1.0 / mult);
+        P.r_w.push_back(1.0);
         P.r_gdof.push_back(g);
       }
   }

@@ -190,6 +190,25 @@ def test_feti_ref_preconditioners_agree_with_monolithic(cube8, variant):
         assert tp.n_lam == 732
 
 
+@pytest.mark.parametrize("variant", ["af", "classical"])
+def test_scaled_jump_operator_is_generalised_inverse(variant):
+    """The scaled rows B_D of the preconditioner (eq. (feti_preconditioner))
+    satisfy B B_D^T B = B, so that B_D^T B is a projection; checked on the dense
+    B over all subdomain copies of a 3x3x3-subdomain cube, which has DOFs with
+    1, 2, 4 and 8 copies, on and off the Dirichlet boundary."""
+    m = cube_mesh(6, 3)
+    tp = feti_ref.linear_torn_problem(m, variant)
+    off = np.cumsum([0] + [sd["K"].shape[0] for sd in tp.subs])
+    B = np.zeros((tp.n_lam, off[-1]))
+    for r, row in enumerate(tp.rows):
+        for (sub, ld, c) in row:
+            B[r, off[sub] + ld] = c
+    Pd = (tp.w[:, None] * B).T @ B
+    assert np.abs(B @ Pd - B).max() <= 1e-14
+    assert np.abs(Pd @ Pd - Pd).max() <= 1e-14
+    assert tp.w.min() >= 0.0 and tp.w.max() <= 1.0
+
+
 def test_feti_ref_constraint_residual(cube8):
     m, _ = cube8
     tp = feti_ref.linear_torn_problem(m, "af")
