@@ -110,9 +110,10 @@ typedef struct {
 #define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */
 #define FETI_PROFILE 0x2ull     /* time the dual-operator GEMV and factor-update kernels with
                                    HIP events (reported in feti_stats.kernel_*)              */
-#define FETI_AUTOTUNE 0x4ull    /* pick the output shape of each factor-update launch (64x64 or
-                                   128x64 tiles per workgroup) by timing both in the first two
-                                   factorisations; the factors do not depend on the choice   */
+#define FETI_AUTOTUNE 0x4ull    /* pick the form of each factor-update launch (64x64 tiles,
+                                   128x64 tiles, or 64x64 tiles with double-buffered direct
+                                   global-to-LDS loads) by timing each in one of the first
+                                   three factorisations; the factors do not depend on it     */
 #define FETI_KERNEL6 0x8ull     /* take all six rigid-body modes as the kernel of every floating
                                    subdomain, as the paper does (section 4.3).  Exact for
                                    stress-free tangents.  For stressed ones (Newton steps away
@@ -170,6 +171,8 @@ typedef struct {
                                   FETI_FP64, else 0                                         */
   int32_t autotune_wide;       /* FETI_AUTOTUNE: update launches that use 128x64 tiles once
                                   tuned; -1 while tuning or without FETI_AUTOTUNE          */
+  int32_t autotune_db;         /* FETI_AUTOTUNE: update launches that use the double-buffered
+                                  form once tuned; -1 while tuning or without it          */
 } feti_stats;
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */

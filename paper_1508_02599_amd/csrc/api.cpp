@@ -46,7 +46,7 @@ struct feti_problem {
   // pinned copies of the PCG state after the two replays in flight
   PcgState* h_state = nullptr;
   hipEvent_t ev_rep[2] = {nullptr, nullptr};
-  bool forked = false;
+  bool side_pending = false;   // work queued on stream2 that the main stream has not waited for
   DeviceAlloc da;
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -118,17 +118,19 @@ struct feti_problem {
   bool profile = false;
   std::vector<hipEvent_t> ev_gemv, ev_upd;   // burst start/end; pairs around update launches
   int n_upd_recorded = 0;
-  // autotuner of the update launches (FETI_AUTOTUNE): the first factorisation
-  // times the 64x64 form of every update launch, the second the 128x64 form;
-  // from then on each launch uses the faster.  Both forms give identical
-  // factors.  Launches are identified by the first task of their 64x64 form.
+  // autotuner of the update launches (FETI_AUTOTUNE): factorisation f < 3
+  // times form f of every update launch (0: 64x64 tiles, 1: 128x64, 2: 64x64
+  // double-buffered); from then on each launch uses its fastest form.  All
+  // forms give identical factors.  Launches are identified by the first task
+  // of their 64x64 form.
+  static constexpr int kForms = 3;
   bool autotune = false;
-  int tune_phase = 0;                          // 0, 1: measuring; 2: decided
+  int tune_phase = 0;                          // < kForms: measuring; kForms: decided
   std::vector<int32_t> upd_first;              // update launches, by first task
-  std::vector<float> t_tile, t_wide;
-  std::vector<uint8_t> use_wide;
+  std::vector<float> t_form[kForms];
+  std::vector<uint8_t> use_form;
   std::vector<hipEvent_t> ev_tune;
-  int n_wide = -1;
+  int n_wide = -1, n_db = -1;
   double prof_gemv_ms = 0.0, prof_upd_ms = 0.0, upd_flops = 0.0, gemv_bytes = 0.0;
   int prof_gemv_n = 0, prof_upd_n = 0;
 };
@@ -193,46 +195,54 @@ int update_index(const feti_problem* p, const HostPlan::Launch& L) {
   return (it != p->upd_first.end() && *it == L.first) ? (int)(it - p->upd_first.begin()) : -1;
 }
 
+// The main stream waits for everything queued so far on the second stream.
+void join_side(feti_problem* p) {
+  if (!p->side_pending) return;
+  (void)hipEventRecord(p->ev_join, p->stream2);
+  (void)hipStreamWaitEvent(p->stream, p->ev_join, 0);
+  p->side_pending = false;
+}
+
+// A launch runs on the second stream if L.side; with L.join it first waits
+// for everything queued so far on the other stream.
 void dense(feti_problem* p, const HostPlan::Launch& L) {
-  hipStream_t stream = p->stream;
+  hipStream_t stream = L.side ? p->stream2 : p->stream;
   if (L.side) {
-    if (!p->forked) {
+    if (L.join) {
       (void)hipEventRecord(p->ev_fork, p->stream);
       (void)hipStreamWaitEvent(p->stream2, p->ev_fork, 0);
-      p->forked = true;
     }
-    stream = p->stream2;
-  } else if (L.join && p->forked) {
-    (void)hipEventRecord(p->ev_join, p->stream2);
-    (void)hipStreamWaitEvent(p->stream, p->ev_join, 0);
-    p->forked = false;
+    p->side_pending = true;
+  } else if (L.join) {
+    join_side(p);
   }
   const bool upd = is_update(L.kind) && L.count > 0 && !L.side;
   const bool timed = p->profile && upd && 2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
   // the interior inverse goes to its own arena
   void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
-  int wide = 0, idx = -1;
+  int form = 0, idx = -1;
   if (upd && p->autotune && (idx = update_index(p, L)) >= 0 && L.wcount > 0)
-    wide = p->tune_phase == 0 ? 0 : p->tune_phase == 1 ? 1 : p->use_wide[idx];
-  const bool tuning = idx >= 0 && p->tune_phase < 2;
+    form = p->tune_phase < feti_problem::kForms ? p->tune_phase : p->use_form[idx];
+  const bool tuning = idx >= 0 && p->tune_phase < feti_problem::kForms;
+  const bool wide = form == 1;
   const Task* t = p->d_tasks + (wide ? L.wfirst : L.first);
   const int count = wide ? L.wcount : L.count, split = wide ? L.wsplit : L.split;
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], stream);
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], stream);
   if (p->P.mixed)
     launch_dense<float>(L.kind, t, count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
-                        (float*)p->d_X, p->d_err, stream, split, wide);
+                        (float*)p->d_X, p->d_err, stream, split, form);
   else
     launch_dense<double>(L.kind, t, count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
-                         (double*)p->d_X, p->d_err, stream, split, wide);
+                         (double*)p->d_X, p->d_err, stream, split, form);
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], stream);
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], stream);
 }
 
 // After a factorisation: collect the autotuner's timings and advance it.
 void autotune_step(feti_problem* p) {
-  if (!p->autotune || p->tune_phase >= 2) return;
-  auto& dst = p->tune_phase == 0 ? p->t_tile : p->t_wide;
+  if (!p->autotune || p->tune_phase >= feti_problem::kForms) return;
+  auto& dst = p->t_form[p->tune_phase];
   for (size_t k = 0; k < p->upd_first.size(); ++k) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p->ev_tune[2 * k], p->ev_tune[2 * k + 1]) != hipSuccess) {
@@ -241,11 +251,15 @@ void autotune_step(feti_problem* p) {
     }
     dst[k] = ms;
   }
-  if (++p->tune_phase == 2) {
-    p->n_wide = 0;
+  if (++p->tune_phase == feti_problem::kForms) {
+    p->n_wide = p->n_db = 0;
     for (size_t k = 0; k < p->upd_first.size(); ++k) {
-      p->use_wide[k] = p->t_wide[k] > 0.f && p->t_wide[k] < p->t_tile[k];
-      p->n_wide += p->use_wide[k];
+      int best = 0;
+      for (int f = 1; f < feti_problem::kForms; ++f)
+        if (p->t_form[f][k] > 0.f && p->t_form[f][k] < p->t_form[best][k]) best = f;
+      p->use_form[k] = (uint8_t)best;
+      p->n_wide += best == 1;
+      p->n_db += best == 2;
     }
   }
 }
@@ -633,9 +647,8 @@ feti_status setup_device(feti_problem* p) {
     for (const auto& L : P.sched_iface) reg(L);
     std::sort(p->upd_first.begin(), p->upd_first.end());
     const size_t nl = p->upd_first.size();
-    p->t_tile.assign(nl, 0.f);
-    p->t_wide.assign(nl, 0.f);
-    p->use_wide.assign(nl, 0);
+    for (auto& tf : p->t_form) tf.assign(nl, 0.f);
+    p->use_form.assign(nl, 0);
     p->ev_tune.resize(2 * nl);
     for (auto& ev : p->ev_tune) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
   }
@@ -787,6 +800,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
                               st);
   }
   for (const auto& L : P.sched_iface) dense(p, L);
+  join_side(p);
   for (const auto& L : P.sched_trtri) dense(p, L);
   dense(p, P.sched_lauum);
   {
@@ -984,6 +998,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     stats->n_lambda = n;
     stats->device_bytes = p->bytes;
     stats->autotune_wide = p->n_wide;
+    stats->autotune_db = p->n_db;
   }
   if (status == FETI_EBREAKDOWN) {
     p->err = "PCG breakdown (s.Fs <= 0)";

@@ -84,30 +84,35 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     widen(L);
   };
   // stage 1: interior columns, left-looking (rows run over every tile row
-  // below).  A column step j > 0 forks: the update of the diagonal tiles and
-  // their factorisation run on the second stream while the main one updates
-  // the tiles below; the panel solve joins them.
+  // below).  A column step j > 0 forks onto the second stream: the diagonal
+  // tile j takes its last update term (k = j - 1) and is factored there while
+  // the main stream updates the tiles below (and subtracts the terms k < j of
+  // diagonal tile j + 1, so that the forked path stays one term long); the
+  // panel solve on the main stream joins the two.
   for (int j = 0; j < max_i; ++j) {
-    const bool fork = j > 0;
-    if (fork) {
+    const bool step = j > 0;
+    if (step) {
       auto Ld = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_i > j) tasks.push_back({s, j, j, 0, j});
+        if (subs[s].nt_i > j) tasks.push_back({s, j, j, j - 1, j});
       finish(Ld);
       Ld.side = 1;
+      Ld.join = 1;
       interior.push_back(Ld);
     }
     auto D = begin(K_DIAG);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_i > j) tasks.push_back({s, j, j, 0, 0});
     finish(D);
-    D.side = fork;
+    D.side = step;
     interior.push_back(D);
-    if (fork) {
+    if (step) {
       auto L = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_i > j)
+        if (subs[s].nt_i > j) {
           for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
+          if (subs[s].nt_i > j + 1) tasks.push_back({s, j + 1, j + 1, 0, j});
+        }
       if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
       else plain(L);
       interior.push_back(L);
@@ -117,7 +122,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
       if (subs[s].nt_i > j)
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
     finish(T);
-    T.join = fork;
+    T.join = step;
     interior.push_back(T);
   }
   // stage 2: Schur complement of the interior on every interface tile (with
@@ -129,30 +134,37 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int I = J; I < subs[s].nt; ++I) tasks.push_back({s, I, J, 0, subs[s].nt_i});
   if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
   else plain(schur);
+  schur.join = 1;
   // stage 4: interface columns (updates only over interface columns), each
-  // update launch carrying the previous block row of the interface inverse
+  // update launch carrying the previous block row of the interface inverse;
+  // the column steps fork as in stage 1
   for (int jb = 0; jb < max_b; ++jb) {
-    const bool fork = jb > 0;
-    if (fork) {
+    const bool step = jb > 0;
+    if (step) {
       auto Ld = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_b > jb) tasks.push_back({s, subs[s].nt_i + jb, subs[s].nt_i + jb, subs[s].nt_i, subs[s].nt_i + jb});
+        if (subs[s].nt_b > jb) {
+          const int j = subs[s].nt_i + jb;
+          tasks.push_back({s, j, j, j - 1, j});
+        }
       finish(Ld);
       Ld.side = 1;
+      Ld.join = 1;
       iface.push_back(Ld);
     }
     auto D = begin(K_DIAG);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_b > jb) tasks.push_back({s, subs[s].nt_i + jb, subs[s].nt_i + jb, 0, 0});
     finish(D);
-    D.side = fork;
+    D.side = step;
     iface.push_back(D);
-    if (fork) {
+    if (step) {
       auto L = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_b > jb) {
           const int j = subs[s].nt_i + jb;
           for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, subs[s].nt_i, j});
+          if (subs[s].nt_b > jb + 1) tasks.push_back({s, j + 1, j + 1, subs[s].nt_i, j});
         }
       fused(L, K_UPD_TRTRI, jb - 1, false);
       iface.push_back(L);
@@ -164,7 +176,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
       }
     finish(T);
-    T.join = fork;
+    T.join = step;
     iface.push_back(T);
   }
   // stage 5: the last block row of the interface inverse
@@ -172,6 +184,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     auto L = begin(K_TRTRI);
     inverse_row(max_b - 1, false);
     finish(L);
+    L.join = 1;
     trtri.push_back(L);
   }
   // stage 6: X = W^T W

@@ -38,6 +38,25 @@ __device__ __forceinline__ int out_row(float, int l, int r) { return 4 * (l >> 4
 
 __device__ __forceinline__ int64_t tidx(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
+// Task of this workgroup.  Workgroups of a launch are handed to the eight
+// XCDs in turn (workgroup b to XCD b mod 8), each XCD with its own L2.  Task
+// lists run subdomain by subdomain, and the tasks of one subdomain share
+// operand tiles (the column panel of a column step, the rows of W in X = W^T W),
+// so XCD x takes the contiguous run of tasks [x n/8, (x+1) n/8) in order:
+// neighbouring tasks, and the tiles they share, stay in one L2.  A bijection
+// of [0, n), whatever the order the hardware actually dispatches in.
+__device__ __forceinline__ int xcd_map(int l, int n) {
+  const int q = n >> 3, r = n & 7, x = l & 7;
+  return x * q + min(x, r) + (l >> 3);
+}
+__device__ __forceinline__ int xcd_task() { return xcd_map((int)blockIdx.x, (int)gridDim.x); }
+// Launches that carry tasks of two kinds (updates [0, n_upd), then rows of an
+// inverse) remap each range on its own, so that both spread over every XCD.
+__device__ __forceinline__ int xcd_task_split(int n_upd) {
+  const int b = (int)blockIdx.x, n = (int)gridDim.x;
+  return b < n_upd ? xcd_map(b, n_upd) : n_upd + xcd_map(b - n_upd, n - n_upd);
+}
+
 // LDS operand layout: s[k*LD + m] holds op(A)(m, k) (or op(B)(k, m)).
 // Tiles are read with 16-byte vector loads, all issued before any LDS store,
 // so that a workgroup keeps a whole 64x64 tile of loads in flight.
@@ -113,17 +132,19 @@ struct Acc {
 };
 
 // acc += opA * opB for one 64x64x64 product; wave w owns the 32x32 block (w>>1, w&1).
-template <typename T>
+// LDX: leading dimension of the LDS operands.
+// KC: number of k-values held (a multiple of 4; 64 = the whole tile).
+template <typename T, int LDX = LD, int KC = TS>
 __device__ __forceinline__ void mma64w(Acc<T>& acc, const T* sA, const T* sB, int w) {
   const int lane = threadIdx.x & 63;
   const int wr = w >> 1, wc = w & 1, lr = lane & 15, lk = lane >> 4;
   // fully unrolled, so the LDS reads of later k-slices issue ahead of the
   // MFMAs that consume earlier ones
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) {
+  for (int kk = 0; kk < KC / 4; ++kk) {
     const int k = 4 * kk + lk;
-    const T a0 = sA[k * LD + 32 * wr + lr], a1 = sA[k * LD + 32 * wr + 16 + lr];
-    const T b0 = sB[k * LD + 32 * wc + lr], b1 = sB[k * LD + 32 * wc + 16 + lr];
+    const T a0 = sA[k * LDX + 32 * wr + lr], a1 = sA[k * LDX + 32 * wr + 16 + lr];
+    const T b0 = sB[k * LDX + 32 * wc + lr], b1 = sB[k * LDX + 32 * wc + 16 + lr];
     acc.c[0][0] = mfma4(a0, b0, acc.c[0][0]);
     acc.c[0][1] = mfma4(a0, b1, acc.c[0][1]);
     acc.c[1][0] = mfma4(a1, b0, acc.c[1][0]);
@@ -206,9 +227,86 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, 
                                                 const SubInfo* __restrict__ subs, T* arena,
                                                 const T* __restrict__ linv, T* W, int interior) {
   __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
-  if ((int)blockIdx.x < n_upd) update_tile<T>(t, subs, arena, sA, sB);
+  const int b = xcd_task_split(n_upd);
+  const Task t = tasks[b];
+  if (b < n_upd) update_tile<T>(t, subs, arena, sA, sB);
   else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
+}
+
+// Copy N consecutive elements from global memory into LDS unchanged
+// (s[e] = g[e]) with the direct global-to-LDS loads of gfx950: each
+// instruction moves 16 bytes per lane, 1 KiB per wave, to consecutive LDS
+// addresses from a wave-uniform base, without passing through registers.
+// Their completion is counted by vmcnt.
+template <typename T, int N>
+__device__ __forceinline__ void dma_copy(T* s, const T* __restrict__ g) {
+  constexpr int RUNS = N * (int)sizeof(T) / 1024;   // 1 KiB runs
+  constexpr int PER_WAVE = RUNS / 4;
+  static_assert(PER_WAVE * 4 * 1024 == N * (int)sizeof(T), "whole 1 KiB runs per wave");
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < PER_WAVE; ++q) {
+    const int run = w * PER_WAVE + q;
+    __builtin_amdgcn_global_load_lds(
+        (const __attribute__((address_space(1))) void*)((const char*)g + run * 1024 + lane * 16),
+        (__attribute__((address_space(3))) void*)((char*)s + run * 1024), 16, 0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(0): every global (and global-to-LDS) load of this wave done
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Double-buffered form of k_update: the operands advance in chunks of KC
+// k-values (KC consecutive columns of a column-major tile: 64 KC contiguous
+// elements).  The next chunk of both operands streams straight into the other
+// LDS buffer (dma_copy) while this chunk's MFMAs read the current one, with
+// one barrier per chunk.  LDS rows are unpadded (64 elements): each 16-lane
+// group of an operand read takes 16 consecutive elements.  Same products in
+// the same order as update_tile, so the results are bit-identical.  With
+// KC = 32 the buffers take 64 KiB in FP64, two workgroups per compute unit.
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k_update_db(const Task* __restrict__ tasks, int n_upd,
+                                                   const SubInfo* __restrict__ subs, T* arena,
+                                                   const T* __restrict__ linv, T* W, int interior) {
+  constexpr int CH = TS * KC;                 // elements per chunk
+  constexpr int PARTS = TS / KC;              // chunks per tile
+  constexpr int NLDS = 4 * CH > 2 * TS * LD ? 4 * CH : 2 * TS * LD;
+  __shared__ T lds[NLDS];                     // [buffer][A, B][chunk]; the inverse rows use 2 TS LD
+  const int b = xcd_task_split(n_upd);
+  const Task t = tasks[b];
+  if (b >= n_upd) {
+    trtri_tile<T>(t, subs, arena, linv, W, interior, lds, lds + TS * LD);
+    return;
+  }
+  T* base = arena + subs[t.sub].tile_off;
+  const int w = threadIdx.x >> 6;
+  const int steps = (t.k1 - t.k0) * PARTS;
+  Acc<T> acc;
+  acc.zero();
+  if (steps > 0) {
+    dma_copy<T, CH>(lds, base + tidx(t.i, t.k0) * TS2);
+    dma_copy<T, CH>(lds + CH, base + tidx(t.j, t.k0) * TS2);
+  }
+  for (int st = 0; st < steps; ++st) {
+    const int cur = st & 1;
+    // this chunk has landed (every wave's share), and every wave is done
+    // reading the other buffer
+    wait_vm();
+    __syncthreads();
+    if (st + 1 < steps) {
+      const int k = t.k0 + (st + 1) / PARTS, part = (st + 1) % PARTS;
+      T* nxt = lds + (cur ^ 1) * 2 * CH;
+      dma_copy<T, CH>(nxt, base + tidx(t.i, k) * TS2 + part * CH);
+      dma_copy<T, CH>(nxt + CH, base + tidx(t.j, k) * TS2 + part * CH);
+    }
+    const T* sa = lds + cur * 2 * CH;
+    mma64w<T, TS, KC>(acc, sa, sa + CH, w);
+  }
+  __syncthreads();
+  acc_to_lds(lds, acc, T(-1), true);
+  __syncthreads();
+  T* C = base + tidx(t.i, t.j) * TS2;
+  for (int e = threadIdx.x; e < TS2; e += 256) C[e] += lds[(e >> 6) * LD + (e & 63)];
 }
 
 // Wide form: one workgroup of eight waves updates output tiles (i, j) and
@@ -222,7 +320,7 @@ template <typename T>
 __global__ __launch_bounds__(512) void k_update_wide(const Task* __restrict__ tasks,
                                                      const SubInfo* __restrict__ subs, T* arena) {
   __shared__ T sA0[TS * LD], sA1[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+  const Task t = tasks[xcd_task()];
   T* base = arena + subs[t.sub].tile_off;
   const int w = threadIdx.x >> 6;
   const int h = w >> 2, wl = w & 3;
@@ -342,7 +440,7 @@ __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
                                               const SubInfo* __restrict__ subs, T* arena,
                                               const T* __restrict__ linv) {
   __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+  const Task t = tasks[xcd_task()];
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.i, t.j) * TS2;
   lds_direct(sA, C);
@@ -408,7 +506,7 @@ __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
                                                const T* __restrict__ arena,
                                                const T* __restrict__ linv, T* W, int interior) {
   __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+  const Task t = tasks[xcd_task()];
   trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
 }
 
@@ -418,7 +516,7 @@ __global__ __launch_bounds__(256) void k_lauum(const Task* __restrict__ tasks,
                                                const SubInfo* __restrict__ subs,
                                                const T* __restrict__ W, T* X) {
   __shared__ T sA[TS * LD], sB[TS * LD];
-  const Task t = tasks[blockIdx.x];
+  const Task t = tasks[xcd_task()];
   const SubInfo s = subs[t.sub];
   const T* Wb = W + s.x_off;
   Acc<T> acc;
@@ -644,9 +742,16 @@ __global__ __launch_bounds__(256) void k_init_arena(const Task* __restrict__ tas
 // launchers
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
-                  T* W, T* X, int* err, hipStream_t st, int split, int wide) {
+                  T* W, T* X, int* err, hipStream_t st, int split, int form) {
   if (count <= 0) return;
-  if (wide) {   // update launches only: the task list is the wide form, then the inverse rows
+  if (form == 2) {   // update launches only: double-buffered form of k_update
+    const int nupd = kind == K_UPDATE ? count : split;
+    const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
+    hipLaunchKernelGGL((k_update_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, nupd, subs, arena,
+                       (const T*)linv, W, interior);
+    return;
+  }
+  if (form == 1) {   // update launches only: the task list is the wide form, then the inverse rows
     const int nupd = kind == K_UPDATE ? count : split;
     const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
     if (nupd > 0) hipLaunchKernelGGL(k_update_wide<T>, dim3(nupd), dim3(512), 0, st, tasks, subs, arena);

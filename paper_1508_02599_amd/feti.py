@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 FETI_DEVICE_PTRS = 1
 FETI_PROFILE = 2
 FETI_AUTOTUNE = 4
+AUTOTUNE_FACTORISATIONS = 3   # factorisations that time the update forms (FETI_AUTOTUNE)
 FETI_KERNEL6 = 8
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -65,7 +66,8 @@ class feti_stats(C.Structure):
                 ("kernel_gemv_launches", C.c_int32), ("kernel_update_launches", C.c_int32),
                 ("kernel_gemv_ms", C.c_double), ("kernel_update_ms", C.c_double),
                 ("gemv_bytes", C.c_double), ("update_flops", C.c_double), ("res_primal", C.c_double),
-                ("autotune_wide", C.c_int32)]
+                ("autotune_wide", C.c_int32),
+                ("autotune_db", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -240,22 +240,25 @@ def test_mixed_precision_newton_step():
 # ---------------------------------------------------------------- autotuned update shapes
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_autotune_update_forms_identical(precision):
-    """The first factorisation uses 64x64 update tiles, the second 128x64, later
-    ones the faster per launch: the displacements are bit-identical throughout
-    (same products, same order) and match the oracle."""
+    """The first three factorisations use the three update forms (64x64 tiles,
+    128x64 tiles, 64x64 double-buffered), later ones the fastest per launch:
+    the displacements are bit-identical throughout (same products, same order)
+    and match the oracle."""
     m, ref = _oracle("cube32_s4")
     kw = dict(rtol=1e-10) if precision == "fp64" else dict(rtol=1e-8, ir_tol=1e-12)
-    outs, wide = [], []
+    outs, wide, db = [], [], []
     with _problem(m, variant="af", precond="lumped", precision=precision, autotune=True, **kw) as p:
-        for _ in range(3):
+        for _ in range(4):
             p.factor()
             u, st = p.solve()
             outs.append(u)
             wide.append(st["autotune_wide"])
-    print(f"autotune {precision}: wide launches per factorisation after tuning = {wide}")
-    assert wide[0] == -1 and wide[2] >= 0
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
-    assert _rel(outs[2], ref) <= 1e-9
+            db.append(st["autotune_db"])
+    print(f"autotune {precision}: launches per form after tuning: wide {wide}, double-buffered {db}")
+    assert wide[0] == -1 and db[0] == -1 and wide[3] >= 0 and db[3] >= 0
+    for k in range(1, 4):
+        assert np.array_equal(outs[0], outs[k]), k
+    assert _rel(outs[3], ref) <= 1e-9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
