@@ -39,14 +39,9 @@ struct feti_problem {
   feti_options opt{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // second stream of the factorisation (diagonal tiles of a column step,
-  // concurrent with the rest of its updates) and its fork/join events
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // pinned copies of the PCG state after the two replays in flight
   PcgState* h_state = nullptr;
   hipEvent_t ev_rep[2] = {nullptr, nullptr};
-  bool side_pending = false;   // work queued on stream2 that the main stream has not waited for
   DeviceAlloc da;
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -188,35 +183,15 @@ feti_status upload(feti_problem* p, T*& out, const std::vector<T>& v) {
 size_t elt(const feti_problem* p) { return p->P.mixed ? sizeof(float) : sizeof(double); }
 
 // Dense launches on the subdomain batch in the working precision.
-bool is_update(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI || kind == K_UPD_TRTRI_INT; }
 
 int update_index(const feti_problem* p, const HostPlan::Launch& L) {
   const auto it = std::lower_bound(p->upd_first.begin(), p->upd_first.end(), L.first);
   return (it != p->upd_first.end() && *it == L.first) ? (int)(it - p->upd_first.begin()) : -1;
 }
 
-// The main stream waits for everything queued so far on the second stream.
-void join_side(feti_problem* p) {
-  if (!p->side_pending) return;
-  (void)hipEventRecord(p->ev_join, p->stream2);
-  (void)hipStreamWaitEvent(p->stream, p->ev_join, 0);
-  p->side_pending = false;
-}
-
-// A launch runs on the second stream if L.side; with L.join it first waits
-// for everything queued so far on the other stream.
 void dense(feti_problem* p, const HostPlan::Launch& L) {
-  hipStream_t stream = L.side ? p->stream2 : p->stream;
-  if (L.side) {
-    if (L.join) {
-      (void)hipEventRecord(p->ev_fork, p->stream);
-      (void)hipStreamWaitEvent(p->stream2, p->ev_fork, 0);
-    }
-    p->side_pending = true;
-  } else if (L.join) {
-    join_side(p);
-  }
-  const bool upd = is_update(L.kind) && L.count > 0 && !L.side;
+  hipStream_t stream = p->stream;
+  const bool upd = is_update_kind(L.kind) && L.count > 0;
   const bool timed = p->profile && upd && 2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
   // the interior inverse goes to its own arena
   void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
@@ -231,10 +206,10 @@ void dense(feti_problem* p, const HostPlan::Launch& L) {
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], stream);
   if (p->P.mixed)
     launch_dense<float>(L.kind, t, count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
-                        (float*)p->d_X, p->d_err, stream, split, form);
+                        (float*)p->d_X, p->d_err, stream, split, form, L.ndiag);
   else
     launch_dense<double>(L.kind, t, count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
-                         (double*)p->d_X, p->d_err, stream, split, form);
+                         (double*)p->d_X, p->d_err, stream, split, form, L.ndiag);
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], stream);
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], stream);
 }
@@ -624,11 +599,8 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bco, (size_t)P.NB));
   TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
-  HIPCHK(hipStreamCreateWithFlags(&p->stream2, hipStreamNonBlocking));
   HIPCHK(hipHostMalloc((void**)&p->h_state, 2 * sizeof(PcgState), hipHostMallocDefault));
   for (auto& ev : p->ev_rep) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
     p->ev_gemv.resize(2);
@@ -640,7 +612,7 @@ feti_status setup_device(feti_problem* p) {
   p->autotune = (p->opt.flags & FETI_AUTOTUNE) != 0;
   if (p->autotune) {
     auto reg = [&](const HostPlan::Launch& L) {
-      if (is_update(L.kind) && L.count > 0 && L.wcount > 0) p->upd_first.push_back(L.first);
+      if (is_update_kind(L.kind) && L.count > 0 && L.wcount > 0) p->upd_first.push_back(L.first);
     };
     for (const auto& L : P.sched_interior) reg(L);
     reg(P.sched_schur);
@@ -665,7 +637,7 @@ feti_status setup_device(feti_problem* p) {
       return std::min(TS, si.n_b - (t - si.nt_i) * TS);
     };
     auto add = [&](const HostPlan::Launch& L) {
-      if (!is_update(L.kind) || L.side) return;   // side launches are not timed
+      if (!is_update_kind(L.kind)) return;
       const int nupd = L.kind == K_UPDATE ? L.count : L.split;
       for (int k = 0; k < L.count; ++k) {
         const Task& t = P.tasks[L.first + k];
@@ -800,7 +772,6 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
                               st);
   }
   for (const auto& L : P.sched_iface) dense(p, L);
-  join_side(p);
   for (const auto& L : P.sched_trtri) dense(p, L);
   dense(p, P.sched_lauum);
   {
@@ -851,7 +822,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     asm_coarse(c, st);
     auto qd = [&](const HostPlan::Launch& L) {
       launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
-                           p->d_qX, p->d_err + 1, st, L.split);
+                           p->d_qX, p->d_err + 1, st, L.split, 0, L.ndiag);
     };
     const int big2 = 0x7fffffff;
     HIPCHK(hipMemcpyAsync(p->d_err + 1, &big2, sizeof(int), hipMemcpyHostToDevice, st));
@@ -1440,15 +1411,9 @@ void feti_destroy(feti_problem* p) {
     if (p->da.fr) p->da.fr(a, p->da.ctx);
     else (void)hipFree(a);
   }
-  if (p->stream2) {
-    (void)hipStreamSynchronize(p->stream2);
-    (void)hipStreamDestroy(p->stream2);
-  }
-  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   for (auto& ev : p->ev_rep)
     if (ev) (void)hipEventDestroy(ev);
   if (p->h_state) (void)hipHostFree(p->h_state);
-  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }

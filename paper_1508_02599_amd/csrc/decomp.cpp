@@ -41,12 +41,13 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
   };
   // the wide form of an update launch: consecutive tasks of one subdomain and
-  // column with adjacent rows become one two-tile task; the inverse-row tasks
-  // follow unchanged
+  // column with adjacent rows become one two-tile task; the diagonal tasks
+  // before them and the inverse-row tasks after them are kept unchanged
   auto widen = [&](HostPlan::Launch& L) {
     const int32_t nupd = L.kind == K_UPDATE ? L.count : L.split;
     std::vector<Task> w;
-    for (int32_t k = 0; k < nupd;) {
+    for (int32_t k = 0; k < L.ndiag; ++k) w.push_back(tasks[L.first + k]);
+    for (int32_t k = L.ndiag; k < nupd;) {
       Task a = tasks[L.first + k];
       if (k + 1 < nupd) {
         const Task& b = tasks[L.first + k + 1];
@@ -84,30 +85,23 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     widen(L);
   };
   // stage 1: interior columns, left-looking (rows run over every tile row
-  // below).  A column step j > 0 forks onto the second stream: the diagonal
-  // tile j takes its last update term (k = j - 1) and is factored there while
-  // the main stream updates the tiles below (and subtracts the terms k < j of
-  // diagonal tile j + 1, so that the forked path stays one term long); the
-  // panel solve on the main stream joins the two.
+  // below).  Column step j > 0 is one update launch and the panel solve.  The
+  // launch's first tasks take the diagonal tiles: the last update term
+  // (k = j - 1), factorisation and inverse; the others update the tiles below
+  // (and subtract the terms k < j of diagonal tile j + 1, so that the
+  // diagonal tasks of the next step carry one term only).
   for (int j = 0; j < max_i; ++j) {
-    const bool step = j > 0;
-    if (step) {
-      auto Ld = begin(K_UPDATE);
+    if (j == 0) {
+      auto D = begin(K_DIAG);
+      for (int s = 0; s < ns; ++s)
+        if (subs[s].nt_i > 0) tasks.push_back({s, 0, 0, 0, 0});
+      finish(D);
+      interior.push_back(D);
+    } else {
+      auto L = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_i > j) tasks.push_back({s, j, j, j - 1, j});
-      finish(Ld);
-      Ld.side = 1;
-      Ld.join = 1;
-      interior.push_back(Ld);
-    }
-    auto D = begin(K_DIAG);
-    for (int s = 0; s < ns; ++s)
-      if (subs[s].nt_i > j) tasks.push_back({s, j, j, 0, 0});
-    finish(D);
-    D.side = step;
-    interior.push_back(D);
-    if (step) {
-      auto L = begin(K_UPDATE);
+      L.ndiag = (int32_t)tasks.size() - L.first;
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_i > j) {
           for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
@@ -122,7 +116,6 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
       if (subs[s].nt_i > j)
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
     finish(T);
-    T.join = step;
     interior.push_back(T);
   }
   // stage 2: Schur complement of the interior on every interface tile (with
@@ -134,32 +127,24 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int I = J; I < subs[s].nt; ++I) tasks.push_back({s, I, J, 0, subs[s].nt_i});
   if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
   else plain(schur);
-  schur.join = 1;
   // stage 4: interface columns (updates only over interface columns), each
-  // update launch carrying the previous block row of the interface inverse;
-  // the column steps fork as in stage 1
+  // update launch carrying the diagonal tasks of its column, as in stage 1,
+  // and the previous block row of the interface inverse
   for (int jb = 0; jb < max_b; ++jb) {
-    const bool step = jb > 0;
-    if (step) {
-      auto Ld = begin(K_UPDATE);
+    if (jb == 0) {
+      auto D = begin(K_DIAG);
+      for (int s = 0; s < ns; ++s)
+        if (subs[s].nt_b > 0) tasks.push_back({s, subs[s].nt_i, subs[s].nt_i, 0, 0});
+      finish(D);
+      iface.push_back(D);
+    } else {
+      auto L = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_b > jb) {
           const int j = subs[s].nt_i + jb;
           tasks.push_back({s, j, j, j - 1, j});
         }
-      finish(Ld);
-      Ld.side = 1;
-      Ld.join = 1;
-      iface.push_back(Ld);
-    }
-    auto D = begin(K_DIAG);
-    for (int s = 0; s < ns; ++s)
-      if (subs[s].nt_b > jb) tasks.push_back({s, subs[s].nt_i + jb, subs[s].nt_i + jb, 0, 0});
-    finish(D);
-    D.side = step;
-    iface.push_back(D);
-    if (step) {
-      auto L = begin(K_UPDATE);
+      L.ndiag = (int32_t)tasks.size() - L.first;
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_b > jb) {
           const int j = subs[s].nt_i + jb;
@@ -176,7 +161,6 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
         for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
       }
     finish(T);
-    T.join = step;
     iface.push_back(T);
   }
   // stage 5: the last block row of the interface inverse
@@ -184,7 +168,6 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     auto L = begin(K_TRTRI);
     inverse_row(max_b - 1, false);
     finish(L);
-    L.join = 1;
     trtri.push_back(L);
   }
   // stage 6: X = W^T W

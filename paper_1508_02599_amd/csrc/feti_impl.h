@@ -126,9 +126,9 @@ struct HostPlan {
   struct Launch {
     int kind;
     int32_t first, count;
-    int32_t split = 0;
-    int32_t wfirst = 0, wcount = 0, wsplit = 0;
-    int32_t side = 0, join = 0;
+    int32_t split = 0;                      // update kinds: tasks before the rows of an inverse
+    int32_t wfirst = 0, wcount = 0, wsplit = 0;   // the same launch in the wide form
+    int32_t ndiag = 0;                      // update kinds: leading diagonal tasks
   };
   std::vector<Task> tasks;
   std::vector<Launch> sched_interior;   // stage 1
@@ -143,6 +143,7 @@ struct HostPlan {
 
 enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4, K_TRTRI_INT = 5,
                   K_UPD_TRTRI = 6, K_UPD_TRTRI_INT = 7 };   // update tasks, then rows of the inverse
+inline bool is_update_kind(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI || kind == K_UPD_TRTRI_INT; }
 
 // Builds the plan; returns an empty string on success, else an error message.
 std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);

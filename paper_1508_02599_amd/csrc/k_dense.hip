@@ -50,11 +50,11 @@ __device__ __forceinline__ int xcd_map(int l, int n) {
   return x * q + min(x, r) + (l >> 3);
 }
 __device__ __forceinline__ int xcd_task() { return xcd_map((int)blockIdx.x, (int)gridDim.x); }
-// Launches that carry tasks of two kinds (updates [0, n_upd), then rows of an
-// inverse) remap each range on its own, so that both spread over every XCD.
-__device__ __forceinline__ int xcd_task_split(int n_upd) {
-  const int b = (int)blockIdx.x, n = (int)gridDim.x;
-  return b < n_upd ? xcd_map(b, n_upd) : n_upd + xcd_map(b - n_upd, n - n_upd);
+// Launches that carry tasks of several kinds remap each range on its own, so
+// that every kind spreads over all XCDs: l in [0, n), the first n_first of
+// them one range, the rest another.
+__device__ __forceinline__ int xcd_split(int l, int n, int n_first) {
+  return l < n_first ? xcd_map(l, n_first) : n_first + xcd_map(l - n_first, n - n_first);
 }
 
 // LDS operand layout: s[k*LD + m] holds op(A)(m, k) (or op(B)(k, m)).
@@ -218,16 +218,39 @@ template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
                            const T* __restrict__ linv, T* W, int interior, T* sA, T* sB);
 
-// Tile updates of a column step (blocks below n_upd); the blocks after them,
-// if any, compute one block row of the inverse of the factor (trtri_tile),
-// whose inputs are complete once the previous column step is done.  Fusing the
-// two keeps the serial chain of launches short.
+// FP64 LDS scratch of a diagonal block (diag_block), in doubles
+constexpr int DIAG_SMEM = 3 * TS + TS * LD;
+// LDS of a kernel whose blocks hold `elems` elements of T or a diagonal
+// block's scratch, in doubles
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, int n_upd,
+constexpr int smem_doubles(int elems) {
+  return (elems * (int)sizeof(T) > DIAG_SMEM * 8 ? elems * (int)sizeof(T) : DIAG_SMEM * 8) / 8;
+}
+
+template <typename T>
+__device__ __forceinline__ void diag_block(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                           int* err, T* sA, T* sB, double* scratch);
+
+// One launch per column step.  Blocks below n_diag take the diagonal tiles
+// of the column (diag_block: the tile's last update term, its factorisation
+// and inverse); the hardware dispatches them first.  Blocks from n_diag to
+// n_upd update the tiles below (update_tile); the blocks after them, if any,
+// compute one block row of the inverse of the factor (trtri_tile), whose
+// inputs are complete once the previous column step is done.  Fusing them
+// keeps the serial chain of launches short and needs no second stream.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                 const SubInfo* __restrict__ subs, T* arena,
-                                                const T* __restrict__ linv, T* W, int interior) {
-  __shared__ T sA[TS * LD], sB[TS * LD];
-  const int b = xcd_task_split(n_upd);
+                                                T* linv, T* W, int interior, int* err) {
+  __shared__ double smem[smem_doubles<T>(2 * TS * LD)];
+  T* sA = reinterpret_cast<T*>(smem);
+  T* sB = sA + TS * LD;
+  const int b0 = (int)blockIdx.x;
+  if (b0 < n_diag) {
+    diag_block<T>(tasks[b0], subs, arena, linv, err, sA, sB, smem);
+    return;
+  }
+  const int b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
   const Task t = tasks[b];
   if (b < n_upd) update_tile<T>(t, subs, arena, sA, sB);
   else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
@@ -265,14 +288,21 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 // the same order as update_tile, so the results are bit-identical.  With
 // KC = 32 the buffers take 64 KiB in FP64, two workgroups per compute unit.
 template <typename T, int KC>
-__global__ __launch_bounds__(256) void k_update_db(const Task* __restrict__ tasks, int n_upd,
+__global__ __launch_bounds__(256) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                    const SubInfo* __restrict__ subs, T* arena,
-                                                   const T* __restrict__ linv, T* W, int interior) {
+                                                   T* linv, T* W, int interior, int* err) {
   constexpr int CH = TS * KC;                 // elements per chunk
   constexpr int PARTS = TS / KC;              // chunks per tile
   constexpr int NLDS = 4 * CH > 2 * TS * LD ? 4 * CH : 2 * TS * LD;
-  __shared__ T lds[NLDS];                     // [buffer][A, B][chunk]; the inverse rows use 2 TS LD
-  const int b = xcd_task_split(n_upd);
+  // [buffer][A, B][chunk]; the inverse rows use 2 TS LD; the diagonal blocks their scratch
+  __shared__ double smem[smem_doubles<T>(NLDS)];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int b0 = (int)blockIdx.x;
+  if (b0 < n_diag) {
+    diag_block<T>(tasks[b0], subs, arena, linv, err, lds, lds + TS * LD, smem);
+    return;
+  }
+  const int b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
   const Task t = tasks[b];
   if (b >= n_upd) {
     trtri_tile<T>(t, subs, arena, linv, W, interior, lds, lds + TS * LD);
@@ -357,21 +387,40 @@ __global__ __launch_bounds__(512) void k_update_wide(const Task* __restrict__ ta
   }
 }
 
+// Broadcast lane `lane`'s value of v to the whole wave (two v_readlane_b32).
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Order the LDS accesses of a one-wave workgroup: a wave's LDS instructions
+// execute in issue order, so keeping the compiler from moving them across
+// this point is all a write-then-read by other lanes needs.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
-// and the explicit inverse L_jj^{-1}.  One wave per tile with the tile in
-// registers (lane r holds row r, loops fully unrolled).  Each elimination
-// step broadcasts its pivot and then its column of L through LDS (single-wave
-// barriers), so a trailing update costs one broadcast LDS read and one
-// register FMA per entry.  The inverse (lane j holds column j) reads L back
-// from LDS by broadcast.  A non-positive or non-finite pivot records the
-// subdomain in *err.
+// and the explicit inverse L_jj^{-1}.  One wave (the lanes of wave 0) with
+// the tile in registers (lane r holds row r, loops fully unrolled).  Each
+// elimination step reads its pivot from the owning lane (readlane), scales
+// the column by the reciprocal of its square root, and broadcasts the column
+// through LDS (two buffers in turn, ordered by wave_sync), so a trailing
+// update costs one broadcast LDS read and one register FMA per entry.  The
+// inverse (lane j holds column j) reads L back from LDS by broadcast and
+// multiplies by the stored reciprocals of the pivots.  A non-positive or
+// non-finite pivot records the subdomain in *err.  scratch: DIAG_SMEM doubles
+// of LDS.
 template <typename T>
-__global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
-                                             const SubInfo* __restrict__ subs, T* arena, T* linv,
-                                             int* err) {
-  __shared__ double piv[TS], colv[TS];
-  __shared__ double sL[TS * LD];
-  const Task t = tasks[blockIdx.x];
+__device__ __forceinline__ void diag_wave(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv, int* err,
+                          double* scratch) {
+  double* colv = scratch;            // [2][TS]
+  double* rinv = scratch + 2 * TS;   // [TS]
+  double* sL = scratch + 3 * TS;     // [TS * LD]
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
   T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
@@ -380,27 +429,36 @@ __global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
 #pragma unroll
   for (int c = 0; c < TS; ++c) a[c] = (double)C[c * TS + r];
   bool bad = false;
+  double my_inv = 1.0;
   // right-looking elimination: a[cc] of lane r is A(r, cc); its lower part is kept
 #pragma unroll
   for (int c = 0; c < TS; ++c) {
-    piv[r] = a[c];   // every lane stores (a store under a lane condition makes the compiler spill)
-    __syncthreads();
-    const double d = piv[c];
+    const double d = readlane_d(a[c], c);
     const bool ok = (d > 0.0) && (d < 1e300);
     bad |= !ok;
-    const double sd = sqrt(ok ? d : 1.0);
-    // two plain selects (a nested conditional here makes the compiler spill)
-    double l = a[c] / sd;
+    // 1/sqrt(d): hardware estimate and one Newton step (relative error near
+    // the rounding unit), then sqrt(d) = d / sqrt(d)
+    const double dd = ok ? d : 1.0;
+    double inv = __builtin_amdgcn_rsq(dd);
+    inv = inv * (1.5 - 0.5 * dd * inv * inv);
+    const double sd = dd * inv;
+    // plain selects (a nested conditional here makes the compiler spill)
+    double l = a[c] * inv;
     l = r > c ? l : 0.0;
     l = r == c ? sd : l;
+    my_inv = r == c ? inv : my_inv;
     a[c] = l;
-    colv[r] = l;
-    __syncthreads();
+    colv[(c & 1) * TS + r] = l;   // every lane stores (a store under a lane condition makes the compiler spill)
+    wave_sync();
+    // loads in batches of 16 (a whole column's worth at once needs too many registers)
 #pragma unroll
-    for (int cc = c + 1; cc < TS; ++cc) a[cc] -= l * colv[cc];
-    __syncthreads();
+    for (int cc = c + 1; cc < TS; ++cc) {
+      a[cc] -= l * colv[(c & 1) * TS + cc];
+      if (((cc - c) & 15) == 0) __builtin_amdgcn_sched_barrier(0);
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
+  rinv[r] = my_inv;
 #pragma unroll
   for (int c = 0; c < TS; ++c) {
     double v = a[c];
@@ -408,7 +466,7 @@ __global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
     C[c * TS + r] = (T)v;
     sL[c * LD + r] = v;
   }
-  __syncthreads();
+  wave_sync();
   // X = L^{-1} with lane j holding column j:
   // X(i, j) = (delta_ij - sum_{k<i} L(i, k) X(k, j)) / L(i, i), X(k, j) = 0 for k < j
   const int j = r;
@@ -417,21 +475,50 @@ __global__ __launch_bounds__(64) void k_diag(const Task* __restrict__ tasks,
   for (int i = 0; i < TS; ++i) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < i; ++k) acc[k & 3] += sL[k * LD + i] * x[k];
+    for (int k = 0; k < i; ++k) {
+      acc[k & 3] += sL[k * LD + i] * x[k];
+      if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+    }
     const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    double xi = ((i == j ? 1.0 : 0.0) - sum) / sL[i * LD + i];
+    const double xi = ((i == j ? 1.0 : 0.0) - sum) * rinv[i];
     x[i] = i < j ? 0.0 : xi;
     // keep the loads of later rows from being hoisted (register pressure)
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int i = 0; i < TS; ++i) sL[j * LD + i] = x[i];
-  __syncthreads();
+  wave_sync();
 #pragma unroll 8
   for (int c = 0; c < TS; ++c) Li[c * TS + r] = (T)sL[c * LD + r];
   if (bad) atomicMin(err, t.sub);
+}
+
+// A diagonal task (j, j, k0, k1) of a 256-thread block: the four waves
+// subtract the update terms k0 <= k < k1 (update_tile, usually the one term
+// k = j - 1, the others having been subtracted by the previous column step),
+// then wave 0 factors and inverts the tile (diag_wave) with `scratch`, which
+// may alias sA and sB.
+template <typename T>
+__device__ __forceinline__ void diag_block(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                           int* err, T* sA, T* sB, double* scratch) {
+  if (t.k0 < t.k1) {
+    update_tile<T>(t, subs, arena, sA, sB);
+    __syncthreads();   // the updated tile is in memory and sA, sB are free
+  }
+  if (threadIdx.x < 64) diag_wave<T>(t, subs, arena, linv, err, scratch);
+}
+
+// Diagonal tasks alone (the first column of a stage, and the launches whose
+// update form cannot host them).
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(const Task* __restrict__ tasks,
+                                              const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                              int* err) {
+  __shared__ double smem[smem_doubles<T>(2 * TS * LD)];
+  T* sA = reinterpret_cast<T*>(smem);
+  diag_block<T>(tasks[blockIdx.x], subs, arena, linv, err, sA, sA + TS * LD, smem);
 }
 
 // L_ij <- C_ij L_jj^{-T}   (panel solve by the explicit diagonal inverse)
@@ -742,37 +829,41 @@ __global__ __launch_bounds__(256) void k_init_arena(const Task* __restrict__ tas
 // launchers
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
-                  T* W, T* X, int* err, hipStream_t st, int split, int form) {
+                  T* W, T* X, int* err, hipStream_t st, int split, int form, int ndiag) {
   if (count <= 0) return;
-  if (form == 2) {   // update launches only: double-buffered form of k_update
-    const int nupd = kind == K_UPDATE ? count : split;
-    const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
-    hipLaunchKernelGGL((k_update_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, nupd, subs, arena,
-                       (const T*)linv, W, interior);
-    return;
-  }
-  if (form == 1) {   // update launches only: the task list is the wide form, then the inverse rows
-    const int nupd = kind == K_UPDATE ? count : split;
-    const int interior = kind == K_UPD_TRTRI_INT ? 1 : 0;
-    if (nupd > 0) hipLaunchKernelGGL(k_update_wide<T>, dim3(nupd), dim3(512), 0, st, tasks, subs, arena);
-    if (count > nupd)
-      hipLaunchKernelGGL(k_trtri<T>, dim3(count - nupd), dim3(256), 0, st, tasks + nupd, subs, (const T*)arena,
-                         (const T*)linv, W, interior);
+  const int interior = (kind == K_UPD_TRTRI_INT || kind == K_TRTRI_INT) ? 1 : 0;
+  if (is_update_kind(kind)) {
+    const int nupd = kind == K_UPDATE ? count : split;   // diagonal and update tasks
+    if (form == 2) {
+      hipLaunchKernelGGL((k_update_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena,
+                         linv, W, interior, err);
+    } else if (form == 1) {
+      // the task list is the wide form: diagonal tasks, two-tile updates, inverse rows
+      if (ndiag > 0) hipLaunchKernelGGL(k_diag<T>, dim3(ndiag), dim3(256), 0, st, tasks, subs, arena, linv, err);
+      if (nupd > ndiag)
+        hipLaunchKernelGGL(k_update_wide<T>, dim3(nupd - ndiag), dim3(512), 0, st, tasks + ndiag, subs, arena);
+      if (count > nupd)
+        hipLaunchKernelGGL(k_trtri<T>, dim3(count - nupd), dim3(256), 0, st, tasks + nupd, subs, (const T*)arena,
+                           (const T*)linv, W, interior);
+    } else {
+      hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena, linv, W,
+                         interior, err);
+    }
     return;
   }
   switch (kind) {
-    case K_UPDATE: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, count, subs, arena, (const T*)linv, W, 0); break;
-    case K_UPD_TRTRI: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, split, subs, arena, (const T*)linv, W, 0); break;
-    case K_UPD_TRTRI_INT: hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, split, subs, arena, (const T*)linv, W, 1); break;
-    case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(64), 0, st, tasks, subs, arena, linv, err); break;
+    case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, linv, err); break;
     case K_TRSM: hipLaunchKernelGGL(k_trsm<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, (const T*)linv); break;
-    case K_TRTRI: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W, 0); break;
-    case K_TRTRI_INT: hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W, 1); break;
+    case K_TRTRI:
+    case K_TRTRI_INT:
+      hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W,
+                         interior);
+      break;
     case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
   }
 }
-template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int, int);
-template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t, int, int);
+template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int, int, int);
+template void launch_dense<float>(int, const Task*, int, const SubInfo*, float*, float*, float*, float*, int*, hipStream_t, int, int, int);
 
 template <typename T>
 void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st) {

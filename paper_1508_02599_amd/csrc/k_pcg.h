@@ -25,10 +25,11 @@ struct DevIdx {
 };
 
 // --- dense factor kernels (k_dense.hip)
-// form (update kinds): 0 64x64 tiles, 1 the wide task list (128x64), 2 double-buffered 64x64
+// form (update kinds): 0 64x64 tiles, 1 the wide task list (128x64), 2 double-buffered 64x64;
+// ndiag: leading diagonal tasks of an update launch
 template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv, T* W, T* X,
-                  int* err, hipStream_t st, int split = 0, int form = 0);
+                  int* err, hipStream_t st, int split = 0, int form = 0, int ndiag = 0);
 template <typename T>
 void launch_init_arena(const Task* tasks, int count, const SubInfo* subs, T* arena, hipStream_t st);
 template <typename T>
