@@ -2,6 +2,8 @@
 
     python -m paper_1508_02599_amd.prof_summary trace <dir> [--top N] [--min-us T]
     python -m paper_1508_02599_amd.prof_summary pmc <counter_dir> [--kernel NAME] [--min-kib K]
+    python -m paper_1508_02599_amd.prof_summary traffic --fp64 FETCH_DIR WRITE_DIR
+                                                        [--mixed FETCH_DIR WRITE_DIR]
 
 ``trace`` reads ``*_kernel_trace.csv`` and prints, per kernel, the launch count,
 total device time, the mean over all launches and the mean over launches that
@@ -13,15 +15,24 @@ the library's profiling mode.
 ``pmc`` reads ``*_counter_collection.csv`` of a single-counter run and prints,
 per kernel, the mean counter value per dispatch (KiB), over all dispatches and
 over dispatches reading at least ``--min-kib``.
+
+``traffic`` turns FETCH_SIZE and WRITE_SIZE runs of ``bench.py`` into the HBM
+bytes per launch of the factor update (last factorisation of the run) and of
+the GEMV, scaled by the copy calibration, and writes profiles/traffic.json
+with the hash of each kernel's source (bench.py drops a figure whose source
+has changed since).
 """
 from __future__ import annotations
 
 import argparse
+import json
 import csv
 import glob
 import os
 import re
 from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def _short(name: str) -> str:
@@ -77,19 +88,99 @@ def pmc_table(d: str, kernel: str | None = None, min_kib: float = 0.0):
     return "\n".join(out)
 
 
+def _dispatches(d: str):
+    """(dispatch id, kernel, workgroups, counter value) of a single-counter run, in order."""
+    f = _one(os.path.join(d, "**", "*counter_collection.csv"))
+    out = []
+    with open(f) as fh:
+        for row in csv.DictReader(fh):
+            wg = int(row["Grid_Size"]) // max(1, int(row["Workgroup_Size"]))
+            out.append((int(row["Dispatch_Id"]), _short(row["Kernel_Name"]), wg, float(row["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def update_bytes_per_launch(fetch_dir: str, write_dir: str, fetch_scale: float, write_scale: float):
+    """HBM bytes per factor-update launch, from the last factorisation of the
+    run: the dispatches from the last full-size k_init_arena to the next
+    k_coarse_q (where the coarse factorisation begins).  Every update launch
+    is one k_update / k_update_db / k_update_wide dispatch; counter values are
+    KiB per dispatch, scaled by the copy calibration."""
+    tot, n = 0.0, 0
+    for d, scale in ((fetch_dir, fetch_scale), (write_dir, write_scale)):
+        rows = _dispatches(d)
+        starts = [i for i, r in enumerate(rows) if r[1].startswith("k_init_arena") and r[2] > 10000]
+        i0 = starts[-1]
+        i1 = next((i for i in range(i0, len(rows)) if rows[i][1].startswith("k_coarse_q")), len(rows))
+        upd = [r for r in rows[i0:i1] if r[1].startswith("k_update")]
+        tot += scale * 1024.0 * sum(r[3] for r in upd)
+        n = len(upd)
+    return tot / n, n
+
+
+def gemv_bytes_per_launch(fetch_dir: str, write_dir: str, fetch_scale: float, write_scale: float,
+                          min_kib: float = 1000.0):
+    """HBM bytes per GEMV launch: mean over the k_symv_tiles dispatches that did
+    the work (a replayed graph block's launches after the stopping rule return
+    at once and read nothing)."""
+    f = [r[3] for r in _dispatches(fetch_dir) if r[1].startswith("k_symv_tiles") and r[3] >= min_kib]
+    w = [r[3] for r in _dispatches(write_dir) if r[1].startswith("k_symv_tiles")]
+    w = sorted(w)[len(w) - len(f):] if len(w) >= len(f) else w
+    return 1024.0 * (fetch_scale * sum(f) / len(f) + write_scale * sum(w) / max(1, len(w)))
+
+
+def write_traffic(out: str, runs: dict, fetch_scale: float, write_scale: float, summary: str):
+    """runs: precision -> (fetch_dir, write_dir).  Writes the per-launch HBM
+    bytes of the update and GEMV kernels with the hash of their sources."""
+    import hashlib
+    root = os.path.dirname(HERE)
+
+    def sha(rel):
+        with open(os.path.join(root, rel), "rb") as fh:
+            return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+    rec = {}
+    for prec, (fd, wd) in runs.items():
+        suffix = "" if prec == "fp64" else "_f32"
+        ub, n = update_bytes_per_launch(fd, wd, fetch_scale, write_scale)
+        gb = gemv_bytes_per_launch(fd, wd, fetch_scale, write_scale)
+        rec["k_update" + suffix] = {"source": "paper_1508_02599_amd/csrc/k_dense.hip",
+                                    "source_sha": sha("paper_1508_02599_amd/csrc/k_dense.hip"),
+                                    "hbm_bytes_per_launch": round(ub), "launches": n, "summary": summary}
+        rec["k_symv_tiles" + suffix] = {"source": "paper_1508_02599_amd/csrc/k_symv.hip",
+                                        "source_sha": sha("paper_1508_02599_amd/csrc/k_symv.hip"),
+                                        "hbm_bytes_per_launch": round(gb), "summary": summary}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc"])
-    ap.add_argument("dir")
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic"])
+    ap.add_argument("dir", nargs="?")
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--min-us", type=float, default=0.0)
     ap.add_argument("--kernel", default=None)
     ap.add_argument("--min-kib", type=float, default=0.0)
+    ap.add_argument("--fp64", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--mixed", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--fetch-scale", type=float, default=2.0)
+    ap.add_argument("--write-scale", type=float, default=1.0)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles", "traffic.json"))
+    ap.add_argument("--summary", default="profiles/feti_cube32_s4_traffic.md")
     a = ap.parse_args()
     if a.mode == "trace":
         print(trace_table(a.dir, a.top, a.min_us))
-    else:
+    elif a.mode == "pmc":
         print(pmc_table(a.dir, a.kernel, a.min_kib))
+    else:
+        runs = {}
+        if a.fp64:
+            runs["fp64"] = tuple(a.fp64)
+        if a.mixed:
+            runs["mixed"] = tuple(a.mixed)
+        print(json.dumps(write_traffic(a.out, runs, a.fetch_scale, a.write_scale, a.summary), indent=1))
 
 
 if __name__ == "__main__":
