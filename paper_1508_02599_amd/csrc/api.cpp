@@ -39,6 +39,13 @@ struct feti_problem {
   feti_options opt{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // stream of the coarse factorisation (concurrent with the local one), its
+  // fork/join events and the host data its uploads read
+  hipStream_t stream_c = nullptr;
+  hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
+  SubInfo h_qsub{};
+  std::vector<Task> h_qt;
+  const int h_big = 0x7fffffff;
   // pinned copies of the PCG state after the two replays in flight
   PcgState* h_state = nullptr;
   hipEvent_t ev_rep[2] = {nullptr, nullptr};
@@ -600,6 +607,9 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
   HIPCHK(hipHostMalloc((void**)&p->h_state, 2 * sizeof(PcgState), hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&p->stream_c, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_cfork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_cjoin, hipEventDisableTiming));
   for (auto& ev : p->ev_rep) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
@@ -669,6 +679,58 @@ feti_status setup_device(feti_problem* p) {
 }
 
 // ---------------------------------------------------------------------------
+// Coarse matrix Q = G^T G, its Cholesky factor and explicit inverse (FP64),
+// on stream st.  Needs the kernel bases and the coarse layout only, so it
+// runs beside the batched local factorisation.  The host data it uploads
+// (h_qsub, h_qt, h_big) live in the problem until the copies are done.
+feti_status coarse_factor(feti_problem* p, hipStream_t st) {
+  HostPlan& P = p->P;
+  SubInfo& q = p->h_qsub;
+  q = SubInfo{};
+  q.n_ii = 0;
+  q.n_b = p->n_coarse;
+  q.nt_i = 0;
+  q.nt_b = p->nq;
+  q.nt = p->nq;
+  q.floating = 0;
+  HIPCHK(hipMemcpyAsync(p->d_qsub, &q, sizeof(SubInfo), hipMemcpyHostToDevice, st));
+  std::vector<SubInfo> qs{q};
+  std::vector<Task>& qt = p->h_qt;
+  qt.clear();
+  std::vector<HostPlan::Launch> qi, qf, qr;
+  HostPlan::Launch qsch, qla, qx, qall;
+  build_factor_schedule(qs, qt, qi, qsch, qf, qr, qla, qx, qall);
+  p->q_xtiles = qx;
+  if ((int)qt.size() > p->qtask_cap * (p->nq + 2)) {
+    p->err = "coarse task list overflow";
+    return FETI_EDEVICE;
+  }
+  HIPCHK(hipMemcpyAsync(p->d_qtasks, qt.data(), qt.size() * sizeof(Task), hipMemcpyHostToDevice, st));
+  launch_init_arena<double>(p->d_qtasks + qall.first, qall.count, p->d_qsub, p->d_qarena, st);
+  CoarseArgs c;
+  c.n_pairs = (int)P.qp_s.size();
+  c.qp_s = p->d_qp_s;
+  c.qp_t = p->d_qp_t;
+  c.qp_ptr = p->d_qp_ptr;
+  c.qe_bs = p->d_qe_bs;
+  c.qe_bt = p->d_qe_bt;
+  c.qe_c = p->d_qe_c;
+  c.subs = p->d_sub;
+  c.rb = p->d_rb;
+  c.q = p->d_qarena;
+  asm_coarse(c, st);
+  auto qd = [&](const HostPlan::Launch& L) {
+    launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
+                         p->d_qX, p->d_err + 1, st, L.split, 0, L.ndiag);
+  };
+  HIPCHK(hipMemcpyAsync(p->d_err + 1, &p->h_big, sizeof(int), hipMemcpyHostToDevice, st));
+  for (const auto& L : qf) qd(L);
+  for (const auto& L : qr) qd(L);
+  qd(qla);
+  coarse_to_dense(p->n_coarse, p->n_coarse, p->d_qX, p->d_qdense, st);
+  return FETI_OK;
+}
+
 feti_status do_factor(feti_problem* p, const double* U_dev) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
@@ -744,6 +806,13 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   p->nq = (off + TS - 1) / TS;
   HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
   fill_bco(p->di, p->d_sub, p->d_bco, p->d_rco, st);
+  // the coarse problem on its own stream, beside the local factorisation
+  if (p->n_coarse > 0) {
+    HIPCHK(hipEventRecord(p->ev_cfork, st));
+    HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_cfork, 0));
+    TRY(coarse_factor(p, p->stream_c));
+    HIPCHK(hipEventRecord(p->ev_cjoin, p->stream_c));
+  }
   // batched factorisation
   p->n_upd_recorded = 0;
   p->prof_upd_ms = 0.0;
@@ -786,52 +855,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
                                 (double*)p->d_X, p->d_rb, p->d_rho, p->d_work, p->d_wbm, st);
     }
   }
-  // coarse matrix Q = G^T G, its Cholesky factor and explicit inverse (FP64)
-  if (p->n_coarse > 0) {
-    SubInfo q{};
-    q.n_ii = 0;
-    q.n_b = p->n_coarse;
-    q.nt_i = 0;
-    q.nt_b = p->nq;
-    q.nt = p->nq;
-    q.floating = 0;
-    HIPCHK(hipMemcpyAsync(p->d_qsub, &q, sizeof(SubInfo), hipMemcpyHostToDevice, st));
-    std::vector<SubInfo> qs{q};
-    std::vector<Task> qt;
-    std::vector<HostPlan::Launch> qi, qf, qr;
-    HostPlan::Launch qsch, qla, qx, qall;
-    build_factor_schedule(qs, qt, qi, qsch, qf, qr, qla, qx, qall);
-    p->q_xtiles = qx;
-    if ((int)qt.size() > p->qtask_cap * (p->nq + 2)) {
-      p->err = "coarse task list overflow";
-      return FETI_EDEVICE;
-    }
-    HIPCHK(hipMemcpyAsync(p->d_qtasks, qt.data(), qt.size() * sizeof(Task), hipMemcpyHostToDevice, st));
-    launch_init_arena<double>(p->d_qtasks + qall.first, qall.count, p->d_qsub, p->d_qarena, st);
-    CoarseArgs c;
-    c.n_pairs = (int)P.qp_s.size();
-    c.qp_s = p->d_qp_s;
-    c.qp_t = p->d_qp_t;
-    c.qp_ptr = p->d_qp_ptr;
-    c.qe_bs = p->d_qe_bs;
-    c.qe_bt = p->d_qe_bt;
-    c.qe_c = p->d_qe_c;
-    c.subs = p->d_sub;
-    c.rb = p->d_rb;
-    c.q = p->d_qarena;
-    asm_coarse(c, st);
-    auto qd = [&](const HostPlan::Launch& L) {
-      launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
-                           p->d_qX, p->d_err + 1, st, L.split, 0, L.ndiag);
-    };
-    const int big2 = 0x7fffffff;
-    HIPCHK(hipMemcpyAsync(p->d_err + 1, &big2, sizeof(int), hipMemcpyHostToDevice, st));
-    for (const auto& L : qf) qd(L);
-    for (const auto& L : qr) qd(L);
-    qd(qla);
-    coarse_to_dense(p->n_coarse, p->n_coarse, p->d_qX, p->d_qdense, st);
-    HIPCHK(hipStreamSynchronize(st));   // task list upload must complete before qt goes out of scope
-  }
+  if (p->n_coarse > 0) HIPCHK(hipStreamWaitEvent(st, p->ev_cjoin, 0));
   HIPCHK(hipEventRecord(p->ev[2], st));
   int errs[2] = {0x7fffffff, 0x7fffffff};
   HIPCHK(hipMemcpyAsync(errs, p->d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1414,6 +1438,12 @@ void feti_destroy(feti_problem* p) {
   for (auto& ev : p->ev_rep)
     if (ev) (void)hipEventDestroy(ev);
   if (p->h_state) (void)hipHostFree(p->h_state);
+  if (p->stream_c) {
+    (void)hipStreamSynchronize(p->stream_c);
+    (void)hipStreamDestroy(p->stream_c);
+  }
+  if (p->ev_cfork) (void)hipEventDestroy(p->ev_cfork);
+  if (p->ev_cjoin) (void)hipEventDestroy(p->ev_cjoin);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
