@@ -324,8 +324,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of "
-              "the method is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the subdomains "
+              "over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

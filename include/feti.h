@@ -58,9 +58,11 @@ typedef enum {
  * multipliers so every subdomain is floating (section 4.2). */
 typedef enum { FETI_CLASSICAL = 0, FETI_ALL_FLOATING = 1 } feti_variant;
 
-/* Preconditioner sum_i B_D,i Y_i B_D,i^T (eq. (feti_preconditioner)) with
- * multiplicity-scaled rows: Y_i = I, Y_i = K_i (lumped, eq. (LumpedVK)) or the
- * interface Schur complement (Dirichlet, eq. (DirichletVK)). */
+/* Preconditioner sum_i B_D,i Y_i B_D,i^T (eq. (feti_preconditioner)): Y_i = I,
+ * Y_i = K_i (lumped, eq. (LumpedVK)) or the interface Schur complement
+ * (Dirichlet, eq. (DirichletVK)).  Rows of B_D: weight 1/m on the gluing rows
+ * of a DOF with m subdomain copies; at a Dirichlet DOF of all-floating FETI,
+ * weight 1 on its Dirichlet rows and 0 on its gluing rows. */
 typedef enum { FETI_PREC_IDENTITY = 0, FETI_PREC_LUMPED = 1, FETI_PREC_DIRICHLET = 2 } feti_precond;
 
 /* FETI_FP64: every step in FP64.  FETI_MIXED: local factors and local solves
@@ -177,7 +179,7 @@ typedef struct {
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */
 
-/* Decompose the mesh, build multiplier rows, multiplicities and index maps,
+/* Decompose the mesh, build multiplier rows, their weights and index maps,
  * reserve device memory and upload the static data.  *out receives a new
  * problem (NULL on failure).  opts may be NULL (defaults: all-floating,
  * lumped, FP64).  Errors: EINVAL, ENOMEM, EDEVICE. */

@@ -17,7 +17,7 @@ Oracle module (test infrastructure only).  It follows section 4 of the paper:
   by preconditioned CG from lambda_0 = G (G^T G)^{-1} e, and the recovery of
   gamma and u_i (end of section 4.3);
 * preconditioners of the form sum B_D,i Y_i B_D,i^T (eq. (feti_preconditioner))
-  with multiplicity-scaled rows: lumped (Y_i = K_i, eq. (LumpedVK)),
+  with scaled rows B_D: lumped (Y_i = K_i, eq. (LumpedVK)),
   Dirichlet (Y_i = Schur complement on the interface, eq. (DirichletVK)) and
   identity (section 4.4, last paragraph).
 

@@ -323,7 +323,7 @@ void apply_F(feti_problem* p, const double* v, double* q, const double* base, do
   pcg_scatter(p->di, 0, p->d_yb, base, sgn, q, st, p->stream);
 }
 
-// out = M^{-1} w (multiplicity-scaled; lumped, Dirichlet or identity)
+// out = M^{-1} w (scaled rows B_D; lumped, Dirichlet or identity)
 void precondition(feti_problem* p, const double* w, double* out, const PcgState* st) {
   pcg_gather(p->di, 1, w, p->d_xb, st, p->stream);
   const double* y = p->d_xb;

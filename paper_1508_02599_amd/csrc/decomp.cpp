@@ -1,5 +1,5 @@
 // Host side of feti_setup: validation, tearing of the mesh into subdomains,
-// multiplier rows, multiplicity weights, interior-first DOF ordering, index
+// multiplier rows, their weights, interior-first DOF ordering, index
 // maps for the device kernels and the tile schedule of the batched factor.
 //
 // Paper references: non-overlapping decomposition and reordering into interior

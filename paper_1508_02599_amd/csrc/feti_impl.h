@@ -94,7 +94,7 @@ struct HostPlan {
   // ---- multipliers
   int64_t n_lam = 0;
   std::vector<int64_t> r_b0, r_b1;      // b-space index of the two entries (-1 if none)
-  std::vector<double> r_c0, r_c1, r_w;  // coefficients and multiplicity weight
+  std::vector<double> r_c0, r_c1, r_w;  // coefficients and weight of the row in B_D
   std::vector<int64_t> r_gdof;          // Dirichlet dof of an AF Dirichlet row, else -1
   std::vector<int32_t> g_ptr;           // [NB+1] multiplier rows touching each b entry
   std::vector<int32_t> g_row;

@@ -1,6 +1,6 @@
 // Kernels of the dual iteration (paper section 4.3): the action of
 // F = sum_i B_i K_i^+ B_i^T through the jump operators, the projection
-// P = I - G (G^T G)^{-1} G^T, the multiplicity-scaled preconditioners of
+// P = I - G (G^T G)^{-1} G^T, the scaled-row (B_D) preconditioners of
 // section 4.4, deterministic dot products and the CG recurrences.
 //
 // All reductions use a fixed partition and a fixed summation order, so a
