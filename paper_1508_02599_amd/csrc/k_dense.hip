@@ -218,8 +218,11 @@ template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
                            const T* __restrict__ linv, T* W, int interior, T* sA, T* sB);
 
-// FP64 LDS scratch of a diagonal block (diag_block), in doubles
-constexpr int DIAG_SMEM = 3 * TS + TS * LD;
+// Blocked factorisation of a diagonal tile (diag_block): 16x16 blocks.
+constexpr int DB = 16;
+// FP64 LDS scratch of a diagonal block, in doubles: the tile (TS LD), the
+// inverses of its four diagonal 16x16 blocks, and three 16x16 partial products
+constexpr int DIAG_SMEM = TS * LD + 4 * DB * DB + 3 * DB * DB;
 // LDS of a kernel whose blocks hold `elems` elements of T or a diagonal
 // block's scratch, in doubles
 template <typename T>
@@ -395,111 +398,159 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Order the LDS accesses of a one-wave workgroup: a wave's LDS instructions
-// execute in issue order, so keeping the compiler from moving them across
-// this point is all a write-then-read by other lanes needs.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64 arithmetic)
-// and the explicit inverse L_jj^{-1}.  One wave (the lanes of wave 0) with
-// the tile in registers (lane r holds row r, loops fully unrolled).  Each
-// elimination step reads its pivot from the owning lane (readlane), scales
-// the column by the reciprocal of its square root, and broadcasts the column
-// through LDS (two buffers in turn, ordered by wave_sync), so a trailing
-// update costs one broadcast LDS read and one register FMA per entry.  The
-// inverse (lane j holds column j) reads L back from LDS by broadcast and
-// multiplies by the stored reciprocals of the pivots.  A non-positive or
-// non-finite pivot records the subdomain in *err.  scratch: DIAG_SMEM doubles
-// of LDS.
+// Diagonal tile of a column step: C_jj = L_jj L_jj^T (in place, FP64
+// arithmetic) and the explicit inverse L_jj^{-1}, by all four waves of the
+// workgroup on the tile held in LDS, in 16x16 blocks.  For each block column p:
+// wave 0 factors the diagonal block in registers (lane r holds row r; pivots
+// read from the owning lane with readlane; one reciprocal square root with a
+// Newton step per pivot) and inverts it; the rows below are solved against
+// that inverse (one thread per row); the trailing lower triangle takes the
+// rank-16 update.  The off-diagonal blocks of the inverse follow block
+// diagonal by block diagonal: X_qp = -X_qq sum_{p<=k<q} L_qk X_kp, stored
+// transposed in the unused upper triangle of the tile.  The serial chain is
+// 4 x 16 pivots instead of 64.  A non-positive or non-finite pivot records
+// the subdomain in *err.  scratch: DIAG_SMEM doubles of LDS.
 template <typename T>
-__device__ __forceinline__ void diag_wave(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv, int* err,
-                          double* scratch) {
-  double* colv = scratch;            // [2][TS]
-  double* rinv = scratch + 2 * TS;   // [TS]
-  double* sL = scratch + 3 * TS;     // [TS * LD]
+__device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv,
+                                             int* err, double* scratch) {
+  double* A = scratch;                    // A(r, c) = A[c * LD + r]
+  double* Dinv = scratch + TS * LD;       // Dinv_p(i, k) = Dinv[p * 256 + i * 16 + k]
+  double* Tmp = Dinv + 4 * DB * DB;       // [3][16 * 16]
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
   T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
-  const int r = threadIdx.x;
-  double a[TS];
-#pragma unroll
-  for (int c = 0; c < TS; ++c) a[c] = (double)C[c * TS + r];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < TS2; e += 256) A[(e >> 6) * LD + (e & 63)] = (double)C[e];
+  __syncthreads();
   bool bad = false;
-  double my_inv = 1.0;
-  // right-looking elimination: a[cc] of lane r is A(r, cc); its lower part is kept
+  for (int p = 0; p < 4; ++p) {
+    const int p0 = DB * p;
+    if (w == 0) {
+      // lane r holds row p0 + (r & 15) of the diagonal block; lanes 16..63
+      // repeat the rows of lanes 0..15 and write nothing
+      const int r = lane & 15;
+      double a[DB];
 #pragma unroll
-  for (int c = 0; c < TS; ++c) {
-    const double d = readlane_d(a[c], c);
-    const bool ok = (d > 0.0) && (d < 1e300);
-    bad |= !ok;
-    // 1/sqrt(d): hardware estimate and one Newton step (relative error near
-    // the rounding unit), then sqrt(d) = d / sqrt(d)
-    const double dd = ok ? d : 1.0;
-    double inv = __builtin_amdgcn_rsq(dd);
-    inv = inv * (1.5 - 0.5 * dd * inv * inv);
-    const double sd = dd * inv;
-    // plain selects (a nested conditional here makes the compiler spill)
-    double l = a[c] * inv;
-    l = r > c ? l : 0.0;
-    l = r == c ? sd : l;
-    my_inv = r == c ? inv : my_inv;
-    a[c] = l;
-    colv[(c & 1) * TS + r] = l;   // every lane stores (a store under a lane condition makes the compiler spill)
-    wave_sync();
-    // loads in batches of 16 (a whole column's worth at once needs too many registers)
+      for (int c = 0; c < DB; ++c) a[c] = A[(p0 + c) * LD + p0 + r];
+      double my_inv = 1.0;
 #pragma unroll
-    for (int cc = c + 1; cc < TS; ++cc) {
-      a[cc] -= l * colv[(c & 1) * TS + cc];
-      if (((cc - c) & 15) == 0) __builtin_amdgcn_sched_barrier(0);
+      for (int c = 0; c < DB; ++c) {
+        const double d = readlane_d(a[c], c);
+        const bool ok = (d > 0.0) && (d < 1e300);
+        bad |= !ok;
+        // 1/sqrt(d): hardware estimate and one Newton step, then sqrt(d) = d / sqrt(d)
+        const double dd = ok ? d : 1.0;
+        double inv = __builtin_amdgcn_rsq(dd);
+        inv = inv * (1.5 - 0.5 * dd * inv * inv);
+        const double sd = dd * inv;
+        double l = a[c] * inv;
+        l = r > c ? l : 0.0;
+        l = r == c ? sd : l;
+        my_inv = r == c ? inv : my_inv;
+        a[c] = l;
+#pragma unroll
+        for (int cc = c + 1; cc < DB; ++cc) a[cc] -= l * readlane_d(l, cc);
+      }
+      // inverse of the block: lane j holds column j,
+      // X(i, j) = (delta_ij - sum_{k<i} L(i, k) X(k, j)) / L(i, i)
+      const int j = r;
+      double x[DB];
+#pragma unroll
+      for (int i = 0; i < DB; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc += readlane_d(a[k], i) * x[k];
+        const double xi = ((i == j ? 1.0 : 0.0) - acc) * readlane_d(my_inv, i);
+        x[i] = i < j ? 0.0 : xi;
+      }
+      if (lane < DB) {
+#pragma unroll
+        for (int c = 0; c < DB; ++c) A[(p0 + c) * LD + p0 + r] = c > r ? 0.0 : a[c];
+#pragma unroll
+        for (int i = 0; i < DB; ++i) Dinv[p * DB * DB + i * DB + j] = x[i];
+      }
     }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  rinv[r] = my_inv;
+    __syncthreads();
+    const int n = TS - p0 - DB;   // rows below the block column
+    if (n > 0) {
+      // L(r, p0 + c) = sum_{k <= c} A(r, p0 + k) X_pp(c, k), one thread per row
+      if (tid < n) {
+        const int r = p0 + DB + tid;
+        double a[DB];
 #pragma unroll
-  for (int c = 0; c < TS; ++c) {
-    double v = a[c];
-    v = c > r ? 0.0 : v;
-    C[c * TS + r] = (T)v;
-    sL[c * LD + r] = v;
-  }
-  wave_sync();
-  // X = L^{-1} with lane j holding column j:
-  // X(i, j) = (delta_ij - sum_{k<i} L(i, k) X(k, j)) / L(i, i), X(k, j) = 0 for k < j
-  const int j = r;
-  double x[TS];
+        for (int k = 0; k < DB; ++k) a[k] = A[(p0 + k) * LD + r];
 #pragma unroll
-  for (int i = 0; i < TS; ++i) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < DB; ++c) {
+          double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < i; ++k) {
-      acc[k & 3] += sL[k * LD + i] * x[k];
-      if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+          for (int k = 0; k <= c; ++k) acc += a[k] * Dinv[p * DB * DB + c * DB + k];
+          A[(p0 + c) * LD + r] = acc;
+        }
+      }
+      __syncthreads();
+      // A(r, c) -= sum_k L(r, p0 + k) L(c, p0 + k) for p0 + 16 <= c <= r
+      for (int e = tid; e < n * n; e += 256) {
+        const int r = p0 + DB + e / n, c = p0 + DB + e % n;
+        if (c <= r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < DB; ++k) acc += A[(p0 + k) * LD + r] * A[(p0 + k) * LD + c];
+          A[c * LD + r] -= acc;
+        }
+      }
+      __syncthreads();
     }
-    const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    const double xi = ((i == j ? 1.0 : 0.0) - sum) * rinv[i];
-    x[i] = i < j ? 0.0 : xi;
-    // keep the loads of later rows from being hoisted (register pressure)
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
   }
-  wave_sync();
+  // off-diagonal blocks of X = L^{-1}, block diagonal d = q - p at a time;
+  // X(R, C) for block(R) > block(C) is kept at A[R * LD + C]
+  {
+    const int i = tid >> 4, jj = tid & 15;
+    for (int d = 1; d < 4; ++d) {
+      for (int p = 0; p + d < 4; ++p) {
+        const int q = p + d;
+        // T(i, jj) = sum_{k=p}^{q-1} sum_m L_qk(i, m) X_kp(m, jj)
+        double acc = 0.0;
+        for (int k = p; k < q; ++k)
 #pragma unroll
-  for (int i = 0; i < TS; ++i) sL[j * LD + i] = x[i];
-  wave_sync();
-#pragma unroll 8
-  for (int c = 0; c < TS; ++c) Li[c * TS + r] = (T)sL[c * LD + r];
-  if (bad) atomicMin(err, t.sub);
+          for (int m = 0; m < DB; ++m) {
+            const double l = A[(DB * k + m) * LD + DB * q + i];
+            const double xv = k == p ? Dinv[p * DB * DB + m * DB + jj] : A[(DB * k + m) * LD + DB * p + jj];
+            acc += l * xv;
+          }
+        Tmp[p * DB * DB + i * DB + jj] = acc;
+      }
+      __syncthreads();
+      for (int p = 0; p + d < 4; ++p) {
+        const int q = p + d;
+        // X_qp(i, jj) = -sum_{m <= i} X_qq(i, m) T(m, jj)
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < DB; ++m)
+          acc += (m <= i ? Dinv[q * DB * DB + i * DB + m] : 0.0) * Tmp[p * DB * DB + m * DB + jj];
+        A[(DB * q + i) * LD + DB * p + jj] = -acc;
+      }
+      __syncthreads();
+    }
+  }
+  // L to the tile (upper triangle zero) and X to the inverse arena, column-major
+  for (int e = tid; e < TS2; e += 256) {
+    const int row = e & 63, col = e >> 6;
+    C[e] = (T)(row >= col ? A[col * LD + row] : 0.0);
+    double xv = 0.0;
+    if (row >= col) {
+      const int br = row >> 4, bc = col >> 4;
+      xv = br == bc ? Dinv[br * DB * DB + (row & 15) * DB + (col & 15)] : A[row * LD + col];
+    }
+    Li[e] = (T)xv;
+  }
+  if (bad && tid == 0) atomicMin(err, t.sub);
 }
 
 // A diagonal task (j, j, k0, k1) of a 256-thread block: the four waves
 // subtract the update terms k0 <= k < k1 (update_tile, usually the one term
 // k = j - 1, the others having been subtracted by the previous column step),
-// then wave 0 factors and inverts the tile (diag_wave) with `scratch`, which
-// may alias sA and sB.
+// then factor and invert the tile (diag_blocked) with `scratch`, which may
+// alias sA and sB.
 template <typename T>
 __device__ __forceinline__ void diag_block(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv,
                                            int* err, T* sA, T* sB, double* scratch) {
@@ -507,7 +558,7 @@ __device__ __forceinline__ void diag_block(const Task& t, const SubInfo* __restr
     update_tile<T>(t, subs, arena, sA, sB);
     __syncthreads();   // the updated tile is in memory and sA, sB are free
   }
-  if (threadIdx.x < 64) diag_wave<T>(t, subs, arena, linv, err, scratch);
+  diag_blocked<T>(t, subs, arena, linv, err, scratch);
 }
 
 // Diagonal tasks alone (the first column of a stage, and the launches whose
