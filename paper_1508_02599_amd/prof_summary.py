@@ -102,17 +102,17 @@ def _dispatches(d: str):
 
 def update_bytes_per_launch(fetch_dir: str, write_dir: str, fetch_scale: float, write_scale: float):
     """HBM bytes per factor-update launch, from the last factorisation of the
-    run: the dispatches from the last full-size k_init_arena to the next
-    k_coarse_q (where the coarse factorisation begins).  Every update launch
-    is one k_update / k_update_db / k_update_wide dispatch; counter values are
-    KiB per dispatch, scaled by the copy calibration."""
+    run: the dispatches after the last full-size k_init_arena.  Every update
+    launch of the batched factorisation is one k_update / k_update_db /
+    k_update_wide dispatch of at least 64 workgroups (the diagonal tiles of
+    its column alone are 64 for cube32_s4); the coarse factorisation's update
+    launches are far smaller and left out.  Counter values are KiB per
+    dispatch, scaled by the copy calibration."""
     tot, n = 0.0, 0
     for d, scale in ((fetch_dir, fetch_scale), (write_dir, write_scale)):
         rows = _dispatches(d)
         starts = [i for i, r in enumerate(rows) if r[1].startswith("k_init_arena") and r[2] > 10000]
-        i0 = starts[-1]
-        i1 = next((i for i in range(i0, len(rows)) if rows[i][1].startswith("k_coarse_q")), len(rows))
-        upd = [r for r in rows[i0:i1] if r[1].startswith("k_update")]
+        upd = [r for r in rows[starts[-1]:] if r[1].startswith("k_update") and r[2] >= 64]
         tot += scale * 1024.0 * sum(r[3] for r in upd)
         n = len(upd)
     return tot / n, n
