@@ -246,17 +246,20 @@ void autotune_step(feti_problem* p) {
   }
 }
 
-void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st) {
+// yb = M xb over the trailing blocks of all subdomains.  iface_only: the rows
+// and columns of DOFs without multipliers are left out (the dual operator and
+// the Dirichlet preconditioner); otherwise the whole trailing block takes part
+// (the local pseudo-inverse).
+void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st,
+                int iface_only) {
   const HostPlan::Launch& L = p->P.sched_xtiles;
   if (p->P.mixed)
     pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)M, xb, p->d_part, p->di.NB,
-                    p->di.b_sub, yb, st, p->stream);
+                    p->di.b_sub, yb, st, p->stream, iface_only);
   else
     pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)M, xb, p->d_part, p->di.NB,
-                     p->di.b_sub, yb, st, p->stream);
+                     p->di.b_sub, yb, st, p->stream, iface_only);
 }
-
-void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, const PcgState* st);
 
 // z = K^+ g for every subdomain (full local vectors), see k_kp_tiles.
 template <typename T>
@@ -267,7 +270,7 @@ void kpinv_t(feti_problem* p, const double* g, double* z) {
   hipStream_t st = p->stream;
   local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
   local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
-  symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr);
+  symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
   local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
   local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
   vec_set_b2f(p->di, p->d_kb2, z, st);
@@ -288,7 +291,7 @@ void kpinv_b_t(feti_problem* p, const double* g, double* zb) {
   hipStream_t st = p->stream;
   local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
   local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
-  symv_local(p, p->d_X, p->d_kb1, zb, nullptr);
+  symv_local(p, p->d_X, p->d_kb1, zb, nullptr, 0);
 }
 void kpinv_b(feti_problem* p, const double* g, double* zb) {
   if (p->P.mixed) kpinv_b_t<float>(p, g, zb);
@@ -299,7 +302,7 @@ void kpinv_b(feti_problem* p, const double* g, double* zb) {
 void coarse_solve(feti_problem* p, const double* g, double* alpha, const PcgState* st) {
   if (p->n_coarse == 0) return;
   pcg_symv<double>(p->d_qtasks + p->q_xtiles.first, p->q_xtiles.count, p->d_qsub, p->d_qX, g, p->d_qpart,
-                   (int64_t)p->nq * TS, p->d_qbsub, alpha, st, p->stream);
+                   (int64_t)p->nq * TS, p->d_qbsub, alpha, st, p->stream, 0);
 }
 
 // Projection by the fused kernels: g = Rb^T B^T x per subdomain, a = Q^{-1} g
@@ -319,7 +322,7 @@ void project_fused(feti_problem* p, int mode, int init, double* x, double* out, 
 // q = F v
 void apply_F(feti_problem* p, const double* v, double* q, const double* base, double sgn, const PcgState* st) {
   pcg_gather(p->di, 0, v, p->d_xb, st, p->stream);
-  symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
+  symv_local(p, p->d_X, p->d_xb, p->d_yb, st, 1);
   pcg_scatter(p->di, 0, p->d_yb, base, sgn, q, st, p->stream);
 }
 
@@ -331,7 +334,7 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
     pcg_lumped(p->di, p->P.w_bb, p->d_bb_col, p->d_bb_val, p->d_xb, p->d_yb, st, p->stream);
     y = p->d_yb;
   } else if (p->P.precond == FETI_PREC_DIRICHLET) {
-    symv_local(p, p->d_S, p->d_xb, p->d_yb, st);
+    symv_local(p, p->d_S, p->d_xb, p->d_yb, st, 1);
     y = p->d_yb;
   }
   pcg_scatter(p->di, 1, y, nullptr, 1.0, out, st, p->stream);
@@ -348,7 +351,7 @@ void pcg_iteration(feti_problem* p) {
   hipStream_t s = p->stream;
   const int nc = p->n_coarse;
   pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, s);
-  symv_local(p, p->d_X, p->d_xb, p->d_yb, st);
+  symv_local(p, p->d_X, p->d_xb, p->d_yb, st, 1);
   pcg_scatter_dot_alpha_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, p->d_yb, p->d_zv, p->d_s, p->d_q,
                            p->d_apart, st, p->d_gpart, p->ldg, s);
   if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
@@ -361,7 +364,7 @@ void pcg_iteration(feti_problem* p) {
     pcg_lumped(p->di, p->P.w_bb, p->d_bb_col, p->d_bb_val, p->d_xb, p->d_yb, st, s);
     y = p->d_yb;
   } else if (p->P.precond == FETI_PREC_DIRICHLET) {
-    symv_local(p, p->d_S, p->d_xb, p->d_yb, st);
+    symv_local(p, p->d_S, p->d_xb, p->d_yb, st, 1);
     y = p->d_yb;
   }
   pcg_scatter_w_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, y, p->d_tv, st, p->d_gpart, p->ldg, s);
@@ -641,7 +644,7 @@ feti_status setup_device(feti_problem* p) {
   {
     const double es = (double)elt(p);
     double bytes = 0.0, fl = 0.0;
-    for (const auto& si : P.sub) bytes += 0.5 * si.n_b * (si.n_b + 1.0) * es;
+    for (const auto& si : P.sub) bytes += 0.5 * si.n_if * (si.n_if + 1.0) * es;
     auto real = [&](const SubInfo& si, int t) -> double {
       if (t < si.nt_i) return std::min(TS, si.n_ii - t * TS);
       return std::min(TS, si.n_b - (t - si.nt_i) * TS);
@@ -689,6 +692,7 @@ feti_status coarse_factor(feti_problem* p, hipStream_t st) {
   q = SubInfo{};
   q.n_ii = 0;
   q.n_b = p->n_coarse;
+  q.n_if = p->n_coarse;
   q.nt_i = 0;
   q.nt_b = p->nq;
   q.nt = p->nq;
@@ -1029,10 +1033,10 @@ feti_status profile_gemv(feti_problem* p) {
   for (int r = 0; r < kBurst; ++r) {
     if (p->P.mixed)
       pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)p->d_X, p->d_xb, p->d_part,
-                      p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream);
+                      p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream, 1);
     else
       pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)p->d_X, p->d_xb, p->d_part,
-                       p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream);
+                       p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream, 1);
   }
   HIPCHK(hipEventRecord(p->ev_gemv[1], p->stream));
   HIPCHK(hipEventSynchronize(p->ev_gemv[1]));

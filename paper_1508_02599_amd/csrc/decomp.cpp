@@ -394,21 +394,34 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
         if (is_b[ld]) n_b++;
         else n_ii++;
       }
-    si.n_ii = n_ii;
-    si.n_b = n_b;
-    si.nt_i = ceil_tiles(n_ii);
-    si.nt_b = ceil_tiles(n_b);
+    // The interior block holds whole tiles only when that costs no interface
+    // tile: the last n_ii mod 64 interior DOFs then join the trailing block,
+    // behind the interface DOFs.  Eliminating fewer DOFs first gives another
+    // generalised inverse of K_i; the projected dual iteration and the
+    // displacements do not depend on that choice (they differ by terms in
+    // range(G)).  The Dirichlet preconditioner needs the Schur complement on
+    // exactly the interface DOFs and keeps the split as it is.
+    int r_move = 0;
+    if (P.precond != FETI_PREC_DIRICHLET) {
+      const int r = n_ii % TS;
+      if (r > 0 && ceil_tiles(n_b + r) == ceil_tiles(n_b)) r_move = r;
+    }
+    si.n_if = n_b;
+    si.n_ii = n_ii - r_move;
+    si.n_b = n_b + r_move;
+    si.nt_i = ceil_tiles(si.n_ii);
+    si.nt_b = ceil_tiles(si.n_b);
     si.nt = si.nt_i + si.nt_b;
     si.floating = (P.af || !has_dir) ? 1 : 0;
     si.n_modes = si.floating ? 6 : 0;
     if (si.floating && n_b == 0) return "floating subdomain " + std::to_string(s) + " has no interface";
-    int pi = 0, pb = si.nt_i * TS;
+    int pi = 0, pb = si.nt_i * TS, px = si.nt_i * TS + si.n_if;
     for (int q = 0; q < si.n_nodes; ++q)
       for (int c = 0; c < 3; ++c) {
         const int64_t ld = 3 * (int64_t)(si.node_off + q) + c;
         const int64_t g = 3 * P.loc_node[si.node_off + q] + c;
         if (!P.af && P.dir_mask[g]) continue;
-        P.loc_pos[ld] = is_b[ld] ? pb++ : pi++;
+        P.loc_pos[ld] = is_b[ld] ? pb++ : (pi < si.n_ii ? pi++ : px++);
       }
     si.tile_off = tile_off;
     si.linv_off = linv_off;
@@ -585,12 +598,12 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     for (int s = 0; s < ns; ++s) {
       const SubInfo& si = P.sub[s];
       const int bstart = si.nt_i * TS;
-      for (int pb = 0; pb < si.n_b; ++pb) {
+      for (int pb = 0; pb < si.n_if; ++pb) {
         const int64_t row = si.full_off + bstart + pb;
         auto& L = rows[si.b_off + pb];
         for (int k = 0; k < ELLW; ++k) {
           const int c = P.ell_col[(int64_t)k * P.NF + row];
-          if (c >= bstart) L.push_back({k, (int32_t)(si.b_off + c - bstart)});
+          if (c >= bstart && c < bstart + si.n_if) L.push_back({k, (int32_t)(si.b_off + c - bstart)});
         }
         w = std::max<int32_t>(w, (int32_t)L.size());
       }

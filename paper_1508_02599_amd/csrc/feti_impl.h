@@ -34,6 +34,7 @@ struct SubInfo {
   int32_t floating;     // has a rigid-body kernel
   int32_t n_modes;      // kernel dimension used (0, 3..6)
   int32_t coarse_off;   // first coarse index of this subdomain
+  int32_t n_if;         // interface DOFs (with multipliers): the first n_if of the trailing block
   int64_t tile_off;     // element offset into the factor arena
   int64_t linv_off;     // element offset into the diagonal-inverse arena
   int64_t x_off;        // element offset into the interface arenas (X, W, S)

@@ -53,7 +53,7 @@ void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* b
 // phase only).
 template <typename T>
 void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
-              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s);
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s, int iface_only);
 void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
              const PcgState* st, hipStream_t s);
 void pcg_alpha(const double* part, PcgState* st, hipStream_t s);

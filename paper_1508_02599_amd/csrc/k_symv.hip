@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tas
                                                     const SubInfo* __restrict__ subs,
                                                     const T* __restrict__ M,
                                                     const double* __restrict__ xb, double* part,
-                                                    const PcgState* st) {
+                                                    const PcgState* st, int iface_only) {
   if (halted(st)) return;
   __shared__ T sM[TS * LDV];
   __shared__ double xI[TS], xJ[TS];
@@ -35,10 +35,12 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tas
   const int tid = threadIdx.x;
   {
     // only the stored entries that take part are read: rows beyond the last
-    // real interface DOF (the padding of the last tile row meets zero inputs
-    // and its outputs are dropped) and the upper half of a diagonal tile (the
-    // lower half is mirrored) are not fetched
-    const int rows = t.i == s.nt_b - 1 ? s.n_b - TS * (s.nt_b - 1) : TS;
+    // real DOF of the block (the padding of the last tile row meets zero
+    // inputs and its outputs are dropped; with iface_only, in the dual
+    // operator, so do trailing-block DOFs without multipliers) and the upper
+    // half of a diagonal tile (the lower half is mirrored) are not fetched
+    const int nreal = iface_only ? s.n_if : s.n_b;
+    const int rows = t.i == s.nt_b - 1 ? nreal - TS * (s.nt_b - 1) : TS;
     const int row = tid & 63;
     T v[16];
 #pragma unroll
@@ -113,12 +115,12 @@ __global__ void k_symv_reduce(int64_t NB, const int32_t* __restrict__ b_sub, con
 
 template <typename T>
 void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
-              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s) {
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s, int iface_only) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st);
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st, iface_only);
   if (yb) hipLaunchKernelGGL(k_symv_reduce, grid1(NB), dim3(256), 0, s, NB, b_sub, subs, (const double*)part, yb, st);
 }
-template void pcg_symv<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
-template void pcg_symv<float>(const Task*, int, const SubInfo*, const float*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t);
+template void pcg_symv<double>(const Task*, int, const SubInfo*, const double*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t, int);
+template void pcg_symv<float>(const Task*, int, const SubInfo*, const float*, const double*, double*, int64_t, const int32_t*, double*, const PcgState*, hipStream_t, int);
 
 }  // namespace feti
