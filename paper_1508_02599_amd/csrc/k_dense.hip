@@ -290,8 +290,12 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 // group of an operand read takes 16 consecutive elements.  Same products in
 // the same order as update_tile, so the results are bit-identical.  With
 // KC = 32 the buffers take 64 KiB in FP64, two workgroups per compute unit.
+// Occupancy asked of the double-buffered update: three waves per SIMD in
+// FP32 (its LDS allows three workgroups per compute unit), two in FP64.
+template <typename T>
+struct UpdOcc { static constexpr int waves = sizeof(T) == 4 ? 3 : 2; };
 template <typename T, int KC>
-__global__ __launch_bounds__(256) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                    const SubInfo* __restrict__ subs, T* arena,
                                                    T* linv, T* W, int interior, int* err) {
   constexpr int CH = TS * KC;                 // elements per chunk
