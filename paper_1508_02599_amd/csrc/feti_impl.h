@@ -117,13 +117,12 @@ struct HostPlan {
   std::vector<int64_t> qe_bs, qe_bt;
   std::vector<double> qe_c;                       // c_s * c_t
 
-  // ---- factor schedule (task lists, launched in order)
-  // split: for a fused update + inverse-row launch, the number of update tasks.
-  // wfirst/wcount/wsplit: the same launch with the tile updates paired into
-  // 128x64 outputs (wcount = 0: no such form).
-  // side: runs on the second stream, forked from the main one (the update of
-  // the diagonal tile and its factorisation, concurrent with the rest of the
-  // column's updates); join: the main stream waits for the second before it.
+  // ---- factor schedule (task lists, launched in order on one stream)
+  // split: for a fused update + inverse-row launch, the number of tasks before
+  // the inverse rows.  ndiag: the leading diagonal tasks of an update launch
+  // (last update term, factorisation and inverse of the column's diagonal
+  // tiles).  wfirst/wcount/wsplit: the same launch with the tile updates
+  // paired into 128x64 outputs (wcount = 0: no such form).
   struct Launch {
     int kind;
     int32_t first, count;
