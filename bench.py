@@ -297,6 +297,18 @@ def tube_load_path(args):
     return line
 
 
+def workload_text(args, mesh):
+    """One-line description of a linear workload, with its sizes."""
+    kind = "all-floating" if args.variant == "af" else "classical"
+    tail = f"{args.precond} preconditioner, PCG rtol {args.rtol:g}"
+    if args.config.startswith("random"):
+        return (f"{args.config}: unit cube 64^3 Q1 elements in 8x8x8 {kind} boxes with seeded slab "
+                f"widths in 4..12 elements ({mesh.n_sub} subdomains of 300-6000 DOFs), E = 1, nu = 0.3, "
+                f"smooth random body force, {tail}")
+    return (f"{args.config}: unit cube 32^3 Q1 elements in 4x4x4 {kind} subdomains of 8^3 elements "
+            f"(2187 DOFs each), nu per subdomain ~ U[0.25,0.35] (seed 0), {tail}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,10 +371,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-local/f64-global",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: unit cube 32^3 Q1 elements in 4x4x4 "
-                               f"{'all-floating' if args.variant == 'af' else 'classical'} subdomains "
-                               f"of 8^3 elements (2187 DOFs each), nu per subdomain ~ U[0.25,0.35] "
-                               f"(seed 0), {args.precond} preconditioner, PCG rtol {args.rtol:g}",
+        "config": {"workload": workload_text(args, mesh),
                    "subdomains": mesh.n_sub, "global_dofs": mesh.n_dofs,
                    "multipliers": st["n_lambda"], "coarse_dim": st["n_coarse"]},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
