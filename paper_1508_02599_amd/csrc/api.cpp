@@ -96,7 +96,7 @@ struct feti_problem {
   double *d_qarena = nullptr, *d_qlinv = nullptr, *d_qW = nullptr, *d_qX = nullptr, *d_qpart = nullptr;
   HostPlan::Launch q_xtiles{};
   // vectors
-  double *d_f = nullptr, *d_z = nullptr, *d_w = nullptr, *d_u = nullptr, *d_gfull = nullptr;
+  double *d_f = nullptr, *d_w = nullptr, *d_u = nullptr;
   double *d_xb = nullptr, *d_yb = nullptr, *d_vb = nullptr, *d_part = nullptr;
   double *d_lam = nullptr, *d_r = nullptr, *d_s = nullptr, *d_q = nullptr, *d_wv = nullptr, *d_zv = nullptr;
   double *d_tv = nullptr, *d_d = nullptr, *d_bv = nullptr;
@@ -279,6 +279,23 @@ void kpinv_t(feti_problem* p, const double* g, double* z) {
 void kpinv(feti_problem* p, const double* g, double* z) {
   if (p->P.mixed) kpinv_t<float>(p, g, z);
   else kpinv_t<double>(p, g, z);
+}
+
+// z = K^+ (f - B^T lambda) after kpinv_b(f): the right-hand side differs from
+// f on interface DOFs only, so the interior forward solve w = L_II^{-1} f_I
+// (d_w) and f_b - L_bI w (d_kb1) left by kpinv_b still hold; only xb = B^T
+// lambda is subtracted before the interface and backward passes.
+template <typename T>
+void kpinv_recover_t(feti_problem* p, const double* xb, double* z) {
+  const HostPlan& P = p->P;
+  const T* A = (const T*)p->d_arena;
+  const T* Wi = (const T*)p->d_Wi;
+  hipStream_t st = p->stream;
+  vec_axpby(P.NB, -1.0, xb, 1.0, p->d_kb1, st);
+  symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  vec_set_b2f(p->di, p->d_kb2, z, st);
 }
 
 // Interface part only, zb = (K^+ g)_b = X (g_b - L_bI L_II^{-1} g_I), as a
@@ -566,10 +583,8 @@ feti_status setup_device(feti_problem* p) {
   vec_fill((int64_t)nq_max * TS, 0.0, p->d_e, p->stream);
   // vectors
   TRY(dalloc(p, p->d_f, (size_t)P.NF));
-  TRY(dalloc(p, p->d_z, (size_t)P.NF));
   TRY(dalloc(p, p->d_w, (size_t)P.NF));
   TRY(dalloc(p, p->d_u, (size_t)P.NF));
-  TRY(dalloc(p, p->d_gfull, (size_t)P.NF));
   TRY(dalloc(p, p->d_t, (size_t)P.NF));
   TRY(dalloc(p, p->d_kb1, (size_t)P.NB));
   TRY(dalloc(p, p->d_kb2, (size_t)P.NB));
@@ -967,10 +982,9 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
       kappa = lanczos_kappa(h, std::min(iters, p->hist_cap));
     }
     // gamma = -Q^{-1} G^T r ; u = K^+(f - B^T lambda) + R gamma
-    vec_axpby(P.NF, 1.0, p->d_f, 0.0, p->d_gfull, st);
     pcg_gather(p->di, 0, p->d_lam, p->d_xb, nullptr, st);
-    vec_add_b2f(p->di, p->d_xb, -1.0, p->d_gfull, st);
-    kpinv(p, p->d_gfull, p->d_u);
+    if (P.mixed) kpinv_recover_t<float>(p, p->d_xb, p->d_u);
+    else kpinv_recover_t<double>(p, p->d_xb, p->d_u);
     if (p->n_coarse) {
       pcg_gather(p->di, 0, p->d_r, p->d_xb, nullptr, st);
       pcg_coarse_gt(P.n_sub, p->d_sub, p->d_rb, p->d_xb, p->d_cg, nullptr, st);

@@ -74,7 +74,6 @@ void pcg_lumped(const DevIdx& d, int w_bb, const int32_t* bb_col, const double* 
 void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double* ell_val, double* bb_val,
                  hipStream_t s);
 void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s);
-void vec_add_b2f(const DevIdx& d, const double* b, double sgn, double* full, hipStream_t s);
 void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s);
 void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, const double* ufull,
                 const uint8_t* dmask, const double* dvals, double* out, int sum_mode, hipStream_t s);

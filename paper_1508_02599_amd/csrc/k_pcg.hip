@@ -303,13 +303,6 @@ __global__ void k_copy_b2f(int64_t NB, const int64_t* __restrict__ b2full, const
   if (k < NB) b[k] = full[b2full[k]];
 }
 
-// full[b2full[k]] += sgn * b[k]
-__global__ void k_add_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ b,
-                          double sgn, double* full) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < NB) full[b2full[k]] += sgn * b[k];
-}
-
 // Multiplier right-hand side b: prescribed value of an all-floating Dirichlet row, else 0.
 __global__ void k_bvec(int64_t n_lam, const int64_t* __restrict__ gdof, const double* __restrict__ dvals,
                        double* __restrict__ out) {
@@ -927,9 +920,6 @@ void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double
 }
 void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_copy_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, full, b);
-}
-void vec_add_b2f(const DevIdx& d, const double* b, double sgn, double* full, hipStream_t s) {
-  if (d.NB) hipLaunchKernelGGL(k_add_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, sgn, full);
 }
 void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s) {
   if (d.n_lam) hipLaunchKernelGGL(k_bvec, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_gdof, dvals, out);
