@@ -96,7 +96,7 @@ struct feti_problem {
   double *d_qarena = nullptr, *d_qlinv = nullptr, *d_qW = nullptr, *d_qX = nullptr, *d_qpart = nullptr;
   HostPlan::Launch q_xtiles{};
   // vectors
-  double *d_f = nullptr, *d_w = nullptr, *d_u = nullptr;
+  double *d_f = nullptr, *d_w = nullptr, *d_u = nullptr, *d_ul = nullptr;
   double *d_xb = nullptr, *d_yb = nullptr, *d_vb = nullptr, *d_part = nullptr;
   double *d_lam = nullptr, *d_r = nullptr, *d_s = nullptr, *d_q = nullptr, *d_wv = nullptr, *d_zv = nullptr;
   double *d_tv = nullptr, *d_d = nullptr, *d_bv = nullptr;
@@ -585,6 +585,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_f, (size_t)P.NF));
   TRY(dalloc(p, p->d_w, (size_t)P.NF));
   TRY(dalloc(p, p->d_u, (size_t)P.NF));
+  TRY(dalloc(p, p->d_ul, (size_t)P.NF));
   TRY(dalloc(p, p->d_t, (size_t)P.NF));
   TRY(dalloc(p, p->d_kb1, (size_t)P.NB));
   TRY(dalloc(p, p->d_kb2, (size_t)P.NB));
@@ -1085,7 +1086,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
       double fnorm = 0.0, rnorm = 0.0;
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
       local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
-                     p->d_ell_val, p->d_dmask, p->d_uglob, p->d_f, p->d_f0, st);
+                     p->d_ell_val, p->d_dmask, p->d_uglob, p->d_ul, p->d_f, p->d_f0, st);
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
       TRY(dev_norm(p, p->d_out, nd, &rnorm));
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
@@ -1109,7 +1110,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   double amp = 10.0, eta = 1.0, rprev = 0.0;
   for (;;) {
     local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
-                   p->d_ell_val, p->d_dmask, p->d_uglob, p->d_f0, p->d_f, st);
+                   p->d_ell_val, p->d_dmask, p->d_uglob, p->d_ul, p->d_f0, p->d_f, st);
     vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
     TRY(dev_norm(p, p->d_out, nd, &rnorm));
     if (!(rnorm > p->opt.ir_tol * fnorm) || sweeps >= p->opt.ir_max) break;

@@ -111,7 +111,8 @@ void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hip
 void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s);
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                    const uint8_t* dmask, const double* uglob, const double* f, double* r, hipStream_t s);
+                    const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
+                    hipStream_t s);
 void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s);
 

@@ -755,16 +755,30 @@ __global__ void k_tiles_to_dense(int nc, int ld, const double* __restrict__ tile
 
 // ---------------------------------------------------------------------------
 // FP64 residual of the assembled problem for the mixed-precision refinement:
-// the global displacement is restricted to every subdomain, the local residual
-// f_i - K_i u_i is formed with the FP64 sparse rows of the local stiffness
-// (free columns only: Dirichlet lifting is already in f_i), and summed over
-// the subdomain copies afterwards.
-__global__ void k_local_residual(int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
-                                 const int64_t* __restrict__ loc_node, const int32_t* __restrict__ f_sub,
-                                 const SubInfo* __restrict__ subs, const int32_t* __restrict__ ell_col,
-                                 const double* __restrict__ ell_val, const uint8_t* __restrict__ dmask,
-                                 const double* __restrict__ uglob, const double* __restrict__ f,
-                                 double* __restrict__ r) {
+// the global displacement is restricted to every subdomain (k_restrict), the
+// local residual f_i - K_i u_i is formed with the FP64 sparse rows of the
+// local stiffness (free columns only: Dirichlet lifting is already in f_i),
+// and summed over the subdomain copies afterwards.
+// ul[q] = uglob[global DOF of local position q] (0 for padding)
+__global__ void k_restrict(int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
+                           const int64_t* __restrict__ loc_node, const double* __restrict__ uglob,
+                           double* __restrict__ ul) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= NF) return;
+  const int32_t ln = fpos_lnode[q];
+  ul[q] = ln < 0 ? 0.0 : uglob[loc_node[ln] * 3 + fpos_comp[q]];
+}
+
+// One row per thread over the slot-major ELL; the column indices and values of
+// RES_C slots are loaded before their products, so the loads overlap.  Empty
+// slots add an exact zero, so the sum is that of the filled slots in slot order.
+constexpr int RES_C = 9;
+static_assert(ELLW % RES_C == 0, "whole groups of slots");
+__global__ __launch_bounds__(256) void k_local_residual(
+    int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
+    const int64_t* __restrict__ loc_node, const int32_t* __restrict__ f_sub, const SubInfo* __restrict__ subs,
+    const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val, const uint8_t* __restrict__ dmask,
+    const double* __restrict__ ul, const double* __restrict__ f, double* __restrict__ r) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NF) return;
   // padding, and constrained DOFs (their residual is a reaction, absorbed by
@@ -773,15 +787,21 @@ __global__ void k_local_residual(int64_t NF, const int32_t* __restrict__ fpos_ln
     r[p] = 0.0;
     return;
   }
-  const SubInfo s = subs[f_sub[p]];
+  const double* u = ul + subs[f_sub[p]].full_off;
   double acc = f[p];
-  for (int k = 0; k < ELLW; ++k) {
-    const int c = ell_col[k * NF + p];
-    if (c >= 0) {
-      const int64_t q = s.full_off + c;
-      const int64_t g = loc_node[fpos_lnode[q]] * 3 + fpos_comp[q];
-      acc -= ell_val[k * NF + p] * uglob[g];
+#pragma unroll 1
+  for (int k0 = 0; k0 < ELLW; k0 += RES_C) {
+    int c[RES_C];
+    double v[RES_C], x[RES_C];
+#pragma unroll
+    for (int i = 0; i < RES_C; ++i) c[i] = ell_col[(int64_t)(k0 + i) * NF + p];
+#pragma unroll
+    for (int i = 0; i < RES_C; ++i) {
+      v[i] = c[i] >= 0 ? ell_val[(int64_t)(k0 + i) * NF + p] : 0.0;
+      x[i] = c[i] >= 0 ? u[c[i]] : 0.0;
     }
+#pragma unroll
+    for (int i = 0; i < RES_C; ++i) acc -= v[i] * x[i];
   }
   r[p] = acc;
 }
@@ -946,8 +966,12 @@ void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist
 }
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                    const uint8_t* dmask, const double* uglob, const double* f, double* r, hipStream_t s) {
-  hipLaunchKernelGGL(k_local_residual, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, f_sub, subs, ell_col, ell_val, dmask, uglob, f, r);
+                    const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
+                    hipStream_t s) {
+  if (!NF) return;
+  hipLaunchKernelGGL(k_restrict, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, uglob, ul);
+  hipLaunchKernelGGL(k_local_residual, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, f_sub, subs,
+                     ell_col, ell_val, dmask, ul, f, r);
 }
 void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s) {
