@@ -908,6 +908,20 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
 // data in d_dvals; writes the local displacements to d_u.  A correction solve
 // (first = false) leaves the start event of the PCG phase where the first
 // solve put it.
+// Whether the stopping rule ||w|| <= rtol ||w_0|| is expected within n more
+// PCG iterations of state h, at the faster of the mean reduction rate so far
+// and that since the previous check (prev_it, prev_wn; prev_it = 0: none).
+bool pcg_converges_within(const PcgState& h, int prev_it, double prev_wn, int n) {
+  if (h.it <= 0 || !(h.w0 > 0.0) || !(h.wn > 0.0)) return false;
+  const double ratio = h.wn / h.w0, target = h.rtol;
+  if (ratio <= target) return true;
+  double lrate = std::log(ratio) / h.it;   // log of the mean reduction per iteration
+  if (prev_it > 0 && h.it > prev_it && prev_wn > 0.0)
+    lrate = std::min(lrate, std::log(h.wn / prev_wn) / (h.it - prev_it));
+  if (!(lrate < 0.0)) return false;
+  return std::log(target / ratio) / lrate <= n;
+}
+
 feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool first = true) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
@@ -952,27 +966,41 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
       (void)hipGraphDestroy(gr);
       p->graph_iters = gb;
     }
-    // Two replays in flight: the host checks the state copied after one while
-    // the next already runs (kernels of a replay after convergence return at
-    // once), so the GPU does not wait for the host between replays.
+    // Replays are pipelined: the host reads the state copied after one replay
+    // while the next already runs, so the GPU does not wait for the host.  A
+    // replay queued after convergence costs a block of iterations whose
+    // kernels return at once, so no further replay is queued while the one in
+    // flight is expected to reach the stopping rule (pcg_converges_within);
+    // if it does not, the next replay starts after the host has seen it.
+    // The state stops changing once the stopping rule is met.
     PcgState hs{};
-    HIPCHK(hipMemcpyAsync(&p->h_state[0], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(p->ev_rep[0], st));
+    int rd = 0, wr = 0, queued = 0;   // ring of two state copies
+    auto queue_state = [&]() -> hipError_t {
+      hipError_t e = hipMemcpyAsync(&p->h_state[wr], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_rep[wr], st);
+      wr ^= 1;
+      ++queued;
+      return e;
+    };
+    HIPCHK(queue_state());   // state after the initial residual
     HIPCHK(hipGraphLaunch(p->graph, st));
-    HIPCHK(hipMemcpyAsync(&p->h_state[1], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(p->ev_rep[1], st));
-    for (int k = 0;; ++k) {
-      const int slot = k & 1;
-      HIPCHK(hipEventSynchronize(p->ev_rep[slot]));
-      hs = p->h_state[slot];
+    HIPCHK(queue_state());
+    int prev_it = 0;
+    double prev_wn = 0.0;
+    for (;;) {
+      HIPCHK(hipEventSynchronize(p->ev_rep[rd]));
+      hs = p->h_state[rd];
+      rd ^= 1;
+      --queued;
       if (hs.done) break;
-      HIPCHK(hipGraphLaunch(p->graph, st));
-      HIPCHK(hipMemcpyAsync(&p->h_state[slot], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipEventRecord(p->ev_rep[slot], st));
+      if (queued == 0 || !pcg_converges_within(hs, prev_it, prev_wn, gb * queued)) {
+        HIPCHK(hipGraphLaunch(p->graph, st));
+        HIPCHK(queue_state());
+      }
+      prev_it = hs.it;
+      prev_wn = hs.wn;
     }
     HIPCHK(hipStreamSynchronize(st));
-    hs = p->h_state[0].done ? p->h_state[0] : p->h_state[1];
-    if (p->h_state[0].done && p->h_state[1].done && p->h_state[1].it > hs.it) hs = p->h_state[1];
     iters = hs.it;
     status = hs.status;
     rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
