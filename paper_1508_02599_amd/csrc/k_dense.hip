@@ -581,20 +581,39 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
                                               const SubInfo* __restrict__ subs, T* arena,
                                               const T* __restrict__ linv) {
-  __shared__ T sA[TS * LD], sB[TS * LD];
+  // One 64x64x64 product per workgroup: each wave reads the MFMA operands of
+  // its 32x32 block straight from the column-major tiles (16 lanes take 16
+  // consecutive rows of one column, 128 bytes), all before the first MFMA;
+  // only the result passes through LDS.  Same operands and order as mma64.
+  __shared__ T sC[TS * LD];
   const Task t = tasks[xcd_task()];
   const SubInfo s = subs[t.sub];
   T* C = arena + s.tile_off + tidx(t.i, t.j) * TS2;
-  lds_direct(sA, C);
-  lds_direct(sB, linv + s.linv_off + (int64_t)t.j * TS2);   // B(k,n) = Linv(n,k)
-  __syncthreads();
+  const T* Li = linv + s.linv_off + (int64_t)t.j * TS2;   // B(k,n) = Linv(n,k)
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = w >> 1, wc = w & 1, lr = lane & 15, lk = lane >> 4;
+  T a0[TS / 4], a1[TS / 4], b0[TS / 4], b1[TS / 4];
+#pragma unroll
+  for (int kk = 0; kk < TS / 4; ++kk) {
+    const int k = 4 * kk + lk;
+    a0[kk] = C[k * TS + 32 * wr + lr];
+    a1[kk] = C[k * TS + 32 * wr + 16 + lr];
+    b0[kk] = Li[k * TS + 32 * wc + lr];
+    b1[kk] = Li[k * TS + 32 * wc + 16 + lr];
+  }
   Acc<T> acc;
   acc.zero();
-  mma64(acc, sA, sB);
+#pragma unroll
+  for (int kk = 0; kk < TS / 4; ++kk) {
+    acc.c[0][0] = mfma4(a0[kk], b0[kk], acc.c[0][0]);
+    acc.c[0][1] = mfma4(a0[kk], b1[kk], acc.c[0][1]);
+    acc.c[1][0] = mfma4(a1[kk], b0[kk], acc.c[1][0]);
+    acc.c[1][1] = mfma4(a1[kk], b1[kk], acc.c[1][1]);
+  }
+  acc_to_lds(sC, acc, T(1), true);
+  // every wave has read its operands from C before C is overwritten
   __syncthreads();
-  acc_to_lds(sA, acc, T(1), true);
-  __syncthreads();
-  for (int e = threadIdx.x; e < TS2; e += 256) C[e] = sA[(e >> 6) * LD + (e & 63)];
+  for (int e = threadIdx.x; e < TS2; e += 256) C[e] = sC[(e >> 6) * LD + (e & 63)];
 }
 
 // One tile of the inverse W of a Cholesky factor (interface, or interior with
