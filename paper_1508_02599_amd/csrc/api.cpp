@@ -682,7 +682,7 @@ feti_status setup_device(feti_problem* p) {
           const int off = L.kind == K_UPD_TRTRI_INT ? 0 : si.nt_i;
           const double ri = real(si, off + t.i), rj = real(si, off + t.j);
           double inner = 0.0;
-          for (int q = t.j; q < t.i; ++q) inner += real(si, off + q);
+          for (int q = t.k0; q < t.i; ++q) inner += real(si, off + q);
           fl += 2.0 * ri * rj * inner + 2.0 * ri * ri * rj;
         }
       }

@@ -24,8 +24,10 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
                            HostPlan::Launch& lauum, HostPlan::Launch& xtiles, HostPlan::Launch& alltiles,
-                           bool interior_inverse) {
+                           bool interior_inverse, const std::vector<std::vector<int32_t>>* env) {
   const int ns = (int)subs.size();
+  // first possibly nonzero factor tile column of tile row I (0: dense)
+  auto E = [&](int s, int I) -> int { return env ? (*env)[s][I] : 0; };
   int max_i = 0, max_b = 0;
   for (const auto& s : subs) {
     max_i = std::max(max_i, s.nt_i);
@@ -35,10 +37,13 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   auto finish = [&](HostPlan::Launch& L) { L.count = (int32_t)tasks.size() - L.first; };
   // block row ib of the inverse of the interior (or interface) factor, for the
   // subdomains that have it: tasks (ib, jb), jb <= ib
+  // (W_ij sums L_ik W_kj over k in [k0, i): for the interior factor, the
+  // terms left of row ib's envelope are zero; every task still writes its tile)
   auto inverse_row = [&](int ib, bool interior_part) {
     for (int s = 0; s < ns; ++s)
       if ((interior_part ? subs[s].nt_i : subs[s].nt_b) > ib)
-        for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
+        for (int jb = 0; jb <= ib; ++jb)
+          tasks.push_back({s, ib, jb, jb < ib && interior_part ? std::max(jb, E(s, ib)) : jb, ib});
   };
   // the wide form of an update launch: consecutive tasks of one subdomain and
   // column with adjacent rows become one two-tile task; the diagonal tasks
@@ -85,11 +90,13 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     widen(L);
   };
   // stage 1: interior columns, left-looking (rows run over every tile row
-  // below).  Column step j > 0 is one update launch and the panel solve.  The
-  // launch's first tasks take the diagonal tiles: the last update term
-  // (k = j - 1), factorisation and inverse; the others update the tiles below
-  // (and subtract the terms k < j of diagonal tile j + 1, so that the
-  // diagonal tasks of the next step carry one term only).
+  // below that is not left of its envelope).  Column step j > 0 is one update
+  // launch and the panel solve.  The launch's first tasks take the diagonal
+  // tiles: the last update term (k = j - 1, unless left of the envelope),
+  // factorisation and inverse; the others update the tiles below (and
+  // subtract the terms k < j of diagonal tile j + 1, so that the diagonal
+  // tasks of the next step carry one term at most).  Update terms run from
+  // the later envelope of the two tile rows; tasks left with none are dropped.
   for (int j = 0; j < max_i; ++j) {
     if (j == 0) {
       auto D = begin(K_DIAG);
@@ -100,12 +107,15 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     } else {
       auto L = begin(K_UPDATE);
       for (int s = 0; s < ns; ++s)
-        if (subs[s].nt_i > j) tasks.push_back({s, j, j, j - 1, j});
+        if (subs[s].nt_i > j) tasks.push_back({s, j, j, std::max(j - 1, E(s, j)), j});
       L.ndiag = (int32_t)tasks.size() - L.first;
       for (int s = 0; s < ns; ++s)
         if (subs[s].nt_i > j) {
-          for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, j});
-          if (subs[s].nt_i > j + 1) tasks.push_back({s, j + 1, j + 1, 0, j});
+          for (int i = j + 1; i < subs[s].nt; ++i) {
+            const int k0 = std::max(E(s, i), E(s, j));
+            if (E(s, i) <= j && k0 < j) tasks.push_back({s, i, j, k0, j});
+          }
+          if (subs[s].nt_i > j + 1 && E(s, j + 1) < j) tasks.push_back({s, j + 1, j + 1, E(s, j + 1), j});
         }
       if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
       else plain(L);
@@ -114,7 +124,8 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     auto T = begin(K_TRSM);
     for (int s = 0; s < ns; ++s)
       if (subs[s].nt_i > j)
-        for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, 0, 0});
+        for (int i = j + 1; i < subs[s].nt; ++i)
+          if (E(s, i) <= j) tasks.push_back({s, i, j, 0, 0});
     finish(T);
     interior.push_back(T);
   }
@@ -124,7 +135,10 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   for (int s = 0; s < ns; ++s)
     if (subs[s].nt_i > 0)
       for (int J = subs[s].nt_i; J < subs[s].nt; ++J)
-        for (int I = J; I < subs[s].nt; ++I) tasks.push_back({s, I, J, 0, subs[s].nt_i});
+        for (int I = J; I < subs[s].nt; ++I) {
+          const int k0 = std::max(E(s, I), E(s, J));
+          if (k0 < subs[s].nt_i) tasks.push_back({s, I, J, k0, subs[s].nt_i});
+        }
   if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
   else plain(schur);
   // stage 4: interface columns (updates only over interface columns), each
@@ -683,8 +697,21 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     }
     P.qp_ptr.push_back((int32_t)P.qe_bs.size());
   }
+  // tile envelope of every local stiffness (arena order): the first tile
+  // column with an entry of the assembled sparse rows of each tile row
+  std::vector<std::vector<int32_t>> env(ns);
+  for (int s = 0; s < ns; ++s) {
+    const SubInfo& si = P.sub[s];
+    env[s].resize(si.nt);
+    for (int I = 0; I < si.nt; ++I) env[s][I] = I;
+    for (int r = 0; r < si.nt * TS; ++r)
+      for (int k = 0; k < ELLW; ++k) {
+        const int c = P.ell_col[(int64_t)k * P.NF + si.full_off + r];
+        if (c >= 0) env[s][r / TS] = std::min(env[s][r / TS], c / TS);
+      }
+  }
   build_factor_schedule(P.sub, P.tasks, P.sched_interior, P.sched_schur, P.sched_iface, P.sched_trtri,
-                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles, true);
+                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles, true, &env);
   return "";
 }
 

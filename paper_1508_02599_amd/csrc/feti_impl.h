@@ -152,10 +152,15 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);
 // (interior/interface tile counts) into P-like containers.
 // interior_inverse: also compute the inverse of the interior factor, its
 // block rows fused into the interior updates.
+// env (optional): env[s][I] = first tile column holding a nonzero of matrix s
+// in tile row I.  A Cholesky factor has no nonzero left of the first nonzero
+// of its row in the matrix, so factor tiles left of env stay zero: the
+// interior and Schur steps skip them and every product with them.
 void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& tasks,
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
                            HostPlan::Launch& lauum, HostPlan::Launch& xtiles,
-                           HostPlan::Launch& alltiles, bool interior_inverse = false);
+                           HostPlan::Launch& alltiles, bool interior_inverse = false,
+                           const std::vector<std::vector<int32_t>>* env = nullptr);
 
 }  // namespace feti

@@ -618,7 +618,8 @@ __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
 
 // One tile of the inverse W of a Cholesky factor (interface, or interior with
 // `interior`), block row i given rows < i (tile indices local to the block):
-// W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik W_kj for j < i.
+// W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=k0}^{i-1} L_ik W_kj for j < i,
+// where k0 >= j skips the tiles L_ik that are zero (k0 = j: all terms).
 template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
                            const T* __restrict__ linv, T* W, int interior, T* sA, T* sB) {
@@ -635,9 +636,11 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   Acc<T> acc;
   acc.zero();
   TileRegs<T> ra, rb;
-  ra.fetch(Lbase + tidx(ni + t.i, ni + t.j) * TS2);
-  rb.fetch(Wbase + tidx(t.j, t.j) * TS2);
-  for (int k = t.j; k < t.i; ++k) {
+  if (t.k0 < t.i) {
+    ra.fetch(Lbase + tidx(ni + t.i, ni + t.k0) * TS2);
+    rb.fetch(Wbase + tidx(t.k0, t.j) * TS2);
+  }
+  for (int k = t.k0; k < t.i; ++k) {
     ra.template store<false>(sA);
     rb.template store<true>(sB);
     __syncthreads();
