@@ -72,6 +72,7 @@ struct feti_problem {
   uint8_t* d_dmask = nullptr;
   int32_t *d_ps_a = nullptr, *d_ps_b = nullptr, *d_ps_nbr = nullptr, *d_ps_c0 = nullptr, *d_ps_c1 = nullptr;
   int32_t *d_pc_e = nullptr, *d_pc_ab = nullptr, *d_diag_slot = nullptr, *d_ell_col = nullptr;
+  int32_t* d_env = nullptr;   // tile envelopes of the local matrices
   int32_t *d_fpos_lnode = nullptr, *d_f_sub = nullptr;
   int8_t* d_fpos_comp = nullptr;
   int32_t *d_uc_ptr = nullptr, *d_pf_ptr = nullptr, *d_pf_ent = nullptr;
@@ -268,11 +269,11 @@ void kpinv_t(feti_problem* p, const double* g, double* z) {
   const T* A = (const T*)p->d_arena;
   const T* Wi = (const T*)p->d_Wi;
   hipStream_t st = p->stream;
-  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
-  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
-  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
-  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
   vec_set_b2f(p->di, p->d_kb2, z, st);
 }
 
@@ -293,8 +294,8 @@ void kpinv_recover_t(feti_problem* p, const double* xb, double* z) {
   hipStream_t st = p->stream;
   vec_axpby(P.NB, -1.0, xb, 1.0, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
-  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
-  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
   vec_set_b2f(p->di, p->d_kb2, z, st);
 }
 
@@ -306,8 +307,8 @@ void kpinv_b_t(feti_problem* p, const double* g, double* zb) {
   const T* A = (const T*)p->d_arena;
   const T* Wi = (const T*)p->d_Wi;
   hipStream_t st = p->stream;
-  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
-  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, zb, nullptr, 0);
 }
 void kpinv_b(feti_problem* p, const double* g, double* zb) {
@@ -436,6 +437,7 @@ feti_status setup_device(feti_problem* p) {
   p->di.NF = P.NF;
   p->di.n_lam = P.n_lam;
   TRY(upload(p, p->d_sub, P.sub));
+  TRY(upload(p, p->d_env, P.env));
   TRY(upload(p, p->d_tasks, P.tasks));
   TRY(upload(p, p->d_xyz, P.xyz));
   TRY(upload(p, p->d_hex8, P.hex8));

@@ -700,8 +700,9 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   // tile envelope of every local stiffness (arena order): the first tile
   // column with an entry of the assembled sparse rows of each tile row
   std::vector<std::vector<int32_t>> env(ns);
+  P.env.clear();
   for (int s = 0; s < ns; ++s) {
-    const SubInfo& si = P.sub[s];
+    SubInfo& si = P.sub[s];
     env[s].resize(si.nt);
     for (int I = 0; I < si.nt; ++I) env[s][I] = I;
     for (int r = 0; r < si.nt * TS; ++r)
@@ -709,6 +710,8 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
         const int c = P.ell_col[(int64_t)k * P.NF + si.full_off + r];
         if (c >= 0) env[s][r / TS] = std::min(env[s][r / TS], c / TS);
       }
+    si.env_off = (int32_t)P.env.size();
+    P.env.insert(P.env.end(), env[s].begin(), env[s].end());
   }
   build_factor_schedule(P.sub, P.tasks, P.sched_interior, P.sched_schur, P.sched_iface, P.sched_trtri,
                         P.sched_lauum, P.sched_xtiles, P.sched_alltiles, true, &env);

@@ -35,6 +35,7 @@ struct SubInfo {
   int32_t n_modes;      // kernel dimension used (0, 3..6)
   int32_t coarse_off;   // first coarse index of this subdomain
   int32_t n_if;         // interface DOFs (with multipliers): the first n_if of the trailing block
+  int32_t env_off;      // offset of its tile envelope (first nonzero tile column of each tile row)
   int64_t tile_off;     // element offset into the factor arena
   int64_t linv_off;     // element offset into the diagonal-inverse arena
   int64_t x_off;        // element offset into the interface arenas (X, W, S)
@@ -71,6 +72,7 @@ struct HostPlan {
 
   // ---- subdomains
   std::vector<SubInfo> sub;
+  std::vector<int32_t> env;             // tile envelopes of the local matrices, sub[s].env_off onwards
   int64_t n_loc_nodes = 0;              // total local nodes
   std::vector<int64_t> loc_node;        // [n_loc_nodes] global node
   std::vector<int32_t> loc_pos;         // [3*n_loc_nodes] position in local full space, -1 eliminated

@@ -84,8 +84,8 @@ void vec_fill(int64_t n, double v, double* y, hipStream_t s);
 void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s);
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
 template <typename T>
-void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const T* arena, const T* Wi,
-                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s);
+void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
+                    const T* Wi, const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s);
 void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s);
 // fused iteration kernels
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,

@@ -832,12 +832,15 @@ __global__ void k_distribute(int64_t NF, const int32_t* __restrict__ fpos_lnode,
 //   z_I = Wi^T t_I.
 // Each launch runs one workgroup per (tile row or column, subdomain); tile
 // reads are coalesced columns and each workgroup reduces once at the end.
+// Modes 1 and 2 skip the factor tiles L(nt_i+I, J) left of tile row nt_i+I's
+// envelope (env: first nonzero tile column per tile row), which are zero.
 //   mode 0: y_I = sum_{J<=I} Wi(I,J) x_J                 (rows I < nt_i)
 //   mode 1: yb_I = base_b - sum_{J<nt_i} L(nt_i+I, J) x_J   (rows I < nt_b)
 //   mode 2: y_I = base_I - sum_{J<nt_b} L(nt_i+J, I)^T xb_J (cols I < nt_i)
 //   mode 3: y_I = sum_{J>=I} Wi(J,I)^T x_J               (cols I < nt_i)
 template <typename T>
 __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __restrict__ subs,
+                                                  const int32_t* __restrict__ env,
                                                   const T* __restrict__ arena, const T* __restrict__ Wi,
                                                   const double* __restrict__ x, const double* __restrict__ xb,
                                                   const double* __restrict__ base, double* y, double* yb) {
@@ -852,10 +855,11 @@ __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __res
   double acc = 0.0;
   int j0, j1;
   if (mode == 0) { j0 = 0; j1 = I + 1; }
-  else if (mode == 1) { j0 = 0; j1 = s.nt_i; }
+  else if (mode == 1) { j0 = min(env[s.env_off + s.nt_i + I], s.nt_i); j1 = s.nt_i; }
   else if (mode == 2) { j0 = 0; j1 = s.nt_b; }
   else { j0 = I; j1 = s.nt_i; }
   for (int J = j0; J < j1; ++J) {
+    if (mode == 2 && env[s.env_off + s.nt_i + J] > I) continue;
     const T* tile;
     const double* xs;
     if (mode == 0) { tile = Wi + s.wi_off + tidx2(I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
@@ -1023,13 +1027,17 @@ void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t
 }
 
 template <typename T>
-void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const T* arena, const T* Wi,
-                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s) {
+void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
+                    const T* Wi, const double* x, const double* xb, const double* base, double* y, double* yb,
+                    hipStream_t s) {
   if (max_rows > 0)
-    hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, arena, Wi, x, xb, base, y, yb);
+    hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, env, arena, Wi, x, xb,
+                       base, y, yb);
 }
-template void local_kp_tiles<double>(int, int, int, const SubInfo*, const double*, const double*, const double*, const double*, const double*, double*, double*, hipStream_t);
-template void local_kp_tiles<float>(int, int, int, const SubInfo*, const float*, const float*, const double*, const double*, const double*, double*, double*, hipStream_t);
+template void local_kp_tiles<double>(int, int, int, const SubInfo*, const int32_t*, const double*, const double*,
+                                     const double*, const double*, const double*, double*, double*, hipStream_t);
+template void local_kp_tiles<float>(int, int, int, const SubInfo*, const int32_t*, const float*, const float*,
+                                    const double*, const double*, const double*, double*, double*, hipStream_t);
 void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_set_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, full);
 }
