@@ -84,7 +84,7 @@ struct feti_problem {
   // assembly / factor data
   double *d_Ke = nullptr, *d_fint = nullptr, *d_fbody = nullptr, *d_ell_val = nullptr, *d_U = nullptr;
   double *d_fnodal = nullptr;
-  void *d_arena = nullptr, *d_linv = nullptr, *d_W = nullptr, *d_X = nullptr, *d_S = nullptr, *d_Wi = nullptr;
+  void *d_arena = nullptr, *d_linv = nullptr, *d_W = nullptr, *d_X = nullptr, *d_S = nullptr;
   double *d_t = nullptr, *d_kb1 = nullptr, *d_kb2 = nullptr, *d_bb_val = nullptr;
   int32_t *d_bb_slot = nullptr, *d_bb_col = nullptr;
   double *d_rfull = nullptr, *d_rb = nullptr, *d_work = nullptr, *d_rho = nullptr, *d_wbm = nullptr;
@@ -201,8 +201,7 @@ void dense(feti_problem* p, const HostPlan::Launch& L) {
   hipStream_t stream = p->stream;
   const bool upd = is_update_kind(L.kind) && L.count > 0;
   const bool timed = p->profile && upd && 2 * p->n_upd_recorded + 1 < (int)p->ev_upd.size();
-  // the interior inverse goes to its own arena
-  void* W = (L.kind == K_TRTRI_INT || L.kind == K_UPD_TRTRI_INT) ? p->d_Wi : p->d_W;
+  void* W = p->d_W;
   int form = 0, idx = -1;
   if (upd && p->autotune && (idx = update_index(p, L)) >= 0 && L.wcount > 0)
     form = p->tune_phase < feti_problem::kForms ? p->tune_phase : p->use_form[idx];
@@ -262,18 +261,17 @@ void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, co
                      p->di.b_sub, yb, st, p->stream, iface_only);
 }
 
-// z = K^+ g for every subdomain (full local vectors), see k_kp_tiles.
+// z = K^+ g for every subdomain (full local vectors), see k_kp_band and k_kp_tiles.
 template <typename T>
 void kpinv_t(feti_problem* p, const double* g, double* z) {
   const HostPlan& P = p->P;
   const T* A = (const T*)p->d_arena;
-  const T* Wi = (const T*)p->d_Wi;
   hipStream_t st = p->stream;
-  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
-  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  local_kp_band<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, (const T*)p->d_linv, g, p->d_w, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
-  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
-  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_band<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, (const T*)p->d_linv, p->d_t, z, st);
   vec_set_b2f(p->di, p->d_kb2, z, st);
 }
 
@@ -290,12 +288,11 @@ template <typename T>
 void kpinv_recover_t(feti_problem* p, const double* xb, double* z) {
   const HostPlan& P = p->P;
   const T* A = (const T*)p->d_arena;
-  const T* Wi = (const T*)p->d_Wi;
   hipStream_t st = p->stream;
   vec_axpby(P.NB, -1.0, xb, 1.0, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, p->d_kb2, nullptr, 0);
-  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
-  local_kp_tiles<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, p->d_t, nullptr, nullptr, z, nullptr, st);
+  local_kp_tiles<T>(2, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, nullptr, p->d_kb2, p->d_w, p->d_t, nullptr, st);
+  local_kp_band<T>(3, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, (const T*)p->d_linv, p->d_t, z, st);
   vec_set_b2f(p->di, p->d_kb2, z, st);
 }
 
@@ -305,10 +302,9 @@ template <typename T>
 void kpinv_b_t(feti_problem* p, const double* g, double* zb) {
   const HostPlan& P = p->P;
   const T* A = (const T*)p->d_arena;
-  const T* Wi = (const T*)p->d_Wi;
   hipStream_t st = p->stream;
-  local_kp_tiles<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, Wi, g, nullptr, nullptr, p->d_w, nullptr, st);
-  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, Wi, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
+  local_kp_band<T>(0, P.n_sub, P.max_nt_i, p->d_sub, p->d_env, A, (const T*)p->d_linv, g, p->d_w, st);
+  local_kp_tiles<T>(1, P.n_sub, P.max_nt_b, p->d_sub, p->d_env, A, p->d_w, nullptr, g, nullptr, p->d_kb1, st);
   symv_local(p, p->d_X, p->d_kb1, zb, nullptr, 0);
 }
 void kpinv_b(feti_problem* p, const double* g, double* zb) {
@@ -537,9 +533,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_U, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_fnodal, (size_t)P.n_dof));
   {
-    char *a, *l, *w, *x, *s = nullptr, *wi;
-    TRY(dalloc(p, wi, (size_t)P.n_witiles * e));
-    p->d_Wi = wi;
+    char *a, *l, *w, *x, *s = nullptr;
     TRY(dalloc(p, a, (size_t)P.n_tiles * e));
     TRY(dalloc(p, l, (size_t)P.n_linv * e));
     TRY(dalloc(p, w, (size_t)P.n_xtiles * e));
@@ -680,8 +674,8 @@ feti_status setup_device(feti_problem* p) {
           fl += (t.i == t.j ? ri * (ri + 1.0) : 2.0 * ri * rj) * inner;
         } else if (t.i != t.j) {
           // inverse row: sum_k L_ik W_kj, then L_ii^{-1} times it (tile indices
-          // local to the interior or the interface block)
-          const int off = L.kind == K_UPD_TRTRI_INT ? 0 : si.nt_i;
+          // local to the interface block)
+          const int off = si.nt_i;
           const double ri = real(si, off + t.i), rj = real(si, off + t.j);
           double inner = 0.0;
           for (int q = t.k0; q < t.i; ++q) inner += real(si, off + q);

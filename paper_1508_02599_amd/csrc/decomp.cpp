@@ -24,7 +24,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
                            HostPlan::Launch& lauum, HostPlan::Launch& xtiles, HostPlan::Launch& alltiles,
-                           bool interior_inverse, const std::vector<std::vector<int32_t>>* env) {
+                           const std::vector<std::vector<int32_t>>* env) {
   const int ns = (int)subs.size();
   // first possibly nonzero factor tile column of tile row I (0: dense)
   auto E = [&](int s, int I) -> int { return env ? (*env)[s][I] : 0; };
@@ -35,15 +35,12 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   }
   auto begin = [&](int kind) { return HostPlan::Launch{kind, (int32_t)tasks.size(), 0}; };
   auto finish = [&](HostPlan::Launch& L) { L.count = (int32_t)tasks.size() - L.first; };
-  // block row ib of the inverse of the interior (or interface) factor, for the
-  // subdomains that have it: tasks (ib, jb), jb <= ib
-  // (W_ij sums L_ik W_kj over k in [k0, i): for the interior factor, the
-  // terms left of row ib's envelope are zero; every task still writes its tile)
-  auto inverse_row = [&](int ib, bool interior_part) {
+  // block row ib of the inverse of the interface factor, for the subdomains
+  // that have it: tasks (ib, jb), jb <= ib (the interface block is dense)
+  auto inverse_row = [&](int ib) {
     for (int s = 0; s < ns; ++s)
-      if ((interior_part ? subs[s].nt_i : subs[s].nt_b) > ib)
-        for (int jb = 0; jb <= ib; ++jb)
-          tasks.push_back({s, ib, jb, jb < ib && interior_part ? std::max(jb, E(s, ib)) : jb, ib});
+      if (subs[s].nt_b > ib)
+        for (int jb = 0; jb <= ib; ++jb) tasks.push_back({s, ib, jb, jb, ib});
   };
   // the wide form of an update launch: consecutive tasks of one subdomain and
   // column with adjacent rows become one two-tile task; the diagonal tasks
@@ -75,9 +72,9 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   };
   // update launch of a column step, with the previous block row of the
   // inverse appended (its inputs are final once that column step is done)
-  auto fused = [&](HostPlan::Launch& L, int kind_fused, int row, bool interior_part) {
+  auto fused = [&](HostPlan::Launch& L, int kind_fused, int row) {
     const int32_t nupd = (int32_t)tasks.size() - L.first;
-    inverse_row(row, interior_part);
+    inverse_row(row);
     finish(L);
     if (L.count > nupd) {
       L.kind = kind_fused;
@@ -117,8 +114,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
           }
           if (subs[s].nt_i > j + 1 && E(s, j + 1) < j) tasks.push_back({s, j + 1, j + 1, E(s, j + 1), j});
         }
-      if (interior_inverse) fused(L, K_UPD_TRTRI_INT, j - 1, true);
-      else plain(L);
+      plain(L);
       interior.push_back(L);
     }
     auto T = begin(K_TRSM);
@@ -129,8 +125,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     finish(T);
     interior.push_back(T);
   }
-  // stage 2: Schur complement of the interior on every interface tile (with
-  // the last block row of the interior inverse)
+  // stage 2: Schur complement of the interior on every interface tile
   schur = begin(K_UPDATE);
   for (int s = 0; s < ns; ++s)
     if (subs[s].nt_i > 0)
@@ -139,8 +134,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
           const int k0 = std::max(E(s, I), E(s, J));
           if (k0 < subs[s].nt_i) tasks.push_back({s, I, J, k0, subs[s].nt_i});
         }
-  if (interior_inverse && max_i > 0) fused(schur, K_UPD_TRTRI_INT, max_i - 1, true);
-  else plain(schur);
+  plain(schur);
   // stage 4: interface columns (updates only over interface columns), each
   // update launch carrying the diagonal tasks of its column, as in stage 1,
   // and the previous block row of the interface inverse
@@ -165,7 +159,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
           for (int i = j + 1; i < subs[s].nt; ++i) tasks.push_back({s, i, j, subs[s].nt_i, j});
           if (subs[s].nt_b > jb + 1) tasks.push_back({s, j + 1, j + 1, subs[s].nt_i, j});
         }
-      fused(L, K_UPD_TRTRI, jb - 1, false);
+      fused(L, K_UPD_TRTRI, jb - 1);
       iface.push_back(L);
     }
     auto T = begin(K_TRSM);
@@ -180,7 +174,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
   // stage 5: the last block row of the interface inverse
   if (max_b > 0) {
     auto L = begin(K_TRTRI);
-    inverse_row(max_b - 1, false);
+    inverse_row(max_b - 1);
     finish(L);
     trtri.push_back(L);
   }
@@ -394,7 +388,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   }
   // ---- interior-first positions
   P.loc_pos.assign(3 * P.n_loc_nodes, -1);
-  int64_t tile_off = 0, linv_off = 0, x_off = 0, full_off = 0, b_off = 0, part_off = 0, wi_off = 0;
+  int64_t tile_off = 0, linv_off = 0, x_off = 0, full_off = 0, b_off = 0, part_off = 0;
   for (int s = 0; s < ns; ++s) {
     SubInfo& si = P.sub[s];
     int n_ii = 0, n_b = 0;
@@ -443,8 +437,6 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     si.full_off = full_off;
     si.b_off = b_off;
     si.part_off = part_off;
-    si.wi_off = wi_off;
-    wi_off += (int64_t)si.nt_i * (si.nt_i + 1) / 2 * TS2;
     tile_off += (int64_t)si.nt * (si.nt + 1) / 2 * TS2;
     linv_off += (int64_t)si.nt * TS2;
     x_off += (int64_t)si.nt_b * (si.nt_b + 1) / 2 * TS2;
@@ -460,7 +452,6 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   P.NF = full_off;
   P.NB = b_off;
   P.n_part = part_off;
-  P.n_witiles = wi_off;
   if (P.NB >= ((int64_t)1 << 31) || P.n_lam >= ((int64_t)1 << 31)) return "problem too large";
   P.fpos_lnode.assign(P.NF, -1);
   P.fpos_comp.assign(P.NF, 0);
@@ -714,7 +705,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     P.env.insert(P.env.end(), env[s].begin(), env[s].end());
   }
   build_factor_schedule(P.sub, P.tasks, P.sched_interior, P.sched_schur, P.sched_iface, P.sched_trtri,
-                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles, true, &env);
+                        P.sched_lauum, P.sched_xtiles, P.sched_alltiles, &env);
   return "";
 }
 

@@ -39,7 +39,6 @@ struct SubInfo {
   int64_t tile_off;     // element offset into the factor arena
   int64_t linv_off;     // element offset into the diagonal-inverse arena
   int64_t x_off;        // element offset into the interface arenas (X, W, S)
-  int64_t wi_off;       // element offset into the interior-inverse arena
   int64_t full_off;     // offset of the local vector in full-space vectors
   int64_t b_off;        // offset of the interface part in b-space vectors
   int64_t part_off;     // offset into interface GEMV partial sums
@@ -82,7 +81,7 @@ struct HostPlan {
   std::vector<int8_t> fpos_comp;        // [NF] component of a full-space position
   std::vector<int32_t> f_sub;           // [NF] subdomain of a full-space position
   int64_t NF = 0, NB = 0;               // full-space and b-space lengths
-  int64_t n_tiles = 0, n_xtiles = 0, n_linv = 0, n_part = 0, n_witiles = 0;
+  int64_t n_tiles = 0, n_xtiles = 0, n_linv = 0, n_part = 0;
 
   // ---- assembly gather (node pairs inside a subdomain)
   std::vector<int32_t> ps_a, ps_b, ps_nbr, ps_c0, ps_c1;   // per pair slot (a,b: local-node index incl. node_off)
@@ -143,17 +142,15 @@ struct HostPlan {
   int max_nt_i = 0, max_nt_b = 0;
 };
 
-enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4, K_TRTRI_INT = 5,
-                  K_UPD_TRTRI = 6, K_UPD_TRTRI_INT = 7 };   // update tasks, then rows of the inverse
-inline bool is_update_kind(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI || kind == K_UPD_TRTRI_INT; }
+enum LaunchKind { K_UPDATE = 0, K_DIAG = 1, K_TRSM = 2, K_TRTRI = 3, K_LAUUM = 4,
+                  K_UPD_TRTRI = 5 };   // update tasks, then rows of the interface inverse
+inline bool is_update_kind(int kind) { return kind == K_UPDATE || kind == K_UPD_TRTRI; }
 
 // Builds the plan; returns an empty string on success, else an error message.
 std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P);
 
 // Appends the factor schedule of a batch of matrices described by `subs`
 // (interior/interface tile counts) into P-like containers.
-// interior_inverse: also compute the inverse of the interior factor, its
-// block rows fused into the interior updates.
 // env (optional): env[s][I] = first tile column holding a nonzero of matrix s
 // in tile row I.  A Cholesky factor has no nonzero left of the first nonzero
 // of its row in the matrix, so factor tiles left of env stay zero: the
@@ -162,7 +159,7 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
                            std::vector<HostPlan::Launch>& interior, HostPlan::Launch& schur,
                            std::vector<HostPlan::Launch>& iface, std::vector<HostPlan::Launch>& trtri,
                            HostPlan::Launch& lauum, HostPlan::Launch& xtiles,
-                           HostPlan::Launch& alltiles, bool interior_inverse = false,
+                           HostPlan::Launch& alltiles,
                            const std::vector<std::vector<int32_t>>* env = nullptr);
 
 }  // namespace feti

@@ -216,7 +216,7 @@ __device__ __forceinline__ void update_tile(const Task& t, const SubInfo* __rest
 
 template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
-                           const T* __restrict__ linv, T* W, int interior, T* sA, T* sB);
+                           const T* __restrict__ linv, T* W, T* sA, T* sB);
 
 // Blocked factorisation of a diagonal tile (diag_block): 16x16 blocks.
 constexpr int DB = 16;
@@ -244,7 +244,7 @@ __device__ __forceinline__ void diag_block(const Task& t, const SubInfo* __restr
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                 const SubInfo* __restrict__ subs, T* arena,
-                                                T* linv, T* W, int interior, int* err) {
+                                                T* linv, T* W, int* err) {
   __shared__ double smem[smem_doubles<T>(2 * TS * LD)];
   T* sA = reinterpret_cast<T*>(smem);
   T* sB = sA + TS * LD;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_update(const Task* __restrict__ tasks, 
   const int b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
   const Task t = tasks[b];
   if (b < n_upd) update_tile<T>(t, subs, arena, sA, sB);
-  else trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
+  else trtri_tile<T>(t, subs, arena, linv, W, sA, sB);
 }
 
 // Copy N consecutive elements from global memory into LDS unchanged
@@ -297,7 +297,7 @@ struct UpdOcc { static constexpr int waves = sizeof(T) == 4 ? 3 : 2; };
 template <typename T, int KC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                    const SubInfo* __restrict__ subs, T* arena,
-                                                   T* linv, T* W, int interior, int* err) {
+                                                   T* linv, T* W, int* err) {
   constexpr int CH = TS * KC;                 // elements per chunk
   constexpr int PARTS = TS / KC;              // chunks per tile
   constexpr int NLDS = 4 * CH > 2 * TS * LD ? 4 * CH : 2 * TS * LD;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::
   const int b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
   const Task t = tasks[b];
   if (b >= n_upd) {
-    trtri_tile<T>(t, subs, arena, linv, W, interior, lds, lds + TS * LD);
+    trtri_tile<T>(t, subs, arena, linv, W, lds, lds + TS * LD);
     return;
   }
   T* base = arena + subs[t.sub].tile_off;
@@ -616,17 +616,17 @@ __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
   for (int e = threadIdx.x; e < TS2; e += 256) C[e] = sC[(e >> 6) * LD + (e & 63)];
 }
 
-// One tile of the inverse W of a Cholesky factor (interface, or interior with
-// `interior`), block row i given rows < i (tile indices local to the block):
-// W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=k0}^{i-1} L_ik W_kj for j < i,
-// where k0 >= j skips the tiles L_ik that are zero (k0 = j: all terms).
+// One tile of the inverse W of the interface factor, block row i given rows
+// < i (tile indices local to the interface block):
+// W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=k0}^{i-1} L_ik W_kj for j < i
+// (the tasks carry k0 = j: all terms).
 template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
-                           const T* __restrict__ linv, T* W, int interior, T* sA, T* sB) {
+                           const T* __restrict__ linv, T* W, T* sA, T* sB) {
   const SubInfo s = subs[t.sub];
-  const int ni = interior ? 0 : s.nt_i;
+  const int ni = s.nt_i;
   const T* Lbase = arena + s.tile_off;
-  T* Wbase = W + (interior ? s.wi_off : s.x_off);
+  T* Wbase = W + s.x_off;
   T* out = Wbase + tidx(t.i, t.j) * TS2;
   const T* Lii_inv = linv + s.linv_off + (int64_t)(ni + t.i) * TS2;
   if (t.i == t.j) {
@@ -668,10 +668,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
                                                const SubInfo* __restrict__ subs,
                                                const T* __restrict__ arena,
-                                               const T* __restrict__ linv, T* W, int interior) {
+                                               const T* __restrict__ linv, T* W) {
   __shared__ T sA[TS * LD], sB[TS * LD];
   const Task t = tasks[xcd_task()];
-  trtri_tile<T>(t, subs, arena, linv, W, interior, sA, sB);
+  trtri_tile<T>(t, subs, arena, linv, W, sA, sB);
 }
 
 // X_IJ = sum_{k>=I} W_kI^T W_kJ  (I >= J): X = W^T W = (L L^T)^{-1}.
@@ -908,12 +908,11 @@ template <typename T>
 void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T* arena, T* linv,
                   T* W, T* X, int* err, hipStream_t st, int split, int form, int ndiag) {
   if (count <= 0) return;
-  const int interior = (kind == K_UPD_TRTRI_INT || kind == K_TRTRI_INT) ? 1 : 0;
   if (is_update_kind(kind)) {
     const int nupd = kind == K_UPDATE ? count : split;   // diagonal and update tasks
     if (form == 2) {
       hipLaunchKernelGGL((k_update_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena,
-                         linv, W, interior, err);
+                         linv, W, err);
     } else if (form == 1) {
       // the task list is the wide form: diagonal tasks, two-tile updates, inverse rows
       if (ndiag > 0) hipLaunchKernelGGL(k_diag<T>, dim3(ndiag), dim3(256), 0, st, tasks, subs, arena, linv, err);
@@ -921,10 +920,9 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
         hipLaunchKernelGGL(k_update_wide<T>, dim3(nupd - ndiag), dim3(512), 0, st, tasks + ndiag, subs, arena);
       if (count > nupd)
         hipLaunchKernelGGL(k_trtri<T>, dim3(count - nupd), dim3(256), 0, st, tasks + nupd, subs, (const T*)arena,
-                           (const T*)linv, W, interior);
+                           (const T*)linv, W);
     } else {
-      hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena, linv, W,
-                         interior, err);
+      hipLaunchKernelGGL(k_update<T>, dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena, linv, W, err);
     }
     return;
   }
@@ -932,9 +930,7 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
     case K_DIAG: hipLaunchKernelGGL(k_diag<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, linv, err); break;
     case K_TRSM: hipLaunchKernelGGL(k_trsm<T>, dim3(count), dim3(256), 0, st, tasks, subs, arena, (const T*)linv); break;
     case K_TRTRI:
-    case K_TRTRI_INT:
-      hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W,
-                         interior);
+      hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W);
       break;
     case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
   }

@@ -85,7 +85,11 @@ void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipS
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
 template <typename T>
 void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
-                    const T* Wi, const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s);
+                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s);
+// Interior solves y = L_II^{-1} x (mode 0) or L_II^{-T} x (mode 3), tile by tile inside the envelope.
+template <typename T>
+void local_kp_band(int mode, int n_sub, int max_nt_i, const SubInfo* subs, const int32_t* env, const T* arena,
+                   const T* linv, const double* x, double* y, hipStream_t s);
 void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s);
 // fused iteration kernels
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,

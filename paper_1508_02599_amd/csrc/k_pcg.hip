@@ -826,22 +826,20 @@ __global__ void k_distribute(int64_t NF, const int32_t* __restrict__ fpos_lnode,
 
 // ---------------------------------------------------------------------------
 // Local generalised inverse z = K^+ g on the full local vector of each
-// subdomain, by the block formula of the interior-first elimination with the
-// explicit inverse Wi = L_II^{-1} of the interior factor:
-//   w_I = Wi g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,  t_I = w_I - L_bI^T z_b,
-//   z_I = Wi^T t_I.
-// Each launch runs one workgroup per (tile row or column, subdomain); tile
-// reads are coalesced columns and each workgroup reduces once at the end.
-// Modes 1 and 2 skip the factor tiles L(nt_i+I, J) left of tile row nt_i+I's
-// envelope (env: first nonzero tile column per tile row), which are zero.
-//   mode 0: y_I = sum_{J<=I} Wi(I,J) x_J                 (rows I < nt_i)
+// subdomain, by the block formula of the interior-first elimination:
+//   w_I = L_II^{-1} g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,
+//   t_I = w_I - L_bI^T z_b,  z_I = L_II^{-T} t_I.
+// The interior solves are k_kp_band; the two products with L_bI are
+// k_kp_tiles, one workgroup per (tile row or column, subdomain); tile reads are
+// coalesced columns and each workgroup reduces once at the end.  Both skip
+// the factor tiles left of a tile row's envelope (env: first nonzero tile
+// column per tile row), which are zero.
 //   mode 1: yb_I = base_b - sum_{J<nt_i} L(nt_i+I, J) x_J   (rows I < nt_b)
 //   mode 2: y_I = base_I - sum_{J<nt_b} L(nt_i+J, I)^T xb_J (cols I < nt_i)
-//   mode 3: y_I = sum_{J>=I} Wi(J,I)^T x_J               (cols I < nt_i)
 template <typename T>
 __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __restrict__ subs,
                                                   const int32_t* __restrict__ env,
-                                                  const T* __restrict__ arena, const T* __restrict__ Wi,
+                                                  const T* __restrict__ arena,
                                                   const double* __restrict__ x, const double* __restrict__ xb,
                                                   const double* __restrict__ base, double* y, double* yb) {
   __shared__ double red[4][TS];
@@ -849,23 +847,19 @@ __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __res
   const int I = blockIdx.x;
   if (I >= (mode == 1 ? s.nt_b : s.nt_i)) return;
   const int tid = threadIdx.x;
-  const bool trans = mode >= 2;
+  const bool trans = mode == 2;
   const int a = trans ? (tid >> 2) : (tid & 63);   // output row/column handled
   const int q = trans ? (tid & 3) : (tid >> 6);     // quarter of the reduction index
   double acc = 0.0;
   int j0, j1;
-  if (mode == 0) { j0 = 0; j1 = I + 1; }
-  else if (mode == 1) { j0 = min(env[s.env_off + s.nt_i + I], s.nt_i); j1 = s.nt_i; }
-  else if (mode == 2) { j0 = 0; j1 = s.nt_b; }
-  else { j0 = I; j1 = s.nt_i; }
+  if (mode == 1) { j0 = min(env[s.env_off + s.nt_i + I], s.nt_i); j1 = s.nt_i; }
+  else { j0 = 0; j1 = s.nt_b; }
   for (int J = j0; J < j1; ++J) {
     if (mode == 2 && env[s.env_off + s.nt_i + J] > I) continue;
     const T* tile;
     const double* xs;
-    if (mode == 0) { tile = Wi + s.wi_off + tidx2(I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
-    else if (mode == 1) { tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
-    else if (mode == 2) { tile = arena + s.tile_off + tidx2(s.nt_i + J, I) * TS2; xs = xb + s.b_off + (int64_t)J * TS; }
-    else { tile = Wi + s.wi_off + tidx2(J, I) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
+    if (mode == 1) { tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
+    else { tile = arena + s.tile_off + tidx2(s.nt_i + J, I) * TS2; xs = xb + s.b_off + (int64_t)J * TS; }
     if (!trans) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) acc += (double)tile[(16 * q + k) * TS + a] * xs[16 * q + k];
@@ -878,9 +872,82 @@ __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __res
   __syncthreads();
   if (tid < TS) {
     const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    if (mode == 0 || mode == 3) y[s.full_off + (int64_t)I * TS + tid] = v;
-    else if (mode == 1) yb[s.b_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)(s.nt_i + I) * TS + tid] - v;
+    if (mode == 1) yb[s.b_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)(s.nt_i + I) * TS + tid] - v;
     else y[s.full_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)I * TS + tid] - v;
+  }
+}
+
+// Interior solves with the interior factor itself, one workgroup of 1024
+// threads per subdomain, tile by tile (no explicit inverse: the interior block
+// is banded, so each step reads the few factor tiles inside the envelope):
+//   mode 0: y = L_II^{-1} x   (forward: y_I = Linv_II (x_I - sum_{env(I)<=J<I} L_IJ y_J))
+//   mode 3: y = L_II^{-T} x   (backward: y_I = Linv_II^T (x_I - sum_{J>I, env(J)<=I} L_JI^T y_J))
+// x and y are full-space local vectors (interior tile rows only).  Each step
+// loads its Linv_II values with its band tiles (they do not depend on the
+// step's right-hand side), so a step waits for memory once.  The solved
+// segments are kept in LDS (LDSY; else read back from y after a barrier).
+constexpr int BAND_Q = 16;   // column (forward) or row (backward) groups of four per tile
+template <typename T, bool LDSY>
+__global__ __launch_bounds__(1024) void k_kp_band(int mode, const SubInfo* __restrict__ subs,
+                                                  const int32_t* __restrict__ env, const T* __restrict__ arena,
+                                                  const T* __restrict__ linv, const double* __restrict__ x,
+                                                  double* y) {
+  extern __shared__ double ylds[];   // nt_i * TS solved values (LDSY)
+  __shared__ double red[BAND_Q][TS];
+  __shared__ double rv[TS];
+  const SubInfo s = subs[blockIdx.x];
+  const int nti = s.nt_i, tid = threadIdx.x;
+  const bool fwd = mode == 0;
+  // forward: thread (a = row, q = columns 4q..4q+3); backward: (a = column, q = rows 4q..4q+3)
+  const int a = fwd ? (tid & 63) : (tid >> 4);
+  const int q = fwd ? (tid >> 6) : (tid & 15);
+  const T* Lb = arena + s.tile_off;
+  double* yg = y + s.full_off;
+  const double* yr = LDSY ? ylds : yg;
+  for (int step = 0; step < nti; ++step) {
+    const int I = fwd ? step : nti - 1 - step;
+    const T* Li = linv + s.linv_off + (int64_t)I * TS2;
+    T li[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) li[k] = fwd ? Li[(4 * q + k) * TS + a] : Li[a * TS + 4 * q + k];
+    double acc = 0.0;
+    if (fwd) {
+      for (int J = env[s.env_off + I]; J < I; ++J) {
+        const T* tile = Lb + tidx2(I, J) * TS2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += (double)tile[(4 * q + k) * TS + a] * yr[J * TS + 4 * q + k];
+      }
+    } else {
+      for (int J = I + 1; J < nti; ++J) {
+        if (env[s.env_off + J] > I) continue;
+        const T* tile = Lb + tidx2(J, I) * TS2;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += (double)tile[a * TS + 4 * q + k] * yr[J * TS + 4 * q + k];
+      }
+    }
+    red[q][a] = acc;
+    __syncthreads();
+    if (tid < TS) {
+      double sum = 0.0;
+#pragma unroll
+      for (int g = 0; g < BAND_Q; ++g) sum += red[g][tid];
+      rv[tid] = x[s.full_off + (int64_t)I * TS + tid] - sum;
+    }
+    __syncthreads();
+    double acc2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc2 += (double)li[k] * rv[4 * q + k];
+    red[q][a] = acc2;
+    __syncthreads();
+    if (tid < TS) {
+      double v = 0.0;
+#pragma unroll
+      for (int g = 0; g < BAND_Q; ++g) v += red[g][tid];
+      yg[(int64_t)I * TS + tid] = v;
+      if (LDSY) ylds[I * TS + tid] = v;
+    }
+    // the segment is visible for the next steps; red is free again
+    __syncthreads();
   }
 }
 
@@ -1028,16 +1095,29 @@ void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t
 
 template <typename T>
 void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
-                    const T* Wi, const double* x, const double* xb, const double* base, double* y, double* yb,
-                    hipStream_t s) {
+                    const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s) {
   if (max_rows > 0)
-    hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, env, arena, Wi, x, xb,
-                       base, y, yb);
+    hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, env, arena, x, xb, base,
+                       y, yb);
 }
 template void local_kp_tiles<double>(int, int, int, const SubInfo*, const int32_t*, const double*, const double*,
-                                     const double*, const double*, const double*, double*, double*, hipStream_t);
-template void local_kp_tiles<float>(int, int, int, const SubInfo*, const int32_t*, const float*, const float*,
-                                    const double*, const double*, const double*, double*, double*, hipStream_t);
+                                     const double*, const double*, double*, double*, hipStream_t);
+template void local_kp_tiles<float>(int, int, int, const SubInfo*, const int32_t*, const float*, const double*,
+                                    const double*, const double*, double*, double*, hipStream_t);
+template <typename T>
+void local_kp_band(int mode, int n_sub, int max_nt_i, const SubInfo* subs, const int32_t* env, const T* arena,
+                   const T* linv, const double* x, double* y, hipStream_t s) {
+  if (n_sub <= 0 || max_nt_i <= 0) return;
+  const size_t ybytes = (size_t)max_nt_i * TS * sizeof(double);
+  if (ybytes <= 48 * 1024)
+    hipLaunchKernelGGL((k_kp_band<T, true>), dim3(n_sub), dim3(1024), ybytes, s, mode, subs, env, arena, linv, x, y);
+  else
+    hipLaunchKernelGGL((k_kp_band<T, false>), dim3(n_sub), dim3(1024), 0, s, mode, subs, env, arena, linv, x, y);
+}
+template void local_kp_band<double>(int, int, int, const SubInfo*, const int32_t*, const double*, const double*,
+                                    const double*, double*, hipStream_t);
+template void local_kp_band<float>(int, int, int, const SubInfo*, const int32_t*, const float*, const float*,
+                                   const double*, double*, hipStream_t);
 void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_set_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, full);
 }
