@@ -57,6 +57,34 @@ __device__ __forceinline__ int xcd_split(int l, int n, int n_first) {
   return l < n_first ? xcd_map(l, n_first) : n_first + xcd_map(l - n_first, n - n_first);
 }
 
+// The elements e = threadIdx.x + NT u (u < TS2 / NT) of a tile that one thread
+// of an NT-thread block handles.  The loops below have a compile-time trip
+// count, so every load of a tile is issued before the first use; a loop
+// bounded by threadIdx.x is kept rolled and waits on each load in turn.
+// tile_rmw: C[e] = f(e, C[e]) for every element.
+template <int NT = 256, typename T, typename F>
+__device__ __forceinline__ void tile_rmw(T* C, F f) {
+  constexpr int N = TS2 / NT;
+  T c[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) c[u] = C[threadIdx.x + NT * u];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    const int e = threadIdx.x + NT * u;
+    C[e] = f(e, c[u]);
+  }
+}
+// tile_copy: dst[e] = src[e] for every element.
+template <typename T>
+__device__ __forceinline__ void tile_copy(T* dst, const T* __restrict__ src) {
+  constexpr int N = TS2 / 256;
+  T c[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) c[u] = src[threadIdx.x + 256 * u];
+#pragma unroll
+  for (int u = 0; u < N; ++u) dst[threadIdx.x + 256 * u] = c[u];
+}
+
 // LDS operand layout: s[k*LD + m] holds op(A)(m, k) (or op(B)(k, m)).
 // Tiles are read with 16-byte vector loads, all issued before any LDS store,
 // so that a workgroup keeps a whole 64x64 tile of loads in flight.
@@ -211,7 +239,7 @@ __device__ __forceinline__ void update_tile(const Task& t, const SubInfo* __rest
   acc_to_lds(sA, acc, T(-1), true);
   __syncthreads();
   T* C = base + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 256) C[e] += sA[(e >> 6) * LD + (e & 63)];
+  tile_rmw(C, [&](int e, T c) { return c + sA[(e >> 6) * LD + (e & 63)]; });
 }
 
 template <typename T>
@@ -343,7 +371,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::
   acc_to_lds(lds, acc, T(-1), true);
   __syncthreads();
   T* C = base + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 256) C[e] += lds[(e >> 6) * LD + (e & 63)];
+  tile_rmw(C, [&](int e, T c) { return c + lds[(e >> 6) * LD + (e & 63)]; });
 }
 
 // Wide form: one workgroup of eight waves updates output tiles (i, j) and
@@ -387,10 +415,10 @@ __global__ __launch_bounds__(512) void k_update_wide(const Task* __restrict__ ta
   if (active) acc_to_lds_w(h ? sA1 : sA0, acc, T(-1), true, wl);
   __syncthreads();
   T* C0 = base + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 512) C0[e] += sA0[(e >> 6) * LD + (e & 63)];
+  tile_rmw<512>(C0, [&](int e, T c) { return c + sA0[(e >> 6) * LD + (e & 63)]; });
   if (two) {
     T* C1 = base + tidx(t.i + 1, t.j) * TS2;
-    for (int e = threadIdx.x; e < TS2; e += 512) C1[e] += sA1[(e >> 6) * LD + (e & 63)];
+    tile_rmw<512>(C1, [&](int e, T c) { return c + sA1[(e >> 6) * LD + (e & 63)]; });
   }
 }
 
@@ -424,7 +452,17 @@ __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __res
   T* C = arena + s.tile_off + tidx(t.j, t.j) * TS2;
   T* Li = linv + s.linv_off + (int64_t)t.j * TS2;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < TS2; e += 256) A[(e >> 6) * LD + (e & 63)] = (double)C[e];
+  {
+    constexpr int N = TS2 / 256;
+    T c[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) c[u] = C[tid + 256 * u];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int e = tid + 256 * u;
+      A[(e >> 6) * LD + (e & 63)] = (double)c[u];
+    }
+  }
   __syncthreads();
   bool bad = false;
   for (int p = 0; p < 4; ++p) {
@@ -630,7 +668,7 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   T* out = Wbase + tidx(t.i, t.j) * TS2;
   const T* Lii_inv = linv + s.linv_off + (int64_t)(ni + t.i) * TS2;
   if (t.i == t.j) {
-    for (int e = threadIdx.x; e < TS2; e += 256) out[e] = Lii_inv[e];
+    tile_copy(out, Lii_inv);
     return;
   }
   Acc<T> acc;
@@ -716,7 +754,7 @@ __global__ __launch_bounds__(256) void k_copy_iface(const Task* __restrict__ tas
   const SubInfo s = subs[t.sub];
   const T* src = arena + s.tile_off + tidx(s.nt_i + t.i, s.nt_i + t.j) * TS2;
   T* dst = S + s.x_off + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 256) dst[e] = src[e];
+  tile_copy(dst, src);
 }
 
 // rho_s = mean of the diagonal of the interface Schur complement (real DOFs).
@@ -755,12 +793,12 @@ __global__ __launch_bounds__(256) void k_regularise(const Task* __restrict__ tas
   T* C = arena + s.tile_off + tidx(s.nt_i + t.i, s.nt_i + t.j) * TS2;
   const double* Ri = rb + (s.b_off + (int64_t)t.i * TS) * 6;
   const double* Rj = rb + (s.b_off + (int64_t)t.j * TS) * 6;
-  for (int e = threadIdx.x; e < TS2; e += 256) {
+  tile_rmw(C, [&](int e, T cv) {
     const int c = e >> 6, r = e & 63;
     double acc = 0.0;
     for (int k = 0; k < 6; ++k) acc += Ri[r * 6 + k] * Rj[c * 6 + k];
-    C[e] = (T)((double)C[e] + r0 * acc);
-  }
+    return (T)((double)cv + r0 * acc);
+  });
 }
 
 // Exact generalised inverse for stressed floating subdomains.  With V the
@@ -860,7 +898,7 @@ __global__ __launch_bounds__(256) void k_wb_update(const Task* __restrict__ task
   T* C = X + s.x_off + tidx(t.i, t.j) * TS2;
   const double* Yi = Y + (s.b_off + (int64_t)t.i * TS) * 3;
   const double* Yj = Y + (s.b_off + (int64_t)t.j * TS) * 3;
-  for (int e = threadIdx.x; e < TS2; e += 256) {
+  tile_rmw(C, [&](int e, T cv) {
     const int c = e >> 6, r = e & 63;
     double acc = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -868,8 +906,8 @@ __global__ __launch_bounds__(256) void k_wb_update(const Task* __restrict__ task
       for (int l = 0; l < 3; ++l) mk += M[3 * k + l] * Yj[c * 3 + l];
       acc += Yi[r * 3 + k] * mk;
     }
-    C[e] = (T)((double)C[e] + acc);
-  }
+    return (T)((double)cv + acc);
+  });
 }
 
 template <typename T>
