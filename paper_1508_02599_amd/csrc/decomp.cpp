@@ -189,10 +189,13 @@ void build_factor_schedule(const std::vector<SubInfo>& subs, std::vector<Task>& 
     for (int I = 0; I < subs[s].nt_b; ++I)
       for (int J = 0; J <= I; ++J) tasks.push_back({s, I, J, 0, 0});
   finish(xtiles);
+  // the tiles any step reads: inside the envelope, and the whole interface
+  // block (dense after the Schur update)
   alltiles = begin(-1);
   for (int s = 0; s < ns; ++s)
     for (int i = 0; i < subs[s].nt; ++i)
-      for (int j = 0; j <= i; ++j) tasks.push_back({s, i, j, 0, 0});
+      for (int j = 0; j <= i; ++j)
+        if (E(s, i) <= j || j >= subs[s].nt_i) tasks.push_back({s, i, j, 0, 0});
   finish(alltiles);
 }
 

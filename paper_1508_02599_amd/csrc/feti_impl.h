@@ -138,7 +138,7 @@ struct HostPlan {
   std::vector<Launch> sched_trtri;      // stage 5
   Launch sched_lauum{0, 0, 0};          // stage 6
   Launch sched_xtiles{0, 0, 0};         // all interface lower tiles (sub, I, J)
-  Launch sched_alltiles{0, 0, 0};       // all factor tiles (sub, i, j)
+  Launch sched_alltiles{0, 0, 0};       // factor tiles that are read (sub, i, j): inside the envelope, and the interface block
   int max_nt_i = 0, max_nt_b = 0;
 };
 
