@@ -43,6 +43,9 @@ struct feti_problem {
   // fork/join events and the host data its uploads read
   hipStream_t stream_c = nullptr;
   hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
+  hipEvent_t ev_asm = nullptr, ev_modes = nullptr;   // assembly done; rigid modes done (coarse stream)
+  int32_t* h_nmodes = nullptr;                        // pinned: kernel dimension per subdomain
+  SubInfo* h_sub = nullptr;                           // pinned: subdomain table with the coarse layout
   SubInfo h_qsub{};
   std::vector<Task> h_qt;
   const int h_big = 0x7fffffff;
@@ -625,6 +628,10 @@ feti_status setup_device(feti_problem* p) {
   HIPCHK(hipStreamCreateWithFlags(&p->stream_c, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&p->ev_cfork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_cjoin, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_asm, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_modes, hipEventDisableTiming));
+  HIPCHK(hipHostMalloc((void**)&p->h_nmodes, std::max(1, P.n_sub) * sizeof(int32_t), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&p->h_sub, std::max<size_t>(1, P.sub.size()) * sizeof(SubInfo), hipHostMallocDefault));
   for (auto& ev : p->ev_rep) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   p->profile = (p->opt.flags & FETI_PROFILE) != 0;
   if (p->profile) {
@@ -805,31 +812,17 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.rb = p->d_rb;
   m.n_modes = p->d_nmodes;
   m.work = p->d_work;
-  asm_modes(m, st);
   if (P.precond == FETI_PREC_LUMPED) lumped_fill(p->di, P.w_bb, p->d_bb_slot, p->d_ell_val, p->d_bb_val, st);
   HIPCHK(hipEventRecord(p->ev[1], st));
-  // coarse layout from the kernel dimensions
-  std::vector<int32_t> nm(P.n_sub);
-  HIPCHK(hipMemcpyAsync(nm.data(), p->d_nmodes, P.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  int off = 0;
-  for (int s = 0; s < P.n_sub; ++s) {
-    P.sub[s].n_modes = nm[s];
-    P.sub[s].coarse_off = off;
-    off += nm[s];
-  }
-  p->n_coarse = off;
-  p->nq = (off + TS - 1) / TS;
-  HIPCHK(hipMemcpyAsync(p->d_sub, P.sub.data(), P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
-  fill_bco(p->di, p->d_sub, p->d_bco, p->d_rco, st);
-  // the coarse problem on its own stream, beside the local factorisation
-  if (p->n_coarse > 0) {
-    HIPCHK(hipEventRecord(p->ev_cfork, st));
-    HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_cfork, 0));
-    TRY(coarse_factor(p, p->stream_c));
-    HIPCHK(hipEventRecord(p->ev_cjoin, p->stream_c));
-  }
-  // batched factorisation
+  // The rigid-body modes read only the assembled sparse rows, and the interior
+  // steps and the Schur update do not need them: they run on the coarse
+  // stream beside those steps, with the kernel dimensions copied back.
+  HIPCHK(hipEventRecord(p->ev_asm, st));
+  HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_asm, 0));
+  asm_modes(m, p->stream_c);
+  HIPCHK(hipMemcpyAsync(p->h_nmodes, p->d_nmodes, P.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream_c));
+  HIPCHK(hipEventRecord(p->ev_modes, p->stream_c));
+  // batched factorisation: interior steps and Schur update
   p->n_upd_recorded = 0;
   p->prof_upd_ms = 0.0;
   p->prof_upd_n = 0;
@@ -839,6 +832,30 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
   for (const auto& L : P.sched_interior) dense(p, L);
   dense(p, P.sched_schur);
+  // coarse layout from the kernel dimensions (the host waits for the modes
+  // while the GPU runs the steps above); the table is uploaded after the Schur
+  // update in stream order, so no kernel before it sees it change
+  HIPCHK(hipEventSynchronize(p->ev_modes));
+  int off = 0;
+  for (int s = 0; s < P.n_sub; ++s) {
+    P.sub[s].n_modes = p->h_nmodes[s];
+    P.sub[s].coarse_off = off;
+    off += p->h_nmodes[s];
+  }
+  p->n_coarse = off;
+  p->nq = (off + TS - 1) / TS;
+  std::copy(P.sub.begin(), P.sub.end(), p->h_sub);
+  HIPCHK(hipMemcpyAsync(p->d_sub, p->h_sub, P.sub.size() * sizeof(SubInfo), hipMemcpyHostToDevice, st));
+  fill_bco(p->di, p->d_sub, p->d_bco, p->d_rco, st);
+  // the modes (rb) are read by the regularisation below
+  HIPCHK(hipStreamWaitEvent(st, p->ev_modes, 0));
+  // the coarse problem on its own stream, beside the interface factorisation
+  if (p->n_coarse > 0) {
+    HIPCHK(hipEventRecord(p->ev_cfork, st));
+    HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_cfork, 0));
+    TRY(coarse_factor(p, p->stream_c));
+    HIPCHK(hipEventRecord(p->ev_cjoin, p->stream_c));
+  }
   const auto& XT = P.sched_xtiles;
   if (P.precond == FETI_PREC_DIRICHLET) {
     if (P.mixed)
@@ -1487,6 +1504,10 @@ void feti_destroy(feti_problem* p) {
   }
   if (p->ev_cfork) (void)hipEventDestroy(p->ev_cfork);
   if (p->ev_cjoin) (void)hipEventDestroy(p->ev_cjoin);
+  if (p->ev_asm) (void)hipEventDestroy(p->ev_asm);
+  if (p->ev_modes) (void)hipEventDestroy(p->ev_modes);
+  if (p->h_nmodes) (void)hipHostFree(p->h_nmodes);
+  if (p->h_sub) (void)hipHostFree(p->h_sub);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }
