@@ -44,6 +44,7 @@ struct feti_problem {
   hipStream_t stream_c = nullptr;
   hipEvent_t ev_cfork = nullptr, ev_cjoin = nullptr;
   hipEvent_t ev_asm = nullptr, ev_modes = nullptr;   // assembly done; rigid modes done (coarse stream)
+  hipEvent_t ev_ffork = nullptr, ev_fjoin = nullptr; // arena and ELL reset on the coarse stream
   int32_t* h_nmodes = nullptr;                        // pinned: kernel dimension per subdomain
   SubInfo* h_sub = nullptr;                           // pinned: subdomain table with the coarse layout
   SubInfo h_qsub{};
@@ -630,6 +631,8 @@ feti_status setup_device(feti_problem* p) {
   HIPCHK(hipEventCreateWithFlags(&p->ev_cjoin, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_asm, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_modes, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_ffork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_fjoin, hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&p->h_nmodes, std::max(1, P.n_sub) * sizeof(int32_t), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&p->h_sub, std::max<size_t>(1, P.sub.size()) * sizeof(SubInfo), hipHostMallocDefault));
   for (auto& ev : p->ev_rep) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -770,13 +773,19 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   a.Ke = p->d_Ke;
   a.fint = p->d_fint;
   a.fbody = p->d_fbody;
-  asm_elements(a, P.any_hgo, st);
+  // the arena fill and the ELL reset do not need the element matrices: they
+  // run on the coarse stream while the elements are integrated
+  HIPCHK(hipEventRecord(p->ev_ffork, st));
+  HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_ffork, 0));
   const auto& AT = P.sched_alltiles;
   if (P.mixed)
-    launch_init_arena<float>(p->d_tasks + AT.first, AT.count, p->d_sub, (float*)p->d_arena, st);
+    launch_init_arena<float>(p->d_tasks + AT.first, AT.count, p->d_sub, (float*)p->d_arena, p->stream_c);
   else
-    launch_init_arena<double>(p->d_tasks + AT.first, AT.count, p->d_sub, (double*)p->d_arena, st);
-  vec_fill((int64_t)P.NF * ELLW, 0.0, p->d_ell_val, st);
+    launch_init_arena<double>(p->d_tasks + AT.first, AT.count, p->d_sub, (double*)p->d_arena, p->stream_c);
+  vec_fill((int64_t)P.NF * ELLW, 0.0, p->d_ell_val, p->stream_c);
+  HIPCHK(hipEventRecord(p->ev_fjoin, p->stream_c));
+  asm_elements(a, P.any_hgo, st);
+  HIPCHK(hipStreamWaitEvent(st, p->ev_fjoin, 0));
   GatherArgs g;
   g.n_slots = (int64_t)P.ps_a.size();
   g.ps_a = p->d_ps_a;
@@ -1506,6 +1515,8 @@ void feti_destroy(feti_problem* p) {
   if (p->ev_cjoin) (void)hipEventDestroy(p->ev_cjoin);
   if (p->ev_asm) (void)hipEventDestroy(p->ev_asm);
   if (p->ev_modes) (void)hipEventDestroy(p->ev_modes);
+  if (p->ev_ffork) (void)hipEventDestroy(p->ev_ffork);
+  if (p->ev_fjoin) (void)hipEventDestroy(p->ev_fjoin);
   if (p->h_nmodes) (void)hipHostFree(p->h_nmodes);
   if (p->h_sub) (void)hipHostFree(p->h_sub);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);

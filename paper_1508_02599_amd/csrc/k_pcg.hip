@@ -830,10 +830,10 @@ __global__ void k_distribute(int64_t NF, const int32_t* __restrict__ fpos_lnode,
 //   w_I = L_II^{-1} g_I,  w_b = g_b - L_bI w_I,  z_b = X w_b,
 //   t_I = w_I - L_bI^T z_b,  z_I = L_II^{-T} t_I.
 // The interior solves are k_kp_band; the two products with L_bI are
-// k_kp_tiles, one workgroup per (tile row or column, subdomain); tile reads are
-// coalesced columns and each workgroup reduces once at the end.  Both skip
-// the factor tiles left of a tile row's envelope (env: first nonzero tile
-// column per tile row), which are zero.
+// k_kp_tiles (mode 1, one workgroup per interface tile row and subdomain) and
+// k_kp_cols (mode 2, one per interior tile column); each workgroup reduces
+// once at the end.  Both skip the factor tiles left of a tile row's envelope
+// (env: first nonzero tile column per tile row), which are zero.
 //   mode 1: yb_I = base_b - sum_{J<nt_i} L(nt_i+I, J) x_J   (rows I < nt_b)
 //   mode 2: y_I = base_I - sum_{J<nt_b} L(nt_i+J, I)^T xb_J (cols I < nt_i)
 template <typename T>
@@ -845,35 +845,77 @@ __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __res
   __shared__ double red[4][TS];
   const SubInfo s = subs[blockIdx.y];
   const int I = blockIdx.x;
-  if (I >= (mode == 1 ? s.nt_b : s.nt_i)) return;
+  if (I >= s.nt_b) return;
   const int tid = threadIdx.x;
-  const bool trans = mode == 2;
-  const int a = trans ? (tid >> 2) : (tid & 63);   // output row/column handled
-  const int q = trans ? (tid & 3) : (tid >> 6);     // quarter of the reduction index
+  const int a = tid & 63, q = tid >> 6;   // output row, quarter of the reduction index
   double acc = 0.0;
-  int j0, j1;
-  if (mode == 1) { j0 = min(env[s.env_off + s.nt_i + I], s.nt_i); j1 = s.nt_i; }
-  else { j0 = 0; j1 = s.nt_b; }
-  for (int J = j0; J < j1; ++J) {
-    if (mode == 2 && env[s.env_off + s.nt_i + J] > I) continue;
-    const T* tile;
-    const double* xs;
-    if (mode == 1) { tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2; xs = x + s.full_off + (int64_t)J * TS; }
-    else { tile = arena + s.tile_off + tidx2(s.nt_i + J, I) * TS2; xs = xb + s.b_off + (int64_t)J * TS; }
-    if (!trans) {
+  for (int J = min(env[s.env_off + s.nt_i + I], s.nt_i); J < s.nt_i; ++J) {
+    const T* tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2;
+    const double* xs = x + s.full_off + (int64_t)J * TS;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) acc += (double)tile[(16 * q + k) * TS + a] * xs[16 * q + k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) acc += (double)tile[a * TS + 16 * q + k] * xs[16 * q + k];
-    }
+    for (int k = 0; k < 16; ++k) acc += (double)tile[(16 * q + k) * TS + a] * xs[16 * q + k];
   }
   red[q][a] = acc;
   __syncthreads();
   if (tid < TS) {
     const double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    if (mode == 1) yb[s.b_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)(s.nt_i + I) * TS + tid] - v;
-    else y[s.full_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)I * TS + tid] - v;
+    yb[s.b_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)(s.nt_i + I) * TS + tid] - v;
+  }
+}
+
+// Mode 2 with coalesced loads: column tile I of L_bI is read
+// tile row by tile row, each tile loaded with consecutive threads on
+// consecutive elements and transposed through LDS (a column-wise read of a
+// column-major tile makes every load touch 64 cache lines); the next tile's
+// loads are in flight during this tile's products.
+template <typename T>
+__global__ __launch_bounds__(256) void k_kp_cols(const SubInfo* __restrict__ subs, const int32_t* __restrict__ env,
+                                                 const T* __restrict__ arena, const double* __restrict__ xb,
+                                                 const double* __restrict__ base, double* y) {
+  __shared__ double tl[TS * (TS + 1)];   // tl[c * (TS + 1) + r] = L(r, c)
+  __shared__ double red[4][TS];
+  const SubInfo s = subs[blockIdx.y];
+  const int I = blockIdx.x;
+  if (I >= s.nt_i) return;
+  const int tid = threadIdx.x;
+  const int a = tid & 63, q = tid >> 6;   // column of the tile, quarter of its rows
+  const int32_t* ev = env + s.env_off + s.nt_i;
+  const T* Lb = arena + s.tile_off;
+  int J = 0;
+  while (J < s.nt_b && ev[J] > I) ++J;
+  constexpr int N = TS2 / 256;
+  double v[N];
+  if (J < s.nt_b) {
+    const T* tile = Lb + tidx2(s.nt_i + J, I) * TS2;
+#pragma unroll
+    for (int u = 0; u < N; ++u) v[u] = (double)tile[tid + 256 * u];
+  }
+  double acc = 0.0;
+  while (J < s.nt_b) {
+    int Jn = J + 1;
+    while (Jn < s.nt_b && ev[Jn] > I) ++Jn;
+    __syncthreads();   // the previous tile's reads of tl are done
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int e = tid + 256 * u;
+      tl[(e >> 6) * (TS + 1) + (e & 63)] = v[u];
+    }
+    __syncthreads();
+    if (Jn < s.nt_b) {
+      const T* tile = Lb + tidx2(s.nt_i + Jn, I) * TS2;
+#pragma unroll
+      for (int u = 0; u < N; ++u) v[u] = (double)tile[tid + 256 * u];
+    }
+    const double* xs = xb + s.b_off + (int64_t)J * TS;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += tl[a * (TS + 1) + 16 * q + k] * xs[16 * q + k];
+    J = Jn;
+  }
+  red[q][a] = acc;
+  __syncthreads();
+  if (tid < TS) {
+    const double r = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    y[s.full_off + (int64_t)I * TS + tid] = base[s.full_off + (int64_t)I * TS + tid] - r;
   }
 }
 
@@ -1096,7 +1138,10 @@ void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t
 template <typename T>
 void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
                     const double* x, const double* xb, const double* base, double* y, double* yb, hipStream_t s) {
-  if (max_rows > 0)
+  if (max_rows <= 0) return;
+  if (mode == 2)
+    hipLaunchKernelGGL(k_kp_cols<T>, dim3(max_rows, n_sub), dim3(256), 0, s, subs, env, arena, xb, base, y);
+  else
     hipLaunchKernelGGL(k_kp_tiles<T>, dim3(max_rows, n_sub), dim3(256), 0, s, mode, subs, env, arena, x, xb, base,
                        y, yb);
 }
