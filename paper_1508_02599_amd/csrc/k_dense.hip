@@ -657,7 +657,9 @@ __global__ __launch_bounds__(256) void k_trsm(const Task* __restrict__ tasks,
 // One tile of the inverse W of the interface factor, block row i given rows
 // < i (tile indices local to the interface block):
 // W_ii = L_ii^{-1};  W_ij = -L_ii^{-1} sum_{k=k0}^{i-1} L_ik W_kj for j < i
-// (the tasks carry k0 = j: all terms).
+// (the tasks carry k0 = j: all terms).  W tiles are stored row-major
+// (element (r, c) at r * TS + c), so that X = W^T W streams both of its
+// operands as contiguous row chunks (k_lauum_db).
 template <typename T>
 __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, const T* __restrict__ arena,
                            const T* __restrict__ linv, T* W, T* sA, T* sB) {
@@ -668,7 +670,9 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   T* out = Wbase + tidx(t.i, t.j) * TS2;
   const T* Lii_inv = linv + s.linv_off + (int64_t)(ni + t.i) * TS2;
   if (t.i == t.j) {
-    tile_copy(out, Lii_inv);
+    lds_direct(sA, Lii_inv);   // sA[c * LD + r] = Linv(r, c)
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e & 63) * LD + (e >> 6)];
     return;
   }
   Acc<T> acc;
@@ -680,7 +684,7 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   }
   for (int k = t.k0; k < t.i; ++k) {
     ra.template store<false>(sA);
-    rb.template store<true>(sB);
+    rb.template store<false>(sB);   // row-major W_kj: B(k, n) = W_kj(k, n)
     __syncthreads();
     if (k + 1 < t.i) {
       ra.fetch(Lbase + tidx(ni + t.i, ni + k + 1) * TS2);
@@ -696,7 +700,7 @@ __device__ void trtri_tile(const Task& t, const SubInfo* __restrict__ subs, cons
   acc2.zero();
   mma64(acc2, sA, sB);
   __syncthreads();
-  acc_to_lds(sA, acc2, T(-1), true);
+  acc_to_lds(sA, acc2, T(-1), false);   // row-major
   __syncthreads();
   for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e >> 6) * LD + (e & 63)];
 }
@@ -713,36 +717,46 @@ __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
 }
 
 // X_IJ = sum_{k>=I} W_kI^T W_kJ  (I >= J): X = W^T W = (L L^T)^{-1}.
-template <typename T>
-__global__ __launch_bounds__(256) void k_lauum(const Task* __restrict__ tasks,
-                                               const SubInfo* __restrict__ subs,
-                                               const T* __restrict__ W, T* X) {
-  __shared__ T sA[TS * LD], sB[TS * LD];
+// With the row-major tiles of W both operands are contiguous chunks of KC
+// rows, streamed into two LDS buffers by the direct global-to-LDS loads as in
+// k_update_db.  X tiles are written column-major.
+template <typename T, int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_lauum_db(
+    const Task* __restrict__ tasks, const SubInfo* __restrict__ subs, const T* __restrict__ W, T* X) {
+  constexpr int CH = TS * KC;
+  constexpr int PARTS = TS / KC;
+  constexpr int NLDS = 4 * CH > TS * LD ? 4 * CH : TS * LD;
+  __shared__ double smem[(NLDS * (int)sizeof(T) + 7) / 8];
+  T* lds = reinterpret_cast<T*>(smem);
   const Task t = tasks[xcd_task()];
   const SubInfo s = subs[t.sub];
   const T* Wb = W + s.x_off;
+  const int w = threadIdx.x >> 6;
+  const int steps = (t.k1 - t.k0) * PARTS;
   Acc<T> acc;
   acc.zero();
-  TileRegs<T> ra, rb;
-  if (t.k0 < t.k1) {
-    ra.fetch(Wb + tidx(t.k0, t.i) * TS2);
-    rb.fetch(Wb + tidx(t.k0, t.j) * TS2);
+  if (steps > 0) {
+    dma_copy<T, CH>(lds, Wb + tidx(t.k0, t.i) * TS2);
+    dma_copy<T, CH>(lds + CH, Wb + tidx(t.k0, t.j) * TS2);
   }
-  for (int k = t.k0; k < t.k1; ++k) {
-    ra.template store<true>(sA);
-    rb.template store<true>(sB);
+  for (int st = 0; st < steps; ++st) {
+    const int cur = st & 1;
+    wait_vm();
     __syncthreads();
-    if (k + 1 < t.k1) {
-      ra.fetch(Wb + tidx(k + 1, t.i) * TS2);
-      rb.fetch(Wb + tidx(k + 1, t.j) * TS2);
+    if (st + 1 < steps) {
+      const int k = t.k0 + (st + 1) / PARTS, part = (st + 1) % PARTS;
+      T* nxt = lds + (cur ^ 1) * 2 * CH;
+      dma_copy<T, CH>(nxt, Wb + tidx(k, t.i) * TS2 + part * CH);
+      dma_copy<T, CH>(nxt + CH, Wb + tidx(k, t.j) * TS2 + part * CH);
     }
-    mma64(acc, sA, sB);
-    __syncthreads();
+    const T* sa = lds + cur * 2 * CH;
+    mma64w<T, TS, KC>(acc, sa, sa + CH, w);
   }
-  acc_to_lds(sA, acc, T(1), true);
+  __syncthreads();
+  acc_to_lds(lds, acc, T(1), true);
   __syncthreads();
   T* out = X + s.x_off + tidx(t.i, t.j) * TS2;
-  for (int e = threadIdx.x; e < TS2; e += 256) out[e] = sA[(e >> 6) * LD + (e & 63)];
+  for (int e = threadIdx.x; e < TS2; e += 256) out[e] = lds[(e >> 6) * LD + (e & 63)];
 }
 
 // Copy of the interface Schur complement (for the Dirichlet preconditioner).
@@ -970,7 +984,9 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
     case K_TRTRI:
       hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W);
       break;
-    case K_LAUUM: hipLaunchKernelGGL(k_lauum<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X); break;
+    case K_LAUUM:
+      hipLaunchKernelGGL((k_lauum_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
+      break;
   }
 }
 template void launch_dense<double>(int, const Task*, int, const SubInfo*, double*, double*, double*, double*, int*, hipStream_t, int, int, int);
