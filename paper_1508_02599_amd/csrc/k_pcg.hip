@@ -849,7 +849,25 @@ __global__ __launch_bounds__(256) void k_kp_tiles(int mode, const SubInfo* __res
   const int tid = threadIdx.x;
   const int a = tid & 63, q = tid >> 6;   // output row, quarter of the reduction index
   double acc = 0.0;
-  for (int J = min(env[s.env_off + s.nt_i + I], s.nt_i); J < s.nt_i; ++J) {
+  // tiles in pairs: both tiles' loads are in flight before the products
+  // (same products, same order)
+  int J = min(env[s.env_off + s.nt_i + I], s.nt_i);
+  for (; J + 1 < s.nt_i; J += 2) {
+    const T* t0 = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2;
+    const T* t1 = arena + s.tile_off + tidx2(s.nt_i + I, J + 1) * TS2;
+    T v0[16], v1[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v0[k] = t0[(16 * q + k) * TS + a];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v1[k] = t1[(16 * q + k) * TS + a];
+    const double* x0 = x + s.full_off + (int64_t)J * TS;
+    const double* x1 = x0 + TS;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += (double)v0[k] * x0[16 * q + k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += (double)v1[k] * x1[16 * q + k];
+  }
+  if (J < s.nt_i) {
     const T* tile = arena + s.tile_off + tidx2(s.nt_i + I, J) * TS2;
     const double* xs = x + s.full_off + (int64_t)J * TS;
 #pragma unroll
