@@ -106,7 +106,7 @@ class Server:
     def _estimate(self, key):
         """Device bytes of a new problem of this mesh: measured once a problem
         of it exists, else a bound from its subdomain sizes (dense tile arenas
-        for the factor, the interior and interface inverses, plus 20%)."""
+        for the factor and for the interface inverse and its square)."""
         if key in self.est:
             return self.est[key]
         m = self.mesh(key)
@@ -116,7 +116,7 @@ class Server:
         nt = np.ceil(3 * sub_nodes / 64) + 2
         tiles = (nt * (nt + 1) / 2).sum()
         elt = 4 if self.options.get("precision") == "mixed" else 8
-        # factor arena, plus interior and interface inverses (about half of it),
+        # factor arena, plus the interface arenas (at most as large again),
         # plus sparse rows (81 entries of value and index per local DOF)
         return int(2.0 * tiles * 64 * 64 * elt + 81 * 12 * 3 * sub_nodes.sum())
 
