@@ -56,11 +56,6 @@ void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, con
               int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s, int iface_only);
 void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
              const PcgState* st, hipStream_t s);
-void pcg_alpha(const double* part, PcgState* st, hipStream_t s);
-void pcg_beta(const double* part, PcgState* st, int init, double* hist, hipStream_t s);
-void pcg_update_lr(int64_t n, double* lam, double* r, const double* sv, const double* q, const PcgState* st,
-                   hipStream_t s);
-void pcg_update_s(int64_t n, double* sv, const double* z, const PcgState* st, hipStream_t s);
 void pcg_coarse_gt(int n_sub, const SubInfo* subs, const double* rb, const double* xb, double* g,
                    const PcgState* st, hipStream_t s);
 void pcg_coarse_gt_full(int n_sub, const SubInfo* subs, const double* rf, const double* xf, double* g,
@@ -73,7 +68,6 @@ void pcg_lumped(const DevIdx& d, int w_bb, const int32_t* bb_col, const double* 
                 double* yb, const PcgState* st, hipStream_t s);
 void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double* ell_val, double* bb_val,
                  hipStream_t s);
-void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s);
 void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s);
 void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, const double* ufull,
                 const uint8_t* dmask, const double* dvals, double* out, int sum_mode, hipStream_t s);
@@ -81,7 +75,6 @@ void vec_dirinc(int64_t n_dof, const uint8_t* dmask, const double* dirval, doubl
                 double* dvals, hipStream_t s);
 void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 void vec_fill(int64_t n, double v, double* y, hipStream_t s);
-void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s);
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
 template <typename T>
 void local_kp_tiles(int mode, int n_sub, int max_rows, const SubInfo* subs, const int32_t* env, const T* arena,
@@ -94,8 +87,6 @@ void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s);
 // fused iteration kernels
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,
                   hipStream_t s);
-void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
-                           int* ticket, PcgState* st, hipStream_t s);
 // Fused scatters that also form the coarse right-hand side of the next
 // projection from the interface vector (coarse = 0: no coarse space).
 void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,

@@ -100,79 +100,6 @@ __device__ void sum_parts(const double* part, int nparts, double* o1, double* o2
   *o2 = r2[0];
 }
 
-// alpha = rho / (s.q); breakdown if s.q <= 0.
-__global__ __launch_bounds__(256) void k_alpha(const double* part, int nparts, PcgState* st) {
-  if (st->done) return;
-  double pq, unused;
-  sum_parts(part, nparts, &pq, &unused);
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    if (!(pq > 0.0)) {
-      st->alpha = 0.0;
-      st->done = 1;
-      st->status = FETI_EBREAKDOWN;
-    } else {
-      st->alpha = st->rho / pq;
-    }
-  }
-}
-
-// lam += alpha s ; r -= alpha q
-__global__ void k_update_lr(int64_t n, double* lam, double* r, const double* __restrict__ s,
-                            const double* __restrict__ q, const PcgState* st) {
-  if (halted(st)) return;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const double a = st->alpha;
-  lam[k] += a * s[k];
-  r[k] -= a * q[k];
-}
-
-// rho' = w.z, ||w||; beta = rho'/rho; convergence test on ||w|| <= rtol ||w0||.
-// init != 0: first evaluation (sets rho, w0, no beta).
-__global__ __launch_bounds__(256) void k_beta(const double* part, int nparts, PcgState* st, int init,
-                                              double* hist) {
-  if (st->done) return;
-  double wz, ww;
-  sum_parts(part, nparts, &wz, &ww);
-  if (threadIdx.x == 0) {
-    const double wn = sqrt(ww);
-    if (init) {
-      st->rho = wz;
-      st->w0 = wn;
-      st->wn = wn;
-      st->beta = 0.0;
-      st->it = 0;
-      if (!(wn > st->atol)) { st->done = 1; st->status = FETI_OK; }
-      return;
-    }
-    const int it = st->it;
-    if (hist && it < st->hist_cap) {
-      hist[2 * it] = st->alpha;
-      hist[2 * it + 1] = wz / st->rho;
-    }
-    st->beta = wz / st->rho;
-    st->rho = wz;
-    st->wn = wn;
-    st->it = it + 1;
-    if (wn <= st->rtol * st->w0 || !(wn > st->atol)) {
-      st->done = 1;
-      st->status = FETI_OK;
-    } else if (st->it >= st->max_it) {
-      st->done = 1;
-      st->status = FETI_ENOCONV;
-    }
-  }
-}
-
-// s = z + beta s
-__global__ void k_update_s(int64_t n, double* s, const double* __restrict__ z, const PcgState* st) {
-  if (halted(st)) return;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  s[k] = z[k] + st->beta * s[k];
-}
-
 // g[coarse_off + k] = rb_k . xb over the interface of every floating subdomain.
 __global__ __launch_bounds__(256) void k_coarse_gt(const SubInfo* __restrict__ subs, const double* __restrict__ rb,
                                                    const double* __restrict__ xb, double* g,
@@ -297,12 +224,6 @@ __global__ void k_bb_fill(int64_t NB, int64_t NF, int w_bb, const int32_t* __res
   bb_val[t] = sl >= 0 ? ell_val[(int64_t)sl * NF + b2full[b]] : 0.0;
 }
 
-__global__ void k_copy_b2f(int64_t NB, const int64_t* __restrict__ b2full, const double* __restrict__ full,
-                           double* __restrict__ b) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < NB) b[k] = full[b2full[k]];
-}
-
 // Multiplier right-hand side b: prescribed value of an all-floating Dirichlet row, else 0.
 __global__ void k_bvec(int64_t n_lam, const int64_t* __restrict__ gdof, const double* __restrict__ dvals,
                        double* __restrict__ out) {
@@ -340,12 +261,6 @@ __global__ void k_dirinc(int64_t n_dof, const uint8_t* __restrict__ dmask, const
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) y[k] = (b == 0.0) ? a * x[k] : a * x[k] + b * y[k];   // b == 0: y is not read
-}
-
-__global__ void k_copy_st(int64_t n, const double* __restrict__ x, double* __restrict__ y, const PcgState* st) {
-  if (halted(st)) return;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) y[k] = x[k];
 }
 
 __global__ void k_fill(int64_t n, double v, double* y) {
@@ -455,42 +370,6 @@ __global__ void k_gather_s(int64_t NB, const int32_t* __restrict__ g_ptr, const 
     acc += g_coef[k] * (z[r] + beta * sv[r]);
   }
   xb[b] = acc;
-}
-
-// q = B yb ; s <- z + beta s ; alpha = rho / (s.q)  (breakdown if s.q <= 0)
-__global__ __launch_bounds__(256) void k_scatter_dot_alpha(
-    int64_t n, const int64_t* __restrict__ b0, const double* __restrict__ c0, const int64_t* __restrict__ b1,
-    const double* __restrict__ c1, const double* __restrict__ yb, const double* __restrict__ z, double* sv,
-    double* q, double* part, int* ticket, PcgState* st) {
-  if (st->done) return;
-  __shared__ double ra[256], rb[256];
-  double acc = 0.0, unused = 0.0;
-  const double beta = st->beta;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
-    double v = c0[r] * yb[b0[r]];
-    if (b1[r] >= 0) v += c1[r] * yb[b1[r]];
-    const double sn = z[r] + beta * sv[r];
-    sv[r] = sn;
-    q[r] = v;
-    acc += sn * v;
-  }
-  block_reduce2(acc, unused, ra, rb);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
-  if (!last_block(ticket)) return;
-  double pq = 0.0;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += 256) pq += part[k];
-  block_reduce2(pq, unused, ra, rb);
-  if (threadIdx.x == 0) {
-    *ticket = 0;
-    st->pq = pq;
-    if (!(pq > 0.0)) {
-      st->alpha = 0.0;
-      st->done = 1;
-      st->status = FETI_EBREAKDOWN;
-    } else {
-      st->alpha = st->rho / pq;
-    }
-  }
 }
 
 // Fused: blocks [0, nrow_blocks) do q = B yb, s <- z + beta s and the block
@@ -1032,19 +911,6 @@ void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const
              const PcgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial, dim3(DOT_PARTS), dim3(256), 0, s, n, a, b, c, d, part, st);
 }
-void pcg_alpha(const double* part, PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(256), 0, s, part, DOT_PARTS, st);
-}
-void pcg_beta(const double* part, PcgState* st, int init, double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_beta, dim3(1), dim3(256), 0, s, part, DOT_PARTS, st, init, hist);
-}
-void pcg_update_lr(int64_t n, double* lam, double* r, const double* sv, const double* q, const PcgState* st,
-                   hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_update_lr, grid1(n), dim3(256), 0, s, n, lam, r, sv, q, st);
-}
-void pcg_update_s(int64_t n, double* sv, const double* z, const PcgState* st, hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_update_s, grid1(n), dim3(256), 0, s, n, sv, z, st);
-}
 void pcg_coarse_gt(int n_sub, const SubInfo* subs, const double* rb, const double* xb, double* g,
                    const PcgState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_coarse_gt, dim3(n_sub), dim3(256), 0, s, subs, rb, xb, g, st);
@@ -1069,9 +935,6 @@ void lumped_fill(const DevIdx& d, int w_bb, const int32_t* bb_slot, const double
                  hipStream_t s) {
   if (d.NB && w_bb) hipLaunchKernelGGL(k_bb_fill, grid1(d.NB * w_bb), dim3(256), 0, s, d.NB, d.NF, w_bb, bb_slot, d.b2full, ell_val, bb_val);
 }
-void vec_copy_b2f(const DevIdx& d, const double* full, double* b, hipStream_t s) {
-  if (d.NB) hipLaunchKernelGGL(k_copy_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, full, b);
-}
 void vec_bvec(const DevIdx& d, const double* dvals, double* out, hipStream_t s) {
   if (d.n_lam) hipLaunchKernelGGL(k_bvec, grid1(d.n_lam), dim3(256), 0, s, d.n_lam, d.r_gdof, dvals, out);
 }
@@ -1088,9 +951,6 @@ void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStr
 }
 void vec_fill(int64_t n, double v, double* y, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_fill, grid1(n), dim3(256), 0, s, n, v, y);
-}
-void vec_copy_st(int64_t n, const double* x, double* y, const PcgState* st, hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_copy_st, grid1(n), dim3(256), 0, s, n, x, y, st);
 }
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, rtol, atol, max_it, hist_cap);
@@ -1112,10 +972,6 @@ constexpr int FUSE_BLOCKS = 256;
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,
                   hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_gather_s, grid1(d.NB), dim3(256), 0, s, d.NB, d.g_ptr, d.g_row, d.g_coef, z, sv, xb, st);
-}
-void pcg_scatter_dot_alpha(const DevIdx& d, const double* yb, const double* z, double* sv, double* q, double* part,
-                           int* ticket, PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_dot_alpha, dim3(FUSE_BLOCKS), dim3(256), 0, s, d.n_lam, d.r_b0, d.r_c0, d.r_b1, d.r_c1, yb, z, sv, q, part, ticket, st);
 }
 void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
                               const double* yb, const double* z, double* sv, double* q, double* part,
