@@ -191,12 +191,17 @@ feti_status feti_footprint(const feti_problem* p, size_t* device_bytes);
 /* Assemble the local tangents at displacement U ([3*n_nodes], NULL => 0),
  * compute the rigid-body kernels, factor every K_i (interior-first dense
  * Cholesky, regularised interface Schur complement, its explicit inverse) and
- * the coarse matrix G^T G.  Errors: EINVAL, ENOTSPD, EDEVICE. */
+ * the coarse matrix G^T G.  These are the generalised inverses K_i^+ and the
+ * kernels R_i of section 4.3, eq. (localSolutions), and the coarse operator of
+ * eq. (projection).  Errors: EINVAL, ENOTSPD (the message names the
+ * subdomain), EDEVICE. */
 feti_status feti_factor(feti_problem* p, const double* U);
 
 /* Solve the linear problem K u = lf f_ext with u = lf u_D on the Dirichlet
  * boundary, using the factors of the last feti_factor (which must have been
- * called with U = NULL).  u [3*n_nodes] receives the global nodal
+ * called with U = NULL): the dual problem of section 4.3, eq. (dualProblem),
+ * by projected preconditioned CG from lambda_0 = G (G^T G)^{-1} e, then the
+ * recovery of u_i by eq. (localSolutions).  u [3*n_nodes] receives the global nodal
  * displacements (shared nodes: mean of the subdomain copies; Dirichlet DOFs:
  * their prescribed values).  stats may be NULL.
  * Errors: ESTATE, ENOCONV (u still written), EBREAKDOWN, EDEVICE. */

@@ -61,44 +61,3 @@ def newton_increment(mesh, U, tau):
     inc = tau * mesh.dir_val - U[mesh.dir_dof]
     dU = solve_with_dirichlet(K, r, mesh.dir_dof, inc)
     return dU, float(np.linalg.norm(r[free]))
-
-
-def residual_norm(mesh, U, tau):
-    U = np.asarray(U, dtype=np.float64).reshape(-1)
-    _, f_int, f_ext = fem.assemble(mesh, U.reshape(-1, 3), tau=tau)
-    free = np.ones(mesh.n_dofs, dtype=bool)
-    free[mesh.dir_dof] = False
-    r = f_ext - f_int
-    return float(np.linalg.norm(r[free])), float(np.linalg.norm(f_ext[free]))
-
-
-def newton_load_path(mesh, n_steps=10, rtol=1e-11, max_newton=12, U0=None, line_search=False):
-    """Load stepping with Newton (eq. (loadStepping)): tau_s = s/n_steps, the
-    converged state of step s-1 is the initial guess of step s.
-
-    ``line_search`` halves a step until the residual norm decreases (at most
-    10 times); it is not part of the paper's scheme and only serves to reach
-    equilibria of nearly incompressible meshes whose first linearised step
-    overshoots.  Returns a list of dicts {tau, U, newton_iters, res_hist}.
-    """
-    U = np.zeros(mesh.n_dofs) if U0 is None else np.array(U0, dtype=np.float64)
-    path = []
-    for s in range(1, n_steps + 1):
-        tau = s / n_steps
-        hist = []
-        it = 0
-        for it in range(1, max_newton + 1):
-            dU, rn = newton_increment(mesh, U, tau)
-            a = 1.0
-            if line_search:
-                for _ in range(10):
-                    if residual_norm(mesh, U + a * dU, tau)[0] < rn:
-                        break
-                    a *= 0.5
-            U = U + a * dU
-            rn2, fn = residual_norm(mesh, U, tau)
-            hist.append(rn2)
-            if rn2 <= rtol * max(fn, 1e-300):
-                break
-        path.append(dict(tau=tau, U=U.copy(), newton_iters=it, res_hist=hist))
-    return path

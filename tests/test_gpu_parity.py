@@ -1,8 +1,13 @@
-"""Parity of the HIP FETI path against the CPU oracle (element-wise on the
-global nodal displacements, same seeded inputs), through the C ABI.
+"""Parity of the HIP FETI path against the CPU oracle on the global nodal
+displacements (same seeded inputs), through the C ABI.
 
-Tolerances: FP64 displacements within 1e-9 relative of the monolithic sparse
-direct solution when the dual residual is driven to 1e-11; at the benchmark
+Every comparison checks two norms of the error against the same bar: the
+relative 2-norm ||u - u_ref||_2 / ||u_ref||_2 and the element-wise bound
+max_k |u_k - u_ref,k| <= tol * max_k |u_ref,k|, so that a wrong value on a few
+DOFs cannot hide in the 2-norm of a large vector.
+
+Tolerances: FP64 displacements within 1e-9 of the monolithic sparse direct
+solution when the dual residual is driven to 1e-11; at the benchmark
 tolerance 1e-8 the error is reported and bounded by 1e-7.
 """
 import numpy as np
@@ -27,7 +32,10 @@ def _solve(mesh, **kw):
 
 
 def _rel(u, ref):
-    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    """max(relative 2-norm error, element-wise error relative to max|u_ref|)."""
+    l2 = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    li = float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))
+    return max(l2, li)
 
 
 _ORACLE = {}

@@ -454,3 +454,139 @@ def test_nodal_residual_matches_assembled_rows():
     r[dm.reshape(-1, 3)[nodes]] = 0.0
     res, _ = fem.nodal_residual(t, nodes, du, U=U.reshape(-1, 3), tau=0.7)
     assert np.abs(res - r).max() <= 1e-12 * np.abs(r).max()
+
+
+# ---------------------------------------------------------------- pins added for
+# the condition estimate and the nodal splits of the loads
+def _plain_cg(A, b, n_it):
+    """Textbook CG (x0 = 0) returning its (alpha_k, beta_k)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    al, be = [], []
+    for _ in range(n_it):
+        q = A @ p
+        a = rr / (p @ q)
+        x += a * p
+        r -= a * q
+        rr2 = r @ r
+        al.append(a)
+        be.append(rr2 / rr)
+        p = r + be[-1] * p
+        rr = rr2
+    return al, be
+
+
+def test_lanczos_kappa_exact_on_known_spectrum():
+    """After n CG steps on an n x n SPD matrix the Lanczos tridiagonal built
+    from (alpha, beta) has the matrix's own eigenvalues, so the estimate is
+    exactly lambda_max / lambda_min."""
+    rng = np.random.default_rng(4)
+    lam = np.array([1.0, 1.7, 2.2, 3.0, 4.1, 5.5, 6.0, 7.3, 8.8, 9.5])
+    Qm, _ = np.linalg.qr(rng.standard_normal((10, 10)))
+    A = Qm @ np.diag(lam) @ Qm.T
+    al, be = _plain_cg(A, rng.standard_normal(10), 10)
+    assert abs(feti_ref.lanczos_kappa(al, be) - 9.5) <= 1e-9 * 9.5
+    # fewer steps: Ritz values lie inside the spectrum (interlacing)
+    al, be = _plain_cg(A, rng.standard_normal(10), 5)
+    assert 1.0 <= feti_ref.lanczos_kappa(al, be) <= 9.5 * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("variant", ["af", "classical"])
+def test_lanczos_kappa_matches_spectrum_of_preconditioned_operator(variant):
+    """The FETI reference's condition estimate equals the ratio of the extreme
+    nonzero eigenvalues of (P M P)(P F P), formed explicitly, for every
+    preconditioner.  A random body force excites every eigen-direction, so the
+    Lanczos values reach the extreme eigenvalues at a tight tolerance."""
+    m = cube_mesh(4, 2)
+    rng = np.random.default_rng(5)
+    m.body_force = rng.standard_normal((m.n_elems, 3))
+    tp = feti_ref.linear_torn_problem(m, variant)
+    n = tp.n_lam
+    for pc in ("lumped", "dirichlet", "identity"):
+        fr = feti_ref.FetiRef(tp, pc)
+        if pc == "lumped":
+            Fm = np.stack([fr.F(e) for e in np.eye(n)], axis=1)
+            P = np.eye(n)
+            if fr.n_coarse:
+                Gm = np.stack([fr.G(e) for e in np.eye(fr.n_coarse)], axis=1)
+                P = P - Gm @ np.linalg.solve(Gm.T @ Gm, Gm.T)
+        Mm = np.stack([fr.Mprec(e) for e in np.eye(n)], axis=1)
+        ev = np.sort(np.abs(np.linalg.eigvals((P @ Mm @ P) @ (P @ Fm @ P)).real))
+        nz = ev[ev > 1e-9 * ev[-1]]
+        exact = nz[-1] / nz[0]
+        est = fr.solve(rtol=1e-12)["kappa"]
+        assert abs(est / exact - 1.0) <= 2e-3, (pc, est, exact)
+
+
+def _gauss3():
+    g = np.sqrt(3.0 / 5.0)
+    return [(-g, 5.0 / 9.0), (0.0, 8.0 / 9.0), (g, 5.0 / 9.0)]
+
+
+def test_body_force_nodal_split_on_distorted_element():
+    """int N_a b dX on a distorted trilinear element: N_a det(dX/dxi) has degree
+    3 in each reference coordinate, so a 3-point Gauss rule (written here
+    independently of the element code) gives the exact nodal split."""
+    X = _distorted_element(7) * np.array([1.3, 0.8, 1.1])
+    b = np.array([0.4, -1.2, 0.7])
+    ref = np.zeros((8, 3))
+    for xa, wa in _gauss3():
+        for xb, wb in _gauss3():
+            for xc, wc in _gauss3():
+                xi = np.array([xa, xb, xc])
+                N = np.prod(1.0 + fem.XI * xi, axis=1) / 8.0
+                dN = np.stack([fem.XI[:, k] / 8.0 * np.prod(np.delete(1.0 + fem.XI * xi, k, axis=1), axis=1)
+                               for k in range(3)], axis=1)
+                det = np.linalg.det(X.T @ dN)
+                ref += wa * wb * wc * det * N[:, None] * b[None, :]
+    f = fem.body_force_vector(X[None], b[None])[0].reshape(8, 3)
+    assert np.abs(f - ref).max() <= 1e-14 * np.abs(ref).max() * 10
+    # the split is not the naive equal share on a distorted element
+    assert np.abs(f - f.sum(axis=0) / 8).max() > 1e-4 * np.abs(f).max()
+
+
+def _curved_face(seed=3):
+    rng = np.random.default_rng(seed)
+    xf = np.array([[0, 0, 0], [1.2, 0, 0], [1.1, 0.9, 0], [0, 1.0, 0]], dtype=np.float64)
+    xf[:, 2] = [0.0, 0.25, -0.15, 0.3]            # warped: the four corners are not coplanar
+    return xf + 0.05 * rng.standard_normal((4, 3))
+
+
+def test_pressure_nodal_split_on_warped_face():
+    """f_a = -p int N_a (dx/deta1 x dx/deta2) deta on a warped bilinear face,
+    against a 3x3 Gauss rule written here (the integrand has degree 2 in each
+    variable, so both rules are exact); the corner order of the face is
+    (-1,-1), (1,-1), (1,1), (-1,1)."""
+    xf = _curved_face()
+    p = 1.7
+    eta = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
+    ref = np.zeros((4, 3))
+    for s, ws in _gauss3():
+        for t, wt in _gauss3():
+            N = 0.25 * (1 + eta[:, 0] * s) * (1 + eta[:, 1] * t)
+            dNs = 0.25 * eta[:, 0] * (1 + eta[:, 1] * t)
+            dNt = 0.25 * eta[:, 1] * (1 + eta[:, 0] * s)
+            n = np.cross(dNs @ xf, dNt @ xf)
+            ref += -p * ws * wt * N[:, None] * n[None, :]
+    f = fem.pressure_face_load(xf[None], p)[0]
+    assert np.abs(f - ref).max() <= 1e-14 * np.abs(ref).max() * 10
+
+
+def test_pressure_load_follows_the_geometry():
+    """A follower load on the current surface rotates with a rigid rotation of
+    the face, f(Q x) = Q f(x), and scales with the area, f(s x) = s^2 f(x); a
+    translation leaves it unchanged."""
+    xf = _curved_face(8)
+    rng = np.random.default_rng(9)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] *= -1
+    f = fem.pressure_face_load(xf[None], 0.9)[0]
+    fq = fem.pressure_face_load((xf @ Q.T)[None], 0.9)[0]
+    assert np.abs(fq - f @ Q.T).max() <= 1e-14 * np.abs(f).max() * 10
+    fs = fem.pressure_face_load((2.5 * xf)[None], 0.9)[0]
+    assert np.abs(fs - 6.25 * f).max() <= 1e-14 * np.abs(fs).max() * 10
+    ft = fem.pressure_face_load((xf + np.array([3.0, -1.0, 2.0]))[None], 0.9)[0]
+    assert np.abs(ft - f).max() <= 1e-14 * np.abs(f).max() * 100
