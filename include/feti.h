@@ -207,6 +207,21 @@ feti_status feti_factor(feti_problem* p, const double* U);
  * Errors: ESTATE, ENOCONV (u still written), EBREAKDOWN, EDEVICE. */
 feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stats* stats);
 
+/* feti_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, with the dual iteration's scratch (CG state, reduction ticket
+ * counters, block partial sums, alpha/beta history) taken from a static device
+ * array of 512 KiB that each device holds until the process ends, instead of
+ * the problem's own buffers, and the PCG iterations launched one by one
+ * instead of through an instantiated HIP graph.  It calls no hipMalloc or
+ * hipFree.  The problem must have been set up with FETI_DEVICE_PTRS (u is a
+ * device array) and max_it <= 8192 (the history the array holds); otherwise
+ * FETI_EINVAL.  All calls on one device share the array, which keeps the last
+ * call's contents: calls that overlap on one device race.  Results equal
+ * those of feti_solve.  Errors: as feti_solve, and FETI_EDEVICE if the array's
+ * address could not be obtained at set-up. */
+feti_status feti_solve_noalloc(feti_problem* p, double load_factor, double* u, feti_stats* stats);
+
 /* One Newton step of the nonlinear problem (eqs. (LGS), (loadStepping)):
  * factor at U_k, then solve K'(U_k) dU = tau f_ext(U_k) - f_int(U_k) with
  * dU = tau u_D - U_k on the Dirichlet boundary.  The follower pressure acts on

@@ -106,16 +106,22 @@ struct feti_problem {
   double *d_lam = nullptr, *d_r = nullptr, *d_s = nullptr, *d_q = nullptr, *d_wv = nullptr, *d_zv = nullptr;
   double *d_tv = nullptr, *d_d = nullptr, *d_bv = nullptr;
   double *d_cg = nullptr, *d_calpha = nullptr, *d_gamma = nullptr, *d_e = nullptr;
-  double *d_dvals = nullptr, *d_out = nullptr, *d_dots = nullptr, *d_hist = nullptr;
+  double *d_dvals = nullptr, *d_out = nullptr;
   double *d_f0 = nullptr, *d_uglob = nullptr, *d_zero = nullptr;
-  PcgState* d_state = nullptr;
-  int* d_ticket = nullptr;
-  double *d_fpart = nullptr, *d_qdense = nullptr, *d_gpart = nullptr;
-  double* d_apart = nullptr;   // block partials of s.q (alpha)
+  double* d_qdense = nullptr;
   int32_t* d_bco = nullptr;
   int2* d_rco = nullptr;     // per multiplier row: coarse codes of its two entries
   int ldg = 0;
-  int hist_cap = 0;
+  // scratch of the dual iteration: `own` is allocated at set-up; `sc` is the
+  // set the kernels use (own, or the library's static array in
+  // feti_solve_noalloc)
+  PcgScratch own, sc;
+  void* noalloc_base = nullptr;   // device address of the static scratch array on this device
+  bool use_graph = true;
+  // pinned host copies of the CG history and of dot-product partials, and the
+  // work arrays of the condition estimate (sized at set-up)
+  double *h_hist = nullptr, *h_dots = nullptr;
+  std::vector<double> lz_d, lz_e;
   // graph
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
@@ -330,11 +336,11 @@ void project_fused(feti_problem* p, int mode, int init, double* x, double* out, 
                    double* hist) {
   const int nc = p->n_coarse;
   if (nc) {
-    pcg_proj_gt(p->P.n_sub, p->d_sub, p->di, p->d_rb, x, p->d_q, mode == 1, p->d_gpart, p->ldg, st, p->stream);
-    pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, p->stream);
+    pcg_proj_gt(p->P.n_sub, p->d_sub, p->di, p->d_rb, x, p->d_q, mode == 1, p->sc.gpart, p->ldg, st, p->stream);
+    pcg_coarse_dense(nc, nc, p->d_qdense, p->sc.gpart, p->ldg, p->d_calpha, st, p->stream);
   }
   pcg_proj_apply(mode, init, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, x, p->d_q, p->d_s, p->d_lam, out, w,
-                 p->d_fpart, p->d_ticket + 1, st, hist, p->stream);
+                 p->sc.fpart, p->sc.ticket + 1, st, hist, p->stream);
 }
 
 // q = F v
@@ -365,16 +371,16 @@ void precondition(feti_problem* p, const double* w, double* out, const PcgState*
 //   t = M^{-1} w with G^T t from the preconditioner's interface output;
 //   a = Q^{-1} G^T t;  z = t - G a, beta and the stopping test.
 void pcg_iteration(feti_problem* p) {
-  PcgState* st = p->d_state;
+  PcgState* st = p->sc.state;
   hipStream_t s = p->stream;
   const int nc = p->n_coarse;
   pcg_gather_s(p->di, p->d_zv, p->d_s, p->d_xb, st, s);
   symv_local(p, p->d_X, p->d_xb, p->d_yb, st, 1);
   pcg_scatter_dot_alpha_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, p->d_yb, p->d_zv, p->d_s, p->d_q,
-                           p->d_apart, st, p->d_gpart, p->ldg, s);
-  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
+                           p->sc.apart, st, p->sc.gpart, p->ldg, s);
+  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->sc.gpart, p->ldg, p->d_calpha, st, s);
   pcg_proj_apply(1, 0, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, p->d_r, p->d_q, p->d_s, p->d_lam, p->d_wv,
-                 nullptr, p->d_fpart, p->d_ticket + 1, st, nullptr, s, p->d_apart);
+                 nullptr, p->sc.fpart, p->sc.ticket + 1, st, nullptr, s, p->sc.apart);
   // preconditioner
   pcg_gather(p->di, 1, p->d_wv, p->d_xb, st, s);
   const double* y = p->d_xb;
@@ -385,17 +391,17 @@ void pcg_iteration(feti_problem* p) {
     symv_local(p, p->d_S, p->d_xb, p->d_yb, st, 1);
     y = p->d_yb;
   }
-  pcg_scatter_w_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, y, p->d_tv, st, p->d_gpart, p->ldg, s);
-  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->d_gpart, p->ldg, p->d_calpha, st, s);
+  pcg_scatter_w_gt(p->di, p->P.n_sub, nc > 0, p->d_sub, p->d_rb, y, p->d_tv, st, p->sc.gpart, p->ldg, s);
+  if (nc) pcg_coarse_dense(nc, nc, p->d_qdense, p->sc.gpart, p->ldg, p->d_calpha, st, s);
   pcg_proj_apply(2, 0, p->di, nc > 0, p->d_rco, p->d_rb, p->d_calpha, p->d_tv, p->d_q, p->d_s, p->d_lam, p->d_zv,
-                 p->d_wv, p->d_fpart, p->d_ticket + 1, st, p->d_hist, s);
+                 p->d_wv, p->sc.fpart, p->sc.ticket + 1, st, p->sc.hist, s);
 }
 
 // Condition estimate from the recorded (alpha, beta): extreme eigenvalues of
 // the Lanczos tridiagonal by bisection on Sturm sequences.
-double lanczos_kappa(const std::vector<double>& h, int m) {
-  if (m <= 0) return 1.0;
-  std::vector<double> d(m), e(m, 0.0);
+double lanczos_kappa(const double* h, int m, std::vector<double>& d, std::vector<double>& e) {
+  if (m <= 0 || (int)d.size() < m || (int)e.size() < m) return 1.0;
+  std::fill(e.begin(), e.begin() + m, 0.0);
   for (int k = 0; k < m; ++k) {
     const double a = h[2 * k], b = h[2 * k + 1];
     d[k] = 1.0 / a + (k > 0 ? h[2 * (k - 1) + 1] / h[2 * (k - 1)] : 0.0);
@@ -611,17 +617,28 @@ feti_status setup_device(feti_problem* p) {
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
     vec_fill(P.n_dof, 0.0, p->d_zero, p->stream);
   }
-  TRY(dalloc(p, p->d_dots, 2 * DOT_PARTS));
-  p->hist_cap = std::max(1, p->opt.max_it);
-  TRY(dalloc(p, p->d_hist, 2 * (size_t)p->hist_cap));
-  TRY(dalloc(p, p->d_state, 1));
-  TRY(dalloc(p, p->d_ticket, 4));
-  HIPCHK(hipMemsetAsync(p->d_ticket, 0, 4 * sizeof(int), p->stream));
-  TRY(dalloc(p, p->d_fpart, 2 * 256));
-  TRY(dalloc(p, p->d_apart, 256));
+  PcgScratch& o = p->own;
+  TRY(dalloc(p, o.dots, 2 * DOT_PARTS));
+  o.hist_cap = std::max(1, p->opt.max_it);
+  TRY(dalloc(p, o.hist, 2 * (size_t)o.hist_cap));
+  TRY(dalloc(p, o.state, 1));
+  TRY(dalloc(p, o.ticket, 4));
+  HIPCHK(hipMemsetAsync(o.ticket, 0, 4 * sizeof(int), p->stream));
+  TRY(dalloc(p, o.fpart, 2 * 256));
+  TRY(dalloc(p, o.apart, 256));
   TRY(dalloc(p, p->d_qdense, (size_t)max_coarse * max_coarse));
   p->ldg = max_coarse;
-  TRY(dalloc(p, p->d_gpart, (size_t)4 * max_coarse));
+  TRY(dalloc(p, o.gpart, (size_t)4 * max_coarse));
+  p->sc = o;
+  HIPCHK(hipHostMalloc((void**)&p->h_hist, 2 * (size_t)o.hist_cap * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&p->h_dots, 2 * DOT_PARTS * sizeof(double), hipHostMallocDefault));
+  p->lz_d.resize(o.hist_cap);
+  p->lz_e.resize(o.hist_cap);
+  {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    p->noalloc_base = noalloc_scratch(dev);   // NULL: feti_solve_noalloc reports EDEVICE
+  }
   TRY(dalloc(p, p->d_bco, (size_t)P.NB));
   TRY(dalloc(p, p->d_rco, (size_t)P.n_lam));
   for (auto& ev : p->ev) HIPCHK(hipEventCreate(&ev));
@@ -968,14 +985,15 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     }
     // r = d - F lambda ; w = P r ; z = P M w ; s = z
     apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
-    pcg_init_state(p->d_state, rtol, 0.0, p->opt.max_it, p->hist_cap, st);
+    pcg_init_state(p->sc.state, rtol, 0.0, p->opt.max_it, p->sc.hist_cap, st);
     vec_fill(n, 0.0, p->d_s, st);   // s = z + 0 s in the first iteration
-    project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->d_state, nullptr);
-    precondition(p, p->d_wv, p->d_tv, p->d_state);
-    project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->d_state, nullptr);
-    // graph of graph_block iterations
+    project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->sc.state, nullptr);
+    precondition(p, p->d_wv, p->d_tv, p->sc.state);
+    project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->sc.state, nullptr);
+    // graph of graph_block iterations (feti_solve_noalloc launches the
+    // iterations one by one instead: instantiating a graph may allocate)
     const int gb = std::max(1, p->opt.graph_block);
-    if (!p->graph || p->graph_iters != gb) {
+    if (p->use_graph && (!p->graph || p->graph_iters != gb)) {
       if (p->graph) {
         (void)hipGraphExecDestroy(p->graph);
         p->graph = nullptr;
@@ -998,14 +1016,19 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     PcgState hs{};
     int rd = 0, wr = 0, queued = 0;   // ring of two state copies
     auto queue_state = [&]() -> hipError_t {
-      hipError_t e = hipMemcpyAsync(&p->h_state[wr], p->d_state, sizeof(PcgState), hipMemcpyDeviceToHost, st);
+      hipError_t e = hipMemcpyAsync(&p->h_state[wr], p->sc.state, sizeof(PcgState), hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipEventRecord(p->ev_rep[wr], st);
       wr ^= 1;
       ++queued;
       return e;
     };
+    auto run_block = [&]() -> hipError_t {
+      if (p->use_graph) return hipGraphLaunch(p->graph, st);
+      for (int k = 0; k < gb; ++k) pcg_iteration(p);
+      return hipGetLastError();
+    };
     HIPCHK(queue_state());   // state after the initial residual
-    HIPCHK(hipGraphLaunch(p->graph, st));
+    HIPCHK(run_block());
     HIPCHK(queue_state());
     int prev_it = 0;
     double prev_wn = 0.0;
@@ -1016,7 +1039,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
       --queued;
       if (hs.done) break;
       if (queued == 0 || !pcg_converges_within(hs, prev_it, prev_wn, gb * queued)) {
-        HIPCHK(hipGraphLaunch(p->graph, st));
+        HIPCHK(run_block());
         HIPCHK(queue_state());
       }
       prev_it = hs.it;
@@ -1027,10 +1050,10 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     status = hs.status;
     rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
     if (stats && iters > 0) {
-      std::vector<double> h(2 * (size_t)std::min(iters, p->hist_cap));
-      HIPCHK(hipMemcpyAsync(h.data(), p->d_hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      const int m = std::min(iters, std::min(p->sc.hist_cap, p->own.hist_cap));
+      HIPCHK(hipMemcpyAsync(p->h_hist, p->sc.hist, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      kappa = lanczos_kappa(h, std::min(iters, p->hist_cap));
+      kappa = lanczos_kappa(p->h_hist, m, p->lz_d, p->lz_e);
     }
     // gamma = -Q^{-1} G^T r ; u = K^+(f - B^T lambda) + R gamma
     pcg_gather(p->di, 0, p->d_lam, p->d_xb, nullptr, st);
@@ -1077,12 +1100,11 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
 
 // ||v||_2 of a device vector (deterministic partition, host finish).
 feti_status dev_norm(feti_problem* p, const double* v, int64_t n, double* out) {
-  pcg_dot(n, v, v, nullptr, nullptr, p->d_dots, nullptr, p->stream);
-  std::vector<double> parts(2 * DOT_PARTS);
-  HIPCHK(hipMemcpyAsync(parts.data(), p->d_dots, parts.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  pcg_dot(n, v, v, nullptr, nullptr, p->sc.dots, nullptr, p->stream);
+  HIPCHK(hipMemcpyAsync(p->h_dots, p->sc.dots, 2 * DOT_PARTS * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   double s2 = 0.0;
-  for (int k = 0; k < DOT_PARTS; ++k) s2 += parts[2 * k];
+  for (int k = 0; k < DOT_PARTS; ++k) s2 += p->h_dots[2 * k];
   *out = std::sqrt(s2);
   return FETI_OK;
 }
@@ -1242,6 +1264,9 @@ feti_status load_U(feti_problem* p, const double* U, const double** U_dev) {
   return FETI_OK;
 }
 
+// Body of feti_solve and feti_solve_noalloc (defined after them).
+feti_status solve_linear_call(feti_problem* p, double load_factor, double* u, feti_stats* stats);
+
 }  // namespace
 
 // ===========================================================================
@@ -1331,6 +1356,41 @@ feti_status feti_factor(feti_problem* p, const double* U) {
 feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stats* stats) {
   if (!p) return FETI_EINVAL;
   p->err.clear();
+  return solve_linear_call(p, load_factor, u, stats);
+}
+
+feti_status feti_solve_noalloc(feti_problem* p, double load_factor, double* u, feti_stats* stats) {
+  if (!p) return FETI_EINVAL;
+  p->err.clear();
+  if (!(p->opt.flags & FETI_DEVICE_PTRS)) {
+    p->err = "feti_solve_noalloc needs FETI_DEVICE_PTRS (u on the device)";
+    return FETI_EINVAL;
+  }
+  if (p->opt.max_it > kNoAllocMaxIt) {
+    p->err = "max_it above " + std::to_string(kNoAllocMaxIt) + ", the iteration history the static scratch holds";
+    return FETI_EINVAL;
+  }
+  if (p->P.n_sub > kMaxSub || !p->noalloc_base) {
+    p->err = "static scratch array unavailable on this device";
+    return FETI_EDEVICE;
+  }
+  // the dual iteration's scratch set from the static array; the ticket
+  // counters must start at zero (a fill kernel, not a memset node)
+  p->sc = noalloc_layout(p->noalloc_base, p->P.n_sub);
+  p->sc.hist_cap = std::min(p->sc.hist_cap, p->own.hist_cap);
+  vec_fill(2, 0.0, reinterpret_cast<double*>(p->sc.ticket), p->stream);
+  p->use_graph = false;
+  const feti_status s = solve_linear_call(p, load_factor, u, stats);
+  p->sc = p->own;
+  p->use_graph = true;
+  return s;
+}
+
+}  // extern "C"
+
+namespace {
+
+feti_status solve_linear_call(feti_problem* p, double load_factor, double* u, feti_stats* stats) {
   if (!u) {
     p->err = "u is NULL";
     return FETI_EINVAL;
@@ -1399,6 +1459,10 @@ feti_status feti_solve(feti_problem* p, double load_factor, double* u, feti_stat
   return s;
 }
 
+}  // namespace
+
+extern "C" {
+
 feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, double* dU, double* res_norm,
                              feti_stats* stats) {
   if (!p) return FETI_EINVAL;
@@ -1458,13 +1522,7 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
     r.f = p->d_f;
     asm_rhs(r, st);
     vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_dvals, p->d_out, 1, st);
-    pcg_dot(P.n_dof, p->d_out, p->d_out, nullptr, nullptr, p->d_dots, nullptr, st);
-    std::vector<double> parts(2 * DOT_PARTS);
-    HIPCHK(hipMemcpyAsync(parts.data(), p->d_dots, parts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double s2 = 0.0;
-    for (int k = 0; k < DOT_PARTS; ++k) s2 += parts[2 * k];
-    *res_norm = std::sqrt(s2);
+    TRY(dev_norm(p, p->d_out, P.n_dof, res_norm));
   }
   vec_fill(P.NF, 0.0, p->d_f, st);
   r.dvals = p->d_dvals;
@@ -1507,6 +1565,8 @@ void feti_destroy(feti_problem* p) {
   for (auto& ev : p->ev_rep)
     if (ev) (void)hipEventDestroy(ev);
   if (p->h_state) (void)hipHostFree(p->h_state);
+  if (p->h_hist) (void)hipHostFree(p->h_hist);
+  if (p->h_dots) (void)hipHostFree(p->h_dots);
   if (p->stream_c) {
     (void)hipStreamSynchronize(p->stream_c);
     (void)hipStreamDestroy(p->stream_c);

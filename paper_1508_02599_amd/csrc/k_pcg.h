@@ -14,6 +14,30 @@ struct PcgState {
   int32_t it, max_it, done, status, hist_cap, pad_;
 };
 
+// Scratch of the dual iteration: the device-resident CG state, the ticket
+// counters of the last-block reductions (must start at zero), block partial
+// sums of the dot products and of the coarse right-hand sides, and the
+// (alpha, beta) history of the condition estimate (hist_cap iterations).
+struct PcgScratch {
+  PcgState* state = nullptr;
+  int* ticket = nullptr;       // 4 counters
+  double* fpart = nullptr;     // 2 * 256
+  double* apart = nullptr;     // 256
+  double* dots = nullptr;      // 2 * DOT_PARTS
+  double* gpart = nullptr;     // 4 * 6 * n_sub
+  double* hist = nullptr;      // 2 * hist_cap
+  int hist_cap = 0;
+};
+
+// Static scratch array of feti_solve_noalloc: its size, the largest
+// iteration history it holds, and its device address on `device` (looked up
+// once per device with hipGetSymbolAddress; NULL on failure).
+constexpr size_t kNoAllocScratchBytes = 512 * 1024;
+constexpr int kNoAllocMaxIt = 8192;
+void* noalloc_scratch(int device);
+// Carves the scratch set out of the static array (base from noalloc_scratch).
+PcgScratch noalloc_layout(void* base, int n_sub);
+
 // Device index arrays used by the dual-space kernels.
 struct DevIdx {
   int64_t NB = 0, NF = 0, n_lam = 0;

@@ -6,6 +6,7 @@
 // All reductions use a fixed partition and a fixed summation order, so a
 // solve gives bit-identical results whatever else runs on the device.
 #include <algorithm>
+#include <mutex>
 
 #include "feti_impl.h"
 #include "k_pcg.h"
@@ -1040,5 +1041,60 @@ template void local_kp_band<float>(int, int, int, const SubInfo*, const int32_t*
 void vec_set_b2f(const DevIdx& d, const double* b, double* full, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_set_b2f, grid1(d.NB), dim3(256), 0, s, d.NB, d.b2full, b, full);
 }
+
+// ---------------------------------------------------------------------------
+// Scratch of feti_solve_noalloc: one static array per device, holding the
+// dual iteration's scratch set (PcgScratch) for callers that cannot allocate.
+// Host code never passes the array's name to a kernel: its device address on
+// each device comes from hipGetSymbolAddress, once per device, and only that
+// address is used.  Every call on a device shares the array; calls that
+// overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch(int device) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  if (device < 0 || device >= kMaxDev) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) {
+      (void)hipGetLastError();
+      return nullptr;   // the device must be current
+    }
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    addr[device] = ptr;
+  }
+  return addr[device];
+}
+
+PcgScratch noalloc_layout(void* base, int n_sub) {
+  auto* b = static_cast<unsigned char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = b + off;
+    off += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  PcgScratch sc;
+  sc.state = reinterpret_cast<PcgState*>(take(sizeof(PcgState)));
+  sc.ticket = reinterpret_cast<int*>(take(4 * sizeof(int)));
+  sc.fpart = reinterpret_cast<double*>(take(2 * 256 * sizeof(double)));
+  sc.apart = reinterpret_cast<double*>(take(256 * sizeof(double)));
+  sc.dots = reinterpret_cast<double*>(take(2 * DOT_PARTS * sizeof(double)));
+  sc.gpart = reinterpret_cast<double*>(take((size_t)4 * 6 * std::max(n_sub, 1) * sizeof(double)));
+  sc.hist = reinterpret_cast<double*>(take((size_t)2 * kNoAllocMaxIt * sizeof(double)));
+  sc.hist_cap = kNoAllocMaxIt;
+  return sc;
+}
+static_assert(sizeof(PcgState) <= 256, "state slot");
+static_assert(256 + 256 + 4096 + 2048 + 2 * DOT_PARTS * 8 + (size_t)4 * 6 * kMaxSub * 8 + 256 +
+                  (size_t)2 * kNoAllocMaxIt * 8 <= kNoAllocScratchBytes,
+              "the largest scratch set fits the static array");
 
 }  // namespace feti

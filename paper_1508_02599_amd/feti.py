@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.feti_factor.restype = C.c_int
     lib.feti_solve.argtypes = [P, C.c_double, C.c_void_p, C.POINTER(feti_stats)]
     lib.feti_solve.restype = C.c_int
+    lib.feti_solve_noalloc.argtypes = [P, C.c_double, C.c_void_p, C.POINTER(feti_stats)]
+    lib.feti_solve_noalloc.restype = C.c_int
     lib.feti_newton_step.argtypes = [P, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(feti_stats)]
     lib.feti_newton_step.restype = C.c_int
@@ -110,8 +112,8 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-EXPORTED = ("feti_setup", "feti_footprint", "feti_factor", "feti_solve", "feti_newton_step",
-            "feti_last_error", "feti_destroy")
+EXPORTED = ("feti_setup", "feti_footprint", "feti_factor", "feti_solve", "feti_solve_noalloc",
+            "feti_newton_step", "feti_last_error", "feti_destroy")
 
 
 def _ptr(a, ctype):
@@ -244,6 +246,16 @@ class Problem:
         if not (allow_noconv and st == FETI_ENOCONV):
             _check(self.lib, self.h, st)
         return u, stats.as_dict()
+
+    def solve_noalloc(self, out, load_factor=1.0):
+        """feti_solve_noalloc into the device tensor ``out`` (needs
+        device_ptrs=True); returns (out, stats)."""
+        assert self.device_ptrs and out is not None
+        stats = feti_stats()
+        _check(self.lib, self.h, self.lib.feti_solve_noalloc(self.h, float(load_factor),
+                                                             C.c_void_p(int(out.data_ptr())),
+                                                             C.byref(stats)))
+        return out, stats.as_dict()
 
     def newton_step(self, U, tau, out=None):
         """Returns (dU, residual norm, stats) of one Newton step at U with load factor tau."""
