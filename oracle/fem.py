@@ -273,6 +273,25 @@ def pressure_face_load(xf, p):
     return f
 
 
+def pressure_load_stiffness(xf, p, h=1e-30):
+    """Derivative of the follower pressure load with respect to the current
+    corner positions, D[f, 3a+i, 3b+j] = d f_ai / d x_bj (xf [nf,4,3]).
+
+    The paper drops this term from the tangent and notes that keeping it
+    makes the system non-symmetric (section 3.2, last paragraph).  Computed
+    exactly by complex-step differentiation of :func:`pressure_face_load`.
+    """
+    nf = xf.shape[0]
+    D = np.empty((nf, 12, 12))
+    xc = np.asarray(xf, dtype=np.complex128)
+    for col in range(12):
+        b, j = divmod(col, 3)
+        xp = xc.copy()
+        xp[:, b, j] += 1j * h
+        D[:, :, col] = pressure_face_load(xp, p).reshape(nf, 12).imag / h
+    return D
+
+
 # ---------------------------------------------------------------------------
 # global assembly
 # ---------------------------------------------------------------------------
@@ -346,6 +365,23 @@ def assemble(mesh, U=None, tau=1.0):
         pd = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).ravel()
         f_ext += np.bincount(pd, weights=fp.ravel(), minlength=n)
     return K, f_int, tau * f_ext
+
+
+def assemble_load_stiffness(mesh, U=None):
+    """Global derivative of the follower pressure load f_p(X + U) with respect
+    to U (CSR, n_dofs x n_dofs); zero without pressure faces."""
+    import scipy.sparse as sp
+    n = mesh.n_dofs
+    if mesh.pface is None or mesh.pressure == 0.0:
+        return sp.csr_matrix((n, n))
+    x = mesh.xyz + (0.0 if U is None else np.asarray(U).reshape(-1, 3))
+    D = pressure_load_stiffness(x[mesh.pface], mesh.pressure)
+    dofs = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
+    rows = np.repeat(dofs, 12, axis=1).ravel()
+    cols = np.tile(dofs, (1, 12)).ravel()
+    A = sp.coo_matrix((D.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    return A
 
 
 def nodal_residual(mesh, nodes, u, U=None, tau=1.0):

@@ -165,6 +165,24 @@ def rigid_modes(x):
     return R.reshape(3 * n, 6)
 
 
+def partial_kernel(x, dmask, tol=1e-10):
+    """Rigid modes of the points x that vanish on the DOFs flagged in dmask
+    (node-major), restricted to the other DOFs: the null space of the six
+    modes' rows at the flagged DOFs (rotations scaled by the points' radius),
+    by singular value decomposition.  Returns [n_free, k], k = 6 - rank."""
+    R = rigid_modes(x)
+    L = np.sqrt(np.mean(np.sum((x - x.mean(axis=0)) ** 2, axis=1)))
+    Rs = R * np.array([1, 1, 1, 1 / L, 1 / L, 1 / L])
+    RD = Rs[dmask]
+    if RD.shape[0] == 0:
+        N = np.eye(6)
+    else:
+        _, sv, Vt = np.linalg.svd(RD)
+        sv = np.concatenate([sv, np.zeros(6 - sv.size)])
+        N = Vt.T[:, sv <= tol * sv.max()]
+    return Rs[~dmask] @ N
+
+
 class FetiRef:
     """Classical / all-floating FETI solve of a :class:`TornProblem`."""
 
@@ -181,18 +199,28 @@ class FetiRef:
             bmask[bset] = True
             I = np.nonzero(~bmask)[0]
             Bd = np.nonzero(bmask)[0]
-            floating = (tp.variant == "af") or (not sd["has_dir"])
             R = None
-            if floating:
+            nK = np.linalg.norm(K)
+            if tp.variant == "af" or not sd["has_dir"]:
                 Rfull = rigid_modes(sd["x"])
                 # keep translations; keep a rotation only if K annihilates it
-                nK = np.linalg.norm(K)
                 keep = [0, 1, 2]
                 for k in range(3, 6):
                     r = Rfull[:, k]
                     if np.linalg.norm(K @ r) <= kernel_tol * nK * np.linalg.norm(r):
                         keep.append(k)
                 R = Rfull[:, keep]
+            else:
+                # classical subdomain with Dirichlet DOFs: its kernel is the set of
+                # rigid modes that vanish on them (section 4.3: a subdomain that
+                # touches the Dirichlet boundary at a vertex or an edge keeps a
+                # partial kernel), restricted to the free DOFs
+                R = partial_kernel(sd["x"], tp.dir_mask[sd["gdof_all"]])
+                R = np.stack([r for r in R.T
+                              if np.linalg.norm(K @ r) <= kernel_tol * nK * np.linalg.norm(r)], axis=1) \
+                    if R.shape[1] else R
+                if R.shape[1] == 0:
+                    R = None
             Kii = K[np.ix_(I, I)]
             Kib = K[np.ix_(I, Bd)]
             Kbb = K[np.ix_(Bd, Bd)]

@@ -590,3 +590,100 @@ def test_pressure_load_follows_the_geometry():
     assert np.abs(fs - 6.25 * f).max() <= 1e-14 * np.abs(fs).max() * 10
     ft = fem.pressure_face_load((xf + np.array([3.0, -1.0, 2.0]))[None], 0.9)[0]
     assert np.abs(ft - f).max() <= 1e-14 * np.abs(f).max() * 100
+
+
+# ---------------------------------------------------------------- follower-load stiffness
+def test_pressure_load_stiffness_is_load_derivative():
+    """The complex-step load stiffness equals central finite differences of
+    the pressure load (a different differentiation), and follows from the
+    load's invariances: translations do not change the load (D t = 0) and an
+    infinitesimal rotation W rotates it (D (W x) = W f)."""
+    xf = _curved_face(4)
+    p = 1.3
+    D = fem.pressure_load_stiffness(xf[None], p)[0]
+    eps = 1e-6
+    Dfd = np.zeros((12, 12))
+    for c in range(12):
+        dx = np.zeros(12)
+        dx[c] = eps
+        fp = fem.pressure_face_load((xf.reshape(-1) + dx).reshape(1, 4, 3), p)[0].reshape(-1)
+        fm = fem.pressure_face_load((xf.reshape(-1) - dx).reshape(1, 4, 3), p)[0].reshape(-1)
+        Dfd[:, c] = (fp - fm) / (2 * eps)
+    assert np.abs(D - Dfd).max() <= 1e-8 * np.abs(D).max()
+    for k in range(3):
+        t = np.zeros((4, 3))
+        t[:, k] = 1.0
+        assert np.abs(D @ t.reshape(-1)).max() <= 1e-13 * np.abs(D).max()
+    w = np.array([0.3, -0.7, 0.4])
+    W = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    f = fem.pressure_face_load(xf[None], p)[0]
+    assert np.allclose(D @ (xf @ W.T).reshape(-1), (f @ W.T).reshape(-1), atol=1e-13 * np.abs(f).max())
+
+
+def test_assembled_load_stiffness_symmetric_when_edges_clamped():
+    """A pressure on a surface whose boundary does not move is conservative:
+    the assembled load stiffness is symmetric on the free DOFs (tube with
+    clamped ends), while a single face with free edges gives a non-symmetric
+    one."""
+    t = tube_mesh(nr=1, nth=12, nz=4, sub=(1, 1, 1), pressure=1.5)
+    rng = np.random.default_rng(2)
+    U = 0.05 * rng.standard_normal(t.n_dofs)
+    U[t.dir_dof] = 0.0
+    D = fem.assemble_load_stiffness(t, U).toarray()
+    free = np.setdiff1d(np.arange(t.n_dofs), t.dir_dof)
+    Dff = D[np.ix_(free, free)]
+    assert np.abs(Dff - Dff.T).max() <= 1e-13 * np.abs(Dff).max()
+    assert np.abs(D - D.T).max() > 1e-3 * np.abs(D).max()      # the clamped rows break it
+    Df = fem.pressure_load_stiffness(_curved_face(5)[None], 1.5)[0]
+    assert np.abs(Df - Df.T).max() > 1e-3 * np.abs(Df).max()
+
+
+def test_exact_newton_quadratic_with_follower_load():
+    """With the load stiffness the Newton step is the exact linearisation of
+    the follower-pressure problem and converges quadratically; without it the
+    contraction is only linear (the load stiffness the paper neglects)."""
+    m = tube_mesh(nr=2, nth=16, nz=8, sub=(1, 1, 1))
+    tau = 1.0 / 40.0
+
+    def run(ls, n):
+        U = np.zeros(m.n_dofs)
+        res = []
+        for _ in range(n):
+            dU, rn = monolithic.newton_increment(m, U, tau, load_stiffness=ls)
+            res.append(rn)
+            U = U + dU
+        res.append(monolithic.residual_norm(m, U, tau)[0])
+        return np.array(res) / res[0]
+    r = run(True, 6)
+    assert r[-1] < 1e-10, r
+    q = [r[k + 1] / r[k] ** 2 for k in range(len(r) - 1) if r[k + 1] > 2e-11 and r[k] < 0.1]
+    assert len(q) >= 2 and max(q) < 1.0, (r, q)
+    r0 = run(False, 7)
+    assert r0[-1] > 1e-10 and r0[-1] / r0[-2] ** 2 > 100.0, r0
+
+
+# ---------------------------------------------------------------- partial kernels (classical)
+def test_classical_partial_kernels_match_monolithic():
+    """Classical FETI on a cube whose Dirichlet data touch subdomains only
+    partially (section 4.3): the subdomain at the clamped quarter face has no
+    kernel, the two that touch it along an edge keep one rotation, the one
+    that touches it at a vertex keeps three rotations, and the four whose
+    face has only u_x fixed keep two translations and one rotation; the
+    reference FETI then gives the monolithic solution for every
+    preconditioner, and each kernel is annihilated by its K_i."""
+    from workloads import partial_dirichlet_cube
+    m = partial_dirichlet_cube(4, 2)
+    u_ref = monolithic.solve_linear(m)
+    tp = feti_ref.linear_torn_problem(m, "classical")
+    dims = []
+    for pc in ("lumped", "dirichlet"):
+        fr = feti_ref.FetiRef(tp, pc)
+        dims = [0 if lc["R"] is None else lc["R"].shape[1] for lc in fr.locals]
+        for i, lc in enumerate(fr.locals):
+            if lc["R"] is not None:
+                K = tp.subs[i]["K"]
+                assert np.linalg.norm(K @ lc["R"]) <= 1e-12 * np.linalg.norm(K) * np.linalg.norm(lc["R"])
+        sol = fr.solve(rtol=1e-12)
+        assert np.linalg.norm(sol["u"] - u_ref) <= 1e-9 * np.linalg.norm(u_ref), pc
+    # subdomain id = ix + 2 iy + 4 iz
+    assert dims == [0, 3, 1, 3, 1, 3, 3, 3], dims

@@ -138,6 +138,25 @@ def cube_mesh(n_el: int, n_sub_axis: int, *, E=1.0, nu=0.3, nu_per_sub=None,
                 name=name, meta={"n_el": n_el, "n_sub_axis": n_sub_axis})
 
 
+def partial_dirichlet_cube(n_el=8, n_sub_axis=2, **kw) -> Mesh:
+    """Unit cube in n_sub_axis^3 boxes whose Dirichlet data touch some
+    subdomains only partially: u = 0 on the quarter y, z <= 0.5 of the face
+    x = 0, and u_x = 0 (only that component) on the face x = 1.  With 2^3
+    boxes, one subdomain holds the clamped quarter face, two touch it along an
+    edge, one at a single vertex, and the four at x = 1 have one constrained
+    component on a whole face."""
+    m = cube_mesh(n_el, n_sub_axis, **kw)
+    x = m.xyz
+    tol = 1e-12
+    clamp = np.nonzero((x[:, 0] < tol) & (x[:, 1] < 0.5 + tol) & (x[:, 2] < 0.5 + tol))[0]
+    roller = np.nonzero(x[:, 0] > 1.0 - tol)[0]
+    dofs = np.concatenate([(3 * clamp[:, None] + np.arange(3)[None, :]).ravel(), 3 * roller])
+    m.dir_dof = np.sort(dofs).astype(np.int64)
+    m.dir_val = np.zeros(m.dir_dof.size)
+    m.name = "partial_dirichlet_cube"
+    return m
+
+
 def kelvin_displacement(x, E, nu, src=(1.5, 1.5, 1.5)):
     """Kelvin's fundamental solution of linear elastostatics (paper section 5.1,
     eq. (fundSol)): the displacement at ``x`` caused by a unit point force in
@@ -278,6 +297,9 @@ CONFIGS = {
     "cube32_s4": dict(kind="cube", n_el=32, n_sub_axis=4, nu_seed=0),
     "tube_16x128x64": dict(kind="tube", nr=16, nth=128, nz=64, sub=(1, 16, 8)),
     "random_boxes_64": dict(kind="random", n_el=64, n_box_axis=8, seed=0),
+    # 40^3 cube in 5x5x5 uneven boxes of 450-5616 DOFs (seed 0): boxes as large
+    # as those of random_boxes_64 on a mesh whose direct solve fits a test
+    "random_boxes_40": dict(kind="random", n_el=40, n_box_axis=5, seed=0),
 }
 
 
