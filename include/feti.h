@@ -127,16 +127,26 @@ typedef struct {
                                    that passes the exactness test
                                    ||K r|| <= 1e-12 ||K||_F ||r|| (a direct exact solve)     */
 
+#define FETI_LOAD_STIFFNESS 0x10ull /* feti_newton_step solves the exact linearisation of the
+                                   follower-pressure problem, (K'(U) - tau d f_p / dU) dU =
+                                   tau f_ext - f_int, whose load stiffness the paper neglects
+                                   and notes to be non-symmetric (section 3.2, last paragraph):
+                                   flexible GMRES on the assembled FP64 system, preconditioned
+                                   by the FETI solve of the symmetric tangent K'(U), up to
+                                   ir_tol / ir_max preconditioner applications                */
+
 typedef struct {
   feti_variant variant;
   feti_precond precond;
   feti_precision precision;
   double rtol;                 /* PCG stop: ||P r_k||_2 <= rtol ||P r_0||_2 (0 => 1e-8)  */
   int32_t max_it;              /* PCG iteration cap (0 => 1000)                           */
-  double ir_tol;               /* mixed: target of the outer refinement,
-                                  ||f - K u||_2 <= ir_tol ||f||_2 over free DOFs, FP64,
-                                  assembled (0 => 1e-10)                                  */
-  int32_t ir_max;              /* max correction sweeps of the refinement (negative => 6);
+  double ir_tol;               /* target of the refinement (FETI_MIXED, FETI_KERNEL6 at a
+                                  stressed state, FETI_LOAD_STIFFNESS): flexible GMRES on
+                                  the assembled FP64 system until ||b - A u||_2 <=
+                                  ir_tol ||b||_2 over free DOFs (0 => 1e-10)              */
+  int32_t ir_max;              /* max preconditioner applications (dual solves) of the
+                                  refinement (negative => 6); restart every 30;
                                   0: none (the residual is still reported in res_primal)  */
   int32_t graph_block;         /* PCG iterations captured per HIP graph (0 => 8)          */
   void* hip_stream;            /* hipStream_t to run on, or NULL for a library stream    */
@@ -144,13 +154,14 @@ typedef struct {
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
   uint64_t flags;              /* FETI_DEVICE_PTRS | FETI_PROFILE | FETI_AUTOTUNE |
-                                  FETI_KERNEL6                                            */
+                                  FETI_KERNEL6 | FETI_LOAD_STIFFNESS                      */
 } feti_options;
 
 typedef struct {
   int32_t iters;               /* PCG iterations (summed over refinement sweeps)          */
   int32_t converged;           /* 1 if the stopping rule was met                          */
-  int32_t ir_sweeps;           /* mixed: outer refinement sweeps                           */
+  int32_t ir_sweeps;           /* refinement: preconditioner applications (dual solves)
+                                  after the first solve                                   */
   int32_t n_coarse;            /* dimension of the coarse space (columns of G)            */
   int64_t n_lambda;            /* number of Lagrange multipliers                          */
   double rel_res;              /* final ||P r|| / ||P r_0||                               */

@@ -24,6 +24,8 @@ using namespace feti;
 namespace {
 
 thread_local std::string g_setup_error;
+constexpr int kGmresRestart = 30;   // Krylov vectors per flexible GMRES cycle of the refinement
+constexpr int kDotBatch = 64;       // dot products per multi_dot call
 
 struct DeviceAlloc {
   void* (*fn)(size_t, void*, void*) = nullptr;
@@ -63,6 +65,17 @@ struct feti_problem {
   // (as for mixed precision) recovers the exact step
   bool approx_tangent = false;
   bool refined_out = false;     // the last result is in d_uglob
+  // FETI_LOAD_STIFFNESS in a Newton step: the assembled operator of the
+  // refinement includes -tau d f_p / dU at the state ls_U
+  bool ls_on = false;
+  const double* ls_U = nullptr;
+  double ls_tau = 0.0;
+  // flexible GMRES of the refinement: restart length gm, Krylov vectors V
+  // (gm + 1) and preconditioned vectors Z (gm) of n_dof entries, work vector,
+  // dot-product partials (device and pinned host), Hessenberg and rotations
+  int gm = 0;
+  double *d_gv = nullptr, *d_gz = nullptr, *d_gw = nullptr, *d_gdots = nullptr, *h_gdots = nullptr;
+  std::vector<double> gm_H, gm_g, gm_c, gm_s, gm_y, gm_h;
   int n_coarse = 0;
   int nq = 0;   // coarse tiles
   DevIdx di;
@@ -611,11 +624,26 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_bv, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
-  if (P.mixed || (p->opt.flags & (FETI_PROFILE | FETI_KERNEL6))) {   // refinement / residual report
+  if (P.mixed || (p->opt.flags & (FETI_PROFILE | FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // refinement / residual report
     TRY(dalloc(p, p->d_f0, (size_t)P.NF));
     TRY(dalloc(p, p->d_uglob, (size_t)P.n_dof));
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
     vec_fill(P.n_dof, 0.0, p->d_zero, p->stream);
+  }
+  if (P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // flexible GMRES
+    const int m = std::min(std::max(p->opt.ir_max, 1), kGmresRestart);
+    p->gm = m;
+    TRY(dalloc(p, p->d_gv, (size_t)(m + 1) * P.n_dof));
+    TRY(dalloc(p, p->d_gz, (size_t)m * P.n_dof));
+    TRY(dalloc(p, p->d_gw, (size_t)P.n_dof));
+    TRY(dalloc(p, p->d_gdots, (size_t)kDotBatch * DOT_PARTS));
+    HIPCHK(hipHostMalloc((void**)&p->h_gdots, (size_t)kDotBatch * DOT_PARTS * sizeof(double), hipHostMallocDefault));
+    p->gm_H.assign((size_t)(m + 1) * m, 0.0);
+    p->gm_g.assign(m + 1, 0.0);
+    p->gm_c.assign(m, 0.0);
+    p->gm_s.assign(m, 0.0);
+    p->gm_y.assign(m, 0.0);
+    p->gm_h.assign(m + 1, 0.0);
   }
   PcgScratch& o = p->own;
   TRY(dalloc(p, o.dots, 2 * DOT_PARTS));
@@ -624,8 +652,8 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, o.state, 1));
   TRY(dalloc(p, o.ticket, 4));
   HIPCHK(hipMemsetAsync(o.ticket, 0, 4 * sizeof(int), p->stream));
-  TRY(dalloc(p, o.fpart, 2 * 256));
-  TRY(dalloc(p, o.apart, 256));
+  TRY(dalloc(p, o.fpart, 2 * FUSE_BLOCKS));
+  TRY(dalloc(p, o.apart, FUSE_BLOCKS));
   TRY(dalloc(p, p->d_qdense, (size_t)max_coarse * max_coarse));
   p->ldg = max_coarse;
   TRY(dalloc(p, o.gpart, (size_t)4 * max_coarse));
@@ -832,6 +860,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.ell_col = p->d_ell_col;
   m.ell_val = p->d_ell_val;
   m.NF = P.NF;
+  m.dmask = p->d_dmask;
   m.test_rotations = (P.any_hgo && U_dev && !(p->opt.flags & FETI_KERNEL6)) ? 1 : 0;
   p->approx_tangent = P.any_hgo && U_dev && (p->opt.flags & FETI_KERNEL6);
   m.rfull = p->d_rfull;
@@ -904,7 +933,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   dense(p, P.sched_lauum);
   {
     bool any_partial = false;
-    for (const auto& si : P.sub) any_partial |= (si.floating && si.n_modes < 6);
+    for (const auto& si : P.sub) any_partial |= (si.floating == 1 && si.n_modes < 6);
     if (any_partial) {
       if (P.mixed)
         launch_woodbury<float>(P.n_sub, P.max_nt_b, p->d_tasks + XT.first, XT.count, p->d_sub, (float*)p->d_X,
@@ -1134,21 +1163,68 @@ feti_status profile_gemv(feti_problem* p) {
   return FETI_OK;
 }
 
+// Dot products of w with up to kDotBatch vectors a_i (two per launch), from
+// fixed partitions summed on the host in a fixed order: deterministic.
+feti_status multi_dot(feti_problem* p, int64_t n, const double* const* a, int k, const double* w, double* out) {
+  for (int i = 0; i < k; i += 2)
+    pcg_dot(n, a[i], w, i + 1 < k ? a[i + 1] : nullptr, w, p->d_gdots + (size_t)i * DOT_PARTS, nullptr, p->stream);
+  const size_t cnt = (size_t)((k + 1) / 2) * 2 * DOT_PARTS;
+  HIPCHK(hipMemcpyAsync(p->h_gdots, p->d_gdots, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < k; ++i) {
+    const double* part = p->h_gdots + (size_t)(i / 2) * 2 * DOT_PARTS + (i & 1);
+    double acc = 0.0;
+    for (int b = 0; b < DOT_PARTS; ++b) acc += part[2 * b];
+    out[i] = acc;
+  }
+  return FETI_OK;
+}
+
+// y = A x on the free DOFs of global vectors (Dirichlet DOFs of y are 0),
+// with the FP64 sparse local stiffnesses: A = K, or K - tau d f_p / dU with
+// the follower pressure's load stiffness (exact Newton step).  f0: local
+// loads (y = assembled f0 - A x), or NULL (y = A x).
+void apply_assembled(feti_problem* p, const double* x, const double* f0, double* y) {
+  const HostPlan& P = p->P;
+  hipStream_t st = p->stream;
+  local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
+                 p->d_ell_val, p->d_dmask, x, p->d_ul, f0, p->d_t, st);
+  vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_t, p->d_dmask, p->d_zero, y, 1, st);
+  if (!f0) vec_axpby(P.n_dof, -1.0, y, 0.0, y, st);   // -(0 - K x)
+  if (p->ls_on) {
+    PressureArgs pa;
+    pa.n_nodes = P.n_nodes;
+    pa.xyz = p->d_xyz;
+    pa.U = p->ls_U;
+    pa.pface = p->d_pface;
+    pa.pf_ptr = p->d_pf_ptr;
+    pa.pf_ent = p->d_pf_ent;
+    pa.pressure = P.pressure;
+    asm_pressure_dir(pa, x, p->d_dmask, p->d_out, st);
+    // A x = K x - tau D x;  f0 - A x = (f0 - K x) + tau D x
+    vec_axpby(P.n_dof, f0 ? p->ls_tau : -p->ls_tau, p->d_out, 1.0, y, st);
+  }
+}
+
 // Solve for the local right-hand sides in d_f and the Dirichlet data in
-// d_dvals; the global result goes to d_uglob (mixed) or stays in d_u.
-// FP64: one dual solve.  Mixed (FP32 local factors): iterative refinement on
-// the assembled problem -- the FP64 residual f - K u of the current global
-// displacement is computed from the FP64 sparse local stiffnesses and the
-// correction solves K du = r (zero Dirichlet data) with the FP32 factors, the
-// assembled r split evenly over the subdomain copies of each node (a torn
-// residual would carry the full interface forces into the correction, whose
-// dual error then scales with them rather than with r),
-// until ||r|| <= ir_tol ||f|| or ir_max corrections.
+// d_dvals; the global result goes to d_uglob (refined) or stays in d_u.
+// One dual solve, unless the FETI solve is only an approximation of the
+// assembled FP64 operator A (FP32 local factors; six-mode kernels of stressed
+// tangents; or the exact Newton step, whose A includes the follower-load
+// stiffness that the symmetric local tangents leave out).  Then the result
+// is refined by flexible GMRES on the assembled system A x = b (free DOFs,
+// FP64 sparse local stiffnesses), right-preconditioned by the FETI solve:
+// each preconditioner application is a dual solve with zero Dirichlet data
+// whose load is the Krylov vector split evenly over the subdomain copies of
+// each node (a torn load would carry the full interface forces into the
+// correction).  Classical Gram-Schmidt with one reorthogonalisation, Givens
+// rotations on the host; restarted every kGmresRestart vectors; stops at
+// ||b - A x|| <= ir_tol ||b|| or after ir_max preconditioner applications.
 feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   HostPlan& P = p->P;
   hipStream_t st = p->stream;
   feti_status s = solve_core(p, stats, p->opt.rtol);
-  const bool refine = P.mixed || p->approx_tangent;
+  const bool refine = P.mixed || p->approx_tangent || p->ls_on;
   p->refined_out = false;
   if (!refine || (s != FETI_OK && s != FETI_ENOCONV)) {
     if ((s == FETI_OK || s == FETI_ENOCONV) && p->profile) {
@@ -1173,40 +1249,97 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   int iters = stats ? stats->iters : 0;
   int launches = stats ? stats->kernel_gemv_launches : 0;
   const int64_t nd = P.n_dof;
+  const int m = p->gm;
+  auto V = [&](int j) { return p->d_gv + (size_t)j * nd; };
+  auto Z = [&](int j) { return p->d_gz + (size_t)j * nd; };
   vec_axpby(P.NF, 1.0, p->d_f, 0.0, p->d_f0, st);
   vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
-  double fnorm = 0.0, rnorm = 0.0;
+  double fnorm = 0.0, beta = 0.0;
   vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
   TRY(dev_norm(p, p->d_out, nd, &fnorm));
+  apply_assembled(p, p->d_uglob, p->d_f0, p->d_gw);   // r0 = b - A x0
+  TRY(dev_norm(p, p->d_gw, nd, &beta));
+  const double target = p->opt.ir_tol * fnorm;
+  HIPCHK(hipMemcpyAsync(p->d_dvals, p->d_zero, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
   int sweeps = 0;
-  double amp = 10.0, eta = 1.0, rprev = 0.0;
-  for (;;) {
-    local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
-                   p->d_ell_val, p->d_dmask, p->d_uglob, p->d_ul, p->d_f0, p->d_f, st);
-    vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
-    TRY(dev_norm(p, p->d_out, nd, &rnorm));
-    if (!(rnorm > p->opt.ir_tol * fnorm) || sweeps >= p->opt.ir_max) break;
-    // correction: the assembled residual, split evenly over the subdomain
-    // copies of each node, as loads; homogeneous Dirichlet data.  The dual
-    // solve only has to remove the part of the residual above the target.
-    // A dual reduction eta has reduced the primal residual by about
-    // amp * eta; amp is learnt from the sweeps so far (start: 10), with a
-    // margin of 2, and eta stays within [rtol, 0.1].
-    if (sweeps > 0) amp = std::max(1.0, (rnorm / rprev) / eta);
-    vec_distribute(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->d_uc_ptr, p->d_dmask, p->d_out,
-                   p->d_f, st);
-    HIPCHK(hipMemcpyAsync(p->d_dvals, p->d_zero, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
-    const double need = p->opt.ir_tol * fnorm / rnorm;
-    eta = std::min(0.1, std::max(p->opt.rtol, 0.5 * need / amp));
-    rprev = rnorm;
-    feti_stats cs{};
-    s = solve_core(p, &cs, eta, false);
-    if (s != FETI_OK && s != FETI_ENOCONV) return s;
-    iters += cs.iters;
-    launches += cs.kernel_gemv_launches;
-    vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_zero, p->d_out, 0, st);
-    vec_axpby(nd, 1.0, p->d_out, 1.0, p->d_uglob, st);
-    ++sweeps;
+  std::vector<double>& H = p->gm_H;   // (m+1) x m, column-major
+  std::vector<double>& g = p->gm_g;
+  std::vector<double>& cs = p->gm_c;
+  std::vector<double>& sn = p->gm_s;
+  std::vector<double>& y = p->gm_y;
+  std::vector<double>& hv = p->gm_h;
+  const double* ptrs[kDotBatch];
+  // dual tolerance of a preconditioner application: the reduction still
+  // needed, divided by the observed ratio amp of the primal reduction that a
+  // dual reduction eta achieved (learnt after every application, start 10),
+  // within [rtol, 1e-2].  On ill-conditioned problems a loose dual solve
+  // gives a poor direction, and amp then keeps the inner solves tight.
+  double amp = 10.0;
+  while (beta > target && sweeps < p->opt.ir_max) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    vec_axpby(nd, 1.0 / beta, p->d_gw, 0.0, V(0), st);
+    double cur = beta;
+    int k = 0;   // vectors in this cycle
+    for (int j = 0; j < m && sweeps < p->opt.ir_max; ++j) {
+      // preconditioner: a dual solve on the load V_j, to a relative dual
+      // tolerance that follows the residual still to be removed
+      const double eta = std::min(1e-2, std::max(p->opt.rtol, 0.5 * (target / cur) / amp));
+      vec_distribute(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->d_uc_ptr, p->d_dmask, V(j), p->d_f,
+                     st);
+      feti_stats cst{};
+      s = solve_core(p, &cst, eta, false);
+      if (s != FETI_OK && s != FETI_ENOCONV) return s;
+      iters += cst.iters;
+      launches += cst.kernel_gemv_launches;
+      ++sweeps;
+      vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_zero, Z(j), 0, st);
+      // w = A z_j, orthogonalised against V_0..V_j (two passes)
+      apply_assembled(p, Z(j), nullptr, p->d_gw);
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i <= j; ++i) ptrs[i] = V(i);
+        TRY(multi_dot(p, nd, ptrs, j + 1, p->d_gw, hv.data()));
+        for (int i = 0; i <= j; ++i) {
+          vec_axpby(nd, -hv[i], V(i), 1.0, p->d_gw, st);
+          H[(size_t)j * (m + 1) + i] += hv[i];
+        }
+      }
+      double hn = 0.0;
+      TRY(dev_norm(p, p->d_gw, nd, &hn));
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      if (hn > 0.0) vec_axpby(nd, 1.0 / hn, p->d_gw, 0.0, V(j + 1), st);
+      // Givens rotations of column j
+      double* col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = den > 0 ? col[j] / den : 1.0;
+      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      const double prev = cur;
+      cur = std::fabs(g[j + 1]);
+      if (prev > 0.0) amp = std::max(1.0, (cur / prev) / eta);
+      k = j + 1;
+      if (cur <= target || hn == 0.0) break;
+    }
+    // x += Z y with H(0:k, 0:k) y = g(0:k)
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= H[(size_t)l * (m + 1) + i] * y[l];
+      const double d = H[(size_t)i * (m + 1) + i];
+      y[i] = d != 0.0 ? acc / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) vec_axpby(nd, y[i], Z(i), 1.0, p->d_uglob, st);
+    // true residual of the updated iterate
+    apply_assembled(p, p->d_uglob, p->d_f0, p->d_gw);
+    TRY(dev_norm(p, p->d_gw, nd, &beta));
   }
   p->refined_out = true;
   TRY(profile_gemv(p));
@@ -1215,10 +1348,10 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     stats->ir_sweeps = sweeps;
     stats->kernel_gemv_launches = launches;
     stats->kernel_gemv_ms = p->prof_gemv_n ? p->prof_gemv_ms / p->prof_gemv_n : 0.0;
-    stats->res_primal = fnorm > 0 ? rnorm / fnorm : 0.0;
+    stats->res_primal = fnorm > 0 ? beta / fnorm : 0.0;
   }
-  if (p->opt.ir_max > 0 && !(rnorm <= p->opt.ir_tol * fnorm)) {
-    p->err = "refinement did not reach ir_tol within ir_max corrections";
+  if (p->opt.ir_max > 0 && !(beta <= target)) {
+    p->err = "refinement did not reach ir_tol within ir_max preconditioner applications";
     return FETI_ENOCONV;
   }
   return FETI_OK;
@@ -1391,6 +1524,7 @@ feti_status feti_solve_noalloc(feti_problem* p, double load_factor, double* u, f
 namespace {
 
 feti_status solve_linear_call(feti_problem* p, double load_factor, double* u, feti_stats* stats) {
+  p->ls_on = false;
   if (!u) {
     p->err = "u is NULL";
     return FETI_EINVAL;
@@ -1528,7 +1662,11 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
   r.dvals = p->d_dvals;
   r.f = p->d_f;
   asm_rhs(r, st);
+  p->ls_on = (p->opt.flags & FETI_LOAD_STIFFNESS) && !P.pface.empty() && P.pressure != 0.0 && tau != 0.0;
+  p->ls_U = Ud;
+  p->ls_tau = tau;
   feti_status s = solve_refined(p, stats);
+  p->ls_on = false;
   if (s != FETI_OK && s != FETI_ENOCONV) return s;
   feti_status s2 = write_output(p, dU, 0);
   if (s2 != FETI_OK) return s2;
@@ -1567,6 +1705,7 @@ void feti_destroy(feti_problem* p) {
   if (p->h_state) (void)hipHostFree(p->h_state);
   if (p->h_hist) (void)hipHostFree(p->h_hist);
   if (p->h_dots) (void)hipHostFree(p->h_dots);
+  if (p->h_gdots) (void)hipHostFree(p->h_gdots);
   if (p->stream_c) {
     (void)hipStreamSynchronize(p->stream_c);
     (void)hipStreamDestroy(p->stream_c);

@@ -423,9 +423,13 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     si.nt_i = ceil_tiles(si.n_ii);
     si.nt_b = ceil_tiles(si.n_b);
     si.nt = si.nt_i + si.nt_b;
-    si.floating = (P.af || !has_dir) ? 1 : 0;
-    si.n_modes = si.floating ? 6 : 0;
-    if (si.floating && n_b == 0) return "floating subdomain " + std::to_string(s) + " has no interface";
+    // A classical subdomain with Dirichlet DOFs has the partial kernel of the
+    // rigid modes that vanish on them (none for a clamped face; rotations
+    // about a clamped vertex or edge; modes free of a constrained component),
+    // section 4.3.  Its dimension is found on the device (k_modes).
+    si.floating = (P.af || !has_dir) ? 1 : 2;
+    si.n_modes = si.floating == 1 ? 6 : 0;
+    if (si.floating == 1 && n_b == 0) return "floating subdomain " + std::to_string(s) + " has no interface";
     int pi = 0, pb = si.nt_i * TS, px = si.nt_i * TS + si.n_if;
     for (int q = 0; q < si.n_nodes; ++q)
       for (int c = 0; c < 3; ++c) {

@@ -31,8 +31,11 @@ struct SubInfo {
   int32_t n_ii, n_b;    // interior / constraint DOFs (without padding)
   int32_t nt_i, nt_b, nt;
   int32_t node_off;     // offset into local-node arrays
-  int32_t floating;     // has a rigid-body kernel
-  int32_t n_modes;      // kernel dimension used (0, 3..6)
+  int32_t floating;     // 0: no rigid-body kernel; 1: floating (all six rigid modes regularise,
+                        // the inverse is corrected for those outside the kernel); 2: classical
+                        // subdomain touching the Dirichlet boundary (kernel: the rigid modes that
+                        // vanish on its Dirichlet DOFs, found on the device; only they regularise)
+  int32_t n_modes;      // kernel dimension used (0..6)
   int32_t coarse_off;   // first coarse index of this subdomain
   int32_t n_if;         // interface DOFs (with multipliers): the first n_if of the trailing block
   int32_t env_off;      // offset of its tile envelope (first nonzero tile column of each tile row)

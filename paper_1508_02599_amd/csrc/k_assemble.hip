@@ -415,6 +415,60 @@ void asm_pressure(const PressureArgs& p, hipStream_t s) {
   if (p.n_nodes) hipLaunchKernelGGL(k_pressure, dim3((unsigned)((p.n_nodes + 255) / 256)), dim3(256), 0, s, p);
 }
 
+// Load stiffness of the follower pressure applied to a direction z: the
+// derivative of f_a = -p int N_a (x,1 x x,2) deta along x -> x + z is
+//   out_a = -p int N_a (z,1 x x,2 + x,1 x z,2) deta,
+// with z,k the same bilinear interpolation of the corner values z_c as x,k.
+// One thread per node sums over its faces in a fixed order (no atomics);
+// Dirichlet DOFs (dmask) get 0.
+__global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, const uint8_t* __restrict__ dmask,
+                               double* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P.n_nodes) return;
+  double f[3] = {0, 0, 0};
+  const double g = 0.57735026918962576451;
+  const double e1[4] = {-1, 1, 1, -1}, e2[4] = {-1, -1, 1, 1};
+  for (int k = P.pf_ptr[n]; k < P.pf_ptr[n + 1]; ++k) {
+    const int64_t fc = P.pf_ent[k];
+    const int64_t face = fc / 4;
+    const int cn = (int)(fc % 4);
+    double x[4][3], dz[4][3];
+    for (int q = 0; q < 4; ++q) {
+      const int64_t nd = P.pface[face * 4 + q];
+      for (int d = 0; d < 3; ++d) {
+        x[q][d] = P.xyz[nd * 3 + d] + (P.U ? P.U[nd * 3 + d] : 0.0);
+        dz[q][d] = z[nd * 3 + d];
+      }
+    }
+    for (int g1 = 0; g1 < 2; ++g1)
+      for (int g2 = 0; g2 < 2; ++g2) {
+        const double h1 = g1 ? g : -g, h2 = g2 ? g : -g;
+        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
+        for (int q = 0; q < 4; ++q) {
+          const double d1 = 0.25 * e1[q] * (1 + e2[q] * h2), d2 = 0.25 * e2[q] * (1 + e1[q] * h1);
+          for (int d = 0; d < 3; ++d) {
+            t1[d] += x[q][d] * d1;
+            t2[d] += x[q][d] * d2;
+            s1[d] += dz[q][d] * d1;
+            s2[d] += dz[q][d] * d2;
+          }
+        }
+        // s1 x t2 + t1 x s2
+        const double nv[3] = {s1[1] * t2[2] - s1[2] * t2[1] + t1[1] * s2[2] - t1[2] * s2[1],
+                              s1[2] * t2[0] - s1[0] * t2[2] + t1[2] * s2[0] - t1[0] * s2[2],
+                              s1[0] * t2[1] - s1[1] * t2[0] + t1[0] * s2[1] - t1[1] * s2[0]};
+        const double N = 0.25 * (1 + e1[cn] * h1) * (1 + e2[cn] * h2);
+        for (int d = 0; d < 3; ++d) f[d] += -P.pressure * N * nv[d];
+      }
+  }
+  for (int d = 0; d < 3; ++d) out[3 * n + d] = dmask[3 * n + d] ? 0.0 : f[d];
+}
+
+void asm_pressure_dir(const PressureArgs& p, const double* z, const uint8_t* dmask, double* out, hipStream_t s) {
+  if (p.n_nodes)
+    hipLaunchKernelGGL(k_pressure_dir, dim3((unsigned)((p.n_nodes + 255) / 256)), dim3(256), 0, s, p, z, dmask, out);
+}
+
 // ---------------------------------------------------------------------------
 // Rigid-body kernel of each floating subdomain: translations and rotations
 // about the current centroid (rotations kept only if K annihilates them, for
@@ -476,11 +530,119 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
     for (int k = 0; k < 6; ++k) W[p * 6 + k] = r[k];
   }
   __syncthreads();
-  __shared__ int failed[3], nfail;
+  // A classical subdomain touching the Dirichlet boundary (floating == 2): its
+  // kernel is the set of rigid modes that vanish on its Dirichlet DOFs, the
+  // null space of R_D (the six modes at those DOFs).  With the rotations
+  // scaled by the subdomain's radius Lr, the 6x6 Gram matrix R_D^T R_D is
+  // diagonalised (cyclic Jacobi, one thread) and W is rotated onto its
+  // eigenvectors, smallest eigenvalue first: the columns with eigenvalue at
+  // most 1e-10 of the largest span the kernel.
+  __shared__ int n_cand;
+  if (s.floating == 2) {
+    __shared__ double Mg[6][6], Ev[6][6];
+    double lr = 0.0;
+    for (int q = tid; q < s.n_nodes; q += 256) {
+      const int64_t g = M.loc_node[s.node_off + q];
+      for (int d = 0; d < 3; ++d) {
+        const double x = M.xyz[g * 3 + d] + (M.U ? M.U[g * 3 + d] : 0.0) - cen[d];
+        lr += x * x;
+      }
+    }
+    const double Lr = sqrt(block_sum(lr, red) / s.n_nodes);
+    const double il = Lr > 0.0 ? 1.0 / Lr : 1.0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b) {
+        double acc = 0.0;
+        for (int q = tid; q < s.n_nodes; q += 256) {
+          const int64_t g = M.loc_node[s.node_off + q];
+          double x[3];
+          for (int d = 0; d < 3; ++d) x[d] = (M.xyz[g * 3 + d] + (M.U ? M.U[g * 3 + d] : 0.0) - cen[d]) * il;
+          for (int c = 0; c < 3; ++c) {
+            if (!M.dmask[g * 3 + c]) continue;
+            double r[6] = {0, 0, 0, 0, 0, 0};
+            r[c] = 1.0;
+            if (c == 0) { r[4] = x[2]; r[5] = -x[1]; }
+            if (c == 1) { r[3] = -x[2]; r[5] = x[0]; }
+            if (c == 2) { r[3] = x[1]; r[4] = -x[0]; }
+            acc += r[a] * r[b];
+          }
+        }
+        const double v = block_sum(acc, red);
+        if (tid == 0) Mg[a][b] = Mg[b][a] = v;
+      }
+    if (tid == 0) {
+      double A[6][6], V[6][6];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          A[a][b] = Mg[a][b];
+          V[a][b] = a == b ? 1.0 : 0.0;
+        }
+      for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = 0; b < 6; ++b) (a == b ? dia : off) += A[a][b] * A[a][b];
+        if (off <= 1e-32 * dia) break;
+        for (int a = 0; a < 5; ++a)
+          for (int b = a + 1; b < 6; ++b) {
+            if (A[a][b] == 0.0) continue;
+            const double th = 0.5 * (A[b][b] - A[a][a]) / A[a][b];
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+            for (int k = 0; k < 6; ++k) {
+              const double aka = A[k][a], akb = A[k][b];
+              A[k][a] = c * aka - sn * akb;
+              A[k][b] = sn * aka + c * akb;
+            }
+            for (int k = 0; k < 6; ++k) {
+              const double aak = A[a][k], abk = A[b][k];
+              A[a][k] = c * aak - sn * abk;
+              A[b][k] = sn * aak + c * abk;
+            }
+            for (int k = 0; k < 6; ++k) {
+              const double vka = V[k][a], vkb = V[k][b];
+              V[k][a] = c * vka - sn * vkb;
+              V[k][b] = sn * vka + c * vkb;
+            }
+          }
+      }
+      // eigenvalues ascending; coefficients of the unscaled modes (rotation rows / Lr)
+      int ord[6] = {0, 1, 2, 3, 4, 5};
+      for (int a = 1; a < 6; ++a)
+        for (int b = a; b > 0 && A[ord[b]][ord[b]] < A[ord[b - 1]][ord[b - 1]]; --b) {
+          const int t = ord[b];
+          ord[b] = ord[b - 1];
+          ord[b - 1] = t;
+        }
+      const double lmax = A[ord[5]][ord[5]];
+      int nk = 0;
+      for (int a = 0; a < 6; ++a) nk += A[ord[a]][ord[a]] <= 1e-10 * lmax;
+      n_cand = nk;
+      for (int j = 0; j < 6; ++j)
+        for (int k = 0; k < 6; ++k) Ev[j][k] = V[j][ord[k]] * (j >= 3 ? il : 1.0);
+    }
+    __syncthreads();
+    for (int64_t p = tid; p < n; p += 256) {
+      double r[6];
+      for (int k = 0; k < 6; ++k) {
+        double acc = 0.0;
+        for (int j = 0; j < 6; ++j) acc += W[p * 6 + j] * Ev[j][k];
+        r[k] = acc;
+      }
+      for (int k = 0; k < 6; ++k) W[p * 6 + k] = r[k];
+    }
+  } else if (tid == 0) {
+    n_cand = 6;
+  }
+  __syncthreads();
+  __shared__ int failed[6], nfail;
+  // candidates: floating == 1 keeps the translations (in the kernel of every
+  // tangent) and tests the rotations; floating == 2 tests its n_cand columns
+  const bool partial = s.floating == 2;
+  const int k_first = partial ? 0 : 3, k_last = partial ? n_cand : 6;
   if (tid == 0) {
-    nsel = 3;
+    nsel = k_first;
     nfail = 0;
-    for (int k = 0; k < 3; ++k) sel[k] = k;
+    for (int k = 0; k < k_first; ++k) sel[k] = k;
   }
   __syncthreads();
   if (M.test_rotations) {
@@ -491,7 +653,7 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
         if (M.ell_col[q * M.NF + s.full_off + p] >= 0) kf += v * v;
       }
     const double knorm = sqrt(block_sum(kf, red));
-    for (int k = 3; k < 6; ++k) {
+    for (int k = k_first; k < k_last; ++k) {
       double kr = 0.0, rr = 0.0;
       for (int64_t p = tid; p < n; p += 256) {
         double y = 0.0;
@@ -509,13 +671,16 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
       }
       __syncthreads();
     }
-    // kernel modes first, then the rotations the stressed tangent does not annihilate
-    if (tid == 0)
+    // kernel modes first, then the candidates the stressed tangent does not
+    // annihilate, then (floating == 2) the modes outside the kernel
+    if (tid == 0) {
       for (int q = 0; q < nfail; ++q) sel[nsel + q] = failed[q];
+      for (int k = k_last; k < 6; ++k) sel[nsel + nfail + (k - k_last)] = k;
+    }
     __syncthreads();
   } else {
     if (tid == 0) {
-      nsel = 6;
+      nsel = k_last;
       for (int k = 0; k < 6; ++k) sel[k] = k;
     }
     __syncthreads();
@@ -549,11 +714,15 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
     if (tid < 6) T[tid][k] *= inv;
     __syncthreads();
   }
-  // full basis R T (columns m..5 zero)
+  // full basis R T; a partially constrained subdomain regularises with its
+  // kernel modes only, so its other columns are zero
+  const int m_keep = partial ? n_kernel : m;
+  for (int64_t p = tid; p < nb * 6; p += 256)
+    if ((int)(p % 6) >= m_keep) Q[p] = 0.0;
   for (int64_t p = tid; p < n; p += 256) {
     for (int k = 0; k < 6; ++k) {
       double acc = 0.0;
-      if (k < m)
+      if (k < m_keep)
         for (int j = 0; j < m; ++j) acc += W[p * 6 + sel[j]] * T[j][k];
       rf[p * 6 + k] = acc;
     }

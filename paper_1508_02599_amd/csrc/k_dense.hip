@@ -834,7 +834,7 @@ __global__ __launch_bounds__(256) void k_wb_y(const SubInfo* __restrict__ subs, 
   __shared__ double red[4][TS][3];
   const SubInfo s = subs[blockIdx.y];
   const int I = blockIdx.x;
-  if (!s.floating || s.n_modes >= 6 || I >= s.nt_b) return;
+  if (s.floating != 1 || s.n_modes >= 6 || I >= s.nt_b) return;
   const int mk = s.n_modes, mv = 6 - mk;
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
   double acc[3] = {0, 0, 0};
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(256) void k_wb_m(const SubInfo* __restrict__ subs, 
   __shared__ double red[256];
   __shared__ double Cm[3][3];
   const SubInfo s = subs[blockIdx.x];
-  if (!s.floating || s.n_modes >= 6) return;
+  if (s.floating != 1 || s.n_modes >= 6) return;
   const int mk = s.n_modes, mv = 6 - mk;
   const int64_t nb = (int64_t)s.nt_b * TS;
   for (int k = 0; k < mv; ++k)
@@ -907,7 +907,7 @@ __global__ __launch_bounds__(256) void k_wb_update(const Task* __restrict__ task
                                                    T* X) {
   const Task t = tasks[blockIdx.x];
   const SubInfo s = subs[t.sub];
-  if (!s.floating || s.n_modes >= 6) return;
+  if (s.floating != 1 || s.n_modes >= 6) return;
   const double* M = Mm + t.sub * 9;
   T* C = X + s.x_off + tidx(t.i, t.j) * TS2;
   const double* Yi = Y + (s.b_off + (int64_t)t.i * TS) * 3;

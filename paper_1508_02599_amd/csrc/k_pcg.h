@@ -6,6 +6,7 @@
 namespace feti {
 
 constexpr int DOT_PARTS = 256;   // fixed partition of every dot product
+constexpr int FUSE_BLOCKS = 2048;   // most row blocks of a fused per-multiplier kernel
 
 // Scalars of the projected PCG, resident on the device so that iterations can
 // be captured in a HIP graph and run without host synchronisation.
@@ -21,8 +22,8 @@ struct PcgState {
 struct PcgScratch {
   PcgState* state = nullptr;
   int* ticket = nullptr;       // 4 counters
-  double* fpart = nullptr;     // 2 * 256
-  double* apart = nullptr;     // 256
+  double* fpart = nullptr;     // 2 * FUSE_BLOCKS
+  double* apart = nullptr;     // FUSE_BLOCKS
   double* dots = nullptr;      // 2 * DOT_PARTS
   double* gpart = nullptr;     // 4 * 6 * n_sub
   double* hist = nullptr;      // 2 * hist_cap
@@ -190,6 +191,9 @@ struct PressureArgs {
   double* fnodal = nullptr;           // [n_dof]
 };
 void asm_pressure(const PressureArgs& p, hipStream_t s);
+// out = (d f_p / d x) z: the follower pressure's load stiffness applied to z
+// (global node-major vectors; Dirichlet DOFs of out are 0).
+void asm_pressure_dir(const PressureArgs& p, const double* z, const uint8_t* dmask, double* out, hipStream_t s);
 
 struct ModesArgs {
   int n_sub = 0;
@@ -202,6 +206,7 @@ struct ModesArgs {
   const int32_t* ell_col = nullptr;   // [ELLW][NF] slot-major
   const double* ell_val = nullptr;
   int64_t NF = 0;
+  const uint8_t* dmask = nullptr;      // [n_dof] Dirichlet DOFs (partially constrained subdomains)
   int test_rotations = 0;              // keep a rotation only if K annihilates it
   double kernel_tol = 1e-12;
   double* rfull = nullptr;             // [NF*6]

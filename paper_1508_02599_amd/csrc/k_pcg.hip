@@ -540,7 +540,8 @@ __global__ __launch_bounds__(256) void k_proj_apply(
   if (mode == 1) {
     // alpha = rho / s.q from the scatter's block partials, summed in the same
     // order by every block; block 0 records it (or the breakdown)
-    double pq = threadIdx.x < napart ? apart[threadIdx.x] : 0.0, unused = 0.0;
+    double pq = 0.0, unused = 0.0;
+    for (int k = threadIdx.x; k < napart; k += 256) pq += apart[k];
     block_reduce2(pq, unused, ra, rb);
     if (!(pq > 0.0)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -668,7 +669,7 @@ __global__ __launch_bounds__(256) void k_local_residual(
     return;
   }
   const double* u = ul + subs[f_sub[p]].full_off;
-  double acc = f[p];
+  double acc = f ? f[p] : 0.0;   // f NULL: r = -K u
 #pragma unroll 1
   for (int k0 = 0; k0 < ELLW; k0 += RES_C) {
     int c[RES_C];
@@ -969,7 +970,11 @@ void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_co
                     const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s) {
   hipLaunchKernelGGL(k_distribute, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, uc_ptr, dmask, rg, r);
 }
-constexpr int FUSE_BLOCKS = 256;
+// Row blocks of the fused per-multiplier kernels: up to FUSE_BLOCKS (eight
+// per compute unit, so that the gathers of a row overlap), fewer for short
+// vectors.  The block partial sums of their reductions are then summed in a
+// fixed order.
+int fuse_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(FUSE_BLOCKS, (n + 255) / 256)); }
 void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb, const PcgState* st,
                   hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_gather_s, grid1(d.NB), dim3(256), 0, s, d.NB, d.g_ptr, d.g_row, d.g_coef, z, sv, xb, st);
@@ -977,13 +982,14 @@ void pcg_gather_s(const DevIdx& d, const double* z, const double* sv, double* xb
 void pcg_scatter_dot_alpha_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
                               const double* yb, const double* z, double* sv, double* q, double* part,
                               PcgState* st, double* gpart, int ldg, hipStream_t s) {
-  const int nb = FUSE_BLOCKS + (coarse ? GT_CHUNKS * n_sub : 0);
-  hipLaunchKernelGGL(k_scatter_dot_alpha_gt, dim3(nb), dim3(256), 0, s, d.n_lam, FUSE_BLOCKS, d.r_b0, d.r_c0, d.r_b1,
+  const int nrow = fuse_rows(d.n_lam);
+  const int nb = nrow + (coarse ? GT_CHUNKS * n_sub : 0);
+  hipLaunchKernelGGL(k_scatter_dot_alpha_gt, dim3(nb), dim3(256), 0, s, d.n_lam, nrow, d.r_b0, d.r_c0, d.r_b1,
                      d.r_c1, yb, z, sv, q, part, st, subs, d.c_ptr, d.c_col, d.c_v0, rbv, gpart, ldg);
 }
 void pcg_scatter_w_gt(const DevIdx& d, int n_sub, int coarse, const SubInfo* subs, const double* rbv,
                       const double* y, double* out, const PcgState* st, double* gpart, int ldg, hipStream_t s) {
-  const int nrow = (int)std::min<int64_t>(FUSE_BLOCKS, (d.n_lam + 255) / 256);
+  const int nrow = fuse_rows(d.n_lam);
   const int nb = nrow + (coarse ? GT_CHUNKS * n_sub : 0);
   if (nb) hipLaunchKernelGGL(k_scatter_w_gt, dim3(nb), dim3(256), 0, s, d.n_lam, nrow, d.r_b0, d.r_c0, d.r_b1, d.r_c1,
                              d.r_w, y, out, st, subs, d.c_ptr, d.c_col, d.c_v1, rbv, gpart, ldg);
@@ -1000,7 +1006,8 @@ void pcg_proj_apply(int mode, int init, const DevIdx& d, int coarse, const int2*
                     const double* ac, double* x, const double* q, const double* sv, double* lam, double* out,
                     const double* w, double* part, int* ticket, PcgState* st, double* hist, hipStream_t s,
                     const double* apart) {
-  hipLaunchKernelGGL(k_proj_apply, dim3(FUSE_BLOCKS), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, rco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist, apart, FUSE_BLOCKS);
+  const int nrow = fuse_rows(d.n_lam);
+  hipLaunchKernelGGL(k_proj_apply, dim3(nrow), dim3(256), 0, s, mode, init, d.n_lam, coarse, d.r_b0, d.r_c0, d.r_b1, d.r_c1, rco, rbv, ac, x, q, sv, lam, out, w, part, ticket, st, hist, apart, nrow);
 }
 void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hipStream_t s) {
   if (d.NB) hipLaunchKernelGGL(k_fill_bco, grid1(d.NB), dim3(256), 0, s, d.NB, d.b_sub, subs, bco);
@@ -1084,8 +1091,8 @@ PcgScratch noalloc_layout(void* base, int n_sub) {
   PcgScratch sc;
   sc.state = reinterpret_cast<PcgState*>(take(sizeof(PcgState)));
   sc.ticket = reinterpret_cast<int*>(take(4 * sizeof(int)));
-  sc.fpart = reinterpret_cast<double*>(take(2 * 256 * sizeof(double)));
-  sc.apart = reinterpret_cast<double*>(take(256 * sizeof(double)));
+  sc.fpart = reinterpret_cast<double*>(take(2 * FUSE_BLOCKS * sizeof(double)));
+  sc.apart = reinterpret_cast<double*>(take(FUSE_BLOCKS * sizeof(double)));
   sc.dots = reinterpret_cast<double*>(take(2 * DOT_PARTS * sizeof(double)));
   sc.gpart = reinterpret_cast<double*>(take((size_t)4 * 6 * std::max(n_sub, 1) * sizeof(double)));
   sc.hist = reinterpret_cast<double*>(take((size_t)2 * kNoAllocMaxIt * sizeof(double)));
@@ -1093,7 +1100,7 @@ PcgScratch noalloc_layout(void* base, int n_sub) {
   return sc;
 }
 static_assert(sizeof(PcgState) <= 256, "state slot");
-static_assert(256 + 256 + 4096 + 2048 + 2 * DOT_PARTS * 8 + (size_t)4 * 6 * kMaxSub * 8 + 256 +
+static_assert(256 + 256 + 2 * FUSE_BLOCKS * 8 + FUSE_BLOCKS * 8 + 2 * DOT_PARTS * 8 + (size_t)4 * 6 * kMaxSub * 8 + 256 +
                   (size_t)2 * kNoAllocMaxIt * 8 <= kNoAllocScratchBytes,
               "the largest scratch set fits the static array");
 

@@ -29,6 +29,7 @@ FETI_PROFILE = 2
 FETI_AUTOTUNE = 4
 AUTOTUNE_FACTORISATIONS = 3   # factorisations that time the update forms (FETI_AUTOTUNE)
 FETI_KERNEL6 = 8
+FETI_LOAD_STIFFNESS = 16
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -166,10 +167,10 @@ def _check(lib, handle, status):
 
 def feti_setup(mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-               torch_allocator=False, profile=False, autotune=True, kernel6=False):
+               torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False):
     """Create a problem handle (see :class:`Problem`)."""
     return Problem(mesh, variant, precond, precision, rtol, max_it, graph_block, ir_tol, ir_max,
-                   hip_stream, device_ptrs, torch_allocator, profile, autotune, kernel6)
+                   hip_stream, device_ptrs, torch_allocator, profile, autotune, kernel6, load_stiffness)
 
 
 class Problem:
@@ -177,7 +178,7 @@ class Problem:
 
     def __init__(self, mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                  graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-                 torch_allocator=False, profile=False, autotune=True, kernel6=False):
+                 torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False):
         self.lib = load_library()
         self.n_dof = 3 * int(np.asarray(mesh.xyz).shape[0])
         keep = []
@@ -193,7 +194,8 @@ class Problem:
         o.graph_block = graph_block
         o.hip_stream = hip_stream
         o.flags = ((FETI_DEVICE_PTRS if device_ptrs else 0) | (FETI_PROFILE if profile else 0)
-                   | (FETI_AUTOTUNE if autotune else 0) | (FETI_KERNEL6 if kernel6 else 0))
+                   | (FETI_AUTOTUNE if autotune else 0) | (FETI_KERNEL6 if kernel6 else 0)
+                   | (FETI_LOAD_STIFFNESS if load_stiffness else 0))
         self._cb = None
         if torch_allocator:
             import torch

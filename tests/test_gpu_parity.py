@@ -287,3 +287,56 @@ def test_six_mode_kernel_refined_to_exact_step(precision):
     assert st["n_coarse"] == 6 * m.n_sub
     assert abs(rn - rn_ref) <= 1e-9 * rn_ref
     assert err <= bar
+
+
+# ---------------------------------------------------------------- exact Newton (follower-load stiffness)
+@pytest.mark.parametrize("variant,precision,kernel6", [("af", "fp64", False), ("classical", "fp64", False),
+                                                       ("af", "mixed", False), ("af", "fp64", True)])
+def test_exact_newton_step_with_load_stiffness(variant, precision, kernel6):
+    """FETI_LOAD_STIFFNESS: the Newton step solves (K' - tau d f_p/dU) dU = r,
+    by flexible GMRES on the assembled system preconditioned by the FETI solve
+    of K'; it equals the oracle's exact Newton step (sparse LU of the
+    non-symmetric operator): from rest, and from the equilibrium of the first
+    load step (tau = 1/40) to the second (tau = 2/40), as in the load path."""
+    m = _small_tube()
+    bar = 1e-9 if precision == "fp64" else 1e-8
+    U1 = np.zeros(m.n_dofs)
+    for _ in range(20):
+        dU, rn = monolithic.newton_increment(m, U1, 1 / 40, load_stiffness=True)
+        U1 = U1 + dU
+        if rn < 1e-11:
+            break
+    for step, (U, tau) in enumerate([(np.zeros(m.n_dofs), 1 / 40), (U1, 2 / 40)]):
+        dU_ref, rn_ref = monolithic.newton_increment(m, U, tau, load_stiffness=True)
+        with _problem(m, variant=variant, precond="dirichlet", precision=precision, rtol=1e-8,
+                      ir_tol=1e-12 if precision == "fp64" else 1e-10, ir_max=60, load_stiffness=True,
+                      kernel6=kernel6) as p:
+            dU, rn, st = p.newton_step(U, tau)
+        err = _rel(dU, dU_ref)
+        print(f"exact newton {variant} {precision} k6={kernel6} step {step}: it={st['iters']} "
+              f"gmres={st['ir_sweeps']} err={err:.3e}")
+        assert abs(rn - rn_ref) <= 1e-9 * rn_ref
+        assert err <= bar
+
+
+# ---------------------------------------------------------------- classical FETI with partial kernels
+@pytest.mark.parametrize("variant,precond,precision", [("classical", "dirichlet", "fp64"),
+                                                       ("classical", "lumped", "fp64"),
+                                                       ("classical", "dirichlet", "mixed"),
+                                                       ("af", "lumped", "fp64")])
+def test_partial_kernels_parity(variant, precond, precision):
+    """Subdomains that touch the Dirichlet boundary at a vertex, along an edge,
+    or with one constrained component (section 4.3): the classical variant
+    keeps their partial kernels (3 + 1 + 1 + 4 x 3 coarse columns for the 8^3
+    cube in 2^3 boxes; the subdomain at the clamped quarter face has none) and
+    matches the direct solve."""
+    from workloads import partial_dirichlet_cube
+    m = partial_dirichlet_cube(8, 2)
+    ref = monolithic.solve_linear(m)
+    kw = dict(rtol=1e-11) if precision == "fp64" else dict(rtol=1e-8, ir_tol=1e-11, ir_max=20)
+    u, st = _solve(m, variant=variant, precond=precond, precision=precision, **kw)
+    err = _rel(u, ref)
+    print(f"partial kernels {variant} {precond} {precision}: it={st['iters']} coarse={st['n_coarse']} "
+          f"err={err:.3e}")
+    assert st["n_coarse"] == (17 if variant == "classical" else 48)
+    assert err <= (1e-9 if precision == "fp64" else 1e-8)
