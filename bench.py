@@ -253,84 +253,47 @@ def roofline(st_all, precision):
 
 
 def tube_load_path(args):
-    """The HGO tube under its inner-pressure ramp to 16 mmHg: tau = s/n,
-    s = 1..n (n = --load-steps, default 40: 0.4 mmHg per load step; the paper
+    """The HGO tube under its inner-pressure ramp to 16 mmHg in load
+    increments of 16/n mmHg (n = --load-steps, default 40: 0.4 mmHg; the paper
     likewise reports that its Newton method needs small pressure steps), each
-    load step solved by Newton from the previous equilibrium, every Newton
-    step one exact linearisation (FETI_LOAD_STIFFNESS: the follower-pressure
-    load stiffness is kept, so Newton converges quadratically) until
-    ||r|| <= newton_tol ||r_0|| of the load step.
+    load step solved by Newton from the previous equilibrium
+    (paper_1508_02599_amd.loadpath: inexact Newton forcing, load-step
+    cutting), every Newton step the exact linearisation (FETI_LOAD_STIFFNESS:
+    the follower-pressure load stiffness is kept, so Newton converges
+    quadratically) until ||r|| <= newton_tol ||r_0|| of the load step.
 
-    Each Newton step: assembly and factorisation at U_k with all six rigid
-    modes as the kernel of every floating subdomain (FETI_KERNEL6: stressed
-    local tangents of this mesh are indefinite in rotation directions, which
-    the six-mode regularisation keeps definite), one FETI solve, then flexible
-    GMRES on the assembled exact operator preconditioned by FETI solves until
-    ||b - A dU|| <= ir_tol ||b||.  The metric counts Newton steps (each one
-    factorisation and its FETI-preconditioned solve) per second of the whole
-    path.  Returns the JSON line."""
+    Each Newton step: assembly and factorisation at U_k with the kernels of
+    the stressed floating subdomains (translations, and the rotations whose
+    stress-induced stiffness ||K r|| is at most --kernel-tol ||K|| ||r||; the
+    tangent solved is then approximate and refined below), one FETI solve
+    warm-started from the previous step's multipliers (FETI_WARM_START) whose
+    dual problem is solved by projected GMRES (FETI_DUAL_GMRES: the stressed
+    local tangents are indefinite in rotation directions, so F is), then
+    flexible GMRES on the assembled exact operator preconditioned by FETI
+    solves.  The metric counts Newton steps (each one factorisation and its
+    FETI-preconditioned solve) per second of the whole path, rejected
+    attempts included in the time.  Returns the JSON line."""
     import torch
     from workloads import config_mesh
-    from paper_1508_02599_amd.feti import Problem, FetiError
+    from paper_1508_02599_amd.feti import Problem
+    from paper_1508_02599_amd.loadpath import run_load_path
 
     mesh = config_mesh(args.config)
     n = mesh.n_dofs
-    p = Problem(mesh, variant=args.variant, precond="dirichlet", precision=args.precision,
-                rtol=args.rtol if args.precision == "fp64" else args.mixed_rtol,
-                ir_tol=args.newton_ir_tol, ir_max=60, max_it=3000, device_ptrs=True, kernel6=True,
-                load_stiffness=True)
+    rtol = args.rtol if args.precision == "fp64" else args.mixed_rtol
+    p = Problem(mesh, variant=args.variant, precond="dirichlet", precision=args.precision, rtol=rtol,
+                ir_tol=args.newton_eta_max, ir_max=60, max_it=3000, device_ptrs=True, load_stiffness=True,
+                warm_start=not args.cold_start, dual_gmres=True, kernel_tol=args.kernel_tol)
     U = torch.zeros(n, dtype=torch.float64, device="cuda")
     for _ in range(2):      # autotuning factorisations (untimed)
         p.factor(U)
-    lat, its, gm, res_hist, newton_per_load = [], [], [], [], []
-
-    def step(Ux, tau):
-        d = torch.empty_like(Ux)
-        a = time.perf_counter()
-        _, rn, st = p.newton_step(Ux, tau, out=d)
-        lat.append(time.perf_counter() - a)
-        its.append(st["iters"])
-        gm.append(st["ir_sweeps"])
-        print(f"tau={tau:.4f} newton step {len(lat)}: res={rn:.3e} pcg_it={st['iters']} "
-              f"gmres={st['ir_sweeps']} {1e3 * lat[-1]:.0f} ms", file=sys.stderr, flush=True)
-        return d, rn
-
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    failed = None
-    nload = args.load_steps
-    for s in range(1, nload + 1):
-        tau = s / nload
-        r_start = None
-        k = 0
-        try:
-            while True:
-                dU, rn = step(U, tau)
-                if r_start is None:
-                    r_start = rn
-                if rn <= args.newton_tol * r_start:
-                    break
-                if k >= args.max_newton:
-                    failed = (f"Newton did not reach {args.newton_tol:g} in load step {s} (tau = {tau:g}) "
-                              f"within {args.max_newton} steps: |r| = {rn / r_start:.2e} of its start value")
-                    break
-                U += dU
-                k += 1
-        except FetiError as e:
-            failed = f"load step {s} (tau = {tau:g}), Newton step {k}: {e}"
-        newton_per_load.append(k)
-        if r_start:
-            res_hist.append(rn / r_start)
-        if failed:
-            break
-        if time.perf_counter() - t0 > args.time_budget:
-            failed = f"time budget of {args.time_budget:g} s spent after load step {s}"
-            break
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    r = run_load_path(p, U, args.load_steps, rtol=rtol, newton_tol=args.newton_tol, eta_max=args.newton_eta_max,
+                      max_newton=args.max_newton, time_budget=args.time_budget)
     p.close()
+    lat, its, gm = r["latency"], r["pcg"], r["gmres"]
     nsteps = len(lat)
-    done = len(newton_per_load) - (1 if failed and "load step" in failed and "budget" not in failed else 0)
+    total = r["wall_s"]
     line = {
         "metric": "FETI Newton steps/s on the HGO tube load path (each step one factorisation and its "
                   "FETI-preconditioned exact solve)",
@@ -339,19 +302,22 @@ def tube_load_path(args):
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-local/f64-global",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: two-layer HGO tube, 16x128x64 Q1-P0 elements in "
-                               f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, six-mode "
-                               f"kernels), inner pressure 16 mmHg x s/{nload}, s = 1..{nload}, exact Newton "
+                               f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, kernel "
+                               f"tolerance {args.kernel_tol:g}, projected dual GMRES, "
+                               f"{'cold' if args.cold_start else 'warm'} starts), inner pressure to 16 mmHg in "
+                               f"increments of {16.0 / args.load_steps:g} mmHg (halved on failure), exact Newton "
                                f"(follower-load stiffness) to |r| <= {args.newton_tol:g} |r_0| per load step",
                    "global_dofs": n},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
-        "load_steps_done": done, "load_steps": nload, "pressure_reached_mmHg": 16.0 * done / nload,
-        "newton_steps_per_load_step": newton_per_load,
-        "pcg_iterations": {"mean": float(np.mean(its)), "max": int(np.max(its))},
+        "pressure_reached_mmHg": 16.0 * r["tau_reached"], "load_steps_done": len(r["taus"]),
+        "newton_steps_per_load_step": r["newton_per_load"],
+        "accepted_steps": r["accepted_steps"], "rejected_steps": r["rejected_steps"], "cuts": r["cuts"],
+        "pcg_iterations": {"mean": float(np.mean(its)), "max": int(np.max(its)), "total": int(np.sum(its))},
         "gmres_iterations": {"mean": float(np.mean(gm)), "max": int(np.max(gm))},
-        "final_relative_residuals": res_hist,
+        "final_relative_residuals": r["res"],
     }
-    if failed:
-        line["error"] = failed
+    if r["error"]:
+        line["error"] = r["error"]
     return line
 
 
@@ -385,9 +351,12 @@ def main():
                     help="tube load path: residual reduction (relative to the start of a load step) "
                          "that ends it")
     ap.add_argument("--max-newton", type=int, default=12, help="tube load path: Newton steps per load step")
-    ap.add_argument("--newton-ir-tol", type=float, default=1e-10,
-                    help="tube load path: GMRES target of each Newton step, ||b - A dU|| <= tol ||b||")
+    ap.add_argument("--newton-eta-max", type=float, default=1e-3,
+                    help="tube load path: loosest GMRES target of a Newton step (inexact Newton)")
     ap.add_argument("--load-steps", type=int, default=40, help="tube load path: load increments to 16 mmHg")
+    ap.add_argument("--cold-start", action="store_true", help="tube load path: no multiplier warm starts")
+    ap.add_argument("--kernel-tol", type=float, default=1e-6,
+                    help="tube load path: rotations with ||K r|| <= tol ||K|| ||r|| join the local kernels")
     ap.add_argument("--time-budget", type=float, default=240.0,
                     help="tube load path: wall-clock limit (s); a partial path is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -135,6 +135,20 @@ typedef struct {
                                    by the FETI solve of the symmetric tangent K'(U), up to
                                    ir_tol / ir_max preconditioner applications                */
 
+#define FETI_WARM_START 0x20ull  /* the first dual solve of feti_solve / feti_newton_step starts
+                                   from the previous call's multipliers: lambda_0 = G (G^T G)^{-1} e
+                                   + c P lambda_prev, which keeps the constraint G^T lambda = e,
+                                   with the scale c that minimises the F-norm of the error along
+                                   P lambda_prev (one extra F application).  For sequences of
+                                   related solves: load ramps, Newton steps, request streams  */
+
+#define FETI_DUAL_GMRES 0x40ull  /* the dual problem is solved by projected GMRES (restarted every
+                                   100 vectors, right-preconditioned by P M^{-1} P) instead of PCG:
+                                   for local operators that are not positive definite, such as the
+                                   stressed tangents of a floating subdomain whose rotations are
+                                   not in its kernel (section 3.2 notes that the FETI methods work
+                                   with GMRES).  Same stopping rule; kappa_est is not computed  */
+
 typedef struct {
   feti_variant variant;
   feti_precond precond;
@@ -154,7 +168,14 @@ typedef struct {
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
   uint64_t flags;              /* FETI_DEVICE_PTRS | FETI_PROFILE | FETI_AUTOTUNE |
-                                  FETI_KERNEL6 | FETI_LOAD_STIFFNESS                      */
+                                  FETI_KERNEL6 | FETI_LOAD_STIFFNESS | FETI_WARM_START |
+                                  FETI_DUAL_GMRES                                         */
+  double kernel_tol;           /* rotation test of stressed floating subdomains: a rotation
+                                  r joins the kernel if ||K r|| <= kernel_tol ||K||_F ||r||
+                                  (0 => 1e-12, an exact kernel).  A larger value treats
+                                  rotations of small stress-induced stiffness as kernel
+                                  modes (an approximate tangent, refined by the flexible
+                                  GMRES against the exact operator as with FETI_KERNEL6)  */
 } feti_options;
 
 typedef struct {
@@ -186,6 +207,13 @@ typedef struct {
                                   tuned; -1 while tuning or without FETI_AUTOTUNE          */
   int32_t autotune_db;         /* FETI_AUTOTUNE: update launches that use the double-buffered
                                   form once tuned; -1 while tuning or without it          */
+  int32_t modified_pivots;     /* local pivots of the last factorisation that were not
+                                  positive and were replaced (modified Cholesky).  Allowed
+                                  only where the factors precondition a refinement against
+                                  the exact FP64 operator (FETI_MIXED, FETI_KERNEL6 at a
+                                  stressed state, FETI_LOAD_STIFFNESS), so the result stays
+                                  the exact solution; elsewhere such a pivot is
+                                  FETI_ENOTSPD                                            */
 } feti_stats;
 
 typedef struct feti_problem feti_problem;   /* opaque, owned by the library */
@@ -241,6 +269,13 @@ feti_status feti_solve_noalloc(feti_problem* p, double load_factor, double* u, f
  * Errors: as feti_factor and feti_solve. */
 feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, double* dU,
                              double* res_norm, feti_stats* stats);
+
+/* Change the dual stopping tolerance rtol and the refinement target ir_tol
+ * of later calls (same meaning as in feti_options), e.g. to solve each
+ * Newton step only as accurately as the Newton iteration needs (an inexact
+ * Newton method).  The factors and the captured iteration graph are kept.
+ * Errors: EINVAL (a tolerance outside (0, 1)). */
+feti_status feti_set_tolerances(feti_problem* p, double rtol, double ir_tol);
 
 /* Message of the last failed call on p (or of the last failed feti_setup when
  * p is NULL); valid until the next call on that problem. */

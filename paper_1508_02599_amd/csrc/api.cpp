@@ -26,6 +26,7 @@ namespace {
 thread_local std::string g_setup_error;
 constexpr int kGmresRestart = 30;   // Krylov vectors per flexible GMRES cycle of the refinement
 constexpr int kDotBatch = 64;       // dot products per multi_dot call
+constexpr int kDualRestart = 100;   // Krylov vectors per cycle of the projected dual GMRES
 
 struct DeviceAlloc {
   void* (*fn)(size_t, void*, void*) = nullptr;
@@ -64,6 +65,12 @@ struct feti_problem {
   // tangent, and the outer refinement against the exact sparse tangent
   // (as for mixed precision) recovers the exact step
   bool approx_tangent = false;
+  // the factors of the next factorisation serve only as the preconditioner of
+  // a refinement against the exact operator: non-positive pivots may be
+  // replaced (modified Cholesky); modified_pivots counts them
+  bool allow_modified = false;
+  int modified_pivots = 0;
+  int h_errinit[4] = {0, 0, 0, 0};
   bool refined_out = false;     // the last result is in d_uglob
   // FETI_LOAD_STIFFNESS in a Newton step: the assembled operator of the
   // refinement includes -tau d f_p / dU at the state ls_U
@@ -73,6 +80,18 @@ struct feti_problem {
   // flexible GMRES of the refinement: restart length gm, Krylov vectors V
   // (gm + 1) and preconditioned vectors Z (gm) of n_dof entries, work vector,
   // dot-product partials (device and pinned host), Hessenberg and rotations
+  // FETI_DUAL_GMRES: projected GMRES on the dual problem, restart length dm,
+  // Krylov vectors V (dm + 1), preconditioned vectors Z (dm), work vector;
+  // dual_target: absolute stopping target of a warm-started solve (or < 0)
+  bool dual_gmres = false;
+  int dm = 0;
+  double *d_dv = nullptr, *d_dz = nullptr, *d_dw = nullptr;
+  double dual_target = -1.0;
+  std::vector<double> dg_H, dg_g, dg_c, dg_s, dg_y, dg_h;
+  // FETI_WARM_START: multipliers of the previous call's first dual solve
+  double* d_lamp = nullptr;
+  bool have_prev = false;
+  double warm_scale = 0.0;
   int gm = 0;
   double *d_gv = nullptr, *d_gz = nullptr, *d_gw = nullptr, *d_gdots = nullptr, *h_gdots = nullptr;
   std::vector<double> gm_H, gm_g, gm_c, gm_s, gm_y, gm_h;
@@ -574,7 +593,8 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_rho, (size_t)P.n_sub));
   TRY(dalloc(p, p->d_wbm, (size_t)P.n_sub * 9));
   TRY(dalloc(p, p->d_nmodes, (size_t)P.n_sub));
-  TRY(dalloc(p, p->d_err, 4));
+  TRY(dalloc(p, p->d_err, 8));
+  HIPCHK(hipMemsetAsync(p->d_err, 0, 8 * sizeof(int), p->stream));
   // coarse space: at most 6 per subdomain
   const int max_coarse = 6 * P.n_sub;
   const int nq_max = (max_coarse + TS - 1) / TS;
@@ -622,6 +642,7 @@ feti_status setup_device(feti_problem* p) {
   TRY(dalloc(p, p->d_tv, nl));
   TRY(dalloc(p, p->d_d, nl));
   TRY(dalloc(p, p->d_bv, nl));
+  if (p->opt.flags & FETI_WARM_START) TRY(dalloc(p, p->d_lamp, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
   if (P.mixed || (p->opt.flags & (FETI_PROFILE | FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // refinement / residual report
@@ -630,14 +651,30 @@ feti_status setup_device(feti_problem* p) {
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
     vec_fill(P.n_dof, 0.0, p->d_zero, p->stream);
   }
+  p->dual_gmres = (p->opt.flags & FETI_DUAL_GMRES) != 0;
+  if (p->dual_gmres) {
+    const int m = std::min(std::max(p->opt.max_it, 1), kDualRestart);
+    p->dm = m;
+    TRY(dalloc(p, p->d_dv, (size_t)(m + 1) * nl));
+    TRY(dalloc(p, p->d_dz, (size_t)m * nl));
+    TRY(dalloc(p, p->d_dw, nl));
+    p->dg_H.assign((size_t)(m + 1) * m, 0.0);
+    p->dg_g.assign(m + 1, 0.0);
+    p->dg_c.assign(m, 0.0);
+    p->dg_s.assign(m, 0.0);
+    p->dg_y.assign(m, 0.0);
+    p->dg_h.assign(m + 1, 0.0);
+  }
+  if (p->dual_gmres || P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // multi_dot
+    TRY(dalloc(p, p->d_gdots, (size_t)kDotBatch * DOT_PARTS));
+    HIPCHK(hipHostMalloc((void**)&p->h_gdots, (size_t)kDotBatch * DOT_PARTS * sizeof(double), hipHostMallocDefault));
+  }
   if (P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // flexible GMRES
     const int m = std::min(std::max(p->opt.ir_max, 1), kGmresRestart);
     p->gm = m;
     TRY(dalloc(p, p->d_gv, (size_t)(m + 1) * P.n_dof));
     TRY(dalloc(p, p->d_gz, (size_t)m * P.n_dof));
     TRY(dalloc(p, p->d_gw, (size_t)P.n_dof));
-    TRY(dalloc(p, p->d_gdots, (size_t)kDotBatch * DOT_PARTS));
-    HIPCHK(hipHostMalloc((void**)&p->h_gdots, (size_t)kDotBatch * DOT_PARTS * sizeof(double), hipHostMallocDefault));
     p->gm_H.assign((size_t)(m + 1) * m, 0.0);
     p->gm_g.assign(m + 1, 0.0);
     p->gm_c.assign(m, 0.0);
@@ -792,9 +829,9 @@ feti_status coarse_factor(feti_problem* p, hipStream_t st) {
   asm_coarse(c, st);
   auto qd = [&](const HostPlan::Launch& L) {
     launch_dense<double>(L.kind, p->d_qtasks + L.first, L.count, p->d_qsub, p->d_qarena, p->d_qlinv, p->d_qW,
-                         p->d_qX, p->d_err + 1, st, L.split, 0, L.ndiag);
+                         p->d_qX, p->d_err + 4, st, L.split, 0, L.ndiag);
   };
-  HIPCHK(hipMemcpyAsync(p->d_err + 1, &p->h_big, sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_err + 4, &p->h_big, sizeof(int), hipMemcpyHostToDevice, st));
   for (const auto& L : qf) qd(L);
   for (const auto& L : qr) qd(L);
   qd(qla);
@@ -817,7 +854,17 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   a.U = U_dev;
   a.Ke = p->d_Ke;
   a.fint = p->d_fint;
+  // local factor flags: [0] first failing subdomain, [1] first element
+  // inverted by U, [2] modified pivots allowed, [3] their count; [4..7] the
+  // coarse factor's (never modified)
+  const int big = 0x7fffffff;
+  p->h_errinit[0] = big;
+  p->h_errinit[1] = big;
+  p->h_errinit[2] = p->allow_modified ? 1 : 0;
+  p->h_errinit[3] = 0;
+  HIPCHK(hipMemcpyAsync(p->d_err, p->h_errinit, 4 * sizeof(int), hipMemcpyHostToDevice, st));
   a.fbody = p->d_fbody;
+  a.inverted = p->d_err + 1;
   // the arena fill and the ELL reset do not need the element matrices: they
   // run on the coarse stream while the elements are integrated
   HIPCHK(hipEventRecord(p->ev_ffork, st));
@@ -862,7 +909,10 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.NF = P.NF;
   m.dmask = p->d_dmask;
   m.test_rotations = (P.any_hgo && U_dev && !(p->opt.flags & FETI_KERNEL6)) ? 1 : 0;
-  p->approx_tangent = P.any_hgo && U_dev && (p->opt.flags & FETI_KERNEL6);
+  m.kernel_tol = p->opt.kernel_tol;
+  // the dual solve is of an approximate tangent (refined against the exact
+  // one) with six-mode kernels, or with a kernel test looser than exact
+  p->approx_tangent = P.any_hgo && U_dev && ((p->opt.flags & FETI_KERNEL6) || p->opt.kernel_tol > 1e-12);
   m.rfull = p->d_rfull;
   m.rb = p->d_rb;
   m.n_modes = p->d_nmodes;
@@ -883,8 +933,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   p->prof_upd_n = 0;
   p->prof_gemv_ms = 0.0;
   p->prof_gemv_n = 0;
-  const int big = 0x7fffffff;
-  HIPCHK(hipMemcpyAsync(p->d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
+
   for (const auto& L : P.sched_interior) dense(p, L);
   dense(p, P.sched_schur);
   // coarse layout from the kernel dimensions (the host waits for the modes
@@ -945,8 +994,8 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   }
   if (p->n_coarse > 0) HIPCHK(hipStreamWaitEvent(st, p->ev_cjoin, 0));
   HIPCHK(hipEventRecord(p->ev[2], st));
-  int errs[2] = {0x7fffffff, 0x7fffffff};
-  HIPCHK(hipMemcpyAsync(errs, p->d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  int errs[8] = {0x7fffffff, 0, 0, 0, 0x7fffffff, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(errs, p->d_err, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int k = 0; k < p->n_upd_recorded; ++k) {
     float ms = 0.f;
@@ -963,7 +1012,13 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     p->factored = false;
     return FETI_ENOTSPD;
   }
-  if (p->n_coarse > 0 && errs[1] != 0x7fffffff) {
+  p->modified_pivots = errs[3];
+  if (errs[1] != 0x7fffffff) {
+    p->err = "element " + std::to_string(errs[1]) + " is inverted by the displacement (det F <= 0)";
+    p->factored = false;
+    return FETI_EINVAL;
+  }
+  if (p->n_coarse > 0 && errs[4] != 0x7fffffff) {
     p->err = "coarse matrix G^T G is not positive definite";
     p->factored = false;
     return FETI_ENOTSPD;
@@ -990,8 +1045,102 @@ bool pcg_converges_within(const PcgState& h, int prev_it, double prev_wn, int n)
   return std::log(target / ratio) / lrate <= n;
 }
 
+feti_status dev_norm(feti_problem* p, const double* v, int64_t n, double* out);
+feti_status multi_dot(feti_problem* p, int64_t n, const double* const* a, int k, const double* w, double* out);
+
+// Projected GMRES on the dual problem (FETI_DUAL_GMRES), for local operators
+// that are not positive definite: P^T F lambda = P^T d on lambda_0 +
+// range(P), right-preconditioned by P M^{-1} P (section 4.3 solves this
+// system by CG; the paper notes that the FETI methods work for other systems
+// with GMRES, section 3.2).  Starts from d_lam with d_r = d - F lambda;
+// Arnoldi on w = P F z, z = P M^{-1} v, classical Gram-Schmidt with one
+// reorthogonalisation, Givens rotations on the host, restarts every dm
+// vectors; stops at ||P r|| <= target (rtol ||P r_0||, or the warm start's
+// absolute target).  Leaves lambda in d_lam and d - F lambda in d_r.
+feti_status dual_gmres(feti_problem* p, double rtol, int* iters_out, int* status_out, double* rel_out) {
+  const int64_t n = p->P.n_lam;
+  const int m = p->dm;
+  PcgState* st = p->sc.state;   // initialised, never halted here
+  auto V = [&](int j) { return p->d_dv + (size_t)j * n; };
+  auto Z = [&](int j) { return p->d_dz + (size_t)j * n; };
+  std::vector<double>& H = p->dg_H;
+  std::vector<double>& g = p->dg_g;
+  std::vector<double>& cs = p->dg_c;
+  std::vector<double>& sn = p->dg_s;
+  std::vector<double>& y = p->dg_y;
+  std::vector<double>& hv = p->dg_h;
+  const double* ptrs[kDotBatch];
+  project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
+  double beta = 0.0;
+  TRY(dev_norm(p, p->d_wv, n, &beta));
+  const double beta0 = beta;
+  const double target = p->dual_target >= 0.0 ? p->dual_target : rtol * beta0;
+  int total = 0;
+  while (beta > target && total < p->opt.max_it) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    vec_axpby(n, 1.0 / beta, p->d_wv, 0.0, V(0), p->stream);
+    double cur = beta;
+    int k = 0;
+    for (int j = 0; j < m && total < p->opt.max_it; ++j) {
+      precondition(p, V(j), p->d_tv, st);
+      project_fused(p, 0, 0, p->d_tv, Z(j), nullptr, st, nullptr);
+      apply_F(p, Z(j), p->d_q, nullptr, 1.0, nullptr);
+      project_fused(p, 0, 0, p->d_q, p->d_dw, nullptr, st, nullptr);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i0 = 0; i0 <= j; i0 += kDotBatch) {
+          const int cnt = std::min(kDotBatch, j + 1 - i0);
+          for (int i = 0; i < cnt; ++i) ptrs[i] = V(i0 + i);
+          TRY(multi_dot(p, n, ptrs, cnt, p->d_dw, hv.data() + i0));
+          for (int i = 0; i < cnt; ++i) {
+            vec_axpby(n, -hv[i0 + i], V(i0 + i), 1.0, p->d_dw, p->stream);
+            H[(size_t)j * (m + 1) + i0 + i] += hv[i0 + i];
+          }
+        }
+      double hn = 0.0;
+      TRY(dev_norm(p, p->d_dw, n, &hn));
+      H[(size_t)j * (m + 1) + j + 1] = hn;
+      if (hn > 0.0) vec_axpby(n, 1.0 / hn, p->d_dw, 0.0, V(j + 1), p->stream);
+      double* col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = den > 0 ? col[j] / den : 1.0;
+      sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      cur = std::fabs(g[j + 1]);
+      ++total;
+      k = j + 1;
+      if (cur <= target || hn == 0.0) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= H[(size_t)l * (m + 1) + i] * y[l];
+      const double d = H[(size_t)i * (m + 1) + i];
+      y[i] = d != 0.0 ? acc / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) vec_axpby(n, y[i], Z(i), 1.0, p->d_lam, p->stream);
+    // true residual r = d - F lambda and w = P r of the updated multipliers
+    apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
+    project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
+    TRY(dev_norm(p, p->d_wv, n, &beta));
+  }
+  *iters_out = total;
+  *status_out = beta <= target ? FETI_OK : FETI_ENOCONV;
+  *rel_out = beta0 > 0 ? beta / beta0 : 0.0;
+  return FETI_OK;
+}
+
 feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool first = true) {
   HostPlan& P = p->P;
+  p->dual_target = -1.0;
   hipStream_t st = p->stream;
   const int64_t n = P.n_lam;
   if (first) HIPCHK(hipEventRecord(p->ev[3], st));
@@ -1015,74 +1164,109 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     // r = d - F lambda ; w = P r ; z = P M w ; s = z
     apply_F(p, p->d_lam, p->d_r, p->d_d, -1.0, nullptr);
     pcg_init_state(p->sc.state, rtol, 0.0, p->opt.max_it, p->sc.hist_cap, st);
-    vec_fill(n, 0.0, p->d_s, st);   // s = z + 0 s in the first iteration
-    project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->sc.state, nullptr);
-    precondition(p, p->d_wv, p->d_tv, p->sc.state);
-    project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->sc.state, nullptr);
-    // graph of graph_block iterations (feti_solve_noalloc launches the
-    // iterations one by one instead: instantiating a graph may allocate)
-    const int gb = std::max(1, p->opt.graph_block);
-    if (p->use_graph && (!p->graph || p->graph_iters != gb)) {
-      if (p->graph) {
-        (void)hipGraphExecDestroy(p->graph);
-        p->graph = nullptr;
-      }
-      hipGraph_t gr;
-      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < gb; ++k) pcg_iteration(p);
-      HIPCHK(hipStreamEndCapture(st, &gr));
-      HIPCHK(hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0));
-      (void)hipGraphDestroy(gr);
-      p->graph_iters = gb;
-    }
-    // Replays are pipelined: the host reads the state copied after one replay
-    // while the next already runs, so the GPU does not wait for the host.  A
-    // replay queued after convergence costs a block of iterations whose
-    // kernels return at once, so no further replay is queued while the one in
-    // flight is expected to reach the stopping rule (pcg_converges_within);
-    // if it does not, the next replay starts after the host has seen it.
-    // The state stops changing once the stopping rule is met.
-    PcgState hs{};
-    int rd = 0, wr = 0, queued = 0;   // ring of two state copies
-    auto queue_state = [&]() -> hipError_t {
-      hipError_t e = hipMemcpyAsync(&p->h_state[wr], p->sc.state, sizeof(PcgState), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipEventRecord(p->ev_rep[wr], st);
-      wr ^= 1;
-      ++queued;
-      return e;
-    };
-    auto run_block = [&]() -> hipError_t {
-      if (p->use_graph) return hipGraphLaunch(p->graph, st);
-      for (int k = 0; k < gb; ++k) pcg_iteration(p);
-      return hipGetLastError();
-    };
-    HIPCHK(queue_state());   // state after the initial residual
-    HIPCHK(run_block());
-    HIPCHK(queue_state());
-    int prev_it = 0;
-    double prev_wn = 0.0;
-    for (;;) {
-      HIPCHK(hipEventSynchronize(p->ev_rep[rd]));
-      hs = p->h_state[rd];
-      rd ^= 1;
-      --queued;
-      if (hs.done) break;
-      if (queued == 0 || !pcg_converges_within(hs, prev_it, prev_wn, gb * queued)) {
-        HIPCHK(run_block());
-        HIPCHK(queue_state());
-      }
-      prev_it = hs.it;
-      prev_wn = hs.wn;
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    iters = hs.it;
-    status = hs.status;
-    rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
-    if (stats && iters > 0) {
-      const int m = std::min(iters, std::min(p->sc.hist_cap, p->own.hist_cap));
-      HIPCHK(hipMemcpyAsync(p->h_hist, p->sc.hist, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (first && p->d_lamp && p->have_prev) {
+      // warm start from the previous call's multipliers: lambda_0 += c P lambda_prev,
+      // which keeps G^T lambda_0 = e, with c minimising the F-norm of the error
+      // along that direction: c = (P lambda_prev . r) / (P lambda_prev . F P lambda_prev).
+      // The stopping rule keeps the cold start's target: ||P r_k|| <= rtol ||P r_00||.
+      project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->sc.state, nullptr);
+      project_fused(p, 0, 0, p->d_lamp, p->d_tv, nullptr, p->sc.state, nullptr);
+      apply_F(p, p->d_tv, p->d_q, nullptr, 1.0, nullptr);
+      double a = 0.0, b = 0.0, w00 = 0.0;
+      pcg_dot(n, p->d_tv, p->d_r, p->d_tv, p->d_q, p->sc.dots, nullptr, st);
+      HIPCHK(hipMemcpyAsync(p->h_dots, p->sc.dots, 2 * DOT_PARTS * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      kappa = lanczos_kappa(p->h_hist, m, p->lz_d, p->lz_e);
+      for (int k = 0; k < DOT_PARTS; ++k) {
+        a += p->h_dots[2 * k];
+        b += p->h_dots[2 * k + 1];
+      }
+      TRY(dev_norm(p, p->d_wv, n, &w00));
+      const double c = b > 0.0 ? a / b : 0.0;
+      p->warm_scale = c;
+      if (c != 0.0) {
+        vec_axpby(n, c, p->d_tv, 1.0, p->d_lam, st);
+        vec_axpby(n, -c, p->d_q, 1.0, p->d_r, st);
+      }
+      pcg_init_state(p->sc.state, 0.0, rtol * w00, p->opt.max_it, p->sc.hist_cap, st);
+      p->dual_target = rtol * w00;
+    }
+    if (p->dual_gmres) {
+      TRY(dual_gmres(p, rtol, &iters, &status, &rel));
+      p->dual_target = -1.0;
+    } else {
+      vec_fill(n, 0.0, p->d_s, st);   // s = z + 0 s in the first iteration
+      project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, p->sc.state, nullptr);
+      precondition(p, p->d_wv, p->d_tv, p->sc.state);
+      project_fused(p, 2, 1, p->d_tv, p->d_zv, p->d_wv, p->sc.state, nullptr);
+      // graph of graph_block iterations (feti_solve_noalloc launches the
+      // iterations one by one instead: instantiating a graph may allocate)
+      const int gb = std::max(1, p->opt.graph_block);
+      if (p->use_graph && (!p->graph || p->graph_iters != gb)) {
+        if (p->graph) {
+          (void)hipGraphExecDestroy(p->graph);
+          p->graph = nullptr;
+        }
+        hipGraph_t gr;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < gb; ++k) pcg_iteration(p);
+        HIPCHK(hipStreamEndCapture(st, &gr));
+        HIPCHK(hipGraphInstantiate(&p->graph, gr, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(gr);
+        p->graph_iters = gb;
+      }
+      // Replays are pipelined: the host reads the state copied after one replay
+      // while the next already runs, so the GPU does not wait for the host.  A
+      // replay queued after convergence costs a block of iterations whose
+      // kernels return at once, so no further replay is queued while the one in
+      // flight is expected to reach the stopping rule (pcg_converges_within);
+      // if it does not, the next replay starts after the host has seen it.
+      // The state stops changing once the stopping rule is met.
+      PcgState hs{};
+      int rd = 0, wr = 0, queued = 0;   // ring of two state copies
+      auto queue_state = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(&p->h_state[wr], p->sc.state, sizeof(PcgState), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(p->ev_rep[wr], st);
+        wr ^= 1;
+        ++queued;
+        return e;
+      };
+      auto run_block = [&]() -> hipError_t {
+        if (p->use_graph) return hipGraphLaunch(p->graph, st);
+        for (int k = 0; k < gb; ++k) pcg_iteration(p);
+        return hipGetLastError();
+      };
+      HIPCHK(queue_state());   // state after the initial residual
+      HIPCHK(run_block());
+      HIPCHK(queue_state());
+      int prev_it = 0;
+      double prev_wn = 0.0;
+      for (;;) {
+        HIPCHK(hipEventSynchronize(p->ev_rep[rd]));
+        hs = p->h_state[rd];
+        rd ^= 1;
+        --queued;
+        if (hs.done) break;
+        if (queued == 0 || !pcg_converges_within(hs, prev_it, prev_wn, gb * queued)) {
+          HIPCHK(run_block());
+          HIPCHK(queue_state());
+        }
+        prev_it = hs.it;
+        prev_wn = hs.wn;
+      }
+      HIPCHK(hipStreamSynchronize(st));
+      iters = hs.it;
+      status = hs.status;
+      rel = hs.w0 > 0 ? hs.wn / hs.w0 : 0.0;
+      if (stats && iters > 0) {
+        const int m = std::min(iters, std::min(p->sc.hist_cap, p->own.hist_cap));
+        HIPCHK(hipMemcpyAsync(p->h_hist, p->sc.hist, 2 * (size_t)m * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        kappa = lanczos_kappa(p->h_hist, m, p->lz_d, p->lz_e);
+      }
+    }
+    if (first && p->d_lamp) {   // multipliers of this solve, for the next warm start
+      vec_axpby(n, 1.0, p->d_lam, 0.0, p->d_lamp, st);
+      p->have_prev = true;
     }
     // gamma = -Q^{-1} G^T r ; u = K^+(f - B^T lambda) + R gamma
     pcg_gather(p->di, 0, p->d_lam, p->d_xb, nullptr, st);
@@ -1115,6 +1299,7 @@ feti_status solve_core(feti_problem* p, feti_stats* stats, double rtol, bool fir
     stats->device_bytes = p->bytes;
     stats->autotune_wide = p->n_wide;
     stats->autotune_db = p->n_db;
+    stats->modified_pivots = p->modified_pivots;
   }
   if (status == FETI_EBREAKDOWN) {
     p->err = "PCG breakdown (s.Fs <= 0)";
@@ -1423,6 +1608,7 @@ feti_status feti_setup(const feti_mesh* mesh, const feti_options* opts, feti_pro
   if (p->opt.ir_tol <= 0) p->opt.ir_tol = 1e-10;
   if (p->opt.ir_max < 0) p->opt.ir_max = 6;
   if (p->opt.graph_block <= 0) p->opt.graph_block = 8;
+  if (!(p->opt.kernel_tol > 0.0)) p->opt.kernel_tol = 1e-12;
   p->opt.graph_block = std::min(p->opt.graph_block, 64);   // also bounds the profiling event slots
   if (p->opt.variant != FETI_CLASSICAL && p->opt.variant != FETI_ALL_FLOATING) {
     g_setup_error = "bad variant";
@@ -1481,6 +1667,7 @@ feti_status feti_factor(feti_problem* p, const double* U) {
   p->err.clear();
   const double* Ud = nullptr;
   TRY(load_U(p, U, &Ud));
+  p->allow_modified = p->P.mixed;   // feti_solve refines the mixed path
   feti_status s = do_factor(p, Ud);
   p->factored_linear = (s == FETI_OK && U == nullptr);
   return s;
@@ -1609,6 +1796,9 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
   hipStream_t st = p->stream;
   const double* Ud = nullptr;
   TRY(load_U(p, U_k, &Ud));
+  // a refined Newton step may factor with modified pivots
+  p->allow_modified = P.mixed || (P.any_hgo && Ud && ((p->opt.flags & FETI_KERNEL6) || p->opt.kernel_tol > 1e-12)) ||
+                      ((p->opt.flags & FETI_LOAD_STIFFNESS) && !P.pface.empty() && P.pressure != 0.0 && tau != 0.0);
   TRY(do_factor(p, Ud));
   p->factored_linear = (U_k == nullptr);
   HIPCHK(hipEventRecord(p->ev[5], st));
@@ -1677,6 +1867,18 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
     stats->t_total = stats->t_assemble + stats->t_factor + ev_ms(p->ev[5], p->ev[4]) * 1e-3;
   }
   return s;
+}
+
+feti_status feti_set_tolerances(feti_problem* p, double rtol, double ir_tol) {
+  if (!p) return FETI_EINVAL;
+  p->err.clear();
+  if (!(rtol > 0.0 && rtol < 1.0) || !(ir_tol > 0.0 && ir_tol < 1.0)) {
+    p->err = "tolerances must lie in (0, 1)";
+    return FETI_EINVAL;
+  }
+  p->opt.rtol = rtol;
+  p->opt.ir_tol = ir_tol;
+  return FETI_OK;
 }
 
 const char* feti_last_error(const feti_problem* p) {

@@ -181,6 +181,13 @@ __global__ __launch_bounds__(256) void k_elements(AsmArgs A) {
       }
     double Fi[9], detF;
     inv3(F, Fi, &detF);
+    // an element inverted by U (det F <= 0) has no strain energy: record it
+    // (the host rejects the state) and keep the arithmetic finite
+    if (!(detF > 0.0)) {
+      if (A.inverted) atomicMin(A.inverted, (int)e);
+      detF = 1.0;
+      for (int k = 0; k < 9; ++k) F[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    }
     sJ[w][gp] = detF;
     for (int k = 0; k < 9; ++k) sFp[w][gp][k] = F[k];
   }

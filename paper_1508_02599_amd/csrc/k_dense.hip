@@ -441,7 +441,12 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // diagonal by block diagonal: X_qp = -X_qq sum_{p<=k<q} L_qk X_kp, stored
 // transposed in the unused upper triangle of the tile.  The serial chain is
 // 4 x 16 pivots instead of 64.  A non-positive or non-finite pivot records
-// the subdomain in *err.  scratch: DIAG_SMEM doubles of LDS.
+// the subdomain in err[0] -- unless err[2] allows modified pivots (a factor
+// used only as the preconditioner of a refinement against the exact
+// operator): then a finite non-positive pivot d is replaced by
+// max(|d|, 1e-12 s), s the largest diagonal magnitude of the tile, as in a
+// modified Cholesky factorisation, and err[3] counts the replacements.
+// scratch: DIAG_SMEM doubles of LDS.
 template <typename T>
 __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __restrict__ subs, T* arena, T* linv,
                                              int* err, double* scratch) {
@@ -464,6 +469,13 @@ __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __res
     }
   }
   __syncthreads();
+  const int allow_mod = err[2];
+  double dscale = 0.0;   // largest diagonal magnitude of the tile (wave 0)
+  if (w == 0) {
+    dscale = fabs(A[lane * LD + lane]);
+    for (int o = 32; o > 0; o >>= 1) dscale = fmax(dscale, __shfl_xor(dscale, o, 64));
+  }
+  int nmod = 0;
   bool bad = false;
   for (int p = 0; p < 4; ++p) {
     const int p0 = DB * p;
@@ -479,9 +491,14 @@ __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __res
       for (int c = 0; c < DB; ++c) {
         const double d = readlane_d(a[c], c);
         const bool ok = (d > 0.0) && (d < 1e300);
-        bad |= !ok;
+        double dd = ok ? d : 1.0;
+        if (!ok && allow_mod && fabs(d) < 1e300 && dscale > 0.0) {
+          dd = fmax(fabs(d), 1e-12 * dscale);
+          ++nmod;
+        } else {
+          bad |= !ok;
+        }
         // 1/sqrt(d): hardware estimate and one Newton step, then sqrt(d) = d / sqrt(d)
-        const double dd = ok ? d : 1.0;
         double inv = __builtin_amdgcn_rsq(dd);
         inv = inv * (1.5 - 0.5 * dd * inv * inv);
         const double sd = dd * inv;
@@ -585,7 +602,10 @@ __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __res
     }
     Li[e] = (T)xv;
   }
-  if (bad && tid == 0) atomicMin(err, t.sub);
+  if (w == 0 && lane == 0) {   // wave 0 ran the pivots; lane 0 reports them
+    if (bad) atomicMin(err, t.sub);
+    if (nmod) atomicAdd(err + 3, nmod);
+  }
 }
 
 // A diagonal task (j, j, k0, k1) of a 256-thread block: the four waves

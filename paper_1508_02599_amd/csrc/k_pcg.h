@@ -149,6 +149,7 @@ struct AsmArgs {
   double* Ke = nullptr;               // [n_elems*576]  layout [a][b][i][j]
   double* fint = nullptr;             // [n_elems*24]
   double* fbody = nullptr;            // [n_elems*24]
+  int* inverted = nullptr;            // smallest element with det F <= 0 at U (atomicMin), or NULL
 };
 void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s);
 

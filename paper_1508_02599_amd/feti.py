@@ -30,6 +30,8 @@ FETI_AUTOTUNE = 4
 AUTOTUNE_FACTORISATIONS = 3   # factorisations that time the update forms (FETI_AUTOTUNE)
 FETI_KERNEL6 = 8
 FETI_LOAD_STIFFNESS = 16
+FETI_WARM_START = 32
+FETI_DUAL_GMRES = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -56,7 +58,7 @@ class feti_options(C.Structure):
                 ("rtol", C.c_double), ("max_it", C.c_int32), ("ir_tol", C.c_double),
                 ("ir_max", C.c_int32), ("graph_block", C.c_int32), ("hip_stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("flags", C.c_uint64)]
+                ("flags", C.c_uint64), ("kernel_tol", C.c_double)]
 
 
 class feti_stats(C.Structure):
@@ -68,7 +70,7 @@ class feti_stats(C.Structure):
                 ("kernel_gemv_ms", C.c_double), ("kernel_update_ms", C.c_double),
                 ("gemv_bytes", C.c_double), ("update_flops", C.c_double), ("res_primal", C.c_double),
                 ("autotune_wide", C.c_int32),
-                ("autotune_db", C.c_int32)]
+                ("autotune_db", C.c_int32), ("modified_pivots", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.feti_newton_step.argtypes = [P, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double),
                                      C.POINTER(feti_stats)]
     lib.feti_newton_step.restype = C.c_int
+    lib.feti_set_tolerances.argtypes = [P, C.c_double, C.c_double]
+    lib.feti_set_tolerances.restype = C.c_int
     lib.feti_last_error.argtypes = [P]
     lib.feti_last_error.restype = C.c_char_p
     lib.feti_destroy.argtypes = [P]
@@ -114,7 +118,7 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTED = ("feti_setup", "feti_footprint", "feti_factor", "feti_solve", "feti_solve_noalloc",
-            "feti_newton_step", "feti_last_error", "feti_destroy")
+            "feti_newton_step", "feti_set_tolerances", "feti_last_error", "feti_destroy")
 
 
 def _ptr(a, ctype):
@@ -167,10 +171,12 @@ def _check(lib, handle, status):
 
 def feti_setup(mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-               torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False):
+               torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False,
+               warm_start=False, dual_gmres=False, kernel_tol=0.0):
     """Create a problem handle (see :class:`Problem`)."""
     return Problem(mesh, variant, precond, precision, rtol, max_it, graph_block, ir_tol, ir_max,
-                   hip_stream, device_ptrs, torch_allocator, profile, autotune, kernel6, load_stiffness)
+                   hip_stream, device_ptrs, torch_allocator, profile, autotune, kernel6, load_stiffness,
+                   warm_start, dual_gmres, kernel_tol)
 
 
 class Problem:
@@ -178,7 +184,8 @@ class Problem:
 
     def __init__(self, mesh, variant="af", precond="lumped", precision="fp64", rtol=1e-8, max_it=1000,
                  graph_block=8, ir_tol=1e-10, ir_max=6, hip_stream=None, device_ptrs=False,
-                 torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False):
+                 torch_allocator=False, profile=False, autotune=True, kernel6=False, load_stiffness=False,
+                 warm_start=False, dual_gmres=False, kernel_tol=0.0):
         self.lib = load_library()
         self.n_dof = 3 * int(np.asarray(mesh.xyz).shape[0])
         keep = []
@@ -192,10 +199,12 @@ class Problem:
         o.ir_tol = ir_tol
         o.ir_max = ir_max
         o.graph_block = graph_block
+        o.kernel_tol = kernel_tol
         o.hip_stream = hip_stream
         o.flags = ((FETI_DEVICE_PTRS if device_ptrs else 0) | (FETI_PROFILE if profile else 0)
                    | (FETI_AUTOTUNE if autotune else 0) | (FETI_KERNEL6 if kernel6 else 0)
-                   | (FETI_LOAD_STIFFNESS if load_stiffness else 0))
+                   | (FETI_LOAD_STIFFNESS if load_stiffness else 0) | (FETI_WARM_START if warm_start else 0)
+                   | (FETI_DUAL_GMRES if dual_gmres else 0))
         self._cb = None
         if torch_allocator:
             import torch
@@ -259,8 +268,9 @@ class Problem:
                                                              C.byref(stats)))
         return out, stats.as_dict()
 
-    def newton_step(self, U, tau, out=None):
-        """Returns (dU, residual norm, stats) of one Newton step at U with load factor tau."""
+    def newton_step(self, U, tau, out=None, allow_noconv=False):
+        """Returns (dU, residual norm, stats) of one Newton step at U with load factor tau
+        (allow_noconv: a step whose refinement stopped short of ir_tol is returned)."""
         stats = feti_stats()
         rn = C.c_double()
         if self.device_ptrs:
@@ -272,9 +282,14 @@ class Problem:
             dU = np.empty(self.n_dof) if out is None else out
             uptr = Ua.ctypes.data_as(C.c_void_p)
             optr = dU.ctypes.data_as(C.c_void_p)
-        _check(self.lib, self.h, self.lib.feti_newton_step(self.h, uptr, float(tau), optr, C.byref(rn),
-                                                           C.byref(stats)))
+        st = self.lib.feti_newton_step(self.h, uptr, float(tau), optr, C.byref(rn), C.byref(stats))
+        if not (allow_noconv and st == FETI_ENOCONV):
+            _check(self.lib, self.h, st)
         return dU, rn.value, stats.as_dict()
+
+    def set_tolerances(self, rtol, ir_tol):
+        """feti_set_tolerances: dual rtol and refinement ir_tol of later calls."""
+        _check(self.lib, self.h, self.lib.feti_set_tolerances(self.h, float(rtol), float(ir_tol)))
 
     def close(self):
         if getattr(self, "h", None):

@@ -12,8 +12,10 @@ input.  Cases:
                        (box sizes up to 5616 DOFs)
   tube_step0           first Newton step of the 16x128x64 tube from rest at
                        load factor 1/40 (0.4 mmHg)
-  tube_step1           the Newton step at U_1 = U_0 + dU_0 (a stressed,
-                       non-equilibrium state) for the same load factor
+  tube_step1           the Newton step at U_1 = U_0 + STEP1_SCALE dU_0 (a
+                       stressed, non-equilibrium state; the full first step
+                       of the nearly incompressible wall overshoots into states
+                       with inverted elements) for the same load factor
 """
 import hashlib
 import os
@@ -28,6 +30,7 @@ sys.path.insert(0, ROOT)
 OUT = os.path.join(HERE, "fullsize")
 
 TUBE_TAU = 1.0 / 40.0
+STEP1_SCALE = 0.25
 
 
 def fullsize_key(mesh, *extra):
@@ -64,8 +67,9 @@ def case_tube():
     t0 = time.time()
     dU0, _ = monolithic.newton_increment(m, U0, TUBE_TAU)
     print(f"tube step 0: {time.time() - t0:.0f} s", flush=True)
+    np.save(path_for("tube_step0", fullsize_key(m, U0, np.array([TUBE_TAU]))), dU0)
     out.append(("tube_step0", fullsize_key(m, U0, np.array([TUBE_TAU])), lambda: dU0))
-    U1 = U0 + dU0
+    U1 = U0 + STEP1_SCALE * dU0
     t0 = time.time()
     dU1, _ = monolithic.newton_increment(m, U1, TUBE_TAU)
     print(f"tube step 1: {time.time() - t0:.0f} s", flush=True)

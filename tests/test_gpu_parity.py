@@ -340,3 +340,102 @@ def test_partial_kernels_parity(variant, precond, precision):
           f"err={err:.3e}")
     assert st["n_coarse"] == (17 if variant == "classical" else 48)
     assert err <= (1e-9 if precision == "fp64" else 1e-8)
+
+
+# ---------------------------------------------------------------- warm starts
+def test_warm_start_linear_load_sequence():
+    """FETI_WARM_START on a load sequence of one linear problem: the second
+    solve (load factor 1.1) starts from the first one's multipliers scaled by
+    the F-norm-optimal factor, which is exact here, so it meets the cold
+    start's stopping target at once; both results match the oracle."""
+    m, ref = _oracle("cube8_s2")
+    with _problem(m, variant="af", precond="lumped", rtol=1e-11, warm_start=True) as p:
+        p.factor()
+        u1, st1 = p.solve(load_factor=1.0)
+        u2, st2 = p.solve(load_factor=1.1)
+    print(f"warm start: cold {st1['iters']} iterations, warm {st2['iters']}")
+    assert _rel(u1, ref) <= 1e-9 and _rel(u2, 1.1 * ref) <= 1e-9
+    assert st2["iters"] <= 1 and st1["iters"] > 10
+
+
+def test_warm_start_newton_steps():
+    """Warm-started exact Newton steps of the tube's second load step (from the
+    equilibrium of the first) equal the oracle's steps while the residual is
+    well above the rounding of its own evaluation (|r_k| >= 1e-3 |r_0|; below
+    that the two sides' residuals differ by eps |f_int| and so do their
+    steps); the later steps are solved to Eisenstat-Walker-like tolerances and
+    the iteration must still converge.  The PCG iterations of warm and cold
+    starts over the whole load step are reported."""
+    m = _small_tube()
+    U1 = np.zeros(m.n_dofs)
+    for _ in range(20):
+        dU, rn = monolithic.newton_increment(m, U1, 1 / 40, load_stiffness=True)
+        U1 = U1 + dU
+        if rn < 1e-11:
+            break
+    tau = 2 / 40
+    its = {True: 0, False: 0}
+    for warm in (False, True):
+        U = U1.copy()
+        with _problem(m, variant="af", precond="dirichlet", rtol=1e-8, ir_tol=1e-12, ir_max=60,
+                      load_stiffness=True, kernel6=True, warm_start=warm) as p:
+            r0 = None
+            for k in range(10):
+                dU_ref, rn_ref = monolithic.newton_increment(m, U, tau, load_stiffness=True)
+                r0 = rn_ref if r0 is None else r0
+                if rn_ref <= 1e-10 * r0:
+                    break
+                exact = rn_ref >= 1e-3 * r0
+                p.set_tolerances(1e-8, 1e-12 if exact else min(1e-3, 1e-11 * r0 / rn_ref))
+                print(f"warm={warm} k={k} |r|/|r0|={rn_ref / r0:.2e}", flush=True)
+                dU, rn, st = p.newton_step(U, tau, allow_noconv=not exact)
+                err = _rel(dU, dU_ref)
+                print(f"  it={st['iters']} gmres={st['ir_sweeps']} err={err:.3e}", flush=True)
+                if exact:
+                    assert err <= 1e-9, (warm, k)
+                its[warm] += st["iters"]
+                U = U + dU
+            assert rn_ref <= 1e-10 * r0, (warm, rn_ref / r0)
+    print(f"Newton steps: PCG iterations cold {its[False]}, warm {its[True]}")
+    assert its[True] <= its[False]
+
+
+# ---------------------------------------------------------------- projected GMRES on the dual problem
+@pytest.mark.parametrize("variant,precond", [("af", "lumped"), ("classical", "dirichlet")])
+def test_dual_gmres_linear_parity(variant, precond):
+    """FETI_DUAL_GMRES on the linear cube: same displacements as the direct
+    solve, in a number of iterations close to PCG's (the operator is SPD)."""
+    m, ref = _oracle("cube8_s2")
+    u, st = _solve(m, variant=variant, precond=precond, rtol=1e-11, dual_gmres=True)
+    _, st_cg = _solve(m, variant=variant, precond=precond, rtol=1e-11)
+    err = _rel(u, ref)
+    print(f"dual GMRES {variant} {precond}: it={st['iters']} (PCG {st_cg['iters']}) err={err:.3e}")
+    assert st["converged"] == 1 and err <= 1e-9
+    assert st["iters"] <= st_cg["iters"] + 2
+
+
+def test_dual_gmres_indefinite_local_tangents():
+    """Half of the first Newton step from rest of the nearly incompressible
+    tube: a state whose stressed local tangents are indefinite in rotation
+    directions outside their kernel.  Their exact generalised inverses make F
+    indefinite, so PCG breaks down.  Projected GMRES on the dual problem
+    handles it; with the rotations of small stress-induced stiffness taken
+    into the kernels (kernel_tol 1e-6, an approximate tangent) and the load
+    stiffness, the refined step equals the oracle's exact Newton step."""
+    from paper_1508_02599_amd.feti import FetiError, FETI_EBREAKDOWN, FETI_ENOTSPD
+    m = _small_tube()
+    tau = 1 / 40
+    dU0, _ = monolithic.newton_increment(m, np.zeros(m.n_dofs), tau, load_stiffness=True)
+    U = 0.5 * dU0
+    dU_ref, _ = monolithic.newton_increment(m, U, tau, load_stiffness=True)
+    with _problem(m, variant="af", precond="dirichlet", rtol=1e-8, ir_tol=1e-12, ir_max=60,
+                  load_stiffness=True, dual_gmres=True, kernel_tol=1e-6) as p:
+        dU, rn, st = p.newton_step(U, tau)
+    err = _rel(dU, dU_ref)
+    print(f"indefinite local tangents, dual GMRES: it={st['iters']} outer={st['ir_sweeps']} "
+          f"modified={st['modified_pivots']} coarse={st['n_coarse']} err={err:.3e}")
+    assert err <= 1e-9
+    with _problem(m, variant="af", precond="dirichlet", rtol=1e-8) as p:
+        with pytest.raises(FetiError) as ei:
+            p.newton_step(U, tau)
+        assert ei.value.status in (FETI_EBREAKDOWN, FETI_ENOTSPD)
