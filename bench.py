@@ -283,7 +283,7 @@ def tube_load_path(args):
     rtol = args.rtol if args.precision == "fp64" else args.mixed_rtol
     p = Problem(mesh, variant=args.variant, precond="dirichlet", precision=args.precision, rtol=rtol,
                 ir_tol=args.newton_eta_max, ir_max=60, max_it=3000, device_ptrs=True, load_stiffness=True,
-                warm_start=not args.cold_start, dual_gmres=True, kernel_tol=args.kernel_tol)
+                warm_start=not args.cold_start, dual_gmres=args.dual == "gmres", kernel_tol=args.kernel_tol)
     U = torch.zeros(n, dtype=torch.float64, device="cuda")
     for _ in range(2):      # autotuning factorisations (untimed)
         p.factor(U)
@@ -303,7 +303,8 @@ def tube_load_path(args):
         "data": "synthetic",
         "config": {"workload": f"{args.config}: two-layer HGO tube, 16x128x64 Q1-P0 elements in "
                                f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, kernel "
-                               f"tolerance {args.kernel_tol:g}, projected dual GMRES, "
+                               f"tolerance {args.kernel_tol:g}, "
+                               f"{'projected dual GMRES' if args.dual == 'gmres' else 'dual PCG'}, "
                                f"{'cold' if args.cold_start else 'warm'} starts), inner pressure to 16 mmHg in "
                                f"increments of {16.0 / args.load_steps:g} mmHg (halved on failure), exact Newton "
                                f"(follower-load stiffness) to |r| <= {args.newton_tol:g} |r_0| per load step",
@@ -339,7 +340,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="random_boxes_64")
-    ap.add_argument("--variant", default="af")
+    ap.add_argument("--variant", default=None,
+                    help="af or classical (default: af; classical on the tube load path)")
+    ap.add_argument("--dual", default="gmres", choices=("gmres", "pcg"),
+                    help="tube load path: dual solver (projected GMRES or PCG)")
     ap.add_argument("--precond", default="lumped")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -364,6 +368,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.variant is None:
+        args.variant = "classical" if args.config.startswith("tube") else "af"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the subdomains "
               "over several GPUs is not implemented.", file=sys.stderr)

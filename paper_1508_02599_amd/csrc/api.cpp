@@ -469,6 +469,15 @@ double lanczos_kappa(const double* h, int m, std::vector<double>& d, std::vector
   return lmin > 0 ? lmax / lmin : 0.0;
 }
 
+// Whether a solve of this problem can be refined by the flexible GMRES
+// (solve_refined): mixed precision, FETI_KERNEL6 or a kernel tolerance above
+// the exact test on an HGO problem (an approximate stressed tangent), or the
+// exact Newton step with the load stiffness.
+bool refinable(const feti_problem* p) {
+  return p->P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS)) ||
+         (p->P.any_hgo && p->opt.kernel_tol > 1e-12);
+}
+
 feti_status setup_device(feti_problem* p) {
   HostPlan& P = p->P;
   p->di.NB = P.NB;
@@ -645,7 +654,11 @@ feti_status setup_device(feti_problem* p) {
   if (p->opt.flags & FETI_WARM_START) TRY(dalloc(p, p->d_lamp, nl));
   TRY(dalloc(p, p->d_dvals, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_out, (size_t)P.n_dof));
-  if (P.mixed || (p->opt.flags & (FETI_PROFILE | FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // refinement / residual report
+  // the flexible GMRES refinement runs for mixed precision, six-mode or
+  // tolerance-selected kernels of stressed (HGO) tangents, and the exact
+  // Newton step; its buffers exist exactly then (see refinable())
+  const bool refine = refinable(p);
+  if (refine || (p->opt.flags & FETI_PROFILE)) {   // refinement / residual report
     TRY(dalloc(p, p->d_f0, (size_t)P.NF));
     TRY(dalloc(p, p->d_uglob, (size_t)P.n_dof));
     TRY(dalloc(p, p->d_zero, (size_t)P.n_dof));
@@ -665,11 +678,11 @@ feti_status setup_device(feti_problem* p) {
     p->dg_y.assign(m, 0.0);
     p->dg_h.assign(m + 1, 0.0);
   }
-  if (p->dual_gmres || P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // multi_dot
+  if (p->dual_gmres || refine) {   // multi_dot
     TRY(dalloc(p, p->d_gdots, (size_t)kDotBatch * DOT_PARTS));
     HIPCHK(hipHostMalloc((void**)&p->h_gdots, (size_t)kDotBatch * DOT_PARTS * sizeof(double), hipHostMallocDefault));
   }
-  if (P.mixed || (p->opt.flags & (FETI_KERNEL6 | FETI_LOAD_STIFFNESS))) {   // flexible GMRES
+  if (refine) {   // flexible GMRES
     const int m = std::min(std::max(p->opt.ir_max, 1), kGmresRestart);
     p->gm = m;
     TRY(dalloc(p, p->d_gv, (size_t)(m + 1) * P.n_dof));
@@ -1411,6 +1424,10 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   feti_status s = solve_core(p, stats, p->opt.rtol);
   const bool refine = P.mixed || p->approx_tangent || p->ls_on;
   p->refined_out = false;
+  if (refine && p->gm == 0) {   // cannot happen: refinable() covers every case above
+    p->err = "internal: refinement buffers were not set up";
+    return FETI_EINVAL;
+  }
   if (!refine || (s != FETI_OK && s != FETI_ENOCONV)) {
     if ((s == FETI_OK || s == FETI_ENOCONV) && p->profile) {
       TRY(profile_gemv(p));
@@ -1460,7 +1477,9 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   // within [rtol, 1e-2].  On ill-conditioned problems a loose dual solve
   // gives a poor direction, and amp then keeps the inner solves tight.
   double amp = 10.0;
+  bool stalled = false;
   while (beta > target && sweeps < p->opt.ir_max) {
+    const double beta_start = beta;
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -1525,6 +1544,15 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     // true residual of the updated iterate
     apply_assembled(p, p->d_uglob, p->d_f0, p->d_gw);
     TRY(dev_norm(p, p->d_gw, nd, &beta));
+    if (!(beta < beta_start)) {
+      // the cycle did not reduce the true residual (a preconditioner far
+      // from A, whose Krylov basis lost its accuracy): keep the iterate the
+      // cycle started from and stop
+      for (int i = 0; i < k; ++i) vec_axpby(nd, -y[i], Z(i), 1.0, p->d_uglob, st);
+      beta = beta_start;
+      stalled = true;
+      break;
+    }
   }
   p->refined_out = true;
   TRY(profile_gemv(p));
@@ -1536,7 +1564,8 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
     stats->res_primal = fnorm > 0 ? beta / fnorm : 0.0;
   }
   if (p->opt.ir_max > 0 && !(beta <= target)) {
-    p->err = "refinement did not reach ir_tol within ir_max preconditioner applications";
+    p->err = stalled ? "refinement stalled: a restart cycle did not reduce the residual"
+                     : "refinement did not reach ir_tol within ir_max preconditioner applications";
     return FETI_ENOCONV;
   }
   return FETI_OK;

@@ -22,9 +22,9 @@ import time
 
 
 def run_load_path(p, U, n_inc, *, rtol=1e-8, newton_tol=1e-8, eta_max=1e-3, max_newton=12,
-                  time_budget=float("inf"), record=None, log=sys.stderr):
-    """Ramp tau from 0 to 1 in n_inc nominal increments on Problem p (device
-    pointers) from the displacement tensor U (updated in place).
+                  time_budget=float("inf"), record=None, log=sys.stderr, tau_end=1.0):
+    """Ramp tau from 0 to tau_end in nominal increments of 1/n_inc on Problem
+    p (device pointers) from the displacement tensor U (updated in place).
 
     record(tau, k, U): called with every Newton iterate of every accepted load
     step (k = 0: the previous equilibrium).  Returns a dict of the path's
@@ -54,11 +54,11 @@ def run_load_path(p, U, n_inc, *, rtol=1e-8, newton_tol=1e-8, eta_max=1e-3, max_
     t0 = time.perf_counter()
     nominal = 1.0 / n_inc
     dt, tau_done, streak = nominal, 0.0, 0
-    while tau_done < 1.0 - 1e-12:
+    while tau_done < tau_end - 1e-12:
         if time.perf_counter() - t0 > time_budget:
             out["error"] = f"time budget of {time_budget:g} s spent at tau = {tau_done:g}"
             break
-        tau = min(1.0, tau_done + dt)
+        tau = min(tau_end, tau_done + dt)
         Ut = U.clone()
         iterates = [Ut.clone()]
         r_start, r_prev, k, ok, why, n_try = None, None, 0, False, "", 0
@@ -111,3 +111,29 @@ def run_load_path(p, U, n_inc, *, rtol=1e-8, newton_tol=1e-8, eta_max=1e-3, max_
     out["wall_s"] = time.perf_counter() - t0
     out["tau_reached"] = tau_done
     return out
+
+
+def trajectory_states(p, n_inc=40, n_steps=10, iterates=4, **kw):
+    """Newton iterates along the converged load path of Problem p (device
+    pointers): {(s, k): (tau, U)} for the load steps that end at
+    tau = s / n_inc, s = 1..n_steps, and their iterates k = 0..iterates-1
+    (k = 0: the equilibrium the load step starts from; U a host array).
+    Keyword arguments go to run_load_path."""
+    import numpy as np
+    import torch
+
+    states = {}
+
+    def record(tau, k, Uk):
+        s = tau * n_inc
+        if abs(s - round(s)) < 1e-9 and k < iterates:
+            states[(int(round(s)), k)] = (tau, Uk.double().cpu().numpy())
+
+    U = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    r = run_load_path(p, U, n_inc, record=record, tau_end=n_steps / n_inc, **kw)
+    if r["error"]:
+        raise RuntimeError(f"load path stopped: {r['error']}")
+    missing = [(s, k) for s in range(1, n_steps + 1) for k in range(iterates) if (s, k) not in states]
+    if missing:
+        raise RuntimeError(f"load path converged in fewer than {iterates} Newton steps at {missing[:4]}")
+    return states

@@ -11,11 +11,14 @@ others are on the GPU overlaps with them.  Every reduction of the library has a
 fixed order and each problem owns its buffers, so a request's result does not
 depend on what else runs.
 
-    python -m paper_1508_02599_amd.serve [--requests 64] [--rates 0.5,1,2]
+    python -m paper_1508_02599_amd.serve [--requests 256] [--rate-multiples 0.25,0.5,1,2,4]
                                          [--precision fp64|mixed] [--workers 4]
 
-prints one JSON line per arrival rate: throughput (requests/s), p50/p99
-latency from arrival to result, and the mix of work served.
+computes the tube's load path once (the states of its Newton requests),
+measures the saturation rate (every request at t = 0), then prints one JSON
+line per arrival rate (multiples of the saturation rate): throughput
+(requests/s), p50/p99 latency from arrival to result, and the mix of work
+served.
 """
 from __future__ import annotations
 
@@ -57,10 +60,13 @@ class Server:
     """Admission by slots and device memory; see the module docstring.
 
     mesh_fn(key) builds the mesh of a request key; options are passed to every
-    problem (variant, precond, precision, rtol, ...)."""
+    problem (variant, precond, precision, rtol, ...); options_for(key) adds
+    per-mesh options; states(key, param) gives the displacement and load
+    factor of a Newton request (a state of a precomputed load path)."""
 
-    def __init__(self, mesh_fn, workers=4, hbm_budget=200 << 30, options_for=None, **options):
+    def __init__(self, mesh_fn, workers=4, hbm_budget=200 << 30, options_for=None, states=None, **options):
         self.mesh_fn = mesh_fn
+        self.states = states     # (key, param) -> (U, tau) of a Newton request; None: from rest at tau = param
         self.options = dict(variant="af", precond="lumped", rtol=1e-8, max_it=10000)
         self.options.update(options)
         self.options_for = options_for     # key -> overrides of the problem options
@@ -206,8 +212,8 @@ class Server:
                 slot.factored_linear = True
             u, st = p.solve(load_factor=req.param)
         else:
-            U = np.zeros(p.n_dof)
-            u, _, st = p.newton_step(U, req.param)
+            U, tau = self.states(req.key, req.param) if self.states else (np.zeros(p.n_dof), req.param)
+            u, _, st = p.newton_step(U, tau)
             slot.factored_linear = False
         req.result = u
         req.iters = st["iters"]
@@ -244,16 +250,46 @@ def summary(reqs, wall):
             "errors": sorted({r.error for r in reqs if r.error})[:3]}
 
 
-def tube_dirichlet(key):
-    """Tube requests (nearly incompressible HGO) use the Dirichlet preconditioner."""
-    return dict(precond="dirichlet") if key[0].startswith("tube") else {}
+def tube_options(key):
+    """Options of tube requests (nearly incompressible HGO): classical FETI
+    (the clamped ends stay in the local problems, whose floating versions lose
+    definiteness under load), the Dirichlet preconditioner, the exact Newton
+    step with the follower-load stiffness, rotations of small stress stiffness
+    in the kernels, projected GMRES on the dual problem, and the refinement to
+    1e-4 of the step's residual (an inexact Newton step's accuracy)."""
+    if key[0].startswith("tube"):
+        return dict(variant="classical", precond="dirichlet", load_stiffness=True, kernel_tol=1e-6,
+                    dual_gmres=True, ir_tol=1e-4, ir_max=60)
+    return {}
+
+
+def tube_states(mesh, n_steps=10, n_inc=40, iterates=4, **options):
+    """States (s, k) -> (tau, U) of the tube's converged load path (load
+    steps of 1/n_inc of the full pressure, Newton iterates k < iterates),
+    computed once on the GPU with the tube options (warm starts, inexact
+    Newton forcing: paper_1508_02599_amd.loadpath)."""
+    from .loadpath import trajectory_states
+    opts = tube_options(("tube", 0))
+    opts.update(dict(rtol=1e-8, max_it=3000, warm_start=True))
+    opts.update(options)
+    with Problem(mesh, device_ptrs=True, **opts) as p:
+        return trajectory_states(p, n_inc=n_inc, n_steps=n_steps, iterates=iterates, log=None)
+
+
+def state_fn(trajectories):
+    """states(key, param) of a Server from {tube kind: tube_states(...)}."""
+    def states(key, param):
+        tau, U = trajectories[key[0]][tuple(param)]
+        return U, tau
+    return states
 
 
 def main():
     from workloads import request_mesh, request_stream
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--rates", default="0.5,1,2,4", help="arrival rates, requests/s")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate-multiples", default="0.25,0.5,1,2,4",
+                    help="arrival rates as multiples of the measured saturation rate")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=200.0)
@@ -265,28 +301,37 @@ def main():
     ck = tuple(int(x) for x in a.cube_k.split(","))
     kw = dict(precision=a.precision)
     if a.precision == "mixed":
-        kw.update(rtol=1e-6, ir_tol=1e-8)
+        kw.update(rtol=1e-6, ir_tol=1e-10, ir_max=20)
+    t0 = time.perf_counter()
+    traj = {"tube": tube_states(request_mesh(("tube", 128)))}
+    print(json.dumps({"trajectory_states": len(traj["tube"]), "trajectory_s": time.perf_counter() - t0}), flush=True)
     srv = Server(request_mesh, workers=a.workers, hbm_budget=int(a.budget_gib * 2**30),
-                 options_for=tube_dirichlet, **kw)
+                 options_for=tube_options, states=state_fn(traj), **kw)
+
+    def measure(rate, label):
+        stream = request_stream(a.requests, rate, seed=a.seed, cube_k=ck)
+        t0 = time.perf_counter()
+        reqs = run_stream(srv, stream, t0)
+        wall = max(r.t_done for r in reqs) - t0
+        line = {"metric": "served FETI requests", "precision": a.precision, "arrival": label,
+                "arrival_rate": rate, "workers": a.workers, "budget_gib": a.budget_gib, "wall_s": wall}
+        line.update(summary(reqs, wall))
+        print(json.dumps(line), flush=True)
+        return line
+
     try:
         # warm-up (not timed): one request per distinct mesh sets up its problem
         seen = {}
-        for rate in (float(x) for x in a.rates.split(",")):
-            for r in request_stream(a.requests, rate, seed=a.seed, cube_k=ck):
-                seen.setdefault(r["key"], dict(r, t=0.0))
+        for r in request_stream(a.requests, 1.0, seed=a.seed, cube_k=ck):
+            seen.setdefault(r["key"], dict(r, t=0.0))
         t0 = time.perf_counter()
         run_stream(srv, list(seen.values()))
         print(json.dumps({"warmup_meshes": len(seen), "warmup_s": time.perf_counter() - t0,
                           "held_gib": srv.held / 2**30}), flush=True)
-        for rate in (float(x) for x in a.rates.split(",")):
-            stream = request_stream(a.requests, rate, seed=a.seed, cube_k=ck)
-            t0 = time.perf_counter()
-            reqs = run_stream(srv, stream, t0)
-            wall = max(r.t_done for r in reqs) - t0
-            line = {"metric": "served FETI requests", "precision": a.precision, "arrival_rate": rate,
-                    "workers": a.workers, "budget_gib": a.budget_gib, "wall_s": wall}
-            line.update(summary(reqs, wall))
-            print(json.dumps(line), flush=True)
+        # saturation: every request arrives at once
+        sat = measure(1e9, "all at t=0 (saturation)")["throughput_req_per_s"]
+        for mult in (float(x) for x in a.rate_multiples.split(",")):
+            measure(mult * sat, f"{mult:g} x saturation")
     finally:
         srv.close()
 

@@ -120,14 +120,14 @@ def test_uneven_boxes_displacement_parity(precision, rtol):
 
 @pytest.mark.parametrize("step", [0, 1])
 def test_tube_full_size_step_displacement_parity(step):
-    """The 16x128x64 tube (424k DOFs, 128 subdomains): the first Newton step
-    from rest at load factor 1/40, and the step at U_1 = U_0 + dU_0 / 4 (a
-    stressed state), against the oracle's sparse direct Newton steps.  At the
-    stressed state the local tangents are indefinite in rotation directions
-    outside their kernels: the rotations of small stress-induced stiffness
-    join the kernels (an approximate tangent, refined by flexible GMRES
-    against the exact one) and the dual problem is solved by projected
-    GMRES (<= 1e-9)."""
+    """The 16x128x64 tube (424k DOFs, 128 all-floating subdomains): the first
+    Newton step from rest at load factor 1/40, and the step at
+    U_1 = U_0 + dU_0 / 4 (a stressed state), against the oracle's sparse
+    direct Newton steps (<= 1e-9).  At the stressed state the rotations of
+    small stress-induced stiffness join the kernels (an approximate tangent,
+    refined by flexible GMRES against the exact one) and the dual problem is
+    solved by projected GMRES.  The refinement's target 1e-11 sits above the
+    rounding floor of the assembled residual there (about 1.2e-12 of |b|)."""
     m = _mesh("tube_16x128x64")
     U = np.zeros(m.n_dofs)
     ref0, mk = _reference("tube_step0", m, U, np.array([1.0 / 40.0]))
@@ -137,7 +137,7 @@ def test_tube_full_size_step_displacement_parity(step):
         ref, _ = _reference("tube_step1", m, U, np.array([tau]))
     else:
         ref = ref0
-    kw = dict(dual_gmres=True, kernel_tol=1e-6, ir_tol=1e-12, ir_max=60) if step == 1 else {}
+    kw = dict(dual_gmres=True, kernel_tol=1e-6, ir_tol=1e-11, ir_max=60) if step == 1 else {}
     with _problem(m, variant="af", precond="dirichlet", rtol=1e-10, max_it=10000, **kw) as p:
         dU, rn, st = p.newton_step(U, tau)
     l2, li = _errs(dU, ref)

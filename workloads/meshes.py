@@ -342,12 +342,14 @@ def request_mesh(key):
     raise KeyError(key)
 
 
-def request_stream(n, rate, seed=0, cube_k=(2, 8), tube_subs=(64, 128, 256), tube_kind="tube"):
+def request_stream(n, rate, seed=0, cube_k=(2, 8), tube_subs=(64, 128, 256), tube_kind="tube", n_steps=10,
+                   iterates=4):
     """n requests with Poisson arrivals of the given rate (per second): half
     cube linear solves with k^3 subdomains, k uniform in cube_k (inclusive),
-    and a load factor uniform in [0.5, 2]; half tube Newton steps from rest at
-    load factor tau = s/10, s uniform in 1..10, on one of tube_subs
-    subdomain counts.  Returns a list of dicts (arrival time in s, key, kind,
+    and a load factor uniform in [0.5, 2]; half tube Newton steps on one of
+    tube_subs subdomain counts at a state (s, k) of the tube's converged load
+    path: load step s uniform in 1..n_steps, Newton iterate k uniform in
+    0..iterates-1.  Returns a list of dicts (arrival time in s, key, kind,
     parameter)."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, size=n))
@@ -360,5 +362,5 @@ def request_stream(n, rate, seed=0, cube_k=(2, 8), tube_subs=(64, 128, 256), tub
         else:
             p = int(rng.choice(tube_subs))
             out.append(dict(t=float(t[k]), key=(tube_kind, p), kind="newton",
-                            param=float(rng.integers(1, 11)) / 10.0))
+                            param=(int(rng.integers(1, n_steps + 1)), int(rng.integers(0, iterates)))))
     return out
