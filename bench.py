@@ -231,7 +231,7 @@ def roofline(st_all, precision):
     u_ms = float(np.mean([s["kernel_update_ms"] for s in st_all]))
     u_n = float(np.mean([s["kernel_update_launches"] for s in st_all]))
     gb = st_all[-1]["gemv_bytes"]
-    gemv = {"kernel": "k_symv_tiles", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+    gemv = {"kernel": "k_symv_one", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
             "achieved": gb / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None,
             "avg_launch_ms": g_ms, "launches_per_solve": g_n,
             "algorithmic_bytes_per_launch": gb}

@@ -90,6 +90,7 @@ struct feti_problem {
   std::vector<double> dg_H, dg_g, dg_c, dg_s, dg_y, dg_h;
   // FETI_WARM_START: multipliers of the previous call's first dual solve
   double* d_lamp = nullptr;
+  int64_t* d_gdesc = nullptr;   // interface tile descriptors of the GEMV (gemv_descriptors)
   bool have_prev = false;
   double warm_scale = 0.0;
   int gm = 0;
@@ -296,11 +297,11 @@ void symv_local(feti_problem* p, const void* M, const double* xb, double* yb, co
                 int iface_only) {
   const HostPlan::Launch& L = p->P.sched_xtiles;
   if (p->P.mixed)
-    pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)M, xb, p->d_part, p->di.NB,
-                    p->di.b_sub, yb, st, p->stream, iface_only);
+    pcg_symv_desc<float>(p->d_gdesc, L.count, (const float*)M, xb, p->d_part, p->di.NB, p->di.b_sub, p->d_sub, yb,
+                         st, p->stream, iface_only);
   else
-    pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)M, xb, p->d_part, p->di.NB,
-                     p->di.b_sub, yb, st, p->stream, iface_only);
+    pcg_symv_desc<double>(p->d_gdesc, L.count, (const double*)M, xb, p->d_part, p->di.NB, p->di.b_sub, p->d_sub,
+                          yb, st, p->stream, iface_only);
 }
 
 // z = K^+ g for every subdomain (full local vectors), see k_kp_band and k_kp_tiles.
@@ -486,6 +487,12 @@ feti_status setup_device(feti_problem* p) {
   TRY(upload(p, p->d_sub, P.sub));
   TRY(upload(p, p->d_env, P.env));
   TRY(upload(p, p->d_tasks, P.tasks));
+  {   // descriptors of the interface tiles for the dual-operator GEMV
+    std::vector<int64_t> gd;
+    const HostPlan::Launch& XL = P.sched_xtiles;
+    gemv_descriptors(P.tasks.data() + XL.first, XL.count, P.sub.data(), gd);
+    if (!gd.empty()) TRY(upload(p, p->d_gdesc, gd));
+  }
   TRY(upload(p, p->d_xyz, P.xyz));
   TRY(upload(p, p->d_hex8, P.hex8));
   TRY(upload(p, p->d_elem_mat, P.elem_mat));
@@ -1346,11 +1353,11 @@ feti_status profile_gemv(feti_problem* p) {
   HIPCHK(hipEventRecord(p->ev_gemv[0], p->stream));
   for (int r = 0; r < kBurst; ++r) {
     if (p->P.mixed)
-      pcg_symv<float>(p->d_tasks + L.first, L.count, p->d_sub, (const float*)p->d_X, p->d_xb, p->d_part,
-                      p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream, 1);
+      pcg_symv_desc<float>(p->d_gdesc, L.count, (const float*)p->d_X, p->d_xb, p->d_part, p->di.NB, p->di.b_sub,
+                           p->d_sub, nullptr, nullptr, p->stream, 1);
     else
-      pcg_symv<double>(p->d_tasks + L.first, L.count, p->d_sub, (const double*)p->d_X, p->d_xb, p->d_part,
-                       p->di.NB, p->di.b_sub, nullptr, nullptr, p->stream, 1);
+      pcg_symv_desc<double>(p->d_gdesc, L.count, (const double*)p->d_X, p->d_xb, p->d_part, p->di.NB,
+                            p->di.b_sub, p->d_sub, nullptr, nullptr, p->stream, 1);
   }
   HIPCHK(hipEventRecord(p->ev_gemv[1], p->stream));
   HIPCHK(hipEventSynchronize(p->ev_gemv[1]));

@@ -1,6 +1,8 @@
 // Device-side PCG state and launchers of the dual-iteration and assembly kernels.
 #pragma once
 
+#include <vector>
+
 #include "feti_impl.h"
 
 namespace feti {
@@ -79,6 +81,15 @@ void pcg_scatter(const DevIdx& d, int weighted, const double* y, const double* b
 template <typename T>
 void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
               int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s, int iface_only);
+// The same product over precomputed tile descriptors (gemv_descriptors), one
+// vector load per tile instead of two dependent scalar loads, and 16-byte
+// tile loads: the interface tiles of the dual operator and of the Dirichlet
+// preconditioner.
+void gemv_descriptors(const Task* tasks, int count, const SubInfo* subs, std::vector<int64_t>& out);
+template <typename T>
+void pcg_symv_desc(const int64_t* desc, int count, const T* M, const double* xb, double* part, int64_t NB,
+                   const int32_t* b_sub, const SubInfo* subs, double* yb, const PcgState* st, hipStream_t s,
+                   int iface_only);
 void pcg_dot(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
              const PcgState* st, hipStream_t s);
 void pcg_coarse_gt(int n_sub, const SubInfo* subs, const double* rb, const double* xb, double* g,

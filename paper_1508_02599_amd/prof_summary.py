@@ -120,11 +120,11 @@ def update_bytes_per_launch(fetch_dir: str, write_dir: str, fetch_scale: float, 
 
 def gemv_bytes_per_launch(fetch_dir: str, write_dir: str, fetch_scale: float, write_scale: float,
                           min_kib: float = 1000.0):
-    """HBM bytes per GEMV launch: mean over the k_symv_tiles dispatches that did
+    """HBM bytes per GEMV launch: mean over the k_symv_one dispatches that did
     the work (a replayed graph block's launches after the stopping rule return
     at once and read nothing)."""
-    f = [r[3] for r in _dispatches(fetch_dir) if r[1].startswith("k_symv_tiles") and r[3] >= min_kib]
-    w = [r[3] for r in _dispatches(write_dir) if r[1].startswith("k_symv_tiles")]
+    f = [r[3] for r in _dispatches(fetch_dir) if r[1].startswith("k_symv_one") and r[3] >= min_kib]
+    w = [r[3] for r in _dispatches(write_dir) if r[1].startswith("k_symv_one")]
     w = sorted(w)[len(w) - len(f):] if len(w) >= len(f) else w
     return 1024.0 * (fetch_scale * sum(f) / len(f) + write_scale * sum(w) / max(1, len(w)))
 
@@ -147,7 +147,7 @@ def write_traffic(out: str, runs: dict, fetch_scale: float, write_scale: float, 
         rec["k_update" + suffix] = {"source": "paper_1508_02599_amd/csrc/k_dense.hip",
                                     "source_sha": sha("paper_1508_02599_amd/csrc/k_dense.hip"),
                                     "hbm_bytes_per_launch": round(ub), "launches": n, "summary": summary}
-        rec["k_symv_tiles" + suffix] = {"source": "paper_1508_02599_amd/csrc/k_symv.hip",
+        rec["k_symv_one" + suffix] = {"source": "paper_1508_02599_amd/csrc/k_symv.hip",
                                         "source_sha": sha("paper_1508_02599_amd/csrc/k_symv.hip"),
                                         "hbm_bytes_per_launch": round(gb), "summary": summary}
     with open(out, "w") as fh:

@@ -14,6 +14,7 @@ KEYS = [("cube", 2), ("cube", 3), ("tube_small", 4), ("tube_small", 8)]
 
 
 N_STEPS = 3
+N_INC = 160   # load steps of 0.1 mmHg on the small tube
 
 
 def _stream(n=12, seed=1):
@@ -28,7 +29,7 @@ _TRAJ = {}
 def _states():
     from paper_1508_02599_amd.serve import state_fn, tube_states
     if "tube_small" not in _TRAJ:
-        _TRAJ["tube_small"] = tube_states(request_mesh(("tube_small", 4)), n_steps=N_STEPS)
+        _TRAJ["tube_small"] = tube_states(request_mesh(("tube_small", 4)), n_steps=N_STEPS, n_inc=N_INC)
     return state_fn(_TRAJ)
 
 
