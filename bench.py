@@ -275,7 +275,7 @@ def tube_load_path(args):
     attempts included in the time.  Returns the JSON line."""
     import torch
     from workloads import config_mesh
-    from paper_1508_02599_amd.feti import Problem
+    from paper_1508_02599_amd.feti import AUTOTUNE_FACTORISATIONS, Problem
     from paper_1508_02599_amd.loadpath import run_load_path
 
     mesh = config_mesh(args.config)
@@ -285,7 +285,7 @@ def tube_load_path(args):
                 ir_tol=args.newton_eta_max, ir_max=60, max_it=3000, device_ptrs=True, load_stiffness=True,
                 warm_start=not args.cold_start, dual_gmres=args.dual == "gmres", kernel_tol=args.kernel_tol)
     U = torch.zeros(n, dtype=torch.float64, device="cuda")
-    for _ in range(2):      # autotuning factorisations (untimed)
+    for _ in range(AUTOTUNE_FACTORISATIONS):      # autotuning factorisations (untimed)
         p.factor(U)
     torch.cuda.synchronize()
     r = run_load_path(p, U, args.load_steps, rtol=rtol, newton_tol=args.newton_tol, eta_max=args.newton_eta_max,

@@ -319,29 +319,41 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 // the same order as update_tile, so the results are bit-identical.  With
 // KC = 32 the buffers take 64 KiB in FP64, two workgroups per compute unit.
 // Occupancy asked of the double-buffered update: three waves per SIMD in
-// FP32 (its LDS allows three workgroups per compute unit), two in FP64.
-template <typename T>
-struct UpdOcc { static constexpr int waves = sizeof(T) == 4 ? 3 : 2; };
-template <typename T, int KC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
+// FP32 (its LDS allows three workgroups per compute unit), two in FP64.  The
+// PLAIN form (launches of update tasks only, KC = 16) needs no LDS for the
+// diagonal blocks or the inverse rows: about 33 KiB in FP64, four
+// workgroups per compute unit.
+template <typename T, bool PLAIN = false>
+struct UpdOcc { static constexpr int waves = PLAIN ? 4 : (sizeof(T) == 4 ? 3 : 2); };
+template <typename T, int KC, bool PLAIN = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T, PLAIN>::waves))) void k_update_db(const Task* __restrict__ tasks, int n_diag, int n_upd,
                                                    const SubInfo* __restrict__ subs, T* arena,
                                                    T* linv, T* W, int* err) {
   constexpr int CH = TS * KC;                 // elements per chunk
   constexpr int PARTS = TS / KC;              // chunks per tile
-  constexpr int NLDS = 4 * CH > 2 * TS * LD ? 4 * CH : 2 * TS * LD;
-  // [buffer][A, B][chunk]; the inverse rows use 2 TS LD; the diagonal blocks their scratch
-  __shared__ double smem[smem_doubles<T>(NLDS)];
+  // [buffer][A, B][chunk]; the result tile uses TS LD; the inverse rows 2 TS LD,
+  // the diagonal blocks their scratch
+  constexpr int NFIX = PLAIN ? TS * LD : 2 * TS * LD;
+  constexpr int NLDS = 4 * CH > NFIX ? 4 * CH : NFIX;
+  __shared__ double smem[PLAIN ? (NLDS * (int)sizeof(T) + 7) / 8 : smem_doubles<T>(NLDS)];
   T* lds = reinterpret_cast<T*>(smem);
   const int b0 = (int)blockIdx.x;
-  if (b0 < n_diag) {
-    diag_block<T>(tasks[b0], subs, arena, linv, err, lds, lds + TS * LD, smem);
-    return;
+  int b = b0;
+  if constexpr (!PLAIN) {
+    if (b0 < n_diag) {
+      diag_block<T>(tasks[b0], subs, arena, linv, err, lds, lds + TS * LD, smem);
+      return;
+    }
+    b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
+  } else {
+    b = xcd_task();
   }
-  const int b = n_diag + xcd_split(b0 - n_diag, (int)gridDim.x - n_diag, n_upd - n_diag);
   const Task t = tasks[b];
-  if (b >= n_upd) {
-    trtri_tile<T>(t, subs, arena, linv, W, lds, lds + TS * LD);
-    return;
+  if constexpr (!PLAIN) {
+    if (b >= n_upd) {
+      trtri_tile<T>(t, subs, arena, linv, W, lds, lds + TS * LD);
+      return;
+    }
   }
   T* base = arena + subs[t.sub].tile_off;
   const int w = threadIdx.x >> 6;
@@ -741,7 +753,7 @@ __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
 // rows, streamed into two LDS buffers by the direct global-to-LDS loads as in
 // k_update_db.  X tiles are written column-major.
 template <typename T, int KC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_lauum_db(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T, KC == 16>::waves))) void k_lauum_db(
     const Task* __restrict__ tasks, const SubInfo* __restrict__ subs, const T* __restrict__ W, T* X) {
   constexpr int CH = TS * KC;
   constexpr int PARTS = TS / KC;
@@ -982,7 +994,11 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
   if (count <= 0) return;
   if (is_update_kind(kind)) {
     const int nupd = kind == K_UPDATE ? count : split;   // diagonal and update tasks
-    if (form == 2) {
+    if (form == 3 && ndiag == 0 && nupd == count) {
+      // update tasks only: the 16-wide chunks at four workgroups per CU
+      hipLaunchKernelGGL((k_update_db<T, 16, true>), dim3(count), dim3(256), 0, st, tasks, 0, count, subs, arena,
+                         linv, W, err);
+    } else if (form == 2 || form == 3) {
       hipLaunchKernelGGL((k_update_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, ndiag, nupd, subs, arena,
                          linv, W, err);
     } else if (form == 1) {
@@ -1005,7 +1021,11 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
       hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W);
       break;
     case K_LAUUM:
-      hipLaunchKernelGGL((k_lauum_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
+      // form 1: 16-wide chunks at four workgroups per CU
+      if (form == 1)
+        hipLaunchKernelGGL((k_lauum_db<T, 16>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
+      else
+        hipLaunchKernelGGL((k_lauum_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
       break;
   }
 }

@@ -90,6 +90,36 @@ __global__ __launch_bounds__(256) void k_symv_tiles(const Task* __restrict__ tas
   }
 }
 
+// Phase 2: yb[b] = sum_J part[row I of b][J] in order (loads of a chunk of
+// eight partials in flight together).
+__global__ void k_symv_reduce(int64_t NB, const int32_t* __restrict__ b_sub, const SubInfo* __restrict__ subs,
+                              const double* __restrict__ part, double* __restrict__ yb, const PcgState* st) {
+  if (halted(st)) return;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NB) return;
+  const SubInfo s = subs[b_sub[b]];
+  const int64_t loc = b - s.b_off;
+  const int I = (int)(loc / TS), r = (int)(loc % TS);
+  const double* p = part + s.part_off + (int64_t)I * s.nt_b * TS + r;
+  const int nt = s.nt_b;
+  double acc = 0.0;
+  for (int J0 = 0; J0 < nt; J0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = J0 + k < nt ? p[(int64_t)(J0 + k) * TS] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  yb[b] = acc;
+}
+
+template <typename T>
+void pcg_symv(const Task* tasks, int count, const SubInfo* subs, const T* M, const double* xb, double* part,
+              int64_t NB, const int32_t* b_sub, double* yb, const PcgState* st, hipStream_t s, int iface_only) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_symv_tiles<T>, dim3(count), dim3(256), 0, s, tasks, subs, M, xb, part, st, iface_only);
+  if (yb) hipLaunchKernelGGL(k_symv_reduce, grid1(NB), dim3(256), 0, s, NB, b_sub, subs, (const double*)part, yb, st);
+}
 // Descriptor of one interface tile for k_symv_one: eight int64 fields, read
 // by lanes 0..7 of each wave as one vector load, in place of two dependent
 // scalar loads (task, then its subdomain).  See gemv_descriptors.

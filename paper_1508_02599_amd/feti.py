@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 FETI_DEVICE_PTRS = 1
 FETI_PROFILE = 2
 FETI_AUTOTUNE = 4
-AUTOTUNE_FACTORISATIONS = 3   # factorisations that time the update forms (FETI_AUTOTUNE)
+AUTOTUNE_FACTORISATIONS = 4   # factorisations that time the update forms (FETI_AUTOTUNE)
 FETI_KERNEL6 = 8
 FETI_LOAD_STIFFNESS = 16
 FETI_WARM_START = 32

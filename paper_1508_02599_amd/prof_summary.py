@@ -68,6 +68,42 @@ def trace_table(d: str, top: int = 20, min_us: float = 0.0):
     return "\n".join(out)
 
 
+def overlap_table(d: str):
+    """Concurrency of kernels on different streams in a kernel trace: the
+    time during which at least one kernel ran (busy), the sum of kernel
+    durations (work), and the time with kernels of two or more streams
+    running at once (overlap), in ms."""
+    f = _one(os.path.join(d, "**", "*kernel_trace.csv"))
+    ev = []
+    with open(f) as fh:
+        for row in csv.DictReader(fh):
+            a, b = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+            q = (row.get("Queue_Id"), row.get("Stream_Id"))
+            ev.append((a, 1, q))
+            ev.append((b, -1, q))
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active = defaultdict(int)
+    busy = over = work = 0
+    last = None
+    streams = set()
+    for t, d_, q in ev:
+        if last is not None and t > last:
+            n_str = sum(1 for v in active.values() if v > 0)
+            n_k = sum(active.values())
+            if n_k:
+                busy += t - last
+                work += n_k * (t - last)
+            if n_str >= 2:
+                over += t - last
+        active[q] += d_
+        streams.add(q)
+        last = t
+    span = (ev[-1][0] - ev[0][0]) if ev else 0
+    return (f"streams {len(streams)}; trace span {span * 1e-6:.1f} ms; busy {busy * 1e-6:.1f} ms; "
+            f"kernel time {work * 1e-6:.1f} ms; two or more streams running at once {over * 1e-6:.1f} ms "
+            f"({100 * over / max(1, busy):.0f}% of busy time); kernel time / busy time {work / max(1, busy):.2f}")
+
+
 def pmc_table(d: str, kernel: str | None = None, min_kib: float = 0.0):
     f = _one(os.path.join(d, "**", "*counter_collection.csv"))
     vals = defaultdict(list)
@@ -157,7 +193,7 @@ def write_traffic(out: str, runs: dict, fetch_scale: float, write_scale: float, 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc", "traffic"])
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "overlap"])
     ap.add_argument("dir", nargs="?")
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--min-us", type=float, default=0.0)
@@ -172,6 +208,8 @@ def main():
     a = ap.parse_args()
     if a.mode == "trace":
         print(trace_table(a.dir, a.top, a.min_us))
+    elif a.mode == "overlap":
+        print(overlap_table(a.dir))
     elif a.mode == "pmc":
         print(pmc_table(a.dir, a.kernel, a.min_kib))
     else:

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 import threading
 import time
 from collections import OrderedDict
@@ -82,6 +83,8 @@ class Server:
         self.nworkers = workers
         self.free_workers = workers
         self.jobs: list = []
+        self.n_setup = 0        # problems set up (a new one for each request of a busy or absent mesh)
+        self.n_evict = 0        # idle problems evicted for memory
         self.threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(workers)]
         for t in self.threads:
             t.start()
@@ -157,6 +160,7 @@ class Server:
             self.lock.notify_all()
 
     def _evict(self, s: _Slot):
+        self.n_evict += 1
         self.lru.pop(id(s), None)
         self.slots.remove(s)
         self.held -= s.bytes
@@ -185,6 +189,7 @@ class Server:
                         raise MemoryError(f"problem needs {fp} bytes, budget {self.budget}")
                     slot = _Slot(req.key, p, fp)
                     slot.busy = True
+                    self.n_setup += 1
                     with self.lock:
                         self.est[req.key] = fp
                         self.held += fp - reserved
@@ -219,9 +224,13 @@ class Server:
         req.iters = st["iters"]
 
 
-def run_stream(server: Server, stream, t0=None):
+def run_stream(server: Server, stream, t0=None, progress=None, stall_s=None):
     """Submit the requests of `stream` at their arrival times (relative to
-    t0) and wait for all; returns the Request objects."""
+    t0) and wait for all; returns the Request objects.  progress: a file to
+    which a line is written every 32 submitted requests and every 10 s of
+    waiting; stall_s: when no request finishes for that long, print the
+    server's state, the running requests and every thread's stack, and end
+    the process (exit status 3)."""
     t0 = time.perf_counter() if t0 is None else t0
     reqs = []
     for k, r in enumerate(stream):
@@ -231,8 +240,34 @@ def run_stream(server: Server, stream, t0=None):
         req = Request(k, r["key"], r["kind"], r["param"], t0 + r["t"])
         reqs.append(req)
         server.submit(req)
+        if progress is not None and (k + 1) % 32 == 0:
+            done = sum(q.done.is_set() for q in reqs)
+            print(f"  submitted {k + 1}, done {done}, t = {time.perf_counter() - t0:.1f} s", file=progress, flush=True)
+    last_done, last_t = -1, time.perf_counter()
     for r in reqs:
-        r.done.wait()
+        while not r.done.wait(timeout=10.0):
+            done = sum(q.done.is_set() for q in reqs)
+            if progress is not None:
+                print(f"  done {done} of {len(reqs)}, t = {time.perf_counter() - t0:.1f} s", file=progress,
+                      flush=True)
+            if done != last_done:
+                last_done, last_t = done, time.perf_counter()
+            elif stall_s is not None and time.perf_counter() - last_t > stall_s:
+                # print what runs and end the process at once: worker threads
+                # inside a library call cannot be joined
+                import faulthandler
+                import os
+                now_t = time.perf_counter()
+                with server.lock:
+                    running = [(q.rid, q.key, q.kind, q.param, round(now_t - q.t_start, 1)) for q in reqs
+                               if q.t_start is not None and not q.done.is_set()]
+                    state = (f"pending {len(server.pending)}, jobs {len(server.jobs)}, free workers "
+                             f"{server.free_workers}, held {server.held / 2**30:.2f} GiB, running "
+                             f"(id, key, kind, param, seconds) {running}")
+                print(f"no request finished for {stall_s:g} s: {state}", file=sys.stderr, flush=True)
+                faulthandler.dump_traceback(file=sys.stderr, all_threads=True)
+                sys.stderr.flush()
+                os._exit(3)
     return reqs
 
 
@@ -311,11 +346,13 @@ def main():
     def measure(rate, label):
         stream = request_stream(a.requests, rate, seed=a.seed, cube_k=ck)
         t0 = time.perf_counter()
-        reqs = run_stream(srv, stream, t0)
+        reqs = run_stream(srv, stream, t0, progress=sys.stderr, stall_s=120.0)
         wall = max(r.t_done for r in reqs) - t0
         line = {"metric": "served FETI requests", "precision": a.precision, "arrival": label,
                 "arrival_rate": rate, "workers": a.workers, "budget_gib": a.budget_gib, "wall_s": wall}
         line.update(summary(reqs, wall))
+        line.update({"held_gib": srv.held / 2**30, "problems_resident": len(srv.slots),
+                     "problems_set_up": srv.n_setup, "problems_evicted": srv.n_evict})
         print(json.dumps(line), flush=True)
         return line
 
@@ -330,7 +367,7 @@ def main():
                           "held_gib": srv.held / 2**30}), flush=True)
         # saturation: every request arrives at once
         sat = measure(1e9, "all at t=0 (saturation)")["throughput_req_per_s"]
-        for mult in (float(x) for x in a.rate_multiples.split(",")):
+        for mult in (float(x) for x in a.rate_multiples.split(",") if x):
             measure(mult * sat, f"{mult:g} x saturation")
     finally:
         srv.close()

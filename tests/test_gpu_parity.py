@@ -248,25 +248,26 @@ def test_mixed_precision_newton_step():
 # ---------------------------------------------------------------- autotuned update shapes
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_autotune_update_forms_identical(precision):
-    """The first three factorisations use the three update forms (64x64 tiles,
-    128x64 tiles, 64x64 double-buffered), later ones the fastest per launch:
-    the displacements are bit-identical throughout (same products, same order)
-    and match the oracle."""
+    """The first four factorisations use the four update forms (64x64 tiles,
+    128x64 tiles, 64x64 double-buffered in 32- and in 16-wide chunks; the
+    LAUUM launch in 32- and 16-wide chunks), later ones the fastest per
+    launch: the displacements are bit-identical throughout (same products,
+    same order) and match the oracle."""
     m, ref = _oracle("cube32_s4")
     kw = dict(rtol=1e-10) if precision == "fp64" else dict(rtol=1e-8, ir_tol=1e-12)
     outs, wide, db = [], [], []
     with _problem(m, variant="af", precond="lumped", precision=precision, autotune=True, **kw) as p:
-        for _ in range(4):
+        for _ in range(5):
             p.factor()
             u, st = p.solve()
             outs.append(u)
             wide.append(st["autotune_wide"])
             db.append(st["autotune_db"])
     print(f"autotune {precision}: launches per form after tuning: wide {wide}, double-buffered {db}")
-    assert wide[0] == -1 and db[0] == -1 and wide[3] >= 0 and db[3] >= 0
-    for k in range(1, 4):
+    assert wide[0] == -1 and db[0] == -1 and wide[4] >= 0 and db[4] >= 0
+    for k in range(1, 5):
         assert np.array_equal(outs[0], outs[k]), k
-    assert _rel(outs[3], ref) <= 1e-9
+    assert _rel(outs[4], ref) <= 1e-9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
