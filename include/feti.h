@@ -115,9 +115,8 @@ typedef struct {
 #define FETI_AUTOTUNE 0x4ull    /* pick the form of each factor-update launch (64x64 tiles,
                                    128x64 tiles, or 64x64 tiles with double-buffered direct
                                    global-to-LDS loads in 32- or 16-wide chunks) by timing
-                                   each in one of the first four factorisations, and the
-                                   chunk width of the X = W^T W launch in the first two; the
-                                   factors do not depend on it                                */
+                                   each in one of the first four factorisations; the factors
+                                   do not depend on it                                        */
 #define FETI_KERNEL6 0x8ull     /* take all six rigid-body modes as the kernel of every floating
                                    subdomain, as the paper does (section 4.3).  Exact for
                                    stress-free tangents.  For stressed ones (Newton steps away

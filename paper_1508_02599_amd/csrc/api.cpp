@@ -168,14 +168,9 @@ struct feti_problem {
   // times form f of every update launch (0: 64x64 tiles, 1: 128x64, 2: 64x64
   // double-buffered, 3: double-buffered in 16-wide chunks at four workgroups
   // per CU where the launch holds update tasks only, else as 2); from then on
-  // each launch uses its fastest form.  The LAUUM launch (X = W^T W) is timed
-  // the same way in 32-wide (factorisation 0) and 16-wide chunks (1).  All
-  // forms give identical factors.  Launches are identified by the first task
-  // of their 64x64 form.
+  // each launch uses its fastest form.  All forms give identical factors.
+  // Launches are identified by the first task of their 64x64 form.
   static constexpr int kForms = 4;
-  float t_lauum[2] = {0.f, 0.f};
-  int lauum_form = 0;
-  hipEvent_t ev_lauum[2] = {};
   bool autotune = false;
   int tune_phase = 0;                          // < kForms: measuring; kForms: decided
   std::vector<int32_t> upd_first;              // update launches, by first task
@@ -255,14 +250,11 @@ void dense(feti_problem* p, const HostPlan::Launch& L) {
   if (upd && p->autotune && (idx = update_index(p, L)) >= 0 && L.wcount > 0)
     form = p->tune_phase < feti_problem::kForms ? p->tune_phase : p->use_form[idx];
   const bool tuning = idx >= 0 && p->tune_phase < feti_problem::kForms;
-  const bool lauum_tuning = L.kind == K_LAUUM && p->autotune && p->tune_phase < 2 && L.count > 0;
-  if (L.kind == K_LAUUM) form = lauum_tuning ? p->tune_phase : p->lauum_form;
   const bool wide = form == 1;
   const Task* t = p->d_tasks + (wide ? L.wfirst : L.first);
   const int count = wide ? L.wcount : L.count, split = wide ? L.wsplit : L.split;
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded], stream);
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx], stream);
-  if (lauum_tuning) (void)hipEventRecord(p->ev_lauum[0], stream);
   if (p->P.mixed)
     launch_dense<float>(L.kind, t, count, p->d_sub, (float*)p->d_arena, (float*)p->d_linv, (float*)W,
                         (float*)p->d_X, p->d_err, stream, split, form, L.ndiag);
@@ -270,22 +262,12 @@ void dense(feti_problem* p, const HostPlan::Launch& L) {
     launch_dense<double>(L.kind, t, count, p->d_sub, (double*)p->d_arena, (double*)p->d_linv, (double*)W,
                          (double*)p->d_X, p->d_err, stream, split, form, L.ndiag);
   if (tuning) (void)hipEventRecord(p->ev_tune[2 * idx + 1], stream);
-  if (lauum_tuning) (void)hipEventRecord(p->ev_lauum[1], stream);
   if (timed) (void)hipEventRecord(p->ev_upd[2 * p->n_upd_recorded++ + 1], stream);
 }
 
 // After a factorisation: collect the autotuner's timings and advance it.
 void autotune_step(feti_problem* p) {
   if (!p->autotune || p->tune_phase >= feti_problem::kForms) return;
-  if (p->tune_phase < 2 && p->P.sched_lauum.count > 0) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p->ev_lauum[0], p->ev_lauum[1]) != hipSuccess) {
-      (void)hipGetLastError();
-      ms = 0.f;
-    }
-    p->t_lauum[p->tune_phase] = ms;
-    if (p->tune_phase == 1) p->lauum_form = (p->t_lauum[1] > 0.f && p->t_lauum[1] < p->t_lauum[0]) ? 1 : 0;
-  }
   auto& dst = p->t_form[p->tune_phase];
   for (size_t k = 0; k < p->upd_first.size(); ++k) {
     float ms = 0.f;
@@ -779,7 +761,6 @@ feti_status setup_device(feti_problem* p) {
     p->use_form.assign(nl, 0);
     p->ev_tune.resize(2 * nl);
     for (auto& ev : p->ev_tune) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
-    for (auto& ev : p->ev_lauum) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
   }
   // algorithmic work: bytes of the packed symmetric interface inverses read by
   // one GEMV, and flops of the update launches counted on real (unpadded)
@@ -1953,8 +1934,6 @@ void feti_destroy(feti_problem* p) {
   for (auto& ev : p->ev_upd)
     if (ev) (void)hipEventDestroy(ev);
   for (auto& ev : p->ev_tune)
-    if (ev) (void)hipEventDestroy(ev);
-  for (auto& ev : p->ev_lauum)
     if (ev) (void)hipEventDestroy(ev);
   for (void* a : p->allocs) {
     if (p->da.fr) p->da.fr(a, p->da.ctx);

@@ -446,8 +446,8 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // arithmetic) and the explicit inverse L_jj^{-1}, by all four waves of the
 // workgroup on the tile held in LDS, in 16x16 blocks.  For each block column p:
 // wave 0 factors the diagonal block in registers (lane r holds row r; pivots
-// read from the owning lane with readlane; one reciprocal square root with a
-// Newton step per pivot) and inverts it; the rows below are solved against
+// read from the owning lane with readlane; a correctly rounded square root and
+// its reciprocal per pivot) and inverts it; the rows below are solved against
 // that inverse (one thread per row); the trailing lower triangle takes the
 // rank-16 update.  The off-diagonal blocks of the inverse follow block
 // diagonal by block diagonal: X_qp = -X_qq sum_{p<=k<q} L_qk X_kp, stored
@@ -510,10 +510,11 @@ __device__ __forceinline__ void diag_blocked(const Task& t, const SubInfo* __res
         } else {
           bad |= !ok;
         }
-        // 1/sqrt(d): hardware estimate and one Newton step, then sqrt(d) = d / sqrt(d)
-        double inv = __builtin_amdgcn_rsq(dd);
-        inv = inv * (1.5 - 0.5 * dd * inv * inv);
-        const double sd = dd * inv;
+        // L(c, c) = sqrt(d) and its reciprocal, both correctly rounded, so that
+        // the block inverse built from inv is the inverse of the stored factor
+        // to rounding
+        const double sd = sqrt(dd);
+        const double inv = 1.0 / sd;
         double l = a[c] * inv;
         l = r > c ? l : 0.0;
         l = r == c ? sd : l;
@@ -753,7 +754,7 @@ __global__ __launch_bounds__(256) void k_trtri(const Task* __restrict__ tasks,
 // rows, streamed into two LDS buffers by the direct global-to-LDS loads as in
 // k_update_db.  X tiles are written column-major.
 template <typename T, int KC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T, KC == 16>::waves))) void k_lauum_db(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpdOcc<T>::waves))) void k_lauum_db(
     const Task* __restrict__ tasks, const SubInfo* __restrict__ subs, const T* __restrict__ W, T* X) {
   constexpr int CH = TS * KC;
   constexpr int PARTS = TS / KC;
@@ -1021,11 +1022,7 @@ void launch_dense(int kind, const Task* tasks, int count, const SubInfo* subs, T
       hipLaunchKernelGGL(k_trtri<T>, dim3(count), dim3(256), 0, st, tasks, subs, (const T*)arena, (const T*)linv, W);
       break;
     case K_LAUUM:
-      // form 1: 16-wide chunks at four workgroups per CU
-      if (form == 1)
-        hipLaunchKernelGGL((k_lauum_db<T, 16>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
-      else
-        hipLaunchKernelGGL((k_lauum_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
+      hipLaunchKernelGGL((k_lauum_db<T, 32>), dim3(count), dim3(256), 0, st, tasks, subs, (const T*)W, X);
       break;
   }
 }

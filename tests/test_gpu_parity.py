@@ -249,10 +249,9 @@ def test_mixed_precision_newton_step():
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_autotune_update_forms_identical(precision):
     """The first four factorisations use the four update forms (64x64 tiles,
-    128x64 tiles, 64x64 double-buffered in 32- and in 16-wide chunks; the
-    LAUUM launch in 32- and 16-wide chunks), later ones the fastest per
-    launch: the displacements are bit-identical throughout (same products,
-    same order) and match the oracle."""
+    128x64 tiles, 64x64 double-buffered in 32- and in 16-wide chunks), later
+    ones the fastest per launch: the displacements are bit-identical
+    throughout (same products, same order) and match the oracle."""
     m, ref = _oracle("cube32_s4")
     kw = dict(rtol=1e-10) if precision == "fp64" else dict(rtol=1e-8, ir_tol=1e-12)
     outs, wide, db = [], [], []
