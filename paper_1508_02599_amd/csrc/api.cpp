@@ -25,8 +25,8 @@ namespace {
 
 thread_local std::string g_setup_error;
 constexpr int kGmresRestart = 30;   // Krylov vectors per flexible GMRES cycle of the refinement
-constexpr int kDotBatch = 64;       // dot products per multi_dot call
 constexpr int kDualRestart = 100;   // Krylov vectors per cycle of the projected dual GMRES
+constexpr int kGsMax = (kDualRestart > kGmresRestart ? kDualRestart : kGmresRestart) + 1;   // basis vectors
 
 struct DeviceAlloc {
   void* (*fn)(size_t, void*, void*) = nullptr;
@@ -686,9 +686,9 @@ feti_status setup_device(feti_problem* p) {
     p->dg_y.assign(m, 0.0);
     p->dg_h.assign(m + 1, 0.0);
   }
-  if (p->dual_gmres || refine) {   // multi_dot
-    TRY(dalloc(p, p->d_gdots, (size_t)kDotBatch * DOT_PARTS));
-    HIPCHK(hipHostMalloc((void**)&p->h_gdots, (size_t)kDotBatch * DOT_PARTS * sizeof(double), hipHostMallocDefault));
+  if (p->dual_gmres || refine) {   // cgs2: partial sums, then two coefficient vectors and a norm
+    TRY(dalloc(p, p->d_gdots, (size_t)kGsMax * DOT_PARTS + 2 * kGsMax + 1));
+    HIPCHK(hipHostMalloc((void**)&p->h_gdots, (2 * kGsMax + 1) * sizeof(double), hipHostMallocDefault));
   }
   if (refine) {   // flexible GMRES
     const int m = std::min(std::max(p->opt.ir_max, 1), kGmresRestart);
@@ -1067,7 +1067,7 @@ bool pcg_converges_within(const PcgState& h, int prev_it, double prev_wn, int n)
 }
 
 feti_status dev_norm(feti_problem* p, const double* v, int64_t n, double* out);
-feti_status multi_dot(feti_problem* p, int64_t n, const double* const* a, int k, const double* w, double* out);
+feti_status cgs2(feti_problem* p, int64_t n, const double* V, int64_t ld, int k, double* w, double* h, double* nrm);
 
 // Projected GMRES on the dual problem (FETI_DUAL_GMRES), for local operators
 // that are not positive definite: P^T F lambda = P^T d on lambda_0 +
@@ -1090,7 +1090,6 @@ feti_status dual_gmres(feti_problem* p, double rtol, int* iters_out, int* status
   std::vector<double>& sn = p->dg_s;
   std::vector<double>& y = p->dg_y;
   std::vector<double>& hv = p->dg_h;
-  const double* ptrs[kDotBatch];
   project_fused(p, 0, 0, p->d_r, p->d_wv, nullptr, st, nullptr);
   double beta = 0.0;
   TRY(dev_norm(p, p->d_wv, n, &beta));
@@ -1109,18 +1108,9 @@ feti_status dual_gmres(feti_problem* p, double rtol, int* iters_out, int* status
       project_fused(p, 0, 0, p->d_tv, Z(j), nullptr, st, nullptr);
       apply_F(p, Z(j), p->d_q, nullptr, 1.0, nullptr);
       project_fused(p, 0, 0, p->d_q, p->d_dw, nullptr, st, nullptr);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int i0 = 0; i0 <= j; i0 += kDotBatch) {
-          const int cnt = std::min(kDotBatch, j + 1 - i0);
-          for (int i = 0; i < cnt; ++i) ptrs[i] = V(i0 + i);
-          TRY(multi_dot(p, n, ptrs, cnt, p->d_dw, hv.data() + i0));
-          for (int i = 0; i < cnt; ++i) {
-            vec_axpby(n, -hv[i0 + i], V(i0 + i), 1.0, p->d_dw, p->stream);
-            H[(size_t)j * (m + 1) + i0 + i] += hv[i0 + i];
-          }
-        }
       double hn = 0.0;
-      TRY(dev_norm(p, p->d_dw, n, &hn));
+      TRY(cgs2(p, n, V(0), n, j + 1, p->d_dw, hv.data(), &hn));
+      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = hv[i];
       H[(size_t)j * (m + 1) + j + 1] = hn;
       if (hn > 0.0) vec_axpby(n, 1.0 / hn, p->d_dw, 0.0, V(j + 1), p->stream);
       double* col = &H[(size_t)j * (m + 1)];
@@ -1369,20 +1359,27 @@ feti_status profile_gemv(feti_problem* p) {
   return FETI_OK;
 }
 
-// Dot products of w with up to kDotBatch vectors a_i (two per launch), from
-// fixed partitions summed on the host in a fixed order: deterministic.
-feti_status multi_dot(feti_problem* p, int64_t n, const double* const* a, int k, const double* w, double* out) {
-  for (int i = 0; i < k; i += 2)
-    pcg_dot(n, a[i], w, i + 1 < k ? a[i + 1] : nullptr, w, p->d_gdots + (size_t)i * DOT_PARTS, nullptr, p->stream);
-  const size_t cnt = (size_t)((k + 1) / 2) * 2 * DOT_PARTS;
-  HIPCHK(hipMemcpyAsync(p->h_gdots, p->d_gdots, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(hipStreamSynchronize(p->stream));
-  for (int i = 0; i < k; ++i) {
-    const double* part = p->h_gdots + (size_t)(i / 2) * 2 * DOT_PARTS + (i & 1);
-    double acc = 0.0;
-    for (int b = 0; b < DOT_PARTS; ++b) acc += part[2 * b];
-    out[i] = acc;
+// Classical Gram-Schmidt with one reorthogonalisation of w against the k
+// basis vectors V_i = V + i ld (two passes of k dot products, one launch
+// each, and w -= sum_i c_i V_i), then ||w||, all on the device with one
+// synchronisation at the end: h[i] = the two passes' coefficients summed,
+// *nrm = ||w||.  Every sum has a fixed order: deterministic.
+feti_status cgs2(feti_problem* p, int64_t n, const double* V, int64_t ld, int k, double* w, double* h, double* nrm) {
+  if (k > kGsMax) {   // cannot happen: both restart lengths are below kGsMax
+    p->err = "internal: more Gram-Schmidt vectors than the buffers hold";
+    return FETI_EINVAL;
   }
+  double* part = p->d_gdots;
+  double* c = p->d_gdots + (size_t)kGsMax * DOT_PARTS;
+  for (int pass = 0; pass < 2; ++pass) {
+    vec_multi_dot(n, V, ld, k, w, part, c + pass * kGsMax, p->stream);
+    vec_multi_axpy(n, V, ld, k, c + pass * kGsMax, w, p->stream);
+  }
+  vec_multi_dot(n, w, 0, 1, w, part, c + 2 * kGsMax, p->stream);
+  HIPCHK(hipMemcpyAsync(p->h_gdots, c, (2 * kGsMax + 1) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int i = 0; i < k; ++i) h[i] = p->h_gdots[i] + p->h_gdots[kGsMax + i];
+  *nrm = std::sqrt(std::max(0.0, p->h_gdots[2 * kGsMax]));
   return FETI_OK;
 }
 
@@ -1478,7 +1475,6 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
   std::vector<double>& sn = p->gm_s;
   std::vector<double>& y = p->gm_y;
   std::vector<double>& hv = p->gm_h;
-  const double* ptrs[kDotBatch];
   // dual tolerance of a preconditioner application: the reduction still
   // needed, divided by the observed ratio amp of the primal reduction that a
   // dual reduction eta achieved (learnt after every application, start 10),
@@ -1509,16 +1505,9 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_zero, Z(j), 0, st);
       // w = A z_j, orthogonalised against V_0..V_j (two passes)
       apply_assembled(p, Z(j), nullptr, p->d_gw);
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i <= j; ++i) ptrs[i] = V(i);
-        TRY(multi_dot(p, nd, ptrs, j + 1, p->d_gw, hv.data()));
-        for (int i = 0; i <= j; ++i) {
-          vec_axpby(nd, -hv[i], V(i), 1.0, p->d_gw, st);
-          H[(size_t)j * (m + 1) + i] += hv[i];
-        }
-      }
       double hn = 0.0;
-      TRY(dev_norm(p, p->d_gw, nd, &hn));
+      TRY(cgs2(p, nd, V(0), nd, j + 1, p->d_gw, hv.data(), &hn));
+      for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = hv[i];
       H[(size_t)j * (m + 1) + j + 1] = hn;
       if (hn > 0.0) vec_axpby(nd, 1.0 / hn, p->d_gw, 0.0, V(j + 1), st);
       // Givens rotations of column j

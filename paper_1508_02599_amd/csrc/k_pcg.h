@@ -110,6 +110,13 @@ void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, con
 void vec_dirinc(int64_t n_dof, const uint8_t* dmask, const double* dirval, double tau, const double* U,
                 double* dvals, hipStream_t s);
 void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
+// out[i] = V_i . w for the k vectors V_i = V + i ld, from the fixed partition
+// of every dot product (part: k * DOT_PARTS partial sums of scratch), summed
+// on the device in a fixed order; and y -= sum_i h_i V_i with the k
+// coefficients h on the device.
+void vec_multi_dot(int64_t n, const double* V, int64_t ld, int k, const double* w, double* part, double* out,
+                   hipStream_t s);
+void vec_multi_axpy(int64_t n, const double* V, int64_t ld, int k, const double* h, double* y, hipStream_t s);
 void vec_fill(int64_t n, double v, double* y, hipStream_t s);
 void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist_cap, hipStream_t s);
 template <typename T>

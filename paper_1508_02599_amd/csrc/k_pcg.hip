@@ -259,6 +259,51 @@ __global__ void k_dirinc(int64_t n_dof, const uint8_t* __restrict__ dmask, const
   dvals[g] = dmask[g] ? tau * dirval[g] - (U ? U[g] : 0.0) : 0.0;
 }
 
+// Block partial sums of the k dot products V_i . w (V_i = V + i ld) over the
+// fixed partition of every dot product: part[i * DOT_PARTS + b].  One launch
+// for all k (the Gram-Schmidt step of the GMRES iterations).
+__global__ __launch_bounds__(256) void k_multi_dot(int64_t n, const double* __restrict__ V, int64_t ld,
+                                                   const double* __restrict__ w, double* part) {
+  __shared__ double r1[256];
+  const double* a = V + (int64_t)blockIdx.y * ld;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double s1 = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += 256) s1 += a[k] * w[k];
+  r1[threadIdx.x] = s1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) r1[threadIdx.x] += r1[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = r1[0];
+}
+
+// out[i] = sum of the DOT_PARTS partial sums of product i, in a fixed tree
+// order (one workgroup per product).
+__global__ __launch_bounds__(256) void k_multi_finish(const double* __restrict__ part, double* out) {
+  static_assert(DOT_PARTS == 256, "one partial sum per thread");
+  __shared__ double r1[256];
+  r1[threadIdx.x] = part[(int64_t)blockIdx.x * DOT_PARTS + threadIdx.x];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) r1[threadIdx.x] += r1[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = r1[0];
+}
+
+// y -= sum_{i<k} h_i V_i, the products summed in order i = 0, 1, ...
+__global__ void k_multi_axpy(int64_t n, const double* __restrict__ V, int64_t ld, int k,
+                             const double* __restrict__ h, double* y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < k; ++i) acc += h[i] * V[(int64_t)i * ld + r];
+  y[r] -= acc;
+}
+
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) y[k] = (b == 0.0) ? a * x[k] : a * x[k] + b * y[k];   // b == 0: y is not read
@@ -947,6 +992,15 @@ void vec_global(int64_t n_dof, const int32_t* uc_ptr, const int64_t* uc_idx, con
 void vec_dirinc(int64_t n_dof, const uint8_t* dmask, const double* dirval, double tau, const double* U,
                 double* dvals, hipStream_t s) {
   hipLaunchKernelGGL(k_dirinc, grid1(n_dof), dim3(256), 0, s, n_dof, dmask, dirval, tau, U, dvals);
+}
+void vec_multi_dot(int64_t n, const double* V, int64_t ld, int k, const double* w, double* part, double* out,
+                   hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_multi_dot, dim3(DOT_PARTS, k), dim3(256), 0, s, n, V, ld, w, part);
+  hipLaunchKernelGGL(k_multi_finish, dim3(k), dim3(256), 0, s, part, out);
+}
+void vec_multi_axpy(int64_t n, const double* V, int64_t ld, int k, const double* h, double* y, hipStream_t s) {
+  if (n > 0 && k > 0) hipLaunchKernelGGL(k_multi_axpy, grid1(n), dim3(256), 0, s, n, V, ld, k, h, y);
 }
 void vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_axpby, grid1(n), dim3(256), 0, s, n, a, x, b, y);
