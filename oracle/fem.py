@@ -1,4 +1,4 @@
-"""Q1 hexahedral finite elements, written plainly in NumPy (FP64).
+"""Q1 and Q2 hexahedral finite elements, written plainly in NumPy (FP64).
 
 Oracle module (test infrastructure only).  Each function cites the passage of
 the paper it follows.
@@ -9,7 +9,8 @@ the paper it follows.
   (iso), (aniso_1), (aniso_2)): the strain energy is written out, the second
   Piola-Kirchhoff stress follows the additive split of eq. (additiveStress),
   and the volumetric part uses a pressure that is constant per element and
-  condensed element-wise (section 3.2, static condensation, P0 pressure).
+  condensed element-wise (section 3.2, static condensation, P0 pressure;
+  the paper's Q1-P0 and Q2-P0 pairs).
 * The element internal force is the weak form of eq. (WeakReference); the
   consistent tangent of eq. (Tangent) is obtained as the exact derivative of
   that internal force by complex-step differentiation, so no closed-form
@@ -17,7 +18,14 @@ the paper it follows.
 * Follower pressure on the current surface without load stiffness
   (section 3.2, last paragraph).
 
-Quadrature: 2x2x2 Gauss points at +-1/sqrt(3) for volumes, 2x2 for faces.
+Elements: Q1 = 8-node trilinear hexahedron, local node a = i + 2j + 4k at
+reference point (2i-1, 2j-1, 2k-1), 2x2x2 Gauss points; Q2 = 27-node
+triquadratic hexahedron (section 3.2's quadratic elements), local node
+a = i + 3j + 9k at (i-1, j-1, k-1), 3x3x3 Gauss points.  The element order is
+read from the number of nodes per element (8 or 27).  Pressure faces: Q1
+quadrilaterals of 4 corners (counter-clockwise, 2x2 Gauss points) and Q2
+quadrilaterals of 9 nodes (node i + 3j at face point (i-1, j-1), 3x3 Gauss
+points); both oriented so that dx/ds x dx/dt points out of the body.
 """
 from __future__ import annotations
 
@@ -28,6 +36,12 @@ XI = np.array([[2 * (a & 1) - 1, 2 * ((a >> 1) & 1) - 1, 2 * ((a >> 2) & 1) - 1]
                for a in range(8)], dtype=np.float64)
 _G = 1.0 / np.sqrt(3.0)
 GAUSS_PTS = XI * _G          # 8 points, unit weights
+
+# Q2: reference nodes of local node a = i + 3j + 9k, and the 3-point Gauss rule
+XI27 = np.array([[a % 3 - 1, (a // 3) % 3 - 1, a // 9 - 1] for a in range(27)], dtype=np.float64)
+_G3 = np.sqrt(0.6)
+_G3_PTS = np.array([-_G3, 0.0, _G3])
+_G3_WTS = np.array([5.0, 8.0, 5.0]) / 9.0
 
 
 def shape_hex8(xi):
@@ -42,18 +56,53 @@ def shape_hex8(xi):
     return N, dN
 
 
+def _lagrange3(x):
+    """1D quadratic Lagrange polynomials on the nodes -1, 0, 1 and their
+    derivatives at x: ([L_-1, L_0, L_1], [L'_-1, L'_0, L'_1])."""
+    return (np.array([0.5 * x * (x - 1.0), 1.0 - x * x, 0.5 * x * (x + 1.0)]),
+            np.array([x - 0.5, -2.0 * x, x + 0.5]))
+
+
+def shape_hex27(xi):
+    """Triquadratic shape functions N_a and dN_a/dxi at one reference point:
+    products of 1D quadratic Lagrange polynomials, node a = i + 3j + 9k."""
+    xi = np.asarray(xi, dtype=np.float64)
+    L = [_lagrange3(xi[d]) for d in range(3)]
+    N = np.empty(27)
+    dN = np.empty((27, 3))
+    for a in range(27):
+        ijk = (a % 3, (a // 3) % 3, a // 9)
+        v = [L[d][0][ijk[d]] for d in range(3)]
+        dv = [L[d][1][ijk[d]] for d in range(3)]
+        N[a] = v[0] * v[1] * v[2]
+        dN[a] = (dv[0] * v[1] * v[2], v[0] * dv[1] * v[2], v[0] * v[1] * dv[2])
+    return N, dN
+
+
 _SHAPES = [shape_hex8(g) for g in GAUSS_PTS]
+_WEIGHTS = np.ones(8)
+_SHAPES27 = []
+_WEIGHTS27 = []
+for _k in range(3):
+    for _j in range(3):
+        for _i in range(3):
+            _SHAPES27.append(shape_hex27([_G3_PTS[_i], _G3_PTS[_j], _G3_PTS[_k]]))
+            _WEIGHTS27.append(_G3_WTS[_i] * _G3_WTS[_j] * _G3_WTS[_k])
 
 
 def ref_gradients(Xe):
-    """For each Gauss point: (N, dN/dX [ne,8,3], detJ [ne]) of elements Xe [ne,8,3]."""
+    """For each Gauss point of elements Xe [ne, npe, 3] (npe = 8: Q1, 27: Q2):
+    (N, dN/dX [ne,npe,3], dV [ne]) with dV = Gauss weight x det(dX/dxi), the
+    quadrature weight of the point in the reference configuration."""
+    npe = Xe.shape[1]
+    shapes, weights = (_SHAPES, _WEIGHTS) if npe == 8 else (_SHAPES27, _WEIGHTS27)
     out = []
-    for N, dNxi in _SHAPES:
+    for (N, dNxi), wq in zip(shapes, weights):
         Jm = np.einsum("ead,ak->edk", Xe, dNxi)           # dX_d/dxi_k
         det = np.linalg.det(Jm)
         inv = np.linalg.inv(Jm)                             # dxi_k/dX_d
         dNX = np.einsum("ak,ekd->ead", dNxi, inv)
-        out.append((N, dNX, det))
+        out.append((N, dNX, wq * det))
     return out
 
 
@@ -72,10 +121,10 @@ def linear_stiffness(Xe, lam, mu):
     K_{ai,bj} = int lam dN_a/dX_i dN_b/dX_j + mu (dN_a/dX_j dN_b/dX_i
     + delta_ij grad N_a . grad N_b) dX.
     """
-    ne = Xe.shape[0]
+    ne, npe = Xe.shape[:2]
     lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (ne,))
     mu = np.broadcast_to(np.asarray(mu, dtype=np.float64), (ne,))
-    K = np.zeros((ne, 8, 3, 8, 3))
+    K = np.zeros((ne, npe, 3, npe, 3))
     eye = np.eye(3)
     for _, dN, det in ref_gradients(Xe):
         w = det
@@ -85,16 +134,16 @@ def linear_stiffness(Xe, lam, mu):
         t3 = dot[:, :, None, :, None] * eye[None, None, :, None, :]
         K += w[:, None, None, None, None] * (lam[:, None, None, None, None] * t1
                                              + mu[:, None, None, None, None] * (t2 + t3))
-    return K.reshape(ne, 24, 24)
+    return K.reshape(ne, 3 * npe, 3 * npe)
 
 
 def body_force_vector(Xe, b):
     """f_e[3a+i] = int N_a b_i dX for a force b [ne,3] per unit reference volume."""
-    ne = Xe.shape[0]
-    f = np.zeros((ne, 8, 3))
+    ne, npe = Xe.shape[:2]
+    f = np.zeros((ne, npe, 3))
     for N, _, det in ref_gradients(Xe):
         f += det[:, None, None] * N[None, :, None] * b[:, None, :]
-    return f.reshape(ne, 24)
+    return f.reshape(ne, 3 * npe)
 
 
 # ---------------------------------------------------------------------------
@@ -204,13 +253,14 @@ def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa, acts=None, return_acts=F
 
     Isochoric part: int F S_iso Grad N_a dX.  Volumetric part: p_e g_a with
     p_e = kappa (Jbar_e - 1) and g_a = dv_e/du_a = int J F^{-T} Grad N_a dX.
-    Returns (f [ne,24], p_e [ne], Jbar [ne]) (and the fibre activity per Gauss
-    point if ``return_acts``); ``acts`` imposes a previously decided activity.
+    Returns (f [ne,3 npe], p_e [ne], Jbar [ne]) (and the fibre activity per
+    Gauss point if ``return_acts``); ``acts`` imposes a previously decided
+    activity.
     """
-    ne = Xe.shape[0]
+    ne, npe = Xe.shape[:2]
     dtype = np.result_type(Ue, np.float64)
-    f = np.zeros((ne, 8, 3), dtype=dtype)
-    g = np.zeros((ne, 8, 3), dtype=dtype)
+    f = np.zeros((ne, npe, 3), dtype=dtype)
+    g = np.zeros((ne, npe, 3), dtype=dtype)
     V = np.zeros(ne)
     v = np.zeros(ne, dtype=dtype)
     out_acts = []
@@ -230,21 +280,21 @@ def hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa, acts=None, return_acts=F
     p = kappa * (Jbar - 1.0)
     f = f + p[:, None, None] * g
     if return_acts:
-        return f.reshape(ne, 24), p, Jbar, out_acts
-    return f.reshape(ne, 24), p, Jbar
+        return f.reshape(ne, 3 * npe), p, Jbar, out_acts
+    return f.reshape(ne, 3 * npe), p, Jbar
 
 
 def hgo_element_tangent(Xe, Ue, a1, a2, c, k1, k2, kappa, h=1e-30):
     """Consistent tangent K_e = d f_e / d u_e (eq. (Tangent) with the condensed
     pressure), computed exactly by complex-step differentiation of
     :func:`hgo_element_force`: column (b,j) is Im f(u + i h e_bj) / h.
-    Returns (K [ne,24,24], f [ne,24]).
+    Returns (K [ne,3 npe,3 npe], f [ne,3 npe]).
     """
-    ne = Xe.shape[0]
+    ne, npe = Xe.shape[:2]
     f0, _, _, acts = hgo_element_force(Xe, Ue, a1, a2, c, k1, k2, kappa, return_acts=True)
-    K = np.empty((ne, 24, 24))
+    K = np.empty((ne, 3 * npe, 3 * npe))
     Uc = Ue.astype(np.complex128)
-    for col in range(24):
+    for col in range(3 * npe):
         a, j = divmod(col, 3)
         Up = Uc.copy()
         Up[:, a, j] += 1j * h
@@ -253,42 +303,63 @@ def hgo_element_tangent(Xe, Ue, a1, a2, c, k1, k2, kappa, h=1e-30):
     return K, f0.real
 
 
+def _face_rule(nfn):
+    """Shape values and derivatives of the face element at its Gauss points:
+    [(w, N [nfn], dN/ds [nfn], dN/dt [nfn])]; nfn = 4 (Q1, 2x2 points) or 9
+    (Q2, 3x3 points)."""
+    out = []
+    if nfn == 4:
+        eta = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
+        for g1 in (-_G, _G):
+            for g2 in (-_G, _G):
+                N = 0.25 * (1 + eta[:, 0] * g1) * (1 + eta[:, 1] * g2)
+                d1 = 0.25 * eta[:, 0] * (1 + eta[:, 1] * g2)
+                d2 = 0.25 * eta[:, 1] * (1 + eta[:, 0] * g1)
+                out.append((1.0, N, d1, d2))
+        return out
+    for j in range(3):
+        for i in range(3):
+            Ls, dLs = _lagrange3(_G3_PTS[i])
+            Lt, dLt = _lagrange3(_G3_PTS[j])
+            N = np.array([Ls[a % 3] * Lt[a // 3] for a in range(9)])
+            d1 = np.array([dLs[a % 3] * Lt[a // 3] for a in range(9)])
+            d2 = np.array([Ls[a % 3] * dLt[a // 3] for a in range(9)])
+            out.append((_G3_WTS[i] * _G3_WTS[j], N, d1, d2))
+    return out
+
+
 def pressure_face_load(xf, p):
     """Follower pressure load on quadrilateral faces in the current geometry.
 
-    f_a = -p int N_a n da, with n da = (dx/deta1 x dx/deta2) deta; the corner
-    order makes this normal point out of the body.  xf [nf,4,3] -> [nf,4,3].
+    f_a = -p int N_a n da, with n da = (dx/ds x dx/dt) ds dt; the node order
+    makes this normal point out of the body.  xf [nf,nfn,3] -> [nf,nfn,3]
+    with nfn = 4 (Q1 faces) or 9 (Q2 faces).
     """
-    eta = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
     f = np.zeros_like(xf)
-    for g1 in (-_G, _G):
-        for g2 in (-_G, _G):
-            N = 0.25 * (1 + eta[:, 0] * g1) * (1 + eta[:, 1] * g2)
-            d1 = 0.25 * eta[:, 0] * (1 + eta[:, 1] * g2)
-            d2 = 0.25 * eta[:, 1] * (1 + eta[:, 0] * g1)
-            t1 = np.einsum("fad,a->fd", xf, d1)
-            t2 = np.einsum("fad,a->fd", xf, d2)
-            n = np.cross(t1, t2)
-            f += -p * N[None, :, None] * n[:, None, :]
+    for w, N, d1, d2 in _face_rule(xf.shape[1]):
+        t1 = np.einsum("fad,a->fd", xf, d1)
+        t2 = np.einsum("fad,a->fd", xf, d2)
+        n = np.cross(t1, t2)
+        f += -p * w * N[None, :, None] * n[:, None, :]
     return f
 
 
 def pressure_load_stiffness(xf, p, h=1e-30):
     """Derivative of the follower pressure load with respect to the current
-    corner positions, D[f, 3a+i, 3b+j] = d f_ai / d x_bj (xf [nf,4,3]).
+    node positions, D[f, 3a+i, 3b+j] = d f_ai / d x_bj (xf [nf,nfn,3]).
 
     The paper drops this term from the tangent and notes that keeping it
     makes the system non-symmetric (section 3.2, last paragraph).  Computed
     exactly by complex-step differentiation of :func:`pressure_face_load`.
     """
-    nf = xf.shape[0]
-    D = np.empty((nf, 12, 12))
+    nf, nfn = xf.shape[:2]
+    D = np.empty((nf, 3 * nfn, 3 * nfn))
     xc = np.asarray(xf, dtype=np.complex128)
-    for col in range(12):
+    for col in range(3 * nfn):
         b, j = divmod(col, 3)
         xp = xc.copy()
         xp[:, b, j] += 1j * h
-        D[:, :, col] = pressure_face_load(xp, p).reshape(nf, 12).imag / h
+        D[:, :, col] = pressure_face_load(xp, p).reshape(nf, 3 * nfn).imag / h
     return D
 
 
@@ -315,8 +386,9 @@ def element_matrices(mesh, U=None, chunk=4096, elems=None):
     Xe = mesh.xyz[hex8]
     Ue = np.zeros_like(Xe) if U is None else np.asarray(U).reshape(-1, 3)[hex8]
     m = _elem_material(mesh)[el]
-    Ke = np.empty((ne, 24, 24))
-    fe = np.zeros((ne, 24))
+    nde = 3 * hex8.shape[1]
+    Ke = np.empty((ne, nde, nde))
+    fe = np.zeros((ne, nde))
     hgo = m[:, 0] == MAT_HGO
     lin = ~hgo
     if lin.any():
@@ -325,7 +397,7 @@ def element_matrices(mesh, U=None, chunk=4096, elems=None):
         for s in range(0, idx.size, chunk):
             ii = idx[s:s + chunk]
             Ke[ii] = linear_stiffness(Xe[ii], lam[s:s + chunk], mu[s:s + chunk])
-            fe[ii] = np.einsum("eij,ej->ei", Ke[ii], Ue[ii].reshape(-1, 24))
+            fe[ii] = np.einsum("eij,ej->ei", Ke[ii], Ue[ii].reshape(-1, nde))
     if hgo.any():
         idx = np.nonzero(hgo)[0]
         for s in range(0, idx.size, chunk):
@@ -347,9 +419,10 @@ def assemble(mesh, U=None, tau=1.0):
     """
     import scipy.sparse as sp
     Ke, fe = element_matrices(mesh, U)
-    dofs = (3 * mesh.hex8[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 24)
-    rows = np.repeat(dofs, 24, axis=1).ravel()
-    cols = np.tile(dofs, (1, 24)).ravel()
+    nde = 3 * mesh.hex8.shape[1]
+    dofs = (3 * mesh.hex8[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, nde)
+    rows = np.repeat(dofs, nde, axis=1).ravel()
+    cols = np.tile(dofs, (1, nde)).ravel()
     n = mesh.n_dofs
     K = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(n, n)).tocsr()
     K.sum_duplicates()
@@ -376,9 +449,10 @@ def assemble_load_stiffness(mesh, U=None):
         return sp.csr_matrix((n, n))
     x = mesh.xyz + (0.0 if U is None else np.asarray(U).reshape(-1, 3))
     D = pressure_load_stiffness(x[mesh.pface], mesh.pressure)
-    dofs = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
-    rows = np.repeat(dofs, 12, axis=1).ravel()
-    cols = np.tile(dofs, (1, 12)).ravel()
+    ndf = 3 * mesh.pface.shape[1]
+    dofs = (3 * mesh.pface[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, ndf)
+    rows = np.repeat(dofs, ndf, axis=1).ravel()
+    cols = np.tile(dofs, (1, ndf)).ravel()
     A = sp.coo_matrix((D.ravel(), (rows, cols)), shape=(n, n)).tocsr()
     A.sum_duplicates()
     return A
@@ -400,7 +474,8 @@ def nodal_residual(mesh, nodes, u, U=None, tau=1.0):
     elems = np.nonzero(np.isin(mesh.hex8, nodes).any(axis=1))[0]
     Ke, fe = element_matrices(mesh, U, elems=elems)
     hex8 = mesh.hex8[elems]
-    ue = u[hex8].reshape(-1, 24)
+    npe = hex8.shape[1]
+    ue = u[hex8].reshape(-1, 3 * npe)
     Ku = np.einsum("eij,ej->ei", Ke, ue)
     pos = {int(n): k for k, n in enumerate(nodes)}
     res = np.zeros((nodes.size, 3))
@@ -410,7 +485,7 @@ def nodal_residual(mesh, nodes, u, U=None, tau=1.0):
     if mesh.body_force is not None:
         fb = body_force_vector(mesh.xyz[hex8], mesh.body_force[elems])
     for e in range(elems.size):
-        for a in range(8):
+        for a in range(npe):
             k = loc[e, a]
             if k < 0:
                 continue
@@ -426,7 +501,7 @@ def nodal_residual(mesh, nodes, u, U=None, tau=1.0):
             x = mesh.xyz + (0.0 if U is None else np.asarray(U).reshape(-1, 3))
             fp = pressure_face_load(x[mesh.pface[faces]], mesh.pressure)
             for q, f in enumerate(faces):
-                for a in range(4):
+                for a in range(mesh.pface.shape[1]):
                     k = pos.get(int(mesh.pface[f, a]), -1)
                     if k >= 0:
                         res[k] += tau * fp[q, a]

@@ -80,7 +80,7 @@ class TornProblem:
             K = np.zeros((n, n))
             f = np.zeros(n)
             el = sd["elems"]
-            edofs = loc[(3 * mesh.hex8[el][:, :, None] + np.arange(3)).reshape(-1, 24)]
+            edofs = loc[(3 * mesh.hex8[el][:, :, None] + np.arange(3)).reshape(-1, 3 * mesh.hex8.shape[1])]
             for e in range(el.size):
                 ix = edofs[e]
                 K[np.ix_(ix, ix)] += Ke[el[e]]
@@ -409,7 +409,7 @@ def lanczos_kappa(alphas, betas):
 def linear_torn_problem(mesh, variant, load_factor=1.0):
     """Torn form of the linear elastic problem K u = lf f_ext, u = lf u_D."""
     Ke, _ = fem.element_matrices(mesh, None)
-    fe = np.zeros((mesh.n_elems, 24))
+    fe = np.zeros((mesh.n_elems, 3 * mesh.hex8.shape[1]))
     if mesh.body_force is not None:
         fe = load_factor * fem.body_force_vector(mesh.xyz[mesh.hex8], mesh.body_force)
     return TornProblem(mesh, Ke, fe, np.zeros(mesh.n_dofs), mesh.dir_dof,

@@ -1,17 +1,22 @@
-"""Structured Q1-hexahedral problems with a non-overlapping element partition.
+"""Structured hexahedral problems (Q1 or Q2) with a non-overlapping element
+partition.
 
 Conventions (shared by every consumer):
   * node ids are global, coordinates ``xyz[n_nodes, 3]`` (float64);
-  * ``hex8[n_elems, 8]`` lists the eight corners of a hexahedron in
-    lexicographic order, x fastest: local corner ``a = i + 2 j + 4 k`` sits at
-    reference coordinates ``(2i-1, 2j-1, 2k-1)``;
+  * ``hex8[n_elems, npe]`` lists the nodes of each hexahedron in lexicographic
+    order, x fastest.  Q1 (npe = 8): local corner ``a = i + 2 j + 4 k`` sits at
+    reference coordinates ``(2i-1, 2j-1, 2k-1)``.  Q2 (npe = 27, the 27-node
+    triquadratic element): local node ``a = i + 3 j + 9 k`` sits at
+    ``(i-1, j-1, k-1)``;
   * ``elem_sub[e]`` is the subdomain of element ``e`` (the tearing of the
     domain into non-overlapping subdomains, paper section 4, eq. (decomposition));
   * a Dirichlet degree of freedom is ``3*node + component``;
   * ``body_force[e]`` is a constant force per unit reference volume;
-  * ``pface[f]`` holds four corner nodes of a quadrilateral loaded by a
-    follower pressure, ordered so that the right-hand normal of
-    (x1 - x0) x (x3 - x0) points out of the body.
+  * ``pface[f]`` holds the nodes of a quadrilateral loaded by a follower
+    pressure: Q1, four corners ordered so that the right-hand normal of
+    (x1 - x0) x (x3 - x0) points out of the body; Q2, nine nodes, node
+    ``i + 3 j`` at face coordinates ``(s, t) = (i-1, j-1)`` with
+    dx/ds x dx/dt pointing out of the body.
 
 Materials: ``mat`` is a float64 table with one row per material,
 ``[kind, E, nu, c, k1, k2, kappa]`` where kind 0 is isotropic linear elasticity
@@ -29,7 +34,7 @@ MAT_HGO = 1
 @dataclass
 class Mesh:
     xyz: np.ndarray                 # [n_nodes, 3] f64
-    hex8: np.ndarray                # [n_elems, 8] i64
+    hex8: np.ndarray                # [n_elems, 8 or 27] i64 (Q1 or Q2)
     elem_sub: np.ndarray            # [n_elems] i32
     n_sub: int
     mat: np.ndarray                 # [n_mat, 7] f64 (kind, E, nu, c, k1, k2, kappa)
@@ -38,7 +43,7 @@ class Mesh:
     dir_val: np.ndarray             # [n_dir] f64
     body_force: np.ndarray | None = None   # [n_elems, 3] f64
     fibers: np.ndarray | None = None       # [n_elems, 2, 3] f64 unit vectors
-    pface: np.ndarray | None = None        # [n_pfaces, 4] i64
+    pface: np.ndarray | None = None        # [n_pfaces, 4 or 9] i64
     pressure: float = 0.0
     name: str = ""
     meta: dict = field(default_factory=dict)
@@ -54,6 +59,11 @@ class Mesh:
     @property
     def n_dofs(self) -> int:
         return 3 * self.n_nodes
+
+    @property
+    def order(self) -> int:
+        """Polynomial order of the elements: 1 (8 nodes) or 2 (27 nodes)."""
+        return 1 if self.hex8.shape[1] == 8 else 2
 
 
 def _grid_nodes(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0):
@@ -71,6 +81,17 @@ def _grid_hex(nx, ny, nz):
     sx, sy = nx + 1, (nx + 1) * (ny + 1)
     base = ex + sx * ey + sy * ez
     offs = np.array([0, 1, sx, sx + 1, sy, sy + 1, sy + sx, sy + sx + 1], dtype=np.int64)
+    return (base[:, None] + offs[None, :]).astype(np.int64), np.stack([ex, ey, ez], axis=1)
+
+
+def _grid_hex27(nx, ny, nz):
+    """27-node hexahedra of an (nx, ny, nz) element grid on the node grid of
+    (2nx+1, 2ny+1, 2nz+1) nodes; element id = ex + nx*(ey + ny*ez)."""
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    sx, sy = 2 * nx + 1, (2 * nx + 1) * (2 * ny + 1)
+    base = 2 * ex + sx * 2 * ey + sy * 2 * ez
+    offs = np.array([i + sx * j + sy * k for k in range(3) for j in range(3) for i in range(3)], dtype=np.int64)
     return (base[:, None] + offs[None, :]).astype(np.int64), np.stack([ex, ey, ez], axis=1)
 
 
@@ -98,17 +119,18 @@ def _boundary_nodes_cube(nx, ny, nz):
 
 def cube_mesh(n_el: int, n_sub_axis: int, *, E=1.0, nu=0.3, nu_per_sub=None,
               body_force=(0.0, 0.0, -1.0), dirichlet="zero", dirichlet_fn=None,
-              name="cube") -> Mesh:
-    """Unit cube, ``n_el``^3 Q1 elements, cut into ``n_sub_axis``^3 equal boxes.
+              name="cube", order=1) -> Mesh:
+    """Unit cube, ``n_el``^3 Q1 (order 1) or Q2 (order 2) elements, cut into
+    ``n_sub_axis``^3 equal boxes.
 
     Subdomain order is s = ix + m*iy + m*m*iz.  ``nu_per_sub`` (length m^3)
     gives one Poisson ratio per subdomain; otherwise every element has ``nu``.
     Dirichlet data is imposed on all of the cube's surface: zero, or
     ``dirichlet_fn(xyz) -> [n, 3]`` evaluated at the boundary nodes.
     """
-    assert n_el % n_sub_axis == 0
-    xyz = _grid_nodes(n_el, n_el, n_el)
-    hex8, ijk = _grid_hex(n_el, n_el, n_el)
+    assert n_el % n_sub_axis == 0 and order in (1, 2)
+    xyz = _grid_nodes(order * n_el, order * n_el, order * n_el)
+    hex8, ijk = _grid_hex(n_el, n_el, n_el) if order == 1 else _grid_hex27(n_el, n_el, n_el)
     h = n_el // n_sub_axis
     cuts = list(range(0, n_el + 1, h))
     elem_sub = box_partition(cuts, cuts, cuts, ijk)
@@ -124,7 +146,7 @@ def cube_mesh(n_el: int, n_sub_axis: int, *, E=1.0, nu=0.3, nu_per_sub=None,
     else:
         mat = np.array([[MAT_LINEAR, E, nu, 0, 0, 0, 0]], dtype=np.float64)
         elem_mat = np.zeros(hex8.shape[0], dtype=np.int32)
-    bnodes = _boundary_nodes_cube(n_el, n_el, n_el)
+    bnodes = _boundary_nodes_cube(order * n_el, order * n_el, order * n_el)
     dir_dof = (3 * bnodes[:, None] + np.arange(3)[None, :]).ravel().astype(np.int64)
     if dirichlet_fn is not None:
         dir_val = np.asarray(dirichlet_fn(xyz[bnodes]), dtype=np.float64).reshape(-1)
@@ -135,7 +157,7 @@ def cube_mesh(n_el: int, n_sub_axis: int, *, E=1.0, nu=0.3, nu_per_sub=None,
         bf = np.tile(np.asarray(body_force, dtype=np.float64), (hex8.shape[0], 1))
     return Mesh(xyz=xyz, hex8=hex8, elem_sub=elem_sub, n_sub=n_sub, mat=mat,
                 elem_mat=elem_mat, dir_dof=dir_dof, dir_val=dir_val, body_force=bf,
-                name=name, meta={"n_el": n_el, "n_sub_axis": n_sub_axis})
+                name=name, meta={"n_el": n_el, "n_sub_axis": n_sub_axis, "order": order})
 
 
 def partial_dirichlet_cube(n_el=8, n_sub_axis=2, **kw) -> Mesh:
@@ -222,39 +244,46 @@ ADVENTITIA = dict(c=0.3, k1=0.562, k2=0.7112, angle_deg=62.0)
 
 
 def tube_mesh(nr=16, nth=128, nz=64, sub=(1, 16, 8), r_in=1.0, r_out=1.3, length=4.0,
-              r_layer=1.2, kappa_factor=1000.0, pressure=16.0 * 0.133322) -> Mesh:
-    """Two-layer thick-walled tube, periodic in the circumferential direction.
+              r_layer=1.2, kappa_factor=1000.0, pressure=16.0 * 0.133322, order=1) -> Mesh:
+    """Two-layer thick-walled tube, periodic in the circumferential direction,
+    of nr x nth x nz Q1 (order 1) or Q2 (order 2) elements.
 
-    Nodes sit at r_i = r_in + (r_out-r_in) i/nr, theta_j = 2 pi j/nth,
-    z_k = length k/nz.  Element (er, et, ez) has id er + nr*(et + nth*ez).
-    Elements whose centroid radius is below ``r_layer`` are media, the others
-    adventitia.  Fibre families are cos(a) e_theta +/- sin(a) e_z at the
-    element centroid.  Both ends (z=0 and z=length) are clamped.  The inner
+    Nodes sit at r_i = r_in + (r_out-r_in) i/(order nr), theta_j = 2 pi
+    j/(order nth), z_k = length k/(order nz) (Q2: the mid-side nodes lie on the
+    cylinders).  Element (er, et, ez) has id er + nr*(et + nth*ez).  Elements
+    whose centroid radius (mean of the eight corners) is below ``r_layer`` are
+    media, the others adventitia.  Fibre families are cos(a) e_theta +/- sin(a)
+    e_z at that centroid.  Both ends (z=0 and z=length) are clamped.  The inner
     surface carries a follower pressure, in kPa like the material moduli
-    (default 16 mmHg).  Subdomains are boxes of the
-    (r, theta, z) element grid, id = br + Br*(bt + Bt*bz).
+    (default 16 mmHg).  Subdomains are boxes of the (r, theta, z) element
+    grid, id = br + Br*(bt + Bt*bz).
     """
-    nrn, nthn, nzn = nr + 1, nth, nz + 1
-    ri = r_in + (r_out - r_in) * np.arange(nrn) / nr
-    th = 2.0 * np.pi * np.arange(nthn) / nth
-    zk = length * np.arange(nzn) / nz
+    assert order in (1, 2)
+    q = order
+    nrn, nthn, nzn = q * nr + 1, q * nth, q * nz + 1
+    ri = r_in + (r_out - r_in) * np.arange(nrn) / (q * nr)
+    th = 2.0 * np.pi * np.arange(nthn) / (q * nth)
+    zk = length * np.arange(nzn) / (q * nz)
     K, J, I = np.meshgrid(np.arange(nzn), np.arange(nthn), np.arange(nrn), indexing="ij")
     I, J, K = I.ravel(), J.ravel(), K.ravel()
     xyz = np.stack([ri[I] * np.cos(th[J]), ri[I] * np.sin(th[J]), zk[K]], axis=1)
 
     def nid(i, j, k):
-        return i + nrn * ((j % nth) + nthn * k)
+        return i + nrn * ((j % nthn) + nthn * k)
 
     ez, et, er = np.meshgrid(np.arange(nz), np.arange(nth), np.arange(nr), indexing="ij")
     er, et, ez = er.ravel(), et.ravel(), ez.ravel()
-    hex8 = np.stack([nid(er + di, et + dj, ez + dk)
-                     for dk in (0, 1) for dj in (0, 1) for di in (0, 1)], axis=1).astype(np.int64)
+    hex8 = np.stack([nid(q * er + di, q * et + dj, q * ez + dk)
+                     for dk in range(q + 1) for dj in range(q + 1) for di in range(q + 1)],
+                    axis=1).astype(np.int64)
+    corners = hex8[:, [0, q, q * (q + 1), q * (q + 1) + q, q * (q + 1) ** 2, q * (q + 1) ** 2 + q,
+                       q * (q + 1) ** 2 + q * (q + 1), (q + 1) ** 3 - 1]]
     ijk = np.stack([er, et, ez], axis=1)
     Br, Bt, Bz = sub
     assert nr % Br == 0 and nth % Bt == 0 and nz % Bz == 0
     elem_sub = box_partition(list(range(0, nr + 1, nr // Br)), list(range(0, nth + 1, nth // Bt)),
                              list(range(0, nz + 1, nz // Bz)), ijk)
-    cen = xyz[hex8].mean(axis=1)
+    cen = xyz[corners].mean(axis=1)
     rc = np.sqrt(cen[:, 0] ** 2 + cen[:, 1] ** 2)
     media = rc < r_layer
     etheta = np.stack([-cen[:, 1] / rc, cen[:, 0] / rc, np.zeros_like(rc)], axis=1)
@@ -270,19 +299,24 @@ def tube_mesh(nr=16, nth=128, nz=64, sub=(1, 16, 8), r_in=1.0, r_out=1.3, length
          kappa_factor * ADVENTITIA["c"]],
     ], dtype=np.float64)
     elem_mat = np.where(media, 0, 1).astype(np.int32)
-    ends = np.nonzero((K == 0) | (K == nz))[0]
+    ends = np.nonzero((K == 0) | (K == q * nz))[0]
     dir_dof = (3 * ends[:, None] + np.arange(3)[None, :]).ravel().astype(np.int64)
-    # inner surface faces (radial index 0): corners (j,k),(j,k+1),(j+1,k+1),(j+1,k),
-    # so x1-x0 runs along +z and x3-x0 along +theta; e_z x e_theta = -e_r points
-    # out of the body (towards the axis).
+    # inner surface faces (radial index 0).  Q1: corners (j,k),(j,k+1),(j+1,k+1),
+    # (j+1,k), so x1-x0 runs along +z and x3-x0 along +theta; Q2: node i + 3j at
+    # z offset i and theta offset j, so s runs along +z and t along +theta.
+    # Either way e_z x e_theta = -e_r points out of the body (towards the axis).
     jj, kk = np.meshgrid(np.arange(nth), np.arange(nz), indexing="ij")
     jj, kk = jj.ravel(), kk.ravel()
-    pface = np.stack([nid(0, jj, kk), nid(0, jj, kk + 1), nid(0, jj + 1, kk + 1),
-                      nid(0, jj + 1, kk)], axis=1).astype(np.int64)
+    if q == 1:
+        pface = np.stack([nid(0, jj, kk), nid(0, jj, kk + 1), nid(0, jj + 1, kk + 1),
+                          nid(0, jj + 1, kk)], axis=1).astype(np.int64)
+    else:
+        pface = np.stack([nid(0, 2 * jj + j, 2 * kk + i) for j in range(3) for i in range(3)],
+                         axis=1).astype(np.int64)
     return Mesh(xyz=xyz, hex8=hex8, elem_sub=elem_sub, n_sub=Br * Bt * Bz, mat=mat,
                 elem_mat=elem_mat, dir_dof=dir_dof, dir_val=np.zeros(dir_dof.shape[0]),
                 body_force=None, fibers=fibers, pface=pface, pressure=float(pressure),
-                name="tube", meta={"nr": nr, "nth": nth, "nz": nz, "sub": sub})
+                name="tube", meta={"nr": nr, "nth": nth, "nz": nz, "sub": sub, "order": order})
 
 
 def _cfg2_nu(seed: int, n_sub: int) -> np.ndarray:
