@@ -81,16 +81,20 @@ typedef struct {
   double E, nu, c, k1, k2, kappa;
 } feti_material;
 
-/* The torn problem (section 4, eq. (decomposition)): a Q1 hexahedral mesh,
- * a non-overlapping element partition, materials, Dirichlet data (eq.
+/* The torn problem (section 4, eq. (decomposition)): a Q1 or Q2 hexahedral
+ * mesh, a non-overlapping element partition, materials, Dirichlet data (eq.
  * (Dirichlet)), a body force and a follower pressure (eq. (Neumann)).
- * Node-major DOF numbering: dof = 3*node + component. */
+ * Node-major DOF numbering: dof = 3*node + component.  Q2 elements are the
+ * 27-node triquadratic hexahedra of section 3.2 (with the HGO material, the
+ * Q2-P0 pair: a pressure constant per element, condensed). */
 typedef struct {
   int64_t n_nodes;
   const double* xyz;           /* [n_nodes][3] reference coordinates                   */
   int64_t n_elems;
-  const int64_t* hex8;         /* [n_elems][8] corners, lexicographic (x fastest):
-                                  corner i+2j+4k at reference point (2i-1,2j-1,2k-1)   */
+  const int64_t* hex8;         /* element nodes, lexicographic (x fastest).  Q1:
+                                  [n_elems][8], corner i+2j+4k at reference point
+                                  (2i-1,2j-1,2k-1).  Q2: [n_elems][27], node i+3j+9k
+                                  at reference point (i-1,j-1,k-1)                      */
   int32_t n_sub;
   const int32_t* elem_sub;     /* [n_elems] subdomain id in [0, n_sub); every subdomain
                                   must own at least one element                         */
@@ -104,9 +108,12 @@ typedef struct {
   const double* dir_val;       /* [n_dir] prescribed displacement                       */
   const double* body_force;    /* [n_elems][3] force per unit reference volume, or NULL */
   int64_t n_pfaces;
-  const int64_t* pface;        /* [n_pfaces][4] quadrilateral corners; (x1-x0)x(x3-x0)
-                                  points out of the body                                */
+  const int64_t* pface;        /* Q1: [n_pfaces][4] quadrilateral corners, (x1-x0)x(x3-x0)
+                                  points out of the body.  Q2: [n_pfaces][9], node i+3j
+                                  at face point (s,t) = (i-1,j-1), dx/ds x dx/dt points
+                                  out of the body                                       */
   double pressure;             /* follower pressure on pface, current geometry           */
+  int32_t order;               /* element order: 1 (Q1; 0 is read as 1) or 2 (Q2)       */
 } feti_mesh;
 
 #define FETI_DEVICE_PTRS 0x1ull /* U / u / dU arguments are device pointers */

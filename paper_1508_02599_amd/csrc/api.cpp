@@ -585,10 +585,11 @@ feti_status setup_device(feti_problem* p) {
   }
   // working memory
   const size_t e = elt(p);
-  TRY(dalloc(p, p->d_Ke, (size_t)P.n_elems * 576));
-  TRY(dalloc(p, p->d_fint, (size_t)P.n_elems * 24));
-  TRY(dalloc(p, p->d_fbody, (size_t)P.n_elems * 24));
-  TRY(dalloc(p, p->d_ell_val, (size_t)P.NF * ELLW));
+  const size_t nde = 3 * (size_t)P.npe;   // DOFs per element
+  TRY(dalloc(p, p->d_Ke, (size_t)P.n_elems * nde * nde));
+  TRY(dalloc(p, p->d_fint, (size_t)P.n_elems * nde));
+  TRY(dalloc(p, p->d_fbody, (size_t)P.n_elems * nde));
+  TRY(dalloc(p, p->d_ell_val, (size_t)P.NF * P.ellw));
   TRY(dalloc(p, p->d_U, (size_t)P.n_dof));
   TRY(dalloc(p, p->d_fnodal, (size_t)P.n_dof));
   {
@@ -867,6 +868,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   AsmArgs a;
   a.n_elems = P.n_elems;
   a.xyz = p->d_xyz;
+  a.npe = P.npe;
   a.hex8 = p->d_hex8;
   a.elem_mat = p->d_elem_mat;
   a.mat = p->d_mat;
@@ -895,7 +897,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     launch_init_arena<float>(p->d_tasks + AT.first, AT.count, p->d_sub, (float*)p->d_arena, p->stream_c);
   else
     launch_init_arena<double>(p->d_tasks + AT.first, AT.count, p->d_sub, (double*)p->d_arena, p->stream_c);
-  vec_fill((int64_t)P.NF * ELLW, 0.0, p->d_ell_val, p->stream_c);
+  vec_fill((int64_t)P.NF * P.ellw, 0.0, p->d_ell_val, p->stream_c);
   HIPCHK(hipEventRecord(p->ev_fjoin, p->stream_c));
   asm_elements(a, P.any_hgo, st);
   HIPCHK(hipStreamWaitEvent(st, p->ev_fjoin, 0));
@@ -912,6 +914,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   g.loc_pos = p->d_loc_pos;
   g.subs = p->d_sub;
   g.Ke = p->d_Ke;
+  g.npe = P.npe;
   g.ell_val = p->d_ell_val;
   g.NF = P.NF;
   if (P.mixed) asm_gather<float>(g, (float*)p->d_arena, st);
@@ -928,6 +931,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.ell_col = p->d_ell_col;
   m.ell_val = p->d_ell_val;
   m.NF = P.NF;
+  m.ellw = P.ellw;
   m.dmask = p->d_dmask;
   m.test_rotations = (P.any_hgo && U_dev && !(p->opt.flags & FETI_KERNEL6)) ? 1 : 0;
   m.kernel_tol = p->opt.kernel_tol;
@@ -1391,7 +1395,7 @@ void apply_assembled(feti_problem* p, const double* x, const double* f0, double*
   const HostPlan& P = p->P;
   hipStream_t st = p->stream;
   local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
-                 p->d_ell_val, p->d_dmask, x, p->d_ul, f0, p->d_t, st);
+                 p->d_ell_val, P.ellw, p->d_dmask, x, p->d_ul, f0, p->d_t, st);
   vec_global(P.n_dof, p->d_uc_ptr, p->d_uc_idx, p->d_t, p->d_dmask, p->d_zero, y, 1, st);
   if (!f0) vec_axpby(P.n_dof, -1.0, y, 0.0, y, st);   // -(0 - K x)
   if (p->ls_on) {
@@ -1400,6 +1404,7 @@ void apply_assembled(feti_problem* p, const double* x, const double* f0, double*
     pa.xyz = p->d_xyz;
     pa.U = p->ls_U;
     pa.pface = p->d_pface;
+    pa.nfn = P.nfn;
     pa.pf_ptr = p->d_pf_ptr;
     pa.pf_ent = p->d_pf_ent;
     pa.pressure = P.pressure;
@@ -1441,7 +1446,7 @@ feti_status solve_refined(feti_problem* p, feti_stats* stats) {
       double fnorm = 0.0, rnorm = 0.0;
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_u, p->d_dmask, p->d_dvals, p->d_uglob, 0, st);
       local_residual(P.NF, p->d_fpos_lnode, p->d_fpos_comp, p->d_loc_node, p->di.f_sub, p->d_sub, p->d_ell_col,
-                     p->d_ell_val, p->d_dmask, p->d_uglob, p->d_ul, p->d_f, p->d_f0, st);
+                     p->d_ell_val, P.ellw, p->d_dmask, p->d_uglob, p->d_ul, p->d_f, p->d_f0, st);
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f0, p->d_dmask, p->d_zero, p->d_out, 1, st);
       TRY(dev_norm(p, p->d_out, nd, &rnorm));
       vec_global(nd, p->d_uc_ptr, p->d_uc_idx, p->d_f, p->d_dmask, p->d_zero, p->d_out, 1, st);
@@ -1761,6 +1766,7 @@ feti_status solve_linear_call(feti_problem* p, double load_factor, double* u, fe
     pa.xyz = p->d_xyz;
     pa.U = nullptr;
     pa.pface = p->d_pface;
+    pa.nfn = P.nfn;
     pa.pf_ptr = p->d_pf_ptr;
     pa.pf_ent = p->d_pf_ent;
     pa.pressure = P.pressure;
@@ -1787,6 +1793,8 @@ feti_status solve_linear_call(feti_problem* p, double load_factor, double* u, fe
   r.ell_col = p->d_ell_col;
   r.ell_val = p->d_ell_val;
   r.NF = P.NF;
+  r.ellw = P.ellw;
+  r.npe = P.npe;
   r.dvals = p->d_dvals;
   r.body_scale = load_factor;
   r.int_scale = 0.0;
@@ -1836,6 +1844,7 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
     pa.xyz = p->d_xyz;
     pa.U = Ud;
     pa.pface = p->d_pface;
+    pa.nfn = P.nfn;
     pa.pf_ptr = p->d_pf_ptr;
     pa.pf_ent = p->d_pf_ent;
     pa.pressure = P.pressure;
@@ -1861,6 +1870,8 @@ feti_status feti_newton_step(feti_problem* p, const double* U_k, double tau, dou
   r.ell_col = p->d_ell_col;
   r.ell_val = p->d_ell_val;
   r.NF = P.NF;
+  r.ellw = P.ellw;
+  r.npe = P.npe;
   r.body_scale = tau;
   r.int_scale = 1.0;
   r.nodal_scale = tau;

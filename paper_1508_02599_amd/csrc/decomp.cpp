@@ -210,6 +210,10 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   if (m->n_dir < 0 || (m->n_dir > 0 && (!m->dir_dof || !m->dir_val))) return "bad Dirichlet arrays";
   if (m->n_pfaces < 0 || (m->n_pfaces > 0 && !m->pface)) return "bad pressure faces";
   if (m->n_nodes > (int64_t)1 << 30 || m->n_elems > (int64_t)1 << 30) return "mesh too large";
+  if (m->order != 0 && m->order != 1 && m->order != 2) return "element order must be 1 (Q1) or 2 (Q2)";
+  P.npe = m->order == 2 ? 27 : 8;
+  P.nfn = m->order == 2 ? 9 : 4;
+  P.ellw = m->order == 2 ? ELLW_Q2 : ELLW_Q1;
   P.af = !o || o->variant == FETI_ALL_FLOATING;
   P.precond = o ? (int)o->precond : (int)FETI_PREC_LUMPED;
   P.mixed = o && o->precision == FETI_MIXED;
@@ -221,7 +225,8 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   P.xyz.assign(m->xyz, m->xyz + 3 * m->n_nodes);
   for (double v : P.xyz)
     if (!finite(v)) return "non-finite coordinate";
-  P.hex8.assign(m->hex8, m->hex8 + 8 * m->n_elems);
+  const int npe = P.npe;
+  P.hex8.assign(m->hex8, m->hex8 + (int64_t)npe * m->n_elems);
   for (int64_t v : P.hex8)
     if (v < 0 || v >= m->n_nodes) return "element node id out of range";
   P.elem_sub.assign(m->elem_sub, m->elem_sub + m->n_elems);
@@ -254,7 +259,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
       if (!finite(v)) return "non-finite body force";
   }
   if (m->n_pfaces > 0) {
-    P.pface.assign(m->pface, m->pface + 4 * m->n_pfaces);
+    P.pface.assign(m->pface, m->pface + (int64_t)P.nfn * m->n_pfaces);
     for (int64_t v : P.pface)
       if (v < 0 || v >= m->n_nodes) return "pressure face node out of range";
   }
@@ -289,11 +294,11 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   // ---- local nodes and connectivity check
   P.sub.assign(ns, SubInfo{});
   std::vector<int32_t> g2l(P.n_nodes, -1);
-  std::vector<std::vector<int32_t>> elem_ln(ns);   // per sub: 8 local node ids per element
+  std::vector<std::vector<int32_t>> elem_ln(ns);   // per sub: npe local node ids per element
   for (int s = 0; s < ns; ++s) {
     std::vector<int64_t> nodes;
     for (int64_t k = se_ptr[s]; k < se_ptr[s + 1]; ++k)
-      for (int c = 0; c < 8; ++c) nodes.push_back(P.hex8[se_list[k] * 8 + c]);
+      for (int c = 0; c < npe; ++c) nodes.push_back(P.hex8[se_list[k] * npe + c]);
     std::sort(nodes.begin(), nodes.end());
     nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
     SubInfo& si = P.sub[s];
@@ -305,9 +310,9 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     }
     auto& el = elem_ln[s];
     const int64_t ne = se_ptr[s + 1] - se_ptr[s];
-    el.resize(8 * ne);
+    el.resize(npe * ne);
     for (int64_t k = 0; k < ne; ++k)
-      for (int c = 0; c < 8; ++c) el[8 * k + c] = g2l[P.hex8[se_list[se_ptr[s] + k] * 8 + c]];
+      for (int c = 0; c < npe; ++c) el[npe * k + c] = g2l[P.hex8[se_list[se_ptr[s] + k] * npe + c]];
     // union-find over elements sharing a node
     std::vector<int32_t> parent(ne), owner(nodes.size(), -1);
     std::iota(parent.begin(), parent.end(), 0);
@@ -316,8 +321,8 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
       return x;
     };
     for (int64_t k = 0; k < ne; ++k)
-      for (int c = 0; c < 8; ++c) {
-        const int32_t ln = el[8 * k + c];
+      for (int c = 0; c < npe; ++c) {
+        const int32_t ln = el[npe * k + c];
         if (owner[ln] < 0) owner[ln] = (int32_t)k;
         else parent[findp((int32_t)k)] = findp(owner[ln]);
       }
@@ -551,26 +556,27 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   }
   // ---- node pairs and element contributions (per subdomain, fixed order)
   P.diag_slot.assign(P.n_loc_nodes, -1);
-  P.ell_col.assign(P.NF * ELLW, -1);
+  P.ell_col.assign(P.NF * P.ellw, -1);
+  const int max_nbr = P.ellw / 3;
   for (int s = 0; s < ns; ++s) {
     const SubInfo& si = P.sub[s];
     const auto& el = elem_ln[s];
     const int64_t ne = se_ptr[s + 1] - se_ptr[s];
-    std::vector<int32_t> inc_ptr(si.n_nodes + 1, 0), inc(8 * ne);
+    std::vector<int32_t> inc_ptr(si.n_nodes + 1, 0), inc(npe * ne);
     for (int64_t k = 0; k < ne; ++k)
-      for (int c = 0; c < 8; ++c) inc_ptr[el[8 * k + c] + 1]++;
+      for (int c = 0; c < npe; ++c) inc_ptr[el[npe * k + c] + 1]++;
     for (int q = 0; q < si.n_nodes; ++q) inc_ptr[q + 1] += inc_ptr[q];
     {
       std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
       for (int64_t k = 0; k < ne; ++k)
-        for (int c = 0; c < 8; ++c) inc[fill[el[8 * k + c]]++] = (int32_t)(8 * k + c);
+        for (int c = 0; c < npe; ++c) inc[fill[el[npe * k + c]]++] = (int32_t)(npe * k + c);
     }
     std::vector<std::array<int32_t, 4>> tup;   // (b, elem-local k, la, lb)
     for (int a = 0; a < si.n_nodes; ++a) {
       tup.clear();
       for (int t = inc_ptr[a]; t < inc_ptr[a + 1]; ++t) {
-        const int32_t k = inc[t] / 8, la = inc[t] % 8;
-        for (int lb = 0; lb < 8; ++lb) tup.push_back({el[8 * k + lb], k, la, lb});
+        const int32_t k = inc[t] / npe, la = inc[t] % npe;
+        for (int lb = 0; lb < npe; ++lb) tup.push_back({el[npe * k + lb], k, la, lb});
       }
       std::sort(tup.begin(), tup.end());
       int nbr = -1, prev_b = -1;
@@ -578,7 +584,8 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
         if (tup[t][0] != prev_b) {
           if (nbr >= 0) P.ps_c1.push_back((int32_t)P.pc_e.size());
           ++nbr;
-          if (nbr >= 27) return "node with more than 27 neighbours (not a hexahedral mesh)";
+          if (nbr >= max_nbr)
+            return "node with more than " + std::to_string(max_nbr) + " neighbours (not a hexahedral mesh)";
           prev_b = tup[t][0];
           P.ps_a.push_back(si.node_off + a);
           P.ps_b.push_back(si.node_off + tup[t][0]);
@@ -613,7 +620,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
       for (int pb = 0; pb < si.n_if; ++pb) {
         const int64_t row = si.full_off + bstart + pb;
         auto& L = rows[si.b_off + pb];
-        for (int k = 0; k < ELLW; ++k) {
+        for (int k = 0; k < P.ellw; ++k) {
           const int c = P.ell_col[(int64_t)k * P.NF + row];
           if (c >= bstart && c < bstart + si.n_if) L.push_back({k, (int32_t)(si.b_off + c - bstart)});
         }
@@ -650,15 +657,16 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
   }
   // ---- pressure faces per node
   P.pf_ptr.assign(P.n_nodes + 1, 0);
-  const int64_t nf = (int64_t)P.pface.size() / 4;
+  const int nfn = P.nfn;
+  const int64_t nf = (int64_t)P.pface.size() / nfn;
   for (int64_t f = 0; f < nf; ++f)
-    for (int c = 0; c < 4; ++c) P.pf_ptr[P.pface[4 * f + c] + 1]++;
+    for (int c = 0; c < nfn; ++c) P.pf_ptr[P.pface[nfn * f + c] + 1]++;
   for (int64_t n = 0; n < P.n_nodes; ++n) P.pf_ptr[n + 1] += P.pf_ptr[n];
   P.pf_ent.resize(P.pf_ptr[P.n_nodes]);
   {
     std::vector<int32_t> fill(P.pf_ptr.begin(), P.pf_ptr.end() - 1);
     for (int64_t f = 0; f < nf; ++f)
-      for (int c = 0; c < 4; ++c) P.pf_ent[fill[P.pface[4 * f + c]]++] = (int32_t)(4 * f + c);
+      for (int c = 0; c < nfn; ++c) P.pf_ent[fill[P.pface[nfn * f + c]]++] = (int32_t)(nfn * f + c);
   }
   // ---- coarse pairs: (s >= t) with the rows they share; diagonal pairs use every entry
   {
@@ -704,7 +712,7 @@ std::string build_plan(const feti_mesh* m, const feti_options* o, HostPlan& P) {
     env[s].resize(si.nt);
     for (int I = 0; I < si.nt; ++I) env[s][I] = I;
     for (int r = 0; r < si.nt * TS; ++r)
-      for (int k = 0; k < ELLW; ++k) {
+      for (int k = 0; k < P.ellw; ++k) {
         const int c = P.ell_col[(int64_t)k * P.NF + si.full_off + r];
         if (c >= 0) env[s][r / TS] = std::min(env[s][r / TS], c / TS);
       }

@@ -15,8 +15,11 @@ namespace feti {
 // Edge of the square tiles that every dense local matrix is stored in.
 constexpr int TS = 64;
 constexpr int TS2 = TS * TS;
-// Maximum number of nonzeros in one row of a Q1 stiffness (27 nodes x 3 dofs).
-constexpr int ELLW = 81;
+// Width of the ELL rows of the sparse local stiffnesses: at most 27 neighbour
+// nodes of a Q1 node, 125 of a Q2 node (a Q2 corner node), x 3 DOFs; the Q2
+// width is rounded up to a multiple of 9 slots (whole slot groups).
+constexpr int ELLW_Q1 = 81;
+constexpr int ELLW_Q2 = 378;
 // Maximum number of subdomains: the coarse vector (6 entries per subdomain)
 // of one projection fits in 64 KiB of LDS.
 constexpr int kMaxSub = 1365;
@@ -62,11 +65,14 @@ struct HostPlan {
   bool mixed = false;
   bool any_hgo = false;
   std::vector<double> xyz;
-  std::vector<int64_t> hex8;
+  int npe = 8;                          // nodes per element: 8 (Q1) or 27 (Q2)
+  int nfn = 4;                          // nodes per pressure face: 4 (Q1) or 9 (Q2)
+  int ellw = ELLW_Q1;                   // ELL row width (ELLW_Q1 or ELLW_Q2)
+  std::vector<int64_t> hex8;            // [n_elems][npe] element nodes
   std::vector<int32_t> elem_sub, elem_mat;
   std::vector<feti_material> mat;
   std::vector<double> fibers, body_force;
-  std::vector<int64_t> pface;
+  std::vector<int64_t> pface;           // [n_pfaces][nfn]
   double pressure = 0.0;
   std::vector<uint8_t> dir_mask;        // [n_dof]
   std::vector<double> dir_val;          // [n_dof]
@@ -113,7 +119,7 @@ struct HostPlan {
   std::vector<int32_t> uc_ptr;          // [n_dof+1]
   std::vector<int64_t> uc_idx;          // full-space index of each copy
 
-  // ---- pressure faces: per global node, (face*4+corner) list
+  // ---- pressure faces: per global node, (face*nfn + face node) list
   std::vector<int32_t> pf_ptr, pf_ent;
 
   // ---- coarse problem: neighbour pairs (s >= t) and their shared rows

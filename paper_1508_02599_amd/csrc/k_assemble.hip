@@ -2,7 +2,8 @@
 // the coarse matrix G^T G.
 //
 // Element tangents: one wavefront per Q1 element, lane (a, b) computes the
-// 3x3 block K_ab over the 2x2x2 Gauss points.
+// 3x3 block K_ab over the 2x2x2 Gauss points; one workgroup per Q2 element
+// (3x3x3 Gauss points, below).
 //   * isotropic linear elasticity (section 5.1);
 //   * Holzapfel-Gasser-Ogden (section 2: eqs. (isoaniso), (iso), (aniso_1),
 //     (aniso_2), stress split of eq. (additiveStress)) with the tangent of
@@ -38,6 +39,16 @@ __device__ __forceinline__ double shape(int a, int gp) {
   for (int d = 0; d < 3; ++d) v *= 1.0 + corner(a, d) * corner(gp, d) * g;
   return v;
 }
+
+// 1D quadratic Lagrange polynomial of node i (at -1, 0, 1) and its derivative.
+__device__ __forceinline__ double lag3(int i, double x) {
+  return i == 0 ? 0.5 * x * (x - 1.0) : (i == 1 ? 1.0 - x * x : 0.5 * x * (x + 1.0));
+}
+__device__ __forceinline__ double dlag3(int i, double x) { return i == 0 ? x - 0.5 : (i == 1 ? -2.0 * x : x + 0.5); }
+// 3-point Gauss-Legendre rule on [-1, 1]: points 0, +-sqrt(3/5), weights 8/9, 5/9
+constexpr double kG3 = 0.77459666924148337704;
+__device__ __forceinline__ double gp3(int g) { return g == 0 ? -kG3 : (g == 1 ? 0.0 : kG3); }
+__device__ __forceinline__ double gw3(int g) { return g == 1 ? 8.0 / 9.0 : 5.0 / 9.0; }
 
 __device__ void inv3(const double* A, double* inv, double* det) {
   const double c00 = A[4] * A[8] - A[5] * A[7];
@@ -310,9 +321,232 @@ __global__ __launch_bounds__(256) void k_elements(AsmArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Q2 elements (27-node triquadratic hexahedra, node a = i + 3j + 9k at
+// reference point (i-1, j-1, k-1)), with the same materials as above and, for
+// HGO, the same P0 condensation (the Q2-P0 pair of section 3.2): Jbar is the
+// element's mean dilatation over its 3x3x3 Gauss points.  One 256-thread
+// workgroup per element: threads share the Gauss-point data in LDS, and the
+// 378 node-pair blocks a <= b are spread over the threads (the tangent is
+// symmetric: the bilinear form of linear elasticity, and the second
+// derivative of the HGO energy), each block stored with its transpose.
+
+// N_a and dN_a/dxi at Gauss point q = gi + 3 gj + 9 gk.
+__device__ __forceinline__ void shape27(int a, int q, double* N, double dN[3]) {
+  double L[3], dL[3];
+  const int ia[3] = {a % 3, (a / 3) % 3, a / 9}, iq[3] = {q % 3, (q / 3) % 3, q / 9};
+  for (int d = 0; d < 3; ++d) {
+    const double x = gp3(iq[d]);
+    L[d] = lag3(ia[d], x);
+    dL[d] = dlag3(ia[d], x);
+  }
+  *N = L[0] * L[1] * L[2];
+  dN[0] = dL[0] * L[1] * L[2];
+  dN[1] = L[0] * dL[1] * L[2];
+  dN[2] = L[0] * L[1] * dL[2];
+}
+
+__global__ __launch_bounds__(256) void k_elements27(AsmArgs A) {
+  __shared__ double sX[81], sU[81], sInv[27][9], sW[27], sdN[27][27][3];
+  __shared__ double sJ[27], sFp[27][9], sFi[27][9], sG[81], sSig[27][9];
+  __shared__ HgoPoint sP[27];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const double* m = A.mat + 7 * A.elem_mat[e];
+  const int kind = (int)m[0];
+  const bool hgo = kind == 1, lin = kind == 0;
+  if (t < 81) {
+    const int64_t nd = A.hex8[e * 27 + t / 3];
+    sX[t] = A.xyz[nd * 3 + t % 3];
+    sU[t] = A.U ? A.U[nd * 3 + t % 3] : 0.0;
+  }
+  __syncthreads();
+  // Jacobian dX/dxi, its inverse, and the quadrature weight w_q det J at each point
+  if (t < 27) {
+    double Jm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 27; ++a) {
+      double N, dxi[3];
+      shape27(a, t, &N, dxi);
+      for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < 3; ++k) Jm[3 * d + k] += sX[3 * a + d] * dxi[k];
+    }
+    double det;
+    inv3(Jm, sInv[t], &det);
+    sW[t] = gw3(t % 3) * gw3((t / 3) % 3) * gw3(t / 9) * det;
+  }
+  __syncthreads();
+  for (int pr = t; pr < 729; pr += 256) {   // dN_a/dX at point q
+    const int q = pr / 27, a = pr % 27;
+    double N, dxi[3];
+    shape27(a, q, &N, dxi);
+    for (int d = 0; d < 3; ++d) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += dxi[k] * sInv[q][3 * k + d];
+      sdN[q][a][d] = s;
+    }
+  }
+  __syncthreads();
+  if (t < 27) {
+    double G[9];   // Grad U
+    for (int i = 0; i < 3; ++i)
+      for (int J = 0; J < 3; ++J) {
+        double s = 0.0;
+        for (int a = 0; a < 27; ++a) s += sU[3 * a + i] * sdN[t][a][J];
+        G[3 * i + J] = s;
+      }
+    if (hgo) {
+      double F[9], Fi[9], detF;
+      for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? 1.0 : 0.0);
+      inv3(F, Fi, &detF);
+      // an element inverted by U (det F <= 0) has no strain energy: record it
+      // (the host rejects the state) and keep the arithmetic finite
+      if (!(detF > 0.0)) {
+        if (A.inverted) atomicMin(A.inverted, (int)e);
+        detF = 1.0;
+        for (int k = 0; k < 9; ++k) F[k] = Fi[k] = (k % 4 == 0) ? 1.0 : 0.0;
+      }
+      sJ[t] = detF;
+      for (int k = 0; k < 9; ++k) {
+        sFp[t][k] = F[k];
+        sFi[t][k] = Fi[k];
+      }
+    } else if (lin) {   // Cauchy stress lam tr(eps) I + 2 mu eps of the displacement
+      const double E = m[1], nu = m[2];
+      const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+      const double tr = G[0] + G[4] + G[8];
+      for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J) sSig[t][3 * i + J] = mu * (G[3 * i + J] + G[3 * J + i]) + (i == J ? lam * tr : 0.0);
+    }
+  }
+  __syncthreads();
+  // element pressure, point stresses and tangents, and g_a = int J F^{-T} grad N_a
+  double V = 0.0, p = 0.0;
+  if (hgo) {
+    double v = 0.0;
+    for (int q = 0; q < 27; ++q) {
+      V += sW[q];
+      v += sW[q] * sJ[q];
+    }
+    p = m[6] * (v / V - 1.0);
+    if (t < 27) {
+      const double* a1 = A.fibers + e * 6;
+      hgo_point(sFp[t], sJ[t], p, a1, a1 + 3, m[3], m[4], m[5], sP[t]);
+    }
+    if (t < 81) {
+      const int a = t / 3, i = t % 3;
+      double s = 0.0;
+      for (int q = 0; q < 27; ++q) {
+        double tq = 0.0;
+        for (int I = 0; I < 3; ++I) tq += sFi[q][3 * I + i] * sdN[q][a][I];
+        s += sW[q] * sJ[q] * tq;
+      }
+      sG[t] = s;
+    }
+  }
+  __syncthreads();
+  double* Ke = A.Ke + e * 6561;
+  for (int pr = t; pr < 378; pr += 256) {
+    int a = 0, r = pr;
+    while (r >= 27 - a) {
+      r -= 27 - a;
+      ++a;
+    }
+    const int b = a + r;
+    double K[9];
+    for (int k = 0; k < 9; ++k) K[k] = 0.0;
+    if (lin) {
+      const double E = m[1], nu = m[2];
+      const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+      for (int q = 0; q < 27; ++q) {
+        const double* na = sdN[q][a];
+        const double* nb = sdN[q][b];
+        const double wt = sW[q];
+        const double dot = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            K[3 * i + j] += wt * (lam * na[i] * nb[j] + mu * (na[j] * nb[i] + (i == j ? dot : 0.0)));
+      }
+    } else if (hgo) {
+      for (int q = 0; q < 27; ++q) {
+        const HgoPoint& P = sP[q];
+        const double* na = sdN[q][a];
+        const double* nb = sdN[q][b];
+        const double wt = sW[q];
+        double geo = 0.0;
+        for (int I = 0; I < 3; ++I)
+          for (int J = 0; J < 3; ++J) geo += na[I] * P.S[3 * I + J] * nb[J];
+        double Ba[6][3], Bb[6][3];
+        for (int al = 0; al < 6; ++al) {
+          const int I = VA[al], J = VB[al];
+          for (int i = 0; i < 3; ++i) {
+            if (I == J) {
+              Ba[al][i] = P.F[3 * i + I] * na[I];
+              Bb[al][i] = P.F[3 * i + I] * nb[I];
+            } else {
+              Ba[al][i] = P.F[3 * i + I] * na[J] + P.F[3 * i + J] * na[I];
+              Bb[al][i] = P.F[3 * i + I] * nb[J] + P.F[3 * i + J] * nb[I];
+            }
+          }
+        }
+        for (int j = 0; j < 3; ++j) {
+          double cb[6];
+          for (int al = 0; al < 6; ++al) {
+            double s = 0.0;
+            for (int be = 0; be < 6; ++be) s += P.CV[6 * al + be] * Bb[be][j];
+            cb[al] = s;
+          }
+          for (int i = 0; i < 3; ++i) {
+            double s = 0.0;
+            for (int al = 0; al < 6; ++al) s += Ba[al][i] * cb[al];
+            K[3 * i + j] += wt * (s + (i == j ? geo : 0.0));
+          }
+        }
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K[3 * i + j] += m[6] / V * sG[3 * a + i] * sG[3 * b + j];
+    }
+    double* out = Ke + (a * 27 + b) * 9;
+    for (int k = 0; k < 9; ++k) out[k] = K[k];
+    if (a != b) {
+      double* tr = Ke + (b * 27 + a) * 9;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) tr[3 * j + i] = K[3 * i + j];
+    }
+  }
+  // internal force int P grad N_a (P = F S for HGO, the Cauchy stress for
+  // linear elasticity) and body force int N_a b
+  if (t < 81) {
+    const int a = t / 3, i = t % 3;
+    double fb = 0.0, fi = 0.0;
+    for (int q = 0; q < 27; ++q) {
+      if (A.body) {
+        double N, dxi[3];
+        shape27(a, q, &N, dxi);
+        fb += sW[q] * N * A.body[e * 3 + i];
+      }
+      double tq = 0.0;
+      if (hgo) {
+        const HgoPoint& P = sP[q];
+        for (int J = 0; J < 3; ++J) {
+          double FS = 0.0;
+          for (int I = 0; I < 3; ++I) FS += P.F[3 * i + I] * P.S[3 * I + J];
+          tq += FS * sdN[q][a][J];
+        }
+      } else if (lin) {
+        for (int J = 0; J < 3; ++J) tq += sSig[q][3 * i + J] * sdN[q][a][J];
+      }
+      fi += sW[q] * tq;
+    }
+    A.fbody[e * 81 + t] = fb;
+    A.fint[e * 81 + t] = fi;
+  }
+}
+
 void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s) {
   (void)any_hgo;
-  if (a.n_elems) hipLaunchKernelGGL(k_elements, dim3((unsigned)((a.n_elems + 3) / 4)), dim3(256), 0, s, a);
+  if (!a.n_elems) return;
+  if (a.npe == 27) hipLaunchKernelGGL(k_elements27, dim3((unsigned)a.n_elems), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_elements, dim3((unsigned)((a.n_elems + 3) / 4)), dim3(256), 0, s, a);
 }
 
 // Node-pair gather: K_i[(a,i),(b,j)] = sum over shared elements (fixed order).
@@ -324,7 +558,7 @@ __global__ void k_gather_local(GatherArgs G, T* arena) {
   double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int c = G.ps_c0[sl]; c < G.ps_c1[sl]; ++c) {
     const int e = G.pc_e[c], ab = G.pc_ab[c];
-    const double* src = G.Ke + (int64_t)e * 576 + ((ab & 255) * 8 + (ab >> 8)) * 9;
+    const double* src = G.Ke + (int64_t)e * (9 * G.npe * G.npe) + ((ab & 255) * G.npe + (ab >> 8)) * 9;
     for (int k = 0; k < 9; ++k) K[k] += src[k];
   }
   const SubInfo s = G.subs[G.loc_sub[la]];
@@ -364,14 +598,14 @@ __global__ void k_rhs(RhsArgs R) {
   double fb = 0.0, fi = 0.0;
   for (int c = R.ps_c0[sl]; c < R.ps_c1[sl]; ++c) {
     const int e = R.pc_e[c], lq = R.pc_ab[c] & 255;
-    fb += R.fbody[(int64_t)e * 24 + 3 * lq + i];
-    if (R.int_scale != 0.0) fi += R.fint[(int64_t)e * 24 + 3 * lq + i];
+    fb += R.fbody[(int64_t)e * (3 * R.npe) + 3 * lq + i];
+    if (R.int_scale != 0.0) fi += R.fint[(int64_t)e * (3 * R.npe) + 3 * lq + i];
   }
   double f = R.body_scale * fb - R.int_scale * fi;
   const int64_t g = R.loc_node[la];
   if (R.fnodal) f += R.nodal_scale * R.fnodal[3 * g + i] / R.loc_ncopy[la];
   const int64_t row = s.full_off + pos;
-  for (int k = 0; k < ELLW; ++k) {
+  for (int k = 0; k < R.ellw; ++k) {
     const int cc = R.ell_col[k * R.NF + row];
     if (cc <= -2) f -= R.ell_val[k * R.NF + row] * R.dvals[-(cc + 2)];
   }
@@ -382,28 +616,59 @@ void asm_rhs(const RhsArgs& r, hipStream_t s) {
   if (r.n_loc_nodes) hipLaunchKernelGGL(k_rhs, dim3((unsigned)((3 * r.n_loc_nodes + 255) / 256)), dim3(256), 0, s, r);
 }
 
-// Follower pressure on the current surface: f_a = -p int N_a (x,1 x x,2) deta.
+// Quadrilateral pressure faces.  NFN = 4: bilinear, corners (-1,-1), (1,-1),
+// (1,1), (-1,1), 2x2 Gauss points of weight 1.  NFN = 9: biquadratic, node
+// c = i + 3j at (i-1, j-1), 3x3 Gauss points.
+template <int NFN>
+struct FaceRule;
+template <>
+struct FaceRule<4> {
+  static constexpr int NG = 2;
+  __device__ static double pt(int g) { return g ? 0.57735026918962576451 : -0.57735026918962576451; }
+  __device__ static double wt(int) { return 1.0; }
+  __device__ static void shape(int c, double s, double t, double& N, double& ds, double& dt) {
+    const double e1 = (c == 1 || c == 2) ? 1.0 : -1.0, e2 = c >= 2 ? 1.0 : -1.0;
+    N = 0.25 * (1 + e1 * s) * (1 + e2 * t);
+    ds = 0.25 * e1 * (1 + e2 * t);
+    dt = 0.25 * e2 * (1 + e1 * s);
+  }
+};
+template <>
+struct FaceRule<9> {
+  static constexpr int NG = 3;
+  __device__ static double pt(int g) { return gp3(g); }
+  __device__ static double wt(int g) { return gw3(g); }
+  __device__ static void shape(int c, double s, double t, double& N, double& ds, double& dt) {
+    const int i = c % 3, j = c / 3;
+    N = lag3(i, s) * lag3(j, t);
+    ds = dlag3(i, s) * lag3(j, t);
+    dt = lag3(i, s) * dlag3(j, t);
+  }
+};
+
+// Follower pressure on the current surface: f_a = -p int N_a (x,s x x,t) ds dt.
+// One thread per node sums over its faces in a fixed order (no atomics).
+template <int NFN>
 __global__ void k_pressure(PressureArgs P) {
+  using R = FaceRule<NFN>;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= P.n_nodes) return;
   double f[3] = {0, 0, 0};
-  const double g = 0.57735026918962576451;
-  const double e1[4] = {-1, 1, 1, -1}, e2[4] = {-1, -1, 1, 1};
   for (int k = P.pf_ptr[n]; k < P.pf_ptr[n + 1]; ++k) {
     const int64_t fc = P.pf_ent[k];
-    const int64_t face = fc / 4;
-    const int cn = (int)(fc % 4);
-    double x[4][3];
-    for (int q = 0; q < 4; ++q) {
-      const int64_t nd = P.pface[face * 4 + q];
+    const int64_t face = fc / NFN;
+    const int cn = (int)(fc % NFN);
+    double x[NFN][3];
+    for (int q = 0; q < NFN; ++q) {
+      const int64_t nd = P.pface[face * NFN + q];
       for (int d = 0; d < 3; ++d) x[q][d] = P.xyz[nd * 3 + d] + (P.U ? P.U[nd * 3 + d] : 0.0);
     }
-    for (int g1 = 0; g1 < 2; ++g1)
-      for (int g2 = 0; g2 < 2; ++g2) {
-        const double h1 = g1 ? g : -g, h2 = g2 ? g : -g;
-        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0};
-        for (int q = 0; q < 4; ++q) {
-          const double d1 = 0.25 * e1[q] * (1 + e2[q] * h2), d2 = 0.25 * e2[q] * (1 + e1[q] * h1);
+    for (int g1 = 0; g1 < R::NG; ++g1)
+      for (int g2 = 0; g2 < R::NG; ++g2) {
+        const double h1 = R::pt(g1), h2 = R::pt(g2);
+        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, N, d1, d2;
+        for (int q = 0; q < NFN; ++q) {
+          R::shape(q, h1, h2, N, d1, d2);
           for (int d = 0; d < 3; ++d) {
             t1[d] += x[q][d] * d1;
             t2[d] += x[q][d] * d2;
@@ -411,48 +676,52 @@ __global__ void k_pressure(PressureArgs P) {
         }
         const double nv[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],
                               t1[0] * t2[1] - t1[1] * t2[0]};
-        const double N = 0.25 * (1 + e1[cn] * h1) * (1 + e2[cn] * h2);
-        for (int d = 0; d < 3; ++d) f[d] += -P.pressure * N * nv[d];
+        R::shape(cn, h1, h2, N, d1, d2);
+        const double pw = -P.pressure * (R::wt(g1) * R::wt(g2));
+        for (int d = 0; d < 3; ++d) f[d] += pw * N * nv[d];
       }
   }
   for (int d = 0; d < 3; ++d) P.fnodal[3 * n + d] = f[d];
 }
 
 void asm_pressure(const PressureArgs& p, hipStream_t s) {
-  if (p.n_nodes) hipLaunchKernelGGL(k_pressure, dim3((unsigned)((p.n_nodes + 255) / 256)), dim3(256), 0, s, p);
+  if (!p.n_nodes) return;
+  const dim3 grid((unsigned)((p.n_nodes + 255) / 256));
+  if (p.nfn == 9) hipLaunchKernelGGL(k_pressure<9>, grid, dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_pressure<4>, grid, dim3(256), 0, s, p);
 }
 
 // Load stiffness of the follower pressure applied to a direction z: the
-// derivative of f_a = -p int N_a (x,1 x x,2) deta along x -> x + z is
-//   out_a = -p int N_a (z,1 x x,2 + x,1 x z,2) deta,
-// with z,k the same bilinear interpolation of the corner values z_c as x,k.
+// derivative of f_a = -p int N_a (x,s x x,t) ds dt along x -> x + z is
+//   out_a = -p int N_a (z,s x x,t + x,s x z,t) ds dt,
+// with z,s and z,t interpolated from the nodal values of z like x,s and x,t.
 // One thread per node sums over its faces in a fixed order (no atomics);
 // Dirichlet DOFs (dmask) get 0.
+template <int NFN>
 __global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, const uint8_t* __restrict__ dmask,
                                double* __restrict__ out) {
+  using R = FaceRule<NFN>;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= P.n_nodes) return;
   double f[3] = {0, 0, 0};
-  const double g = 0.57735026918962576451;
-  const double e1[4] = {-1, 1, 1, -1}, e2[4] = {-1, -1, 1, 1};
   for (int k = P.pf_ptr[n]; k < P.pf_ptr[n + 1]; ++k) {
     const int64_t fc = P.pf_ent[k];
-    const int64_t face = fc / 4;
-    const int cn = (int)(fc % 4);
-    double x[4][3], dz[4][3];
-    for (int q = 0; q < 4; ++q) {
-      const int64_t nd = P.pface[face * 4 + q];
+    const int64_t face = fc / NFN;
+    const int cn = (int)(fc % NFN);
+    double x[NFN][3], dz[NFN][3];
+    for (int q = 0; q < NFN; ++q) {
+      const int64_t nd = P.pface[face * NFN + q];
       for (int d = 0; d < 3; ++d) {
         x[q][d] = P.xyz[nd * 3 + d] + (P.U ? P.U[nd * 3 + d] : 0.0);
         dz[q][d] = z[nd * 3 + d];
       }
     }
-    for (int g1 = 0; g1 < 2; ++g1)
-      for (int g2 = 0; g2 < 2; ++g2) {
-        const double h1 = g1 ? g : -g, h2 = g2 ? g : -g;
-        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0};
-        for (int q = 0; q < 4; ++q) {
-          const double d1 = 0.25 * e1[q] * (1 + e2[q] * h2), d2 = 0.25 * e2[q] * (1 + e1[q] * h1);
+    for (int g1 = 0; g1 < R::NG; ++g1)
+      for (int g2 = 0; g2 < R::NG; ++g2) {
+        const double h1 = R::pt(g1), h2 = R::pt(g2);
+        double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0}, N, d1, d2;
+        for (int q = 0; q < NFN; ++q) {
+          R::shape(q, h1, h2, N, d1, d2);
           for (int d = 0; d < 3; ++d) {
             t1[d] += x[q][d] * d1;
             t2[d] += x[q][d] * d2;
@@ -464,16 +733,19 @@ __global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, con
         const double nv[3] = {s1[1] * t2[2] - s1[2] * t2[1] + t1[1] * s2[2] - t1[2] * s2[1],
                               s1[2] * t2[0] - s1[0] * t2[2] + t1[2] * s2[0] - t1[0] * s2[2],
                               s1[0] * t2[1] - s1[1] * t2[0] + t1[0] * s2[1] - t1[1] * s2[0]};
-        const double N = 0.25 * (1 + e1[cn] * h1) * (1 + e2[cn] * h2);
-        for (int d = 0; d < 3; ++d) f[d] += -P.pressure * N * nv[d];
+        R::shape(cn, h1, h2, N, d1, d2);
+        const double pw = -P.pressure * (R::wt(g1) * R::wt(g2));
+        for (int d = 0; d < 3; ++d) f[d] += pw * N * nv[d];
       }
   }
   for (int d = 0; d < 3; ++d) out[3 * n + d] = dmask[3 * n + d] ? 0.0 : f[d];
 }
 
 void asm_pressure_dir(const PressureArgs& p, const double* z, const uint8_t* dmask, double* out, hipStream_t s) {
-  if (p.n_nodes)
-    hipLaunchKernelGGL(k_pressure_dir, dim3((unsigned)((p.n_nodes + 255) / 256)), dim3(256), 0, s, p, z, dmask, out);
+  if (!p.n_nodes) return;
+  const dim3 grid((unsigned)((p.n_nodes + 255) / 256));
+  if (p.nfn == 9) hipLaunchKernelGGL(k_pressure_dir<9>, grid, dim3(256), 0, s, p, z, dmask, out);
+  else hipLaunchKernelGGL(k_pressure_dir<4>, grid, dim3(256), 0, s, p, z, dmask, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,7 +927,7 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
   if (M.test_rotations) {
     double kf = 0.0;
     for (int64_t p = tid; p < n; p += 256)
-      for (int q = 0; q < ELLW; ++q) {
+      for (int q = 0; q < M.ellw; ++q) {
         const double v = M.ell_val[q * M.NF + s.full_off + p];
         if (M.ell_col[q * M.NF + s.full_off + p] >= 0) kf += v * v;
       }
@@ -664,7 +936,7 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
       double kr = 0.0, rr = 0.0;
       for (int64_t p = tid; p < n; p += 256) {
         double y = 0.0;
-        for (int q = 0; q < ELLW; ++q) {
+        for (int q = 0; q < M.ellw; ++q) {
           const int c = M.ell_col[q * M.NF + s.full_off + p];
           if (c >= 0) y += M.ell_val[q * M.NF + s.full_off + p] * W[(int64_t)c * 6 + k];
         }

@@ -149,7 +149,7 @@ void fill_bco(const DevIdx& d, const SubInfo* subs, int32_t* bco, int2* rco, hip
 void coarse_to_dense(int nc, int ld, const double* tiles, double* D, hipStream_t s);
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                    const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
+                    int ellw, const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
                     hipStream_t s);
 void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s);
@@ -158,15 +158,16 @@ void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_co
 struct AsmArgs {
   int64_t n_elems = 0;
   const double* xyz = nullptr;        // [n_nodes*3]
-  const int64_t* hex8 = nullptr;      // [n_elems*8]
+  int npe = 8;                        // nodes per element: 8 (Q1) or 27 (Q2)
+  const int64_t* hex8 = nullptr;      // [n_elems*npe]
   const int32_t* elem_mat = nullptr;
   const double* mat = nullptr;        // [n_mat*7] kind,E,nu,c,k1,k2,kappa
   const double* fibers = nullptr;     // [n_elems*6] or null
   const double* body = nullptr;       // [n_elems*3] or null
   const double* U = nullptr;          // [n_nodes*3] or null
-  double* Ke = nullptr;               // [n_elems*576]  layout [a][b][i][j]
-  double* fint = nullptr;             // [n_elems*24]
-  double* fbody = nullptr;            // [n_elems*24]
+  double* Ke = nullptr;               // [n_elems*(3 npe)^2]  layout [a][b][i][j]
+  double* fint = nullptr;             // [n_elems*3 npe]
+  double* fbody = nullptr;            // [n_elems*3 npe]
   int* inverted = nullptr;            // smallest element with det F <= 0 at U (atomicMin), or NULL
 };
 void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s);
@@ -179,7 +180,8 @@ struct GatherArgs {
   const int32_t* loc_pos = nullptr;   // [3*n_loc_nodes]
   const SubInfo* subs = nullptr;
   const double* Ke = nullptr;
-  double* ell_val = nullptr;          // [ELLW][NF] slot-major
+  int npe = 8;                        // nodes per element of Ke
+  double* ell_val = nullptr;          // [ellw][NF] slot-major
   int64_t NF = 0;
 };
 template <typename T>
@@ -192,9 +194,11 @@ struct RhsArgs {
   const int64_t* loc_node = nullptr;
   const SubInfo* subs = nullptr;
   const double *fbody = nullptr, *fint = nullptr, *fnodal = nullptr;   // fnodal [n_dof] or null
-  const int32_t* ell_col = nullptr;   // [ELLW][NF] slot-major
+  const int32_t* ell_col = nullptr;   // [ellw][NF] slot-major
   const double* ell_val = nullptr;
   int64_t NF = 0;
+  int ellw = ELLW_Q1;
+  int npe = 8;                        // nodes per element of fbody / fint
   const double* dvals = nullptr;      // [n_dof] prescribed values / increments
   double body_scale = 1.0, int_scale = 0.0, nodal_scale = 0.0;
   double* f = nullptr;                // [NF]
@@ -206,6 +210,7 @@ struct PressureArgs {
   const double *xyz = nullptr, *U = nullptr;
   const int64_t* pface = nullptr;
   const int32_t *pf_ptr = nullptr, *pf_ent = nullptr;
+  int nfn = 4;                        // nodes per face: 4 (bilinear) or 9 (biquadratic)
   double pressure = 0.0;
   double* fnodal = nullptr;           // [n_dof]
 };
@@ -222,9 +227,10 @@ struct ModesArgs {
   const int32_t* fpos_lnode = nullptr; // [NF] local-node index (incl. node_off) of a full position, -1 pad
   const int8_t* fpos_comp = nullptr;   // [NF]
   const double *xyz = nullptr, *U = nullptr;
-  const int32_t* ell_col = nullptr;   // [ELLW][NF] slot-major
+  const int32_t* ell_col = nullptr;   // [ellw][NF] slot-major
   const double* ell_val = nullptr;
   int64_t NF = 0;
+  int ellw = ELLW_Q1;
   const uint8_t* dmask = nullptr;      // [n_dof] Dirichlet DOFs (partially constrained subdomains)
   int test_rotations = 0;              // keep a rotation only if K annihilates it
   double kernel_tol = 1e-12;

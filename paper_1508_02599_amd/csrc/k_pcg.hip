@@ -699,12 +699,13 @@ __global__ void k_restrict(int64_t NF, const int32_t* __restrict__ fpos_lnode, c
 // RES_C slots are loaded before their products, so the loads overlap.  Empty
 // slots add an exact zero, so the sum is that of the filled slots in slot order.
 constexpr int RES_C = 9;
-static_assert(ELLW % RES_C == 0, "whole groups of slots");
+static_assert(ELLW_Q1 % RES_C == 0 && ELLW_Q2 % RES_C == 0, "whole groups of slots");
 __global__ __launch_bounds__(256) void k_local_residual(
     int64_t NF, const int32_t* __restrict__ fpos_lnode, const int8_t* __restrict__ fpos_comp,
     const int64_t* __restrict__ loc_node, const int32_t* __restrict__ f_sub, const SubInfo* __restrict__ subs,
-    const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val, const uint8_t* __restrict__ dmask,
-    const double* __restrict__ ul, const double* __restrict__ f, double* __restrict__ r) {
+    const int32_t* __restrict__ ell_col, const double* __restrict__ ell_val, int ellw,
+    const uint8_t* __restrict__ dmask, const double* __restrict__ ul, const double* __restrict__ f,
+    double* __restrict__ r) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NF) return;
   // padding, and constrained DOFs (their residual is a reaction, absorbed by
@@ -716,7 +717,7 @@ __global__ __launch_bounds__(256) void k_local_residual(
   const double* u = ul + subs[f_sub[p]].full_off;
   double acc = f ? f[p] : 0.0;   // f NULL: r = -K u
 #pragma unroll 1
-  for (int k0 = 0; k0 < ELLW; k0 += RES_C) {
+  for (int k0 = 0; k0 < ellw; k0 += RES_C) {
     int c[RES_C];
     double v[RES_C], x[RES_C];
 #pragma unroll
@@ -1013,12 +1014,12 @@ void pcg_init_state(PcgState* st, double rtol, double atol, int max_it, int hist
 }
 void local_residual(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* f_sub, const SubInfo* subs, const int32_t* ell_col, const double* ell_val,
-                    const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
+                    int ellw, const uint8_t* dmask, const double* uglob, double* ul, const double* f, double* r,
                     hipStream_t s) {
   if (!NF) return;
   hipLaunchKernelGGL(k_restrict, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, uglob, ul);
   hipLaunchKernelGGL(k_local_residual, grid1(NF), dim3(256), 0, s, NF, fpos_lnode, fpos_comp, loc_node, f_sub, subs,
-                     ell_col, ell_val, dmask, ul, f, r);
+                     ell_col, ell_val, ellw, dmask, ul, f, r);
 }
 void vec_distribute(int64_t NF, const int32_t* fpos_lnode, const int8_t* fpos_comp, const int64_t* loc_node,
                     const int32_t* uc_ptr, const uint8_t* dmask, const double* rg, double* r, hipStream_t s) {

@@ -50,7 +50,8 @@ class feti_mesh(C.Structure):
                 ("elem_mat", C.POINTER(C.c_int32)), ("elem_fibers", C.POINTER(C.c_double)),
                 ("n_dir", C.c_int64), ("dir_dof", C.POINTER(C.c_int64)),
                 ("dir_val", C.POINTER(C.c_double)), ("body_force", C.POINTER(C.c_double)),
-                ("n_pfaces", C.c_int64), ("pface", C.POINTER(C.c_int64)), ("pressure", C.c_double)]
+                ("n_pfaces", C.c_int64), ("pface", C.POINTER(C.c_int64)), ("pressure", C.c_double),
+                ("order", C.c_int32)]
 
 
 class feti_options(C.Structure):
@@ -159,6 +160,12 @@ def _mesh_struct(mesh, keep):
     m.n_pfaces = 0 if pf is None else pf.shape[0]
     m.pface = _ptr(pf, C.c_int64)
     m.pressure = float(getattr(mesh, "pressure", 0.0))
+    npe = hex8.shape[1] if hex8.ndim == 2 else 8
+    if npe not in (8, 27):
+        raise ValueError(f"elements with {npe} nodes: expected 8 (Q1) or 27 (Q2)")
+    if pf is not None and pf.shape[1] != (4 if npe == 8 else 9):
+        raise ValueError(f"pressure faces with {pf.shape[1]} nodes on {npe}-node elements")
+    m.order = 1 if npe == 8 else 2
     return m
 
 

@@ -74,3 +74,20 @@ def test_valid_mesh_without_gpu_fails_loudly():
     with pytest.raises(feti.FetiError) as ei:
         feti.Problem(config_mesh("cube8_s2"))
     assert ei.value.status == feti.FETI_EDEVICE
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_q2_meshes_pass_validation():
+    """Q2 (27-node) cube and tube meshes pass the host-side plan builder (the
+    failure is the missing device, after the plan is built); a Q2 mesh with
+    4-node pressure faces is refused before the library is called."""
+    from workloads import cube_mesh, tube_mesh
+    feti = _lib()
+    for m in (cube_mesh(4, 2, order=2), tube_mesh(1, 16, 4, sub=(1, 4, 2), order=2)):
+        with pytest.raises(feti.FetiError) as ei:
+            feti.Problem(m)
+        assert ei.value.status == feti.FETI_EDEVICE
+    m = tube_mesh(1, 16, 4, sub=(1, 4, 2), order=2)
+    m.pface = m.pface[:, [0, 2, 8, 6]]
+    with pytest.raises(ValueError):
+        feti.Problem(m)
