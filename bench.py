@@ -301,7 +301,8 @@ def tube_load_path(args):
         "ms_per_step": 1e3 * total / max(1, nsteps), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32-local/f64-global",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: two-layer HGO tube, 16x128x64 Q1-P0 elements in "
+        "config": {"workload": f"{args.config}: two-layer HGO tube, {mesh.meta['nr']}x{mesh.meta['nth']}x"
+                               f"{mesh.meta['nz']} Q{mesh.order}-P0 elements in "
                                f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, kernel "
                                f"tolerance {args.kernel_tol:g}, "
                                f"{'projected dual GMRES' if args.dual == 'gmres' else 'dual PCG'}, "

@@ -76,6 +76,34 @@ def test_tube_full_size_newton_step(precision):
     assert rr <= 1e-8
 
 
+def test_tube_q2_full_size_exact_newton_step():
+    """The same tube with 8x64x32 Q2-P0 elements (27-node hexahedra, the same
+    424,320 DOFs and 128 subdomains): the exact Newton step (follower-load
+    stiffness) of the first load step from rest, classical FETI with the
+    Dirichlet preconditioner, against the oracle's element rows at sampled
+    nodes."""
+    m = _mesh("tube_q2_8x64x32")
+    U = np.zeros(m.n_dofs)
+    tau = 1.0 / 40.0
+    with _problem(m, variant="classical", precond="dirichlet", rtol=1e-10, ir_tol=1e-11, ir_max=60,
+                  max_it=10000, load_stiffness=True) as p:
+        dU, rn, st = p.newton_step(U, tau)
+    # the oracle's rows of the exact linearisation: K' dU - tau dfp/dU dU = r
+    from oracle import fem
+    rng = np.random.default_rng(0)
+    nodes = np.sort(rng.choice(m.n_nodes, size=200, replace=False))
+    res, scale = fem.nodal_residual(m, nodes, dU, U=U.reshape(-1, 3), tau=tau)
+    D = fem.assemble_load_stiffness(m, U.reshape(-1, 3))
+    corr = tau * (D @ dU).reshape(-1, 3)[nodes]
+    dm = np.zeros(m.n_dofs, dtype=bool)
+    dm[m.dir_dof] = True
+    corr[dm.reshape(-1, 3)[nodes]] = 0.0
+    rr = float(np.max(np.abs(res + corr) / np.maximum(scale, 1e-300)))
+    print(f"tube q2 full: dofs={m.n_dofs} it={st['iters']} sweeps={st['ir_sweeps']} res0={rn:.4e} "
+          f"nodal res={rr:.2e} t_factor={st['t_factor']:.3f} t_pcg={st['t_pcg']:.3f}")
+    assert rr <= 1e-8
+
+
 # ---------------------------------------------------------------- displacement parity at full size
 def _reference(case, mesh, *extra):
     """Oracle displacements written by tests/golden/make_fullsize_refs.py for

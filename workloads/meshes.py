@@ -330,6 +330,9 @@ CONFIGS = {
     "cube8_s2": dict(kind="cube", n_el=8, n_sub_axis=2),
     "cube32_s4": dict(kind="cube", n_el=32, n_sub_axis=4, nu_seed=0),
     "tube_16x128x64": dict(kind="tube", nr=16, nth=128, nz=64, sub=(1, 16, 8)),
+    # the same tube with Q2-P0 elements of twice the size: the same nodes
+    # (424,320 DOFs) and subdomains, 27-node elements
+    "tube_q2_8x64x32": dict(kind="tube", nr=8, nth=64, nz=32, sub=(1, 16, 8), order=2),
     "random_boxes_64": dict(kind="random", n_el=64, n_box_axis=8, seed=0),
     # 40^3 cube in 5x5x5 uneven boxes of 450-5616 DOFs (seed 0): boxes as large
     # as those of random_boxes_64 on a mesh whose direct solve fits a test
