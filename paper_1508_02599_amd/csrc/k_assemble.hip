@@ -649,7 +649,7 @@ struct FaceRule<9> {
 // Follower pressure on the current surface: f_a = -p int N_a (x,s x x,t) ds dt.
 // One thread per node sums over its faces in a fixed order (no atomics).
 template <int NFN>
-__global__ void k_pressure(PressureArgs P) {
+__global__ __launch_bounds__(256) void k_pressure(PressureArgs P) {
   using R = FaceRule<NFN>;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= P.n_nodes) return;
@@ -659,6 +659,7 @@ __global__ void k_pressure(PressureArgs P) {
     const int64_t face = fc / NFN;
     const int cn = (int)(fc % NFN);
     double x[NFN][3];
+#pragma unroll
     for (int q = 0; q < NFN; ++q) {
       const int64_t nd = P.pface[face * NFN + q];
       for (int d = 0; d < 3; ++d) x[q][d] = P.xyz[nd * 3 + d] + (P.U ? P.U[nd * 3 + d] : 0.0);
@@ -667,7 +668,8 @@ __global__ void k_pressure(PressureArgs P) {
       for (int g2 = 0; g2 < R::NG; ++g2) {
         const double h1 = R::pt(g1), h2 = R::pt(g2);
         double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, N, d1, d2;
-        for (int q = 0; q < NFN; ++q) {
+    #pragma unroll
+    for (int q = 0; q < NFN; ++q) {
           R::shape(q, h1, h2, N, d1, d2);
           for (int d = 0; d < 3; ++d) {
             t1[d] += x[q][d] * d1;
@@ -698,7 +700,7 @@ void asm_pressure(const PressureArgs& p, hipStream_t s) {
 // One thread per node sums over its faces in a fixed order (no atomics);
 // Dirichlet DOFs (dmask) get 0.
 template <int NFN>
-__global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, const uint8_t* __restrict__ dmask,
+__global__ __launch_bounds__(256) void k_pressure_dir(PressureArgs P, const double* __restrict__ z, const uint8_t* __restrict__ dmask,
                                double* __restrict__ out) {
   using R = FaceRule<NFN>;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -709,6 +711,7 @@ __global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, con
     const int64_t face = fc / NFN;
     const int cn = (int)(fc % NFN);
     double x[NFN][3], dz[NFN][3];
+#pragma unroll
     for (int q = 0; q < NFN; ++q) {
       const int64_t nd = P.pface[face * NFN + q];
       for (int d = 0; d < 3; ++d) {
@@ -720,7 +723,8 @@ __global__ void k_pressure_dir(PressureArgs P, const double* __restrict__ z, con
       for (int g2 = 0; g2 < R::NG; ++g2) {
         const double h1 = R::pt(g1), h2 = R::pt(g2);
         double t1[3] = {0, 0, 0}, t2[3] = {0, 0, 0}, s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0}, N, d1, d2;
-        for (int q = 0; q < NFN; ++q) {
+    #pragma unroll
+    for (int q = 0; q < NFN; ++q) {
           R::shape(q, h1, h2, N, d1, d2);
           for (int d = 0; d < 3; ++d) {
             t1[d] += x[q][d] * d1;
@@ -766,6 +770,7 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
+static_assert(ELLW_Q1 % 9 == 0 && ELLW_Q2 % 9 == 0, "the rotation test reads slots in groups of 9");
 __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
   __shared__ double red[256];
   __shared__ double cen[3], T[6][6];
@@ -925,25 +930,40 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
   }
   __syncthreads();
   if (M.test_rotations) {
-    double kf = 0.0;
-    for (int64_t p = tid; p < n; p += 256)
-      for (int q = 0; q < M.ellw; ++q) {
-        const double v = M.ell_val[q * M.NF + s.full_off + p];
-        if (M.ell_col[q * M.NF + s.full_off + p] >= 0) kf += v * v;
-      }
-    const double knorm = sqrt(block_sum(kf, red));
-    for (int k = k_first; k < k_last; ++k) {
-      double kr = 0.0, rr = 0.0;
-      for (int64_t p = tid; p < n; p += 256) {
-        double y = 0.0;
-        for (int q = 0; q < M.ellw; ++q) {
-          const int c = M.ell_col[q * M.NF + s.full_off + p];
-          if (c >= 0) y += M.ell_val[q * M.NF + s.full_off + p] * W[(int64_t)c * 6 + k];
+    // one sweep over the ELL rows gives ||K||_F and K r_k of every candidate
+    // k (each sum over the filled slots in slot order, as separate sweeps
+    // would take them); slots are read in groups of 9 so the loads overlap
+    double kf = 0.0, kr[6] = {0, 0, 0, 0, 0, 0}, rr[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t p = tid; p < n; p += 256) {
+      const int64_t row = s.full_off + p;
+      double y[6] = {0, 0, 0, 0, 0, 0};
+      for (int q0 = 0; q0 < M.ellw; q0 += 9) {
+        int c[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) c[i] = M.ell_col[(int64_t)(q0 + i) * M.NF + row];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          if (c[i] < 0) continue;
+          const double v = M.ell_val[(int64_t)(q0 + i) * M.NF + row];
+          kf += v * v;
+          const double* w = W + (int64_t)c[i] * 6;
+#pragma unroll
+          for (int k = 0; k < 6; ++k)
+            if (k >= k_first && k < k_last) y[k] += v * w[k];
         }
-        kr += y * y;
-        rr += W[p * 6 + k] * W[p * 6 + k];
       }
-      const double nkr = sqrt(block_sum(kr, red)), nr = sqrt(block_sum(rr, red));
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k >= k_first && k < k_last) {
+          kr[k] += y[k] * y[k];
+          rr[k] += W[p * 6 + k] * W[p * 6 + k];
+        }
+    }
+    const double knorm = sqrt(block_sum(kf, red));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      if (k < k_first || k >= k_last) continue;   // uniform over the workgroup
+      const double nkr = sqrt(block_sum(kr[k], red)), nr = sqrt(block_sum(rr[k], red));
       if (tid == 0) {
         if (nkr <= M.kernel_tol * knorm * nr) sel[nsel++] = k;
         else failed[nfail++] = k;

@@ -93,6 +93,15 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1508_02599_amd.build.build()")
+    # PyTorch ships its own HIP and HSA runtimes under the sonames of the ROCm
+    # ones the library links.  Loaded first, the library pulls in the ROCm
+    # runtimes and a later torch import adds its own: two runtimes in one
+    # process, and the second can fail to see the device.  Importing torch
+    # first makes the library bind to torch's runtime: one per process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.c_void_p
     lib.feti_setup.argtypes = [C.POINTER(feti_mesh), C.POINTER(feti_options), C.POINTER(P)]
