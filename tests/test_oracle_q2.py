@@ -317,3 +317,38 @@ def test_feti_ref_q2_tube_newton_step_matches_monolithic():
     fr = feti_ref.FetiRef(tp, precond="dirichlet")
     dU = fr.solve(rtol=1e-12)["u"]
     assert np.abs(dU - dU_ref).max() <= 1e-8 * np.abs(dU_ref).max()
+
+
+def _l2_error_q2(mesh, u, exact_fn, npts=5):
+    """||u - u_h||_L2 of a Q2 mesh with an npts^3 Gauss-Legendre rule per
+    element (written here, apart from the oracle's 3-point rule)."""
+    pts, wts = np.polynomial.legendre.leggauss(npts)
+    Xe = mesh.xyz[mesh.hex8]
+    ue = u.reshape(-1, 3)[mesh.hex8]
+    err2 = 0.0
+    for a, wa in zip(pts, wts):
+        for b, wb in zip(pts, wts):
+            for c, wc in zip(pts, wts):
+                N, dN = fem.shape_hex27([a, b, c])
+                x = np.einsum("a,ead->ed", N, Xe)
+                det = np.linalg.det(np.einsum("ead,ak->edk", Xe, dN))
+                d = np.einsum("a,ead->ed", N, ue) - exact_fn(x)
+                err2 += np.sum(wa * wb * wc * det * np.sum(d * d, axis=1))
+    return np.sqrt(err2)
+
+
+def test_q2_kelvin_third_order():
+    """Kelvin's solution as Dirichlet data: the L2 error of the quadratic
+    elements falls with order 3 (section 5.1, eqs. (fundSol), (L2Error); the
+    paper's table of the linear cube with quadratic ansatz functions shows
+    eoc 2.97-3.01)."""
+    from workloads import kelvin_displacement
+    E, nu = 1.0, 0.3
+    errs = []
+    for n in (2, 4, 8):
+        m = cube_mesh(n, 1, E=E, nu=nu, body_force=None, order=2,
+                      dirichlet_fn=lambda x: kelvin_displacement(x, E, nu))
+        u = monolithic.solve_linear(m)
+        errs.append(_l2_error_q2(m, u, lambda x: kelvin_displacement(x, E, nu)))
+    eoc = [np.log(errs[i] / errs[i + 1]) / np.log(2.0) for i in range(2)]
+    assert 2.6 < eoc[0] < 3.4 and 2.8 < eoc[1] < 3.2, (errs, eoc)
