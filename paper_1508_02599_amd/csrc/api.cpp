@@ -125,6 +125,7 @@ struct feti_problem {
   double *d_t = nullptr, *d_kb1 = nullptr, *d_kb2 = nullptr, *d_bb_val = nullptr;
   int32_t *d_bb_slot = nullptr, *d_bb_col = nullptr;
   double *d_rfull = nullptr, *d_rb = nullptr, *d_work = nullptr, *d_rho = nullptr, *d_wbm = nullptr;
+  double* d_mpart = nullptr;   // partial sums of the rotation test (k_modes_sweep)
   int32_t *d_nmodes = nullptr, *d_err = nullptr;
   // coarse
   SubInfo* d_qsub = nullptr;
@@ -607,6 +608,7 @@ feti_status setup_device(feti_problem* p) {
   }
   TRY(dalloc(p, p->d_rfull, (size_t)P.NF * 6));
   TRY(dalloc(p, p->d_work, (size_t)P.NF * 6));
+  TRY(dalloc(p, p->d_mpart, (size_t)P.n_sub * MODES_CH * 13));
   TRY(dalloc(p, p->d_rb, (size_t)P.NB * 6));
   TRY(dalloc(p, p->d_rho, (size_t)P.n_sub));
   TRY(dalloc(p, p->d_wbm, (size_t)P.n_sub * 9));
@@ -942,6 +944,7 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   m.rb = p->d_rb;
   m.n_modes = p->d_nmodes;
   m.work = p->d_work;
+  m.part = p->d_mpart;
   if (P.precond == FETI_PREC_LUMPED) lumped_fill(p->di, P.w_bb, p->d_bb_slot, p->d_ell_val, p->d_bb_val, st);
   HIPCHK(hipEventRecord(p->ev[1], st));
   // The rigid-body modes read only the assembled sparse rows, and the interior

@@ -78,7 +78,7 @@ struct HgoPoint {
 
 // Closed-form isochoric + volumetric stress/tangent of the HGO model at C,
 // with the element pressure p (P0) and the element factor J of this point.
-__device__ void hgo_point(const double* F, double J, double p, const double* a1, const double* a2, double c,
+__device__ __forceinline__ void hgo_point(const double* F, double J, double p, const double* a1, const double* a2, double c,
                           double k1, double k2, HgoPoint& out) {
   double C[9];
   for (int I = 0; I < 3; ++I)
@@ -771,10 +771,9 @@ __device__ double block_sum(double v, double* red) {
 }
 
 static_assert(ELLW_Q1 % 9 == 0 && ELLW_Q2 % 9 == 0, "the rotation test reads slots in groups of 9");
-__global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
+__global__ __launch_bounds__(256) void k_modes_setup(ModesArgs M) {
   __shared__ double red[256];
-  __shared__ double cen[3], T[6][6];
-  __shared__ int sel[6], nsel;
+  __shared__ double cen[3];
   const int sid = blockIdx.x;
   const SubInfo s = M.subs[sid];
   const int64_t n = (int64_t)s.nt * TS;
@@ -918,6 +917,76 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
     n_cand = 6;
   }
   __syncthreads();
+  if (tid == 0) M.n_modes[sid] = n_cand;   // the candidate count, until k_modes_finish
+}
+
+// The rotation test's sweep over the ELL rows, split over MODES_CH
+// workgroups per subdomain: each sums, over its rows, ||K row||^2 and, for
+// every candidate k, |(K r_k)_p|^2 and r_k,p^2 (slots in slot order, groups
+// of 9 loaded together); k_modes_finish adds the chunks in order.
+__global__ __launch_bounds__(256) void k_modes_sweep(ModesArgs M) {
+  __shared__ double red[256];
+  const int sid = blockIdx.x;
+  const SubInfo s = M.subs[sid];
+  if (!s.floating) return;
+  const int64_t n = (int64_t)s.nt * TS;
+  const double* W = M.work + s.full_off * 6;
+  const int tid = threadIdx.x;
+  const bool partial = s.floating == 2;
+  const int k_first = partial ? 0 : 3, k_last = partial ? M.n_modes[sid] : 6;
+  const int64_t chunk = (n + MODES_CH - 1) / MODES_CH;
+  const int64_t lo = (int64_t)blockIdx.y * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double kf = 0.0, kr[6] = {0, 0, 0, 0, 0, 0}, rr[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t p = lo + tid; p < hi; p += 256) {
+    const int64_t row = s.full_off + p;
+    double y[6] = {0, 0, 0, 0, 0, 0};
+    for (int q0 = 0; q0 < M.ellw; q0 += 9) {
+      int c[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) c[i] = M.ell_col[(int64_t)(q0 + i) * M.NF + row];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if (c[i] < 0) continue;
+        const double v = M.ell_val[(int64_t)(q0 + i) * M.NF + row];
+        kf += v * v;
+        const double* w = W + (int64_t)c[i] * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (k >= k_first && k < k_last) y[k] += v * w[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k >= k_first && k < k_last) {
+        kr[k] += y[k] * y[k];
+        rr[k] += W[p * 6 + k] * W[p * 6 + k];
+      }
+  }
+  double* out = M.part + ((int64_t)sid * MODES_CH + blockIdx.y) * 13;
+  const double t = block_sum(kf, red);
+  if (tid == 0) out[0] = t;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double a = block_sum(kr[k], red), b = block_sum(rr[k], red);
+    if (tid == 0) {
+      out[1 + k] = a;
+      out[7 + k] = b;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_modes_finish(ModesArgs M) {
+  __shared__ double red[256];
+  __shared__ double T[6][6];
+  __shared__ int sel[6], nsel;
+  const int sid = blockIdx.x;
+  const SubInfo s = M.subs[sid];
+  if (!s.floating) return;
+  const int64_t n = (int64_t)s.nt * TS;
+  double* rf = M.rfull + s.full_off * 6;
+  const double* W = M.work + s.full_off * 6;
+  const int tid = threadIdx.x;
+  const int n_cand = M.n_modes[sid];
   __shared__ int failed[6], nfail;
   // candidates: floating == 1 keeps the translations (in the kernel of every
   // tangent) and tests the rotations; floating == 2 tests its n_cand columns
@@ -930,46 +999,19 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
   }
   __syncthreads();
   if (M.test_rotations) {
-    // one sweep over the ELL rows gives ||K||_F and K r_k of every candidate
-    // k (each sum over the filled slots in slot order, as separate sweeps
-    // would take them); slots are read in groups of 9 so the loads overlap
-    double kf = 0.0, kr[6] = {0, 0, 0, 0, 0, 0}, rr[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t p = tid; p < n; p += 256) {
-      const int64_t row = s.full_off + p;
-      double y[6] = {0, 0, 0, 0, 0, 0};
-      for (int q0 = 0; q0 < M.ellw; q0 += 9) {
-        int c[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) c[i] = M.ell_col[(int64_t)(q0 + i) * M.NF + row];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          if (c[i] < 0) continue;
-          const double v = M.ell_val[(int64_t)(q0 + i) * M.NF + row];
-          kf += v * v;
-          const double* w = W + (int64_t)c[i] * 6;
-#pragma unroll
-          for (int k = 0; k < 6; ++k)
-            if (k >= k_first && k < k_last) y[k] += v * w[k];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (k >= k_first && k < k_last) {
-          kr[k] += y[k] * y[k];
-          rr[k] += W[p * 6 + k] * W[p * 6 + k];
-        }
-    }
-    const double knorm = sqrt(block_sum(kf, red));
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      if (k < k_first || k >= k_last) continue;   // uniform over the workgroup
-      const double nkr = sqrt(block_sum(kr[k], red)), nr = sqrt(block_sum(rr[k], red));
-      if (tid == 0) {
-        if (nkr <= M.kernel_tol * knorm * nr) sel[nsel++] = k;
+    if (tid == 0) {   // the sweep's chunks, added in chunk order
+      const double* pt = M.part + (int64_t)sid * MODES_CH * 13;
+      double v[13];
+      for (int q = 0; q < 13; ++q) v[q] = 0.0;
+      for (int c = 0; c < MODES_CH; ++c)
+        for (int q = 0; q < 13; ++q) v[q] += pt[c * 13 + q];
+      const double knorm = sqrt(v[0]);
+      for (int k = k_first; k < k_last; ++k) {
+        if (sqrt(v[1 + k]) <= M.kernel_tol * knorm * sqrt(v[7 + k])) sel[nsel++] = k;
         else failed[nfail++] = k;
       }
-      __syncthreads();
     }
+    __syncthreads();
     // kernel modes first, then the candidates the stressed tangent does not
     // annihilate, then (floating == 2) the modes outside the kernel
     if (tid == 0) {
@@ -1030,7 +1072,9 @@ __global__ __launch_bounds__(256) void k_modes(ModesArgs M) {
 }
 
 void asm_modes(const ModesArgs& m, hipStream_t s) {
-  hipLaunchKernelGGL(k_modes, dim3(m.n_sub), dim3(256), 0, s, m);
+  hipLaunchKernelGGL(k_modes_setup, dim3(m.n_sub), dim3(256), 0, s, m);
+  if (m.test_rotations) hipLaunchKernelGGL(k_modes_sweep, dim3(m.n_sub, MODES_CH), dim3(256), 0, s, m);
+  hipLaunchKernelGGL(k_modes_finish, dim3(m.n_sub), dim3(256), 0, s, m);
 }
 
 // Coarse matrix Q = G^T G with G = [B_i Rb_i]: block (s, t), s >= t, sums

@@ -219,6 +219,7 @@ void asm_pressure(const PressureArgs& p, hipStream_t s);
 // (global node-major vectors; Dirichlet DOFs of out are 0).
 void asm_pressure_dir(const PressureArgs& p, const double* z, const uint8_t* dmask, double* out, hipStream_t s);
 
+constexpr int MODES_CH = 16;   // workgroups per subdomain of the rotation test's sweep
 struct ModesArgs {
   int n_sub = 0;
   const SubInfo* subs = nullptr;
@@ -238,6 +239,7 @@ struct ModesArgs {
   double* rb = nullptr;                // [NB*6]
   int32_t* n_modes = nullptr;          // [n_sub] (output)
   double* work = nullptr;              // [NF*6] scratch
+  double* part = nullptr;              // [n_sub*MODES_CH*13] partial sums of the rotation test
 };
 void asm_modes(const ModesArgs& m, hipStream_t s);
 
