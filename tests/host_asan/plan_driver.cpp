@@ -62,6 +62,40 @@ Cube cube(int n, int m, bool partial) {
   return c;
 }
 
+// The same node grid with n^3 27-node (Q2) elements, (2n+1)^3 nodes, clamped
+// on the whole boundary, and 9-node pressure faces on x = 0.
+Cube cube27(int n, int m, std::vector<int64_t>& pface) {
+  Cube c;
+  const int nn = 2 * n + 1;
+  for (int k = 0; k < nn; ++k)
+    for (int j = 0; j < nn; ++j)
+      for (int i = 0; i < nn; ++i) {
+        c.xyz.push_back((double)i / (2 * n));
+        c.xyz.push_back((double)j / (2 * n));
+        c.xyz.push_back((double)k / (2 * n));
+      }
+  const int h = n / m;
+  auto id = [&](int i, int j, int k) { return i + (int64_t)nn * (j + (int64_t)nn * k); };
+  for (int ez = 0; ez < n; ++ez)
+    for (int ey = 0; ey < n; ++ey)
+      for (int ex = 0; ex < n; ++ex) {
+        for (int a = 0; a < 27; ++a) c.hex8.push_back(id(2 * ex + a % 3, 2 * ey + (a / 3) % 3, 2 * ez + a / 9));
+        c.esub.push_back(ex / h + m * (ey / h + m * (ez / h)));
+        c.emat.push_back(0);
+        c.body.insert(c.body.end(), {0.0, 0.0, -1.0});
+      }
+  for (int k = 0; k < nn; ++k)
+    for (int j = 0; j < nn; ++j)
+      for (int i = 0; i < nn; ++i)
+        if (i == 0 || j == 0 || k == 0 || i == nn - 1 || j == nn - 1 || k == nn - 1)
+          for (int d = 0; d < 3; ++d) c.ddof.push_back(3 * id(i, j, k) + d);
+  c.dval.assign(c.ddof.size(), 0.0);
+  for (int ez = 0; ez < n; ++ez)
+    for (int ey = 0; ey < n; ++ey)
+      for (int a = 0; a < 9; ++a) pface.push_back(id(0, 2 * ey + a / 3, 2 * ez + a % 3));
+  return c;
+}
+
 feti_mesh view(Cube& c, int m) {
   feti_mesh M{};
   M.n_nodes = (int64_t)c.xyz.size() / 3;
@@ -106,6 +140,29 @@ int main() {
       expect(P.n_lam == (af ? 2556 : 732), "cube8 multipliers " + std::to_string(P.n_lam));
       expect(P.n_sub == 8 && !P.tasks.empty(), "cube8 schedule");
     }
+  // Q2 elements on the node grid of the 8^3 Q1 cube: the same multipliers;
+  // 9-node pressure faces
+  for (int af = 0; af < 2; ++af) {
+    std::vector<int64_t> pf;
+    Cube c = cube27(4, 2, pf);
+    feti_mesh M = view(c, 2);
+    M.order = 2;
+    M.n_pfaces = (int64_t)pf.size() / 9;
+    M.pface = pf.data();
+    M.pressure = 1.0;
+    feti_options o{};
+    o.variant = af ? FETI_ALL_FLOATING : FETI_CLASSICAL;
+    o.precond = FETI_PREC_DIRICHLET;
+    feti::HostPlan P;
+    const std::string e = feti::build_plan(&M, &o, P);
+    expect(e.empty(), "q2 cube plan: " + e);
+    expect(P.n_lam == (af ? 2556 : 732), "q2 cube multipliers " + std::to_string(P.n_lam));
+    expect(P.npe == 27 && P.nfn == 9 && P.ellw == feti::ELLW_Q2, "q2 element and face sizes");
+    expect(P.pf_ptr.back() == (int32_t)pf.size(), "q2 pressure face entries");
+    M.order = 3;
+    feti::HostPlan P2;
+    expect(!feti::build_plan(&M, &o, P2).empty(), "element order 3 accepted");
+  }
   // uneven boxes and partial Dirichlet data
   for (int af = 0; af < 2; ++af) {
     Cube c = cube(12, 3, true);

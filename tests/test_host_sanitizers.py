@@ -1,7 +1,7 @@
 """The host plan builder (decomp.cpp) under AddressSanitizer and
 UndefinedBehaviorSanitizer: a g++ build of it with a driver that plans cube
-meshes (both variants, all preconditioners, uneven and partially constrained
-subdomains) and malformed meshes.  Host code only; no GPU involved."""
+meshes (Q1 and Q2 elements, both variants, all preconditioners, uneven and
+partially constrained subdomains, pressure faces) and malformed meshes.  Host code only; no GPU involved."""
 import os
 import shutil
 import subprocess
