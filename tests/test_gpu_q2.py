@@ -2,8 +2,9 @@
 oracle, through the C ABI: linear cubes (both variants, every
 preconditioner, FP64 and mixed precision), the exact reproduction of a
 quadratic displacement field, and Newton steps of the Q2-P0 HGO tube (from
-rest, from a stressed equilibrium, and the exact step with the follower-load
-stiffness).  Errors are max(relative 2-norm, element-wise max relative to
+rest, from a stressed equilibrium, the exact step with the follower-load
+stiffness in FP64 and mixed precision, and a converged load path at the
+benchmark's settings).  Errors are max(relative 2-norm, element-wise max relative to
 max|u_ref|), as in the Q1 parity tests."""
 import numpy as np
 import pytest
@@ -133,3 +134,56 @@ def test_q2_tube_exact_newton_steps(variant):
               f"coarse={st['n_coarse']} err={err:.3e}")
         assert abs(rn - rn_ref) <= 1e-9 * rn_ref
         assert err <= 1e-9
+
+
+def test_q2_tube_exact_newton_mixed():
+    """Mixed precision (FP32 local factors, FP64 refinement) on the exact
+    Newton step of the Q2-P0 tube from rest: the oracle's step to 1e-8."""
+    m = _q2_tube()
+    U = np.zeros(m.n_dofs)
+    dU_ref, rn_ref = monolithic.newton_increment(m, U, 1 / 40, load_stiffness=True)
+    with _problem(m, variant="af", precond="dirichlet", precision="mixed", rtol=1e-8, ir_tol=1e-10, ir_max=60,
+                  load_stiffness=True) as p:
+        dU, rn, st = p.newton_step(U, 1 / 40)
+    err = _rel(dU, dU_ref)
+    print(f"q2 exact newton mixed: it={st['iters']} gmres={st['ir_sweeps']} err={err:.3e}")
+    assert abs(rn - rn_ref) <= 1e-9 * rn_ref
+    assert err <= 1e-8
+
+
+def test_q2_converged_load_path_parity():
+    """The Q2-P0 tube's load path at the benchmark's settings (classical,
+    Dirichlet preconditioner, exact Newton steps, kernel tolerance 1e-6,
+    projected dual GMRES, warm starts, inexact Newton forcing) ends every load
+    step at the equilibrium the oracle's Newton iteration finds."""
+    import sys
+    import torch
+    from paper_1508_02599_amd.feti import Problem
+    from paper_1508_02599_amd.loadpath import run_load_path
+    m = tube_mesh(nr=1, nth=16, nz=4, sub=(1, 4, 4), order=2)   # end rings clamped, middle rings floating
+    n_inc, n_steps = 160, 4
+    ref, U = {}, np.zeros(m.n_dofs)
+    for s in range(1, n_steps + 1):
+        r0 = None
+        for _ in range(30):
+            dU, rn = monolithic.newton_increment(m, U, s / n_inc, load_stiffness=True)
+            r0 = rn if r0 is None else r0
+            if rn <= 1e-10 * r0:
+                break
+            U = U + dU
+        ref[s] = U.copy()
+    got = {}
+
+    def record(tau, k, Uk):
+        got[round(tau * n_inc, 9)] = Uk.double().cpu().numpy()
+
+    with Problem(m, variant="classical", precond="dirichlet", rtol=1e-10, ir_tol=1e-3, ir_max=60, max_it=3000,
+                 device_ptrs=True, load_stiffness=True, warm_start=True, dual_gmres=True, kernel_tol=1e-6) as p:
+        Ug = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
+        r = run_load_path(p, Ug, n_inc, rtol=1e-10, newton_tol=1e-9, tau_end=n_steps / n_inc, record=record,
+                          log=sys.stdout)
+    assert r["error"] is None and abs(r["tau_reached"] - n_steps / n_inc) < 1e-12, r["error"]
+    errs = [_rel(got[float(s)], ref[s]) for s in range(1, n_steps + 1)]
+    for s, err in zip(range(1, n_steps + 1), errs):
+        print(f"q2 load step {s}: Newton steps {r['newton_per_load'][s - 1]}, error {err:.3e}")
+    assert max(errs) <= 1e-8
