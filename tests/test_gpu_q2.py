@@ -151,11 +151,13 @@ def test_q2_tube_exact_newton_mixed():
     assert err <= 1e-8
 
 
-def test_q2_converged_load_path_parity():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_q2_converged_load_path_parity(precision):
     """The Q2-P0 tube's load path at the benchmark's settings (classical,
     Dirichlet preconditioner, exact Newton steps, kernel tolerance 1e-6,
-    projected dual GMRES, warm starts, inexact Newton forcing) ends every load
-    step at the equilibrium the oracle's Newton iteration finds."""
+    projected dual GMRES, warm starts, inexact Newton forcing; mixed: FP32
+    local factors, first dual solves to 1e-6) ends every load step at the
+    equilibrium the oracle's Newton iteration finds."""
     import sys
     import torch
     from paper_1508_02599_amd.feti import Problem
@@ -177,13 +179,15 @@ def test_q2_converged_load_path_parity():
     def record(tau, k, Uk):
         got[round(tau * n_inc, 9)] = Uk.double().cpu().numpy()
 
-    with Problem(m, variant="classical", precond="dirichlet", rtol=1e-10, ir_tol=1e-3, ir_max=60, max_it=3000,
-                 device_ptrs=True, load_stiffness=True, warm_start=True, dual_gmres=True, kernel_tol=1e-6) as p:
+    rtol = 1e-10 if precision == "fp64" else 1e-6
+    with Problem(m, variant="classical", precond="dirichlet", precision=precision, rtol=rtol, ir_tol=1e-3,
+                 ir_max=60, max_it=3000, device_ptrs=True, load_stiffness=True, warm_start=True, dual_gmres=True,
+                 kernel_tol=1e-6) as p:
         Ug = torch.zeros(m.n_dofs, dtype=torch.float64, device="cuda")
-        r = run_load_path(p, Ug, n_inc, rtol=1e-10, newton_tol=1e-9, tau_end=n_steps / n_inc, record=record,
+        r = run_load_path(p, Ug, n_inc, rtol=rtol, newton_tol=1e-9, tau_end=n_steps / n_inc, record=record,
                           log=sys.stdout)
     assert r["error"] is None and abs(r["tau_reached"] - n_steps / n_inc) < 1e-12, r["error"]
     errs = [_rel(got[float(s)], ref[s]) for s in range(1, n_steps + 1)]
     for s, err in zip(range(1, n_steps + 1), errs):
-        print(f"q2 load step {s}: Newton steps {r['newton_per_load'][s - 1]}, error {err:.3e}")
+        print(f"q2 load step {s} {precision}: Newton steps {r['newton_per_load'][s - 1]}, error {err:.3e}")
     assert max(errs) <= 1e-8
