@@ -97,7 +97,8 @@ struct HostPlan {
   std::vector<int32_t> pc_e;            // contribution element
   std::vector<int32_t> pc_ab;           // la | lb << 8
   std::vector<int32_t> diag_slot;       // [n_loc_nodes] slot of (a, a)
-  std::vector<int32_t> ell_col;         // [ELLW][NF] slot-major: >=0 local pos, -1 empty, <=-2 Dirichlet dof -(g+2)
+  std::vector<int32_t> ell_col;         // [ellw][NF] slot-major: >=0 local pos, -1 empty, <=-2 Dirichlet dof -(g+2);
+                                        // the filled slots of every row form a prefix (kernels stop at the first -1)
   int32_t w_bb = 0;                     // width of the interface-interface block K_bb in slots
   std::vector<int32_t> bb_slot;         // [w_bb][NB] ELL slot of each K_bb entry (-1 none)
   std::vector<int32_t> bb_col;          // [w_bb][NB] b-space column

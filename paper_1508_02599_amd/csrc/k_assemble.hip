@@ -557,36 +557,34 @@ void asm_elements(const AsmArgs& a, int any_hgo, hipStream_t s) {
 }
 
 // Node-pair gather: K_i[(a,i),(b,j)] = sum over shared elements (fixed order).
+// One thread per entry (i, j) of a node pair's 3x3 block, so the nine
+// threads of a pair read each element block's 72 contiguous bytes together.
 template <typename T>
 __global__ void k_gather_local(GatherArgs G, T* arena) {
-  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= G.n_slots) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * G.n_slots) return;
+  const int64_t sl = t / 9;
+  const int k = (int)(t % 9), i = k / 3, j = k % 3;
   const int la = G.ps_a[sl], lb = G.ps_b[sl], nbr = G.ps_nbr[sl];
-  double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int row = G.loc_pos[3 * la + i];
+  if (row < 0) return;
+  double K = 0.0;
   for (int c = G.ps_c0[sl]; c < G.ps_c1[sl]; ++c) {
     const int e = G.pc_e[c], ab = G.pc_ab[c];
-    const double* src = G.Ke + (int64_t)e * (9 * G.npe * G.npe) + ((ab & 255) * G.npe + (ab >> 8)) * 9;
-    for (int k = 0; k < 9; ++k) K[k] += src[k];
+    K += G.Ke[(int64_t)e * (9 * G.npe * G.npe) + ((ab & 255) * G.npe + (ab >> 8)) * 9 + k];
   }
   const SubInfo s = G.subs[G.loc_sub[la]];
-  T* base = arena + s.tile_off;
-  for (int i = 0; i < 3; ++i) {
-    const int row = G.loc_pos[3 * la + i];
-    if (row < 0) continue;
-    for (int j = 0; j < 3; ++j) {
-      G.ell_val[(int64_t)(nbr * 3 + j) * G.NF + s.full_off + row] = K[3 * i + j];
-      const int col = G.loc_pos[3 * lb + j];
-      if (col >= 0 && row >= col) {
-        const int ti = row / TS, tj = col / TS;
-        base[tidx3(ti, tj) * TS2 + (col % TS) * TS + (row % TS)] = (T)K[3 * i + j];
-      }
-    }
+  G.ell_val[(int64_t)(nbr * 3 + j) * G.NF + s.full_off + row] = K;
+  const int col = G.loc_pos[3 * lb + j];
+  if (col >= 0 && row >= col) {
+    const int ti = row / TS, tj = col / TS;
+    arena[s.tile_off + tidx3(ti, tj) * TS2 + (col % TS) * TS + (row % TS)] = (T)K;
   }
 }
 
 template <typename T>
 void asm_gather(const GatherArgs& g, T* arena, hipStream_t s) {
-  if (g.n_slots) hipLaunchKernelGGL(k_gather_local<T>, dim3((unsigned)((g.n_slots + 255) / 256)), dim3(256), 0, s, g, arena);
+  if (g.n_slots) hipLaunchKernelGGL(k_gather_local<T>, dim3((unsigned)((9 * g.n_slots + 255) / 256)), dim3(256), 0, s, g, arena);
 }
 template void asm_gather<double>(const GatherArgs&, double*, hipStream_t);
 template void asm_gather<float>(const GatherArgs&, float*, hipStream_t);
@@ -614,6 +612,7 @@ __global__ void k_rhs(RhsArgs R) {
   const int64_t row = s.full_off + pos;
   for (int k = 0; k < R.ellw; ++k) {
     const int cc = R.ell_col[k * R.NF + row];
+    if (cc == -1) break;   // the filled slots of a row form a prefix
     if (cc <= -2) f -= R.ell_val[k * R.NF + row] * R.dvals[-(cc + 2)];
   }
   R.f[row] = f;
@@ -951,6 +950,7 @@ __global__ __launch_bounds__(256) void k_modes_sweep(ModesArgs M) {
       int c[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) c[i] = M.ell_col[(int64_t)(q0 + i) * M.NF + row];
+      if (c[0] == -1) break;   // the filled slots of a row form a prefix
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         if (c[i] < 0) continue;

@@ -722,6 +722,7 @@ __global__ __launch_bounds__(256) void k_local_residual(
     double v[RES_C], x[RES_C];
 #pragma unroll
     for (int i = 0; i < RES_C; ++i) c[i] = ell_col[(int64_t)(k0 + i) * NF + p];
+    if (c[0] == -1) break;   // the filled slots of a row form a prefix: the rest add 0
 #pragma unroll
     for (int i = 0; i < RES_C; ++i) {
       v[i] = c[i] >= 0 ? ell_val[(int64_t)(k0 + i) * NF + p] : 0.0;

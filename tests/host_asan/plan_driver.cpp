@@ -139,6 +139,16 @@ int main() {
       expect(e.empty(), "cube8 plan: " + e);
       expect(P.n_lam == (af ? 2556 : 732), "cube8 multipliers " + std::to_string(P.n_lam));
       expect(P.n_sub == 8 && !P.tasks.empty(), "cube8 schedule");
+      bool prefix = true;
+      for (int64_t r = 0; r < P.NF; ++r) {
+        bool empty = false;
+        for (int k = 0; k < P.ellw; ++k) {
+          const int cc = P.ell_col[(int64_t)k * P.NF + r];
+          if (cc == -1) empty = true;
+          else if (empty) prefix = false;
+        }
+      }
+      expect(prefix, "cube8 ELL rows are not prefix-filled");
     }
   // Q2 elements on the node grid of the 8^3 Q1 cube: the same multipliers;
   // 9-node pressure faces
@@ -159,6 +169,18 @@ int main() {
     expect(P.n_lam == (af ? 2556 : 732), "q2 cube multipliers " + std::to_string(P.n_lam));
     expect(P.npe == 27 && P.nfn == 9 && P.ellw == feti::ELLW_Q2, "q2 element and face sizes");
     expect(P.pf_ptr.back() == (int32_t)pf.size(), "q2 pressure face entries");
+    // the filled ELL slots of every row form a prefix (the kernels stop at
+    // the first empty slot)
+    bool prefix = true;
+    for (int64_t r = 0; r < P.NF; ++r) {
+      bool empty = false;
+      for (int k = 0; k < P.ellw; ++k) {
+        const int c = P.ell_col[(int64_t)k * P.NF + r];
+        if (c == -1) empty = true;
+        else if (empty) prefix = false;
+      }
+    }
+    expect(prefix, "q2 ELL rows are not prefix-filled");
     M.order = 3;
     feti::HostPlan P2;
     expect(!feti::build_plan(&M, &o, P2).empty(), "element order 3 accepted");
