@@ -2,6 +2,8 @@
 
     python -m paper_1508_02599_amd.prof_summary trace <dir> [--top N] [--min-us T]
     python -m paper_1508_02599_amd.prof_summary pmc <counter_dir> [--kernel NAME] [--min-kib K]
+    python -m paper_1508_02599_amd.prof_summary gaps <dir> [--top N]
+    python -m paper_1508_02599_amd.prof_summary factor-gaps <dir>
     python -m paper_1508_02599_amd.prof_summary traffic --fp64 FETCH_DIR WRITE_DIR
                                                         [--mixed FETCH_DIR WRITE_DIR]
 
@@ -11,6 +13,10 @@ last at least ``--min-us`` microseconds.  The PCG kernels of one replayed graph
 block that run after the stopping rule has been met return at once; the second
 mean leaves those out and is the one to compare with the HIP-event timings of
 the library's profiling mode.
+
+``gaps`` prints the device's idle time between consecutive kernels,
+attributed to the kernel that follows each gap; ``factor-gaps`` the idle time
+between the launches of each factorisation phase.
 
 ``pmc`` reads ``*_counter_collection.csv`` of a single-counter run and prints,
 per kernel, the mean counter value per dispatch (KiB), over all dispatches and
@@ -104,6 +110,70 @@ def overlap_table(d: str):
             f"({100 * over / max(1, busy):.0f}% of busy time); kernel time / busy time {work / max(1, busy):.2f}")
 
 
+def _sorted_kernels(d: str):
+    f = _one(os.path.join(d, "**", "*kernel_trace.csv"))
+    with open(f) as fh:
+        return sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"]))
+                      for r in csv.DictReader(fh))
+
+
+def gaps_table(d: str, top: int = 20):
+    """Idle time of the device between consecutive kernels (any stream),
+    attributed to the kernel that starts after each gap."""
+    rows = _sorted_kernels(d)
+    if not rows:
+        return "empty trace"
+    end = rows[0][1]
+    idle = 0
+    by = defaultdict(lambda: [0, 0])
+    sizes = [0, 0, 0, 0]
+    for s, e, n in rows[1:]:
+        g = s - end
+        if g > 0:
+            idle += g
+            by[n][0] += g
+            by[n][1] += 1
+            sizes[0 if g < 2000 else 1 if g < 10000 else 2 if g < 50000 else 3] += g
+        end = max(end, e)
+    span = rows[-1][1] - rows[0][0]
+    out = [f"span {span * 1e-6:.1f} ms, idle {idle * 1e-6:.1f} ms ({100 * idle / span:.1f}%), kernels {len(rows)}",
+           "idle by gap size (<2us, <10us, <50us, >=50us) ms: " + str([round(x * 1e-6, 1) for x in sizes])]
+    for n, (g, c) in sorted(by.items(), key=lambda kv: -kv[1][0])[:top]:
+        out.append(f"  before {n}: {g * 1e-6:.1f} ms over {c} gaps ({g / c * 1e-3:.1f} us mean)")
+    return "\n".join(out)
+
+
+_FACTOR = ("k_update", "k_diag", "k_trsm", "k_trtri", "k_lauum", "k_copy_iface", "k_regularise", "k_rho", "k_wb")
+_BESIDE = ("k_init_arena", "k_coarse", "k_modes", "copyBuffer")
+
+
+def factor_gaps_table(d: str, last: int = 6):
+    """Idle time inside the factorisation: each maximal run of factor kernels
+    (kernels of the coarse stream that run beside it do not end a run) with
+    its launch count, span and the gaps between its kernels; the last runs."""
+    runs, cur = [], []
+    for s, e, n in _sorted_kernels(d):
+        if any(k in n for k in _FACTOR):
+            cur.append((s, e))
+        elif cur and not any(k in n for k in _BESIDE):
+            if len(cur) > 20:
+                runs.append(cur)
+            cur = []
+    if len(cur) > 20:
+        runs.append(cur)
+    out = []
+    for r in runs[-last:]:
+        span = r[-1][1] - r[0][0]
+        end, gaps = r[0][0], 0
+        for s, e in r:
+            if s > end:
+                gaps += s - end
+            end = max(end, e)
+        out.append(f"factor phase: {len(r)} launches, span {span * 1e-6:.2f} ms, idle gaps {gaps * 1e-6:.2f} ms "
+                   f"({100 * gaps / span:.1f}%)")
+    return "\n".join(out)
+
+
 def pmc_table(d: str, kernel: str | None = None, min_kib: float = 0.0):
     f = _one(os.path.join(d, "**", "*counter_collection.csv"))
     vals = defaultdict(list)
@@ -193,7 +263,7 @@ def write_traffic(out: str, runs: dict, fetch_scale: float, write_scale: float, 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "overlap"])
+    ap.add_argument("mode", choices=["trace", "pmc", "traffic", "overlap", "gaps", "factor-gaps"])
     ap.add_argument("dir", nargs="?")
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--min-us", type=float, default=0.0)
@@ -210,6 +280,10 @@ def main():
         print(trace_table(a.dir, a.top, a.min_us))
     elif a.mode == "overlap":
         print(overlap_table(a.dir))
+    elif a.mode == "gaps":
+        print(gaps_table(a.dir, a.top))
+    elif a.mode == "factor-gaps":
+        print(factor_gaps_table(a.dir))
     elif a.mode == "pmc":
         print(pmc_table(a.dir, a.kernel, a.min_kib))
     else:
