@@ -890,8 +890,10 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   HIPCHK(hipMemcpyAsync(p->d_err, p->h_errinit, 4 * sizeof(int), hipMemcpyHostToDevice, st));
   a.fbody = p->d_fbody;
   a.inverted = p->d_err + 1;
-  // the arena fill and the ELL reset do not need the element matrices: they
-  // run on the coarse stream while the elements are integrated
+  // the arena fill does not need the element matrices: it runs on the coarse
+  // stream while the elements are integrated.  The ELL values need no reset:
+  // the gather writes every filled slot (the node pairs of the plan), and
+  // every reader stops at, or skips, the empty ones.
   HIPCHK(hipEventRecord(p->ev_ffork, st));
   HIPCHK(hipStreamWaitEvent(p->stream_c, p->ev_ffork, 0));
   const auto& AT = P.sched_alltiles;
@@ -899,7 +901,6 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
     launch_init_arena<float>(p->d_tasks + AT.first, AT.count, p->d_sub, (float*)p->d_arena, p->stream_c);
   else
     launch_init_arena<double>(p->d_tasks + AT.first, AT.count, p->d_sub, (double*)p->d_arena, p->stream_c);
-  vec_fill((int64_t)P.NF * P.ellw, 0.0, p->d_ell_val, p->stream_c);
   HIPCHK(hipEventRecord(p->ev_fjoin, p->stream_c));
   asm_elements(a, P.any_hgo, st);
   HIPCHK(hipStreamWaitEvent(st, p->ev_fjoin, 0));
