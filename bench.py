@@ -253,8 +253,9 @@ def roofline(st_all, precision):
 
 
 def tube_load_path(args):
-    """The HGO tube under its inner-pressure ramp to 16 mmHg in load
-    increments of 16/n mmHg (n = --load-steps, default 40: 0.4 mmHg; the paper
+    """The HGO tube under its inner-pressure ramp to P mmHg (--end-mmhg,
+    default 16) in load increments of P/n mmHg (n = --load-steps, default 40:
+    0.4 mmHg; the paper
     likewise reports that its Newton method needs small pressure steps), each
     load step solved by Newton from the previous equilibrium
     (paper_1508_02599_amd.loadpath: inexact Newton forcing, load-step
@@ -278,7 +279,8 @@ def tube_load_path(args):
     from paper_1508_02599_amd.feti import AUTOTUNE_FACTORISATIONS, Problem
     from paper_1508_02599_amd.loadpath import run_load_path
 
-    mesh = config_mesh(args.config)
+    from workloads.meshes import MMHG
+    mesh = config_mesh(args.config, pressure=args.end_mmhg * MMHG)
     n = mesh.n_dofs
     rtol = args.rtol if args.precision == "fp64" else args.mixed_rtol
     p = Problem(mesh, variant=args.variant, precond="dirichlet", precision=args.precision, rtol=rtol,
@@ -306,12 +308,13 @@ def tube_load_path(args):
                                f"{mesh.n_sub} subdomains ({args.variant}, Dirichlet preconditioner, kernel "
                                f"tolerance {args.kernel_tol:g}, "
                                f"{'projected dual GMRES' if args.dual == 'gmres' else 'dual PCG'}, "
-                               f"{'cold' if args.cold_start else 'warm'} starts), inner pressure to 16 mmHg in "
-                               f"increments of {16.0 / args.load_steps:g} mmHg (halved on failure), exact Newton "
+                               f"{'cold' if args.cold_start else 'warm'} starts), inner pressure to {args.end_mmhg:g} "
+                               f"mmHg in increments of {args.end_mmhg / args.load_steps:g} mmHg (halved on failure), "
+                               f"exact Newton "
                                f"(follower-load stiffness) to |r| <= {args.newton_tol:g} |r_0| per load step",
                    "global_dofs": n},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99))},
-        "pressure_reached_mmHg": 16.0 * r["tau_reached"], "load_steps_done": len(r["taus"]),
+        "pressure_reached_mmHg": args.end_mmhg * r["tau_reached"], "load_steps_done": len(r["taus"]),
         "newton_steps_per_load_step": r["newton_per_load"],
         "accepted_steps": r["accepted_steps"], "rejected_steps": r["rejected_steps"], "cuts": r["cuts"],
         "pcg_iterations": {"mean": float(np.mean(its)), "max": int(np.max(its)), "total": int(np.sum(its))},
@@ -358,7 +361,8 @@ def main():
     ap.add_argument("--max-newton", type=int, default=12, help="tube load path: Newton steps per load step")
     ap.add_argument("--newton-eta-max", type=float, default=1e-3,
                     help="tube load path: loosest GMRES target of a Newton step (inexact Newton)")
-    ap.add_argument("--load-steps", type=int, default=40, help="tube load path: load increments to 16 mmHg")
+    ap.add_argument("--load-steps", type=int, default=40, help="tube load path: load increments to --end-mmhg")
+    ap.add_argument("--end-mmhg", type=float, default=16.0, help="tube load path: end pressure (mmHg)")
     ap.add_argument("--cold-start", action="store_true", help="tube load path: no multiplier warm starts")
     ap.add_argument("--kernel-tol", type=float, default=1e-6,
                     help="tube load path: rotations with ||K r|| <= tol ||K|| ||r|| join the local kernels")
