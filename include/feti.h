@@ -45,8 +45,9 @@ typedef enum {
                             input, all-floating problem without Dirichlet data      */
   FETI_ENOMEM = -2,      /* device memory could not be reserved                       */
   FETI_EDEVICE = -3,     /* no usable HIP device, or a HIP runtime error              */
-  FETI_ENOTSPD = -4,     /* non-positive pivot in a local or coarse factor;
-                            feti_last_error names the subdomain                       */
+  FETI_ENOTSPD = -4,     /* non-positive pivot in a local or coarse factor (non-finite
+                            only, where a refined step replaces non-positive local
+                            pivots); feti_last_error names the subdomain              */
   FETI_ENOCONV = -5,     /* max_it reached; outputs are still written,
                             stats.converged = 0                                        */
   FETI_ESTATE = -6,      /* feti_solve called before feti_factor                      */

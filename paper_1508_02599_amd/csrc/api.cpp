@@ -1037,7 +1037,8 @@ feti_status do_factor(feti_problem* p, const double* U_dev) {
   }
   autotune_step(p);
   if (errs[0] != 0x7fffffff) {
-    p->err = "non-positive pivot in the local factor of subdomain " + std::to_string(errs[0]);
+    p->err = std::string(p->allow_modified ? "non-finite" : "non-positive") + " pivot in the local factor of subdomain " +
+             std::to_string(errs[0]);
     p->factored = false;
     return FETI_ENOTSPD;
   }
