@@ -7,9 +7,10 @@ no CPU fallback.  It shares no code with the GPU path: the only common module
 is ``workloads`` (seeded problem descriptions, no solver arithmetic).
 
 Contents
-  fem        Q1 hexahedral element routines: isotropic linear elasticity and the
-             Holzapfel-Gasser-Ogden model with an element-condensed P0 pressure
-             (paper sections 2 and 3).
+  fem        Q1 (8-node) and Q2 (27-node) hexahedral element routines:
+             isotropic linear elasticity and the Holzapfel-Gasser-Ogden model
+             with an element-condensed P0 pressure (paper sections 2 and 3),
+             follower pressure on 4- and 9-node faces.
   monolithic the plain definition of what FETI computes: global assembly,
              Dirichlet elimination and a sparse direct FP64 solve (section 4
              states FETI as an exact reformulation of this system).

@@ -1,6 +1,6 @@
 """Seeded synthetic problem generators shared by the oracle, the tests and the benchmark.
 
-This package only describes problems: node coordinates, Q1 hexahedra, the
+This package only describes problems: node coordinates, Q1 or Q2 hexahedra, the
 subdomain of each element, materials, fibre directions, Dirichlet data, body
 forces and pressure faces.  It contains none of the solver's arithmetic
 (no element integrals, no tearing, no factorisation), so that the CPU oracle
