@@ -334,8 +334,10 @@ def workload_text(args, mesh):
         return (f"{args.config}: unit cube 64^3 Q1 elements in 8x8x8 {kind} boxes with seeded slab "
                 f"widths in 4..12 elements ({mesh.n_sub} subdomains of 300-6000 DOFs), E = 1, nu = 0.3, "
                 f"smooth random body force, {tail}")
-    return (f"{args.config}: unit cube 32^3 Q1 elements in 4x4x4 {kind} subdomains of 8^3 elements "
-            f"(2187 DOFs each), nu per subdomain ~ U[0.25,0.35] (seed 0), {tail}")
+    n_el, ns, q = mesh.meta["n_el"], mesh.meta["n_sub_axis"], mesh.order
+    h = n_el // ns
+    return (f"{args.config}: unit cube {n_el}^3 Q{q} elements in {ns}x{ns}x{ns} {kind} subdomains of {h}^3 "
+            f"elements ({3 * (q * h + 1) ** 3} DOFs each), nu per subdomain ~ U[0.25,0.35] (seed 0), {tail}")
 
 
 def main():

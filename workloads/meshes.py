@@ -329,6 +329,8 @@ def _cfg2_nu(seed: int, n_sub: int) -> np.ndarray:
 CONFIGS = {
     "cube8_s2": dict(kind="cube", n_el=8, n_sub_axis=2),
     "cube32_s4": dict(kind="cube", n_el=32, n_sub_axis=4, nu_seed=0),
+    # the nodes and subdomains of cube32_s4 with 16^3 Q2 elements
+    "cube_q2_16_s4": dict(kind="cube", n_el=16, n_sub_axis=4, nu_seed=0, order=2),
     "tube_16x128x64": dict(kind="tube", nr=16, nth=128, nz=64, sub=(1, 16, 8)),
     # the same tube with Q2-P0 elements of twice the size: the same nodes
     # (424,320 DOFs) and subdomains, 27-node elements
