@@ -352,3 +352,26 @@ def test_q2_kelvin_third_order():
         errs.append(_l2_error_q2(m, u, lambda x: kelvin_displacement(x, E, nu)))
     eoc = [np.log(errs[i] / errs[i + 1]) / np.log(2.0) for i in range(2)]
     assert 2.6 < eoc[0] < 3.4 and 2.8 < eoc[1] < 3.2, (errs, eoc)
+
+
+def test_q2_tube_recipe_geometry_and_face_orientation():
+    """The Q2 tube's nodes lie on their cylinders (mid-side nodes included),
+    it has the Q1 tube's element layers, media/adventitia split and fibres,
+    and every 9-node pressure face has dx/ds x dx/dt pointing out of the wall
+    (towards the axis) at its centre."""
+    m2 = tube_mesh(nr=2, nth=16, nz=4, sub=(1, 4, 2), order=2)
+    m1 = tube_mesh(nr=2, nth=16, nz=4, sub=(1, 4, 2))
+    r = np.sqrt(m2.xyz[:, 0] ** 2 + m2.xyz[:, 1] ** 2)
+    radii = 1.0 + 0.3 * np.arange(5) / 4
+    assert np.abs(r[:, None] - radii[None, :]).min(axis=1).max() < 1e-14
+    assert np.array_equal(m2.elem_mat, m1.elem_mat) and np.allclose(m2.fibers, m1.fibers)
+    xf = m2.xyz[m2.pface]
+    _, dLs = fem._lagrange3(0.0)
+    Ls, _ = fem._lagrange3(0.0)
+    ds = np.array([dLs[a % 3] * Ls[a // 3] for a in range(9)])
+    dt = np.array([Ls[a % 3] * dLs[a // 3] for a in range(9)])
+    n = np.cross(np.einsum("fad,a->fd", xf, ds), np.einsum("fad,a->fd", xf, dt))
+    c = xf[:, 4]
+    radial = n[:, 0] * c[:, 0] + n[:, 1] * c[:, 1]
+    assert (radial < 0).all()
+    assert np.allclose(np.sqrt(c[:, 0] ** 2 + c[:, 1] ** 2), 1.0)
