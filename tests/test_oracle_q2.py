@@ -375,3 +375,22 @@ def test_q2_tube_recipe_geometry_and_face_orientation():
     radial = n[:, 0] * c[:, 0] + n[:, 1] * c[:, 1]
     assert (radial < 0).all()
     assert np.allclose(np.sqrt(c[:, 0] ** 2 + c[:, 1] ** 2), 1.0)
+
+
+def test_q2_workloads_share_the_q1_nodes():
+    """tube_q2_8x64x32 has exactly the nodes (coordinates and numbering),
+    Dirichlet DOFs and subdomain boxes of tube_16x128x64, and cube_q2_16_s4
+    those of cube32_s4."""
+    from workloads import config_mesh
+    for q2, q1 in (("tube_q2_8x64x32", "tube_16x128x64"), ("cube_q2_16_s4", "cube32_s4")):
+        a, b = config_mesh(q2), config_mesh(q1)
+        assert a.order == 2 and b.order == 1
+        assert np.array_equal(a.xyz, b.xyz)
+        assert np.array_equal(a.dir_dof, b.dir_dof)
+        assert a.n_sub == b.n_sub
+        # the Q1 element whose first corner is a Q2 element's centre node lies
+        # inside that Q2 element: both are in the same subdomain box
+        centre = a.hex8[:, 13]
+        q1_sub_at_centre = np.full(b.n_nodes, -1)
+        np.put(q1_sub_at_centre, b.hex8[:, 0], b.elem_sub)
+        assert np.array_equal(q1_sub_at_centre[centre], a.elem_sub)
